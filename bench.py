@@ -1,0 +1,176 @@
+"""Throughput of the coupled hybrid-LB step on one MI355X.
+
+Workload: the 128^3 periodic blue-phase run -- simple-cubic double-twist
+(O2) initial Q of 4x4x4 unit cells of side 32 (q0 = pi/32), kappa = 0.7,
+tau = -0.5, Gamma = 0.3, xi = 0.7, LB tau = 2.5, fluid at rest.  Both forms
+are timed: FP32 (deviation populations, FP32 stencils) is the headline line,
+FP64 is reported beside it.
+
+Prints ONE JSON line.  MLUPS = lattice sites x steps / seconds / 1e6.  The
+step time comes from HIP events on the solver's stream around exactly
+`--steps` steps (after `--warmup` untimed steps), bracketed by device
+synchronisation.  The roofline object is for the kernel that takes the most
+time; its duration is measured in the same process with HIP events recorded
+around every launch on the solver's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+# Algorithmic values moved per site per launch (each array read or written
+# once): reads + writes.
+KERNEL_VALUES = {
+    "k_stress": 5 + 9,            # Q -> Pi
+    "k_lb": (19 + 9) + (19 + 3),  # g, Pi -> g', u
+    "k_qpred": (5 + 3) + 5,       # Q, u -> Q*
+    "k_qcorr": (5 + 5 + 3) + 5,   # Q, Q*, u -> Q
+}
+STATE_VALUES = 48  # f (19) and Q (5) read and written once
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(prec, n, steps, warmup, prof_steps):
+    import torch
+
+    from paper_0901_3293_amd import hlb
+    from paper_0901_3293_amd import inputs as I
+
+    p, Q, u, rho = I.bpii_case(n=n)
+    s = hlb.Solver((n, n, n), prec)
+    s.set_params(p)
+    s.set_fields(Q, u, rho)
+    stream = s.stream
+    s.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    s.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kern = s.step_timed(prof_steps)
+    torch.cuda.synchronize()
+    m, mom, ftot = s.totals()
+    esz = 4 if prec == "fp32" else 8
+    N = n ** 3
+    ms_step = ms / steps
+    mlups = N * steps / (ms / 1e3) / 1e6
+    per_launch = {k: v / prof_steps for k, v in kern.items()}
+    dom = max(per_launch, key=per_launch.get)
+    alg_bytes = KERNEL_VALUES[dom] * esz * N
+    achieved = alg_bytes / (per_launch[dom] / 1e3) / 1e9
+    step_values = sum(KERNEL_VALUES[k] for k in per_launch)
+    out = {
+        "mlups": mlups,
+        "ms_per_step": ms_step,
+        "kernel_ms_per_launch": per_launch,
+        "dominant_kernel": dom,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "alg_bytes_per_launch": alg_bytes},
+        "step_roofline": {
+            "bytes_per_site": step_values * esz,
+            "frac": mlups * 1e6 * step_values * esz / (HBM_PEAK_GBS * 1e9),
+            "frac_vs_state_minimum": mlups * 1e6 * STATE_VALUES * esz / (HBM_PEAK_GBS * 1e9),
+        },
+        "checks": {"mass": m, "momentum": [float(x) for x in mom], "free_energy": ftot,
+                   "finite": bool(math.isfinite(m) and math.isfinite(ftot))},
+    }
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(n, budget_s=15.0):
+    """The FP64 oracle (test infrastructure) on the host: steps of the same
+    128^3 workload until the time budget is spent (at least one step)."""
+    import oracle
+    from paper_0901_3293_amd import inputs as I
+
+    p, Q, u, rho = I.bpii_case(n=n)
+    st = oracle.State(oracle.params(**p.as_dict()), Q, u, rho)
+    st.step(1)  # warm caches and OpenMP pool
+    done, t0 = 0, time.perf_counter()
+    while True:
+        st.step(1)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n ** 3 * done / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{done} FP64 oracle steps of the {n}^3 workload ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--prof-steps", type=int, default=20)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (the step is single-device; --gpus {a.gpus} is not "
+              "supported)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    res = {}
+    for prec in ("fp32", "fp64"):
+        log(f"bench: {prec} {a.n}^3, warmup {a.warmup}, steps {a.steps}")
+        res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps)
+        log(f"bench: {prec} {res[prec]['mlups']:.1f} MLUPS, kernels {res[prec]['kernel_ms_per_launch']}")
+    cpu = None
+    if not a.no_cpu:
+        log("bench: cpu baseline (oracle)")
+        cpu = cpu_baseline(a.n, a.cpu_budget)
+    r32, r64 = res["fp32"], res["fp64"]
+    line = {
+        "metric": "coupled-step MLUPS (FP32 form; FP64 alongside) + % HBM roofline",
+        "value": r32["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"blue-phase O2 lattice {a.n}^3 periodic (4^3 cells of 32), D3Q19 "
+                               "hybrid LB, kappa=0.7 tau=-0.5",
+                   "lattice": [a.n, a.n, a.n], "sites": a.n ** 3, "parallelism": "single GPU"},
+        "roofline": r32["roofline"],
+        "step_roofline": r32["step_roofline"],
+        "kernel_ms_per_launch": r32["kernel_ms_per_launch"],
+        "fp64": {"value": r64["mlups"], "unit": "MLUPS", "dtype": "f64", "ms_per_step": r64["ms_per_step"],
+                 "roofline": r64["roofline"], "step_roofline": r64["step_roofline"],
+                 "kernel_ms_per_launch": r64["kernel_ms_per_launch"]},
+        "checks": {"fp32": r32["checks"], "fp64": r64["checks"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,156 @@
+/*
+ * hlb.h -- C-ABI of the MI355X hybrid lattice-Boltzmann solver for
+ * cholesteric liquid crystals (Henrich, Marenduzzo, Stratford, Cates,
+ * "Domain growth in cholesteric blue phases: hybrid lattice Boltzmann
+ * simulations").
+ *
+ * One time step (Sec. 2.2): the finite-difference side turns Q^n into the
+ * chemical stress and its divergence (Sec. 2.1, Eqs. (1), (2), (6)-(8);
+ * Sec. 2.2, Eq. (19)); a D3Q19 BGK lattice-Boltzmann collide-stream step with
+ * that body force gives u^n (Sec. 2.2, Eqs. (14), (16)); a predictor-corrector
+ * finite-difference step of the Beris-Edwards equation with the material
+ * derivative and co-rotation (Sec. 2.1, Eqs. (2)-(4)) gives Q^{n+1}.
+ * Lattice units dx = dt = 1, periodic in x, y and z.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status (hlb_status): 0 on success, < 0 on
+ *    error.  No C++ exception crosses this boundary.  Errors are sticky per
+ *    context: after a failure every later call on that context returns the
+ *    same code until hlb_destroy; hlb_last_error() gives the message.
+ *  - Host arrays are FP64, structure-of-arrays, component-major
+ *    [c][z][y][x] with x fastest (site index x + nx*(y + ny*z)).  Q uses the
+ *    five stored components (xx, xy, xz, yy, yz); Q_zz = -Q_xx - Q_yy.
+ *  - The caller owns the device workspace (hlb_workspace_bytes bytes, 256-byte
+ *    aligned device memory) and the HIP stream; both must outlive the
+ *    context.  The context owns only host-side metadata.
+ *  - Work is enqueued on the caller's stream.  hlb_step returns before the
+ *    GPU finishes; every hlb_get_* call synchronises that stream.
+ *  - One context per stream; a context must not be used from two threads at
+ *    once.
+ */
+#ifndef HLB_H
+#define HLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HLB_OK = 0,
+    HLB_ERR_ARG = -1,       /* null pointer, bad size, bad enum            */
+    HLB_ERR_PARAM = -2,     /* physical parameters outside their range     */
+    HLB_ERR_HIP = -3,       /* a HIP runtime call failed                   */
+    HLB_ERR_NONFINITE = -4, /* a reduction found NaN or Inf in the state   */
+    HLB_ERR_STATE = -5,     /* call out of order (e.g. step before fields) */
+    HLB_ERR_NOMEM = -6      /* workspace smaller than required             */
+} hlb_status;
+
+typedef enum { HLB_FP64 = 0, HLB_FP32 = 1 } hlb_precision;
+
+/* Opaque solver context. */
+typedef struct hlb_ctx hlb_ctx;
+
+/* LB parameters (Sec. 2.2, Eq. (16)): BGK relaxation time tau (> 1/2), giving
+ * kinematic viscosity (tau - 1/2)/3, and the reference density rho0 (> 0).
+ * Populations are stored as deviations g_i = f_i - w_i rho0. */
+typedef struct {
+    double tau;
+    double rho0;
+} hlb_lb_params;
+
+/* Landau-de Gennes free energy (Sec. 2.1, Eq. (1)): bulk scale A0 (> 0),
+ * control parameter gamma (> 0), one elastic constant K (>= 0) and q0 =
+ * 2 pi / pitch.  The one-constant form adds K/2 (d_b Q_ab)^2 to the printed
+ * chiral term. */
+typedef struct {
+    double A0;
+    double gamma;
+    double K;
+    double q0;
+} hlb_fe_params;
+
+/* Beris-Edwards kinetics (Sec. 2.1, Eqs. (2)-(4)): rotational diffusion
+ * constant Gamma (> 0), flow-aligning parameter xi, and the flow switch of
+ * Sec. 2.1: flow_coupling = 0 imposes u == 0 (pure relaxation; the LB state
+ * is left untouched), 1 couples the fluid. */
+typedef struct {
+    double Gamma;
+    double xi;
+    int flow_coupling;
+} hlb_be_params;
+
+/* Bytes of device workspace a context of this size and precision needs.
+ * Returns 0 if the arguments are invalid (any n < 4, unknown precision, or a
+ * lattice too large to index). */
+size_t hlb_workspace_bytes(int nx, int ny, int nz, int precision);
+
+/* Create a context on the current HIP device for an nx*ny*nz periodic lattice
+ * (each n >= 4).  device_workspace: caller-owned device memory of at least
+ * workspace_bytes bytes, 256-byte aligned.  hip_stream: a hipStream_t (may be
+ * NULL for the null stream).  On success *out receives the context. */
+int hlb_create(int nx, int ny, int nz, int precision, void *device_workspace,
+               size_t workspace_bytes, void *hip_stream, hlb_ctx **out);
+
+/* Map the reduced chirality kappa and reduced temperature tau of Sec. 2.1,
+ * Eqs. (9)-(10), with given q0 and A0, to (A0, gamma, K, q0):
+ *   gamma = 27 / (tau + 9),   K = kappa^2 A0 gamma / (108 q0^2).
+ * Host arithmetic only; needs no context.  Errors: HLB_ERR_ARG for a null out,
+ * HLB_ERR_PARAM for q0 == 0, A0 <= 0 or tau <= -9. */
+int hlb_fe_from_reduced(double kappa, double tau_ldg, double q0, double A0,
+                        hlb_fe_params *out);
+
+/* Set all physical parameters.  Rejected with HLB_ERR_PARAM: tau <= 1/2,
+ * rho0 <= 0, A0 <= 0, gamma <= 0, K < 0, Gamma <= 0, and the explicit
+ * diffusion bound 12 Gamma K >= 2 of the forward-Euler predictor.  Must be
+ * called before hlb_set_fields. */
+int hlb_set_params(hlb_ctx *ctx, const hlb_lb_params *lb, const hlb_fe_params *fe,
+                   const hlb_be_params *be);
+
+/* Load the state from host FP64 arrays: Q5 [5][N], u3 [3][N], rho [N].  The
+ * populations are stored so that the first pull of the next step returns the
+ * equilibrium f^eq(rho, u) at every site; a readout straight after this call
+ * reports u + F/(2 rho) (F from Q).  u3 or rho may be NULL (fluid at rest,
+ * rho = rho0).  Synchronous. */
+int hlb_set_fields(hlb_ctx *ctx, const double *Q5, const double *u3, const double *rho);
+
+/* Enqueue nsteps coupled steps on the context's stream (nsteps >= 0). */
+int hlb_step(hlb_ctx *ctx, int nsteps);
+
+/* Read the current time level into host FP64 arrays (any may be NULL):
+ * Q5 [5][N]; u3 [3][N] = (sum_i f_i e_i + F/2)/rho with F from the current Q
+ * (zero with flow off); rho [N].  Synchronises the stream. */
+int hlb_get_fields(hlb_ctx *ctx, double *Q5, double *u3, double *rho);
+
+/* FP64 totals at the current level: mass sum rho, momentum sum rho u (3),
+ * total free energy sum f.  Fixed-order two-stage device reduction.
+ * HLB_ERR_NONFINITE if any total is NaN or Inf.  Synchronises the stream. */
+int hlb_get_totals(hlb_ctx *ctx, double *mass, double *mom3, double *free_energy);
+
+/* Raw checkpoint of the state (populations and Q in the context's precision).
+ * hlb_state_bytes gives the size; get/set copy exactly that many bytes. */
+size_t hlb_state_bytes(hlb_ctx *ctx);
+int hlb_get_state(hlb_ctx *ctx, void *host_buf, size_t nbytes);
+int hlb_set_state(hlb_ctx *ctx, const void *host_buf, size_t nbytes);
+
+/* Diagnostics: enqueue nsteps steps with a HIP event pair recorded on the
+ * context's stream around every kernel launch, wait for them, and add each
+ * kernel kind's elapsed milliseconds into kernel_ms[k] (zeroed first;
+ * nkernels >= the number of kinds).  Returns the number of kernel kinds
+ * (>= 1) on success, < 0 on error.  The state advances exactly as with
+ * hlb_step.  hlb_kernel_name(k) names kind k ("" past the last). */
+int hlb_step_timed(hlb_ctx *ctx, int nsteps, double *kernel_ms, int nkernels);
+const char *hlb_kernel_name(int k);
+
+/* Message of the last error on this context ("" if none). Never NULL. */
+const char *hlb_last_error(const hlb_ctx *ctx);
+
+/* Release the context (the workspace and stream stay with the caller). */
+void hlb_destroy(hlb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLB_H */

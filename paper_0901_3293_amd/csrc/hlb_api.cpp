@@ -1,0 +1,279 @@
+// hlb_api.cpp -- the C-ABI of include/hlb.h: validation, workspace layout,
+// sticky error handling and the host side of every entry point.  All
+// arithmetic on the state runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/hlb.h"
+#include "kernels.h"
+
+struct hlb_ctx {
+    hlb::Device D;
+    hlb::PhysParams p;
+    int cur;
+    bool have_params;
+    bool have_fields;
+    int status;
+    char msg[512];
+    size_t state_bytes;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t g, Q, Qs, u, Pi, part, res, total;
+};
+
+bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
+{
+    if (nx < 4 || ny < 4 || nz < 4) return false;
+    if (precision != HLB_FP64 && precision != HLB_FP32) return false;
+    const double n = double(nx) * double(ny) * double(nz);
+    if (n >= 2147483647.0 / 2) return false;
+    const size_t N = size_t(nx) * ny * nz;
+    const size_t e = precision == HLB_FP64 ? 8 : 4;
+    L.g = align256(19 * N * e);
+    L.Q = align256(5 * N * e);
+    L.Qs = L.Q;
+    L.u = align256(3 * N * e);
+    L.Pi = align256(9 * N * e);
+    L.part = align256(hlb::partial_doubles(int(N)) * 8);
+    L.res = 256;
+    L.total = 2 * L.g + L.Q + L.Qs + L.u + L.Pi + L.part + L.res;
+    return true;
+}
+
+int set_error(hlb_ctx *c, int code, const char *fmt, ...)
+{
+    if (!c) return code;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->msg, sizeof(c->msg), fmt, ap);
+    va_end(ap);
+    c->status = code;
+    return code;
+}
+
+int hip_fail(hlb_ctx *c, hipError_t e, const char *what)
+{
+    return set_error(c, HLB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HLB_GUARD(c)                          \
+    do {                                      \
+        if (!(c)) return HLB_ERR_ARG;         \
+        if ((c)->status) return (c)->status;  \
+    } while (0)
+
+#define HIP_TRY(c, call)                                       \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
+    } while (0)
+
+double *stage_of(hlb_ctx *c) { return static_cast<double *>(c->D.g[c->cur ^ 1]); }
+
+}  // namespace
+
+extern "C" {
+
+size_t hlb_workspace_bytes(int nx, int ny, int nz, int precision)
+{
+    Layout L;
+    return make_layout(nx, ny, nz, precision, L) ? L.total : 0;
+}
+
+int hlb_create(int nx, int ny, int nz, int precision, void *ws, size_t ws_bytes, void *stream,
+               hlb_ctx **out)
+{
+    if (!out) return HLB_ERR_ARG;
+    *out = nullptr;
+    Layout L;
+    if (!make_layout(nx, ny, nz, precision, L)) return HLB_ERR_ARG;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return HLB_ERR_ARG;
+    if (ws_bytes < L.total) return HLB_ERR_NOMEM;
+    hlb_ctx *c = new (std::nothrow) hlb_ctx;
+    if (!c) return HLB_ERR_NOMEM;
+    std::memset(c, 0, sizeof(*c));
+    char *p = static_cast<char *>(ws);
+    c->D.G = {nx, ny, nz, nx * ny * nz};
+    c->D.fp32 = precision == HLB_FP32;
+    c->D.g[0] = p; p += L.g;
+    c->D.g[1] = p; p += L.g;
+    c->D.Q = p; p += L.Q;
+    c->D.Qs = p; p += L.Qs;
+    c->D.u = p; p += L.u;
+    c->D.Pi = p; p += L.Pi;
+    c->D.part = reinterpret_cast<double *>(p); p += L.part;
+    c->D.res = reinterpret_cast<double *>(p);
+    c->D.stream = static_cast<hipStream_t>(stream);
+    const size_t e = c->D.fp32 ? 4 : 8;
+    c->state_bytes = size_t(24) * c->D.G.N * e;
+    *out = c;
+    return HLB_OK;
+}
+
+int hlb_fe_from_reduced(double kappa, double tau_ldg, double q0, double A0, hlb_fe_params *out)
+{
+    if (!out) return HLB_ERR_ARG;
+    if (!(q0 != 0.0) || !(A0 > 0.0) || !(tau_ldg > -9.0) || !std::isfinite(kappa)) return HLB_ERR_PARAM;
+    const double gamma = 27.0 / (tau_ldg + 9.0);
+    out->A0 = A0;
+    out->gamma = gamma;
+    out->K = kappa * kappa * A0 * gamma / (108.0 * q0 * q0);
+    out->q0 = q0;
+    return HLB_OK;
+}
+
+int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe, const hlb_be_params *be)
+{
+    HLB_GUARD(c);
+    if (!lb || !fe || !be) return set_error(c, HLB_ERR_ARG, "null parameter struct");
+    if (!(lb->tau > 0.5)) return set_error(c, HLB_ERR_PARAM, "tau = %g must exceed 1/2", lb->tau);
+    if (!(lb->rho0 > 0.0)) return set_error(c, HLB_ERR_PARAM, "rho0 = %g must be positive", lb->rho0);
+    if (!(fe->A0 > 0.0)) return set_error(c, HLB_ERR_PARAM, "A0 = %g must be positive", fe->A0);
+    if (!(fe->gamma > 0.0)) return set_error(c, HLB_ERR_PARAM, "gamma = %g must be positive", fe->gamma);
+    if (!(fe->K >= 0.0)) return set_error(c, HLB_ERR_PARAM, "K = %g must be non-negative", fe->K);
+    if (!std::isfinite(fe->q0)) return set_error(c, HLB_ERR_PARAM, "q0 not finite");
+    if (!(be->Gamma > 0.0)) return set_error(c, HLB_ERR_PARAM, "Gamma = %g must be positive", be->Gamma);
+    if (!std::isfinite(be->xi)) return set_error(c, HLB_ERR_PARAM, "xi not finite");
+    if (!(12.0 * be->Gamma * fe->K < 2.0))
+        return set_error(c, HLB_ERR_PARAM, "12 Gamma K = %g violates the explicit diffusion bound 2",
+                         12.0 * be->Gamma * fe->K);
+    c->p = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi,
+            be->flow_coupling ? 1 : 0};
+    c->have_params = true;
+    return HLB_OK;
+}
+
+int hlb_set_fields(hlb_ctx *c, const double *Q5, const double *u3, const double *rho)
+{
+    HLB_GUARD(c);
+    if (!c->have_params) return set_error(c, HLB_ERR_STATE, "hlb_set_params must come first");
+    if (!Q5) return set_error(c, HLB_ERR_ARG, "Q5 is null");
+    const size_t N = c->D.G.N;
+    std::vector<double> host(9 * N);
+    for (size_t s = 0; s < N; ++s) host[s] = rho ? rho[s] : c->p.rho0;
+    if (u3)
+        std::memcpy(host.data() + N, u3, 3 * N * sizeof(double));
+    else
+        std::fill(host.begin() + N, host.begin() + 4 * N, 0.0);
+    std::memcpy(host.data() + 4 * N, Q5, 5 * N * sizeof(double));
+    double *stage = stage_of(c);
+    HIP_TRY(c, hipMemcpyAsync(stage, host.data(), 9 * N * sizeof(double), hipMemcpyHostToDevice, c->D.stream));
+    HIP_TRY(c, hlb::run_init(c->D, c->p, stage, c->cur));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
+    c->have_fields = true;
+    return HLB_OK;
+}
+
+int hlb_step(hlb_ctx *c, int nsteps)
+{
+    HLB_GUARD(c);
+    if (nsteps < 0) return set_error(c, HLB_ERR_ARG, "nsteps = %d", nsteps);
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "hlb_set_fields must come first");
+    HIP_TRY(c, hlb::run_steps(c->D, c->p, nsteps, c->cur));
+    return HLB_OK;
+}
+
+int hlb_get_fields(hlb_ctx *c, double *Q5, double *u3, double *rho)
+{
+    HLB_GUARD(c);
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
+    const size_t N = c->D.G.N;
+    double *stage = stage_of(c);
+    HIP_TRY(c, hlb::run_readout(c->D, c->p, c->cur, stage, nullptr));
+    if (rho) HIP_TRY(c, hipMemcpyAsync(rho, stage, N * 8, hipMemcpyDeviceToHost, c->D.stream));
+    if (u3) HIP_TRY(c, hipMemcpyAsync(u3, stage + N, 3 * N * 8, hipMemcpyDeviceToHost, c->D.stream));
+    if (Q5) HIP_TRY(c, hipMemcpyAsync(Q5, stage + 4 * N, 5 * N * 8, hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
+    return HLB_OK;
+}
+
+int hlb_get_totals(hlb_ctx *c, double *mass, double *mom3, double *free_energy)
+{
+    HLB_GUARD(c);
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
+    double r[5];
+    HIP_TRY(c, hlb::run_readout(c->D, c->p, c->cur, nullptr, c->D.res));
+    HIP_TRY(c, hipMemcpyAsync(r, c->D.res, sizeof(r), hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
+    const double m = double(c->D.G.N) * c->p.rho0 + r[0];
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(r[k])) return set_error(c, HLB_ERR_NONFINITE, "non-finite total (component %d)", k);
+    if (mass) *mass = m;
+    if (mom3)
+        for (int a = 0; a < 3; ++a) mom3[a] = r[1 + a];
+    if (free_energy) *free_energy = r[4];
+    return HLB_OK;
+}
+
+int hlb_step_timed(hlb_ctx *c, int nsteps, double *kernel_ms, int nkernels)
+{
+    HLB_GUARD(c);
+    if (nsteps < 0 || !kernel_ms || nkernels < hlb::K_COUNT)
+        return set_error(c, HLB_ERR_ARG, "hlb_step_timed: bad arguments");
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "hlb_set_fields must come first");
+    hlb::KernelTimer t;
+    hipError_t e = hlb::run_steps(c->D, c->p, nsteps, c->cur, &t);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->D.stream);
+    for (int k = 0; k < nkernels; ++k) kernel_ms[k] = 0.0;
+    for (auto &m : t.events) {
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.start, m.stop);
+        kernel_ms[m.kind] += ms;
+        (void)hipEventDestroy(m.start);
+        (void)hipEventDestroy(m.stop);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hlb_step_timed");
+    return hlb::K_COUNT;
+}
+
+const char *hlb_kernel_name(int k)
+{
+    const char *n = hlb::kernel_name(k);
+    return n ? n : "";
+}
+
+size_t hlb_state_bytes(hlb_ctx *c) { return c ? c->state_bytes : 0; }
+
+int hlb_get_state(hlb_ctx *c, void *buf, size_t nbytes)
+{
+    HLB_GUARD(c);
+    if (!buf || nbytes != c->state_bytes) return set_error(c, HLB_ERR_ARG, "state buffer size mismatch");
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
+    const size_t e = c->D.fp32 ? 4 : 8, N = c->D.G.N;
+    char *b = static_cast<char *>(buf);
+    HIP_TRY(c, hipMemcpyAsync(b, c->D.g[c->cur], 19 * N * e, hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipMemcpyAsync(b + 19 * N * e, c->D.Q, 5 * N * e, hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
+    return HLB_OK;
+}
+
+int hlb_set_state(hlb_ctx *c, const void *buf, size_t nbytes)
+{
+    HLB_GUARD(c);
+    if (!buf || nbytes != c->state_bytes) return set_error(c, HLB_ERR_ARG, "state buffer size mismatch");
+    if (!c->have_params) return set_error(c, HLB_ERR_STATE, "hlb_set_params must come first");
+    const size_t e = c->D.fp32 ? 4 : 8, N = c->D.G.N;
+    const char *b = static_cast<const char *>(buf);
+    HIP_TRY(c, hipMemcpyAsync(c->D.g[c->cur], b, 19 * N * e, hipMemcpyHostToDevice, c->D.stream));
+    HIP_TRY(c, hipMemcpyAsync(c->D.Q, b + 19 * N * e, 5 * N * e, hipMemcpyHostToDevice, c->D.stream));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
+    c->have_fields = true;
+    return HLB_OK;
+}
+
+const char *hlb_last_error(const hlb_ctx *c) { return c ? c->msg : "null context"; }
+
+void hlb_destroy(hlb_ctx *c) { delete c; }
+
+}  // extern "C"

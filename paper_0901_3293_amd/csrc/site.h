@@ -1,0 +1,292 @@
+// site.h -- per-site arithmetic of the hybrid step, templated on the storage
+// and arithmetic type T (double or float).  Pure device functions: no memory
+// access beyond their arguments, so every kernel shape (plain, LDS-tiled,
+// batched) shares one definition of the physics.
+//
+// Tensor conventions: Q is symmetric traceless, five stored components
+// (xx, xy, xz, yy, yz), Q_zz = -Q_xx - Q_yy.  d[g][c] = d_g Q_c (centred),
+// lap[c] = 7-point Laplacian.  W_ab = d_b u_a.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hlb {
+
+// Physical constants of one run, pre-combined in the arithmetic type.
+template <typename T>
+struct Coef {
+    T a;       // A0 (1 - gamma/3)                 bulk quadratic, Sec. 2.1 Eq. (1)
+    T bg;      // A0 gamma                         bulk cubic and quartic
+    T K;       // elastic constant
+    T q0x2;    // 2 q0
+    T Kq0x2;   // 2 K q0                           chiral term of H
+    T Kq0sq4;  // 4 K q0^2
+    T xi;      // flow-aligning parameter, Eqs. (4), (7)
+    T Gamma;   // rotational diffusion, Eq. (2)
+    T rho0;    // reference density of the deviation populations
+    T omega;   // 1 / tau_LB
+    T pref;    // 1 - 1/(2 tau_LB), second-order forcing prefactor
+};
+
+template <typename T>
+__device__ __forceinline__ void full3(const T q[5], T Q[3][3])
+{
+    Q[0][0] = q[0]; Q[0][1] = q[1]; Q[0][2] = q[2];
+    Q[1][0] = q[1]; Q[1][1] = q[3]; Q[1][2] = q[4];
+    Q[2][0] = q[2]; Q[2][1] = q[4]; Q[2][2] = -q[0] - q[3];
+}
+
+// d_g Q_ab as a full tensor from the stored components.
+template <typename T>
+__device__ __forceinline__ void full_grad(const T d[3][5], T dQ[3][3][3])
+{
+#pragma unroll
+    for (int g = 0; g < 3; ++g) full3(d[g], dQ[g]);
+}
+
+// (CQ)_ab = eps_agd d_g Q_db (the curl in Eq. (1)), written out:
+//   row x: d_y Q_zb - d_z Q_yb;  row y: d_z Q_xb - d_x Q_zb;  row z: d_x Q_yb - d_y Q_xb.
+template <typename T>
+__device__ __forceinline__ void curl(const T dQ[3][3][3], T CQ[3][3])
+{
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        CQ[0][b] = dQ[1][2][b] - dQ[2][1][b];
+        CQ[1][b] = dQ[2][0][b] - dQ[0][2][b];
+        CQ[2][b] = dQ[0][1][b] - dQ[1][0][b];
+    }
+}
+
+// Molecular field H (Eq. (2)), symmetric traceless part of -dF/dQ for the
+// free energy of Eq. (1) in its one-constant form:
+//   H = -a Q + bg (Q^2 - tr(Q^2)/3 I) - bg tr(Q^2) Q + K lap Q
+//       - 2 K q0 (CQ + CQ^T) - 4 K q0^2 Q.
+// Returns the five stored components; also hands back Q^2 and tr(Q^2).
+template <typename T>
+__device__ __forceinline__ void molecular_field(const Coef<T> &c, const T Q[3][3], const T CQ[3][3],
+                                                const T lap[5], T H[5], T Q2[3][3], T &trQ2)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Q2[a][b] = Q[a][0] * Q[0][b] + Q[a][1] * Q[1][b] + Q[a][2] * Q[2][b];
+    trQ2 = Q2[0][0] + Q2[1][1] + Q2[2][2];
+    const T third = T(1) / T(3);
+    const T lin = -(c.a + c.bg * trQ2 + c.Kq0sq4);
+    // (a,b) for the stored components
+    const int ia[5] = {0, 0, 0, 1, 1};
+    const int ib[5] = {0, 1, 2, 1, 2};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int a = ia[k], b = ib[k];
+        T v = lin * Q[a][b] + c.bg * Q2[a][b] + c.K * lap[k] - c.Kq0x2 * (CQ[a][b] + CQ[b][a]);
+        if (a == b) v -= c.bg * trQ2 * third;
+        H[k] = v;
+    }
+}
+
+// Free-energy density (Eq. (1) plus K/2 (d_b Q_ab)^2):
+//   f = a/2 tr Q^2 - bg/3 tr Q^3 + bg/4 (tr Q^2)^2 + K/2 |div Q|^2 + K/2 M:M,
+//   M = CQ + 2 q0 Q,  (div Q)_a = d_b Q_ab.
+template <typename T>
+__device__ __forceinline__ T free_energy(const Coef<T> &c, const T Q[3][3], const T Q2[3][3], T trQ2,
+                                         const T div[3], const T M[3][3])
+{
+    T trQ3 = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) trQ3 += Q2[a][b] * Q[b][a];
+    T mm = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) mm += M[a][b] * M[a][b];
+    const T dd = div[0] * div[0] + div[1] * div[1] + div[2] * div[2];
+    return T(0.5) * c.a * trQ2 - c.bg * trQ3 / T(3) + T(0.25) * c.bg * trQ2 * trQ2 + T(0.5) * c.K * (dd + mm);
+}
+
+// Chemical stress (Eqs. (6)-(8), the rho T part of the pressure left to the
+// lattice): Pi_ab = f d_ab + sigma^xi_ab - G_ab + tau_ab with
+//   sigma^xi = 2 xi (Q + I/3)(Q:H) - xi (HQ + QH + 2H/3),
+//   tau      = QH - HQ,
+//   G_ab     = d_a Q_gn Phi_gnb,  Phi_gnb = K [d_nb (div Q)_g + eps_lbg M_ln],
+// i.e. G_ab = K [ d_a Q_gb (div Q)_g + eps_bgl d_a Q_gn M_ln ].
+// Also returns f and H (five components).
+template <typename T>
+__device__ __forceinline__ void site_stress(const Coef<T> &c, const T q[5], const T d[3][5],
+                                            const T lap[5], T Pi[3][3], T &fdens, T H5[5])
+{
+    T Q[3][3], dQ[3][3][3], CQ[3][3], Q2[3][3], trQ2;
+    full3(q, Q);
+    full_grad(d, dQ);
+    curl(dQ, CQ);
+    molecular_field(c, Q, CQ, lap, H5, Q2, trQ2);
+    T H[3][3];
+    full3(H5, H);
+
+    T M[3][3], div[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) M[a][b] = CQ[a][b] + c.q0x2 * Q[a][b];
+        div[a] = dQ[0][a][0] + dQ[1][a][1] + dQ[2][a][2];
+    }
+    fdens = free_energy(c, Q, Q2, trQ2, div, M);
+
+    T HQ[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) HQ[a][b] = H[a][0] * Q[0][b] + H[a][1] * Q[1][b] + H[a][2] * Q[2][b];
+    T QdH = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) QdH += Q[a][b] * H[a][b];
+
+    const T third = T(1) / T(3);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            // G_ab; the eps_bgl M-contraction written out per column b
+            T g = dQ[a][0][b] * div[0] + dQ[a][1][b] * div[1] + dQ[a][2][b] * div[2];
+            const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+#pragma unroll
+            for (int n = 0; n < 3; ++n) g += dQ[a][b1][n] * M[b2][n] - dQ[a][b2][n] * M[b1][n];
+            g *= c.K;
+            // HQ^T = QH for symmetric H and Q
+            T sxi = T(2) * c.xi * (Q[a][b] + (a == b ? third : T(0))) * QdH
+                  - c.xi * (HQ[a][b] + HQ[b][a] + T(2) * third * H[a][b]);
+            T tau = HQ[b][a] - HQ[a][b];
+            Pi[a][b] = (a == b ? fdens : T(0)) + sxi - g + tau;
+        }
+    }
+}
+
+// Right-hand side of the Q equation (Eqs. (2)-(4)) projected on symmetric
+// traceless tensors:
+//   R = P_T[ -u.grad Q + S(W,Q) + Gamma H ],
+//   S = xi (D A + A D) + (w A - A w) - 2 xi A tr(Q W),  A = Q + I/3,
+//   D = (W + W^T)/2, w = (W - W^T)/2, W_ab = d_b u_a.
+template <typename T>
+__device__ __forceinline__ void site_rhs(const Coef<T> &c, const T q[5], const T d[3][5], const T lap[5],
+                                         const T u[3], const T W[3][3], T R[5])
+{
+    T Q[3][3], dQ[3][3][3], CQ[3][3], Q2[3][3], trQ2, H5[5];
+    full3(q, Q);
+    full_grad(d, dQ);
+    curl(dQ, CQ);
+    molecular_field(c, Q, CQ, lap, H5, Q2, trQ2);
+
+    T D[3][3], w[3][3], A[3][3];
+    const T third = T(1) / T(3);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            D[a][b] = T(0.5) * (W[a][b] + W[b][a]);
+            w[a][b] = T(0.5) * (W[a][b] - W[b][a]);
+            A[a][b] = Q[a][b] + (a == b ? third : T(0));
+        }
+    T trQW = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) trQW += Q[a][b] * D[a][b];
+
+    // upper triangle of X = -u.grad Q + S + Gamma H (X is symmetric)
+    const int ia[6] = {0, 0, 0, 1, 1, 2};
+    const int ib[6] = {0, 1, 2, 1, 2, 2};
+    T X[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int a = ia[k], b = ib[k];
+        T da = T(0), wa = T(0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            da += D[a][m] * A[m][b] + A[a][m] * D[m][b];
+            wa += w[a][m] * A[m][b] - A[a][m] * w[m][b];
+        }
+        T S = c.xi * da + wa - T(2) * c.xi * A[a][b] * trQW;
+        T adv = u[0] * dQ[0][a][b] + u[1] * dQ[1][a][b] + u[2] * dQ[2][a][b];
+        T h = (k < 5) ? H5[k] : -H5[0] - H5[3];
+        X[k] = -adv + S + c.Gamma * h;
+    }
+    const T tr3 = (X[0] + X[3] + X[5]) * third;
+    R[0] = X[0] - tr3;
+    R[1] = X[1];
+    R[2] = X[2];
+    R[3] = X[3] - tr3;
+    R[4] = X[4];
+}
+
+// ---------------------------------------------------------------- D3Q19
+// Velocity order (also the order of the populations in the state):
+// 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 = edges (+x+y)(-x-y)(+x-y)(-x+y)
+// (+x+z)(-x-z)(+x-z)(-x+z)(+y+z)(-y-z)(+y-z)(-y+z).  Weights 1/3, 1/18, 1/36.
+constexpr int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+template <typename T>
+__device__ __forceinline__ T lb_weight(int i)
+{
+    return i == 0 ? T(1) / T(3) : (i <= 6 ? T(1) / T(18) : T(1) / T(36));
+}
+
+// Density deviation and bare momentum of the pulled deviations; pairs of
+// opposite velocities are differenced first so the momentum keeps the
+// precision of the small dynamical part.
+template <typename T>
+__device__ __forceinline__ void lb_moments(const T g[19], T &drho, T j[3])
+{
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) s += g[i];
+    drho = s;
+    j[0] = (g[1] - g[2]) + (g[7] - g[8]) + (g[9] - g[10]) + (g[11] - g[12]) + (g[13] - g[14]);
+    j[1] = (g[3] - g[4]) + (g[7] - g[8]) + (g[10] - g[9]) + (g[15] - g[16]) + (g[17] - g[18]);
+    j[2] = (g[5] - g[6]) + (g[11] - g[12]) + (g[14] - g[13]) + (g[15] - g[16]) + (g[18] - g[17]);
+}
+
+// BGK collision with second-order forcing on the deviations (Eq. (16) on
+// D3Q19): rho = rho0 + drho, u = (j + F/2)/rho,
+//   g_i' = g_i - (g_i - g_i^eq)/tau + (1 - 1/(2 tau)) w_i [3(e_i - u) + 9 (e_i.u) e_i].F,
+//   g_i^eq = w_i drho + w_i rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2).
+// g is updated in place; u and rho are returned.
+template <typename T>
+__device__ __forceinline__ void lb_collide(const Coef<T> &c, T g[19], const T F[3], T u[3], T &rho)
+{
+    T drho, j[3];
+    lb_moments(g, drho, j);
+    rho = c.rho0 + drho;
+    const T irho = T(1) / rho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + T(0.5) * F[a]) * irho;
+    const T uu15 = T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    const T keep = T(1) - c.omega;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const T w = lb_weight<T>(i);
+        const T eu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
+        const T eF = T(CX[i]) * F[0] + T(CY[i]) * F[1] + T(CZ[i]) * F[2];
+        const T geq = w * drho + w * rho * (T(3) * eu + T(4.5) * eu * eu - uu15);
+        const T src = c.pref * w * (T(3) * (eF - uF) + T(9) * eu * eF);
+        g[i] = keep * g[i] + c.omega * geq + src;
+    }
+}
+
+// Equilibrium deviation for initialisation.
+template <typename T>
+__device__ __forceinline__ T lb_geq(const Coef<T> &c, int i, T rho, const T u[3])
+{
+    const T w = lb_weight<T>(i);
+    const T eu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return w * (rho - c.rho0) + w * rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
+}
+
+}  // namespace hlb

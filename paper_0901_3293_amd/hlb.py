@@ -1,0 +1,194 @@
+"""Thin ctypes binding of the C-ABI in ``include/hlb.h``.
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libhlb.so``.  PyTorch supplies the device workspace (a uint8 tensor kept
+alive by the solver object) and the HIP stream.  The library must have been
+built (``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhlb.so")
+
+HLB_FP64, HLB_FP32 = 0, 1
+STATUS = {0: "HLB_OK", -1: "HLB_ERR_ARG", -2: "HLB_ERR_PARAM", -3: "HLB_ERR_HIP",
+          -4: "HLB_ERR_NONFINITE", -5: "HLB_ERR_STATE", -6: "HLB_ERR_NOMEM"}
+
+
+class HlbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class LbParams(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("rho0", ctypes.c_double)]
+
+
+class FeParams(ctypes.Structure):
+    _fields_ = [("A0", ctypes.c_double), ("gamma", ctypes.c_double), ("K", ctypes.c_double),
+                ("q0", ctypes.c_double)]
+
+
+class BeParams(ctypes.Structure):
+    _fields_ = [("Gamma", ctypes.c_double), ("xi", ctypes.c_double), ("flow_coupling", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhlb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, I, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_size_t
+        L.hlb_workspace_bytes.argtypes = [I, I, I, I]
+        L.hlb_workspace_bytes.restype = sz
+        L.hlb_create.argtypes = [I, I, I, I, vp, sz, vp, ctypes.POINTER(vp)]
+        L.hlb_fe_from_reduced.argtypes = [ctypes.c_double] * 4 + [ctypes.POINTER(FeParams)]
+        L.hlb_set_params.argtypes = [vp, ctypes.POINTER(LbParams), ctypes.POINTER(FeParams),
+                                     ctypes.POINTER(BeParams)]
+        L.hlb_set_fields.argtypes = [vp, dp, dp, dp]
+        L.hlb_step.argtypes = [vp, I]
+        L.hlb_get_fields.argtypes = [vp, dp, dp, dp]
+        L.hlb_get_totals.argtypes = [vp, dp, dp, dp]
+        L.hlb_state_bytes.argtypes = [vp]
+        L.hlb_state_bytes.restype = sz
+        L.hlb_get_state.argtypes = [vp, vp, sz]
+        L.hlb_set_state.argtypes = [vp, vp, sz]
+        L.hlb_step_timed.argtypes = [vp, I, dp, I]
+        L.hlb_kernel_name.argtypes = [I]
+        L.hlb_kernel_name.restype = ctypes.c_char_p
+        L.hlb_last_error.argtypes = [vp]
+        L.hlb_last_error.restype = ctypes.c_char_p
+        L.hlb_destroy.argtypes = [vp]
+        L.hlb_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def fe_from_reduced(kappa, tau_ldg, q0, A0=0.01):
+    out = FeParams()
+    rc = lib().hlb_fe_from_reduced(kappa, tau_ldg, q0, A0, ctypes.byref(out))
+    if rc:
+        raise HlbError(rc, "hlb_fe_from_reduced")
+    return out
+
+
+def workspace_bytes(nx, ny, nz, precision=HLB_FP64):
+    return lib().hlb_workspace_bytes(nx, ny, nz, precision)
+
+
+class Solver:
+    """One hybrid-LB context on the current CUDA/HIP device.
+
+    ``shape`` is (nx, ny, nz); host arrays are float64 ``[c][z][y][x]``.
+    """
+
+    def __init__(self, shape, precision="fp64", device="cuda", stream=None):
+        self.shape = tuple(int(n) for n in shape)
+        self.prec = {"fp64": HLB_FP64, "fp32": HLB_FP32}[precision]
+        L = lib()
+        nbytes = L.hlb_workspace_bytes(*self.shape, self.prec)
+        if nbytes == 0:
+            raise HlbError(-1, f"invalid lattice {self.shape}")
+        self.device = torch.device(device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        rc = L.hlb_create(*self.shape, self.prec, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc:
+            raise HlbError(rc, "hlb_create")
+        self.ctx = ctx
+
+    @property
+    def N(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+    def _check(self, rc):
+        if rc:
+            raise HlbError(rc, lib().hlb_last_error(self.ctx).decode())
+
+    def set_params(self, p):
+        """p: any object with tau, rho0, A0, gamma, K, q0, Gamma, xi, flow."""
+        lb = LbParams(p.tau, p.rho0)
+        fe = FeParams(p.A0, p.gamma, p.K, p.q0)
+        be = BeParams(p.Gamma, p.xi, 1 if p.flow else 0)
+        self._check(lib().hlb_set_params(self.ctx, ctypes.byref(lb), ctypes.byref(fe), ctypes.byref(be)))
+
+    def set_fields(self, Q5, u3=None, rho=None):
+        nx, ny, nz = self.shape
+        Q5 = np.ascontiguousarray(Q5, dtype=np.float64)
+        assert Q5.shape == (5, nz, ny, nx)
+        if u3 is not None:
+            u3 = np.ascontiguousarray(u3, dtype=np.float64)
+            assert u3.shape == (3, nz, ny, nx)
+        if rho is not None:
+            rho = np.ascontiguousarray(rho, dtype=np.float64)
+            assert rho.shape == (nz, ny, nx)
+        self._check(lib().hlb_set_fields(self.ctx, _dp(Q5), _dp(u3), _dp(rho)))
+
+    def step(self, n=1):
+        self._check(lib().hlb_step(self.ctx, int(n)))
+
+    def step_timed(self, n=1):
+        """Advance n steps timing every kernel with HIP events on the solver's
+        stream; returns {kernel name: total milliseconds}."""
+        ms = np.zeros(16)
+        k = lib().hlb_step_timed(self.ctx, int(n), _dp(ms), ms.size)
+        if k < 0:
+            self._check(k)
+        return {lib().hlb_kernel_name(i).decode(): float(ms[i]) for i in range(k)}
+
+    def fields(self):
+        nx, ny, nz = self.shape
+        Q5 = np.empty((5, nz, ny, nx))
+        u3 = np.empty((3, nz, ny, nx))
+        rho = np.empty((nz, ny, nx))
+        self._check(lib().hlb_get_fields(self.ctx, _dp(Q5), _dp(u3), _dp(rho)))
+        return Q5, u3, rho
+
+    def totals(self):
+        m = np.zeros(1)
+        mom = np.zeros(3)
+        f = np.zeros(1)
+        self._check(lib().hlb_get_totals(self.ctx, _dp(m), _dp(mom), _dp(f)))
+        return float(m[0]), mom, float(f[0])
+
+    def get_state(self):
+        n = lib().hlb_state_bytes(self.ctx)
+        buf = np.empty(n, dtype=np.uint8)
+        self._check(lib().hlb_get_state(self.ctx, buf.ctypes.data_as(ctypes.c_void_p), n))
+        return buf
+
+    def set_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(lib().hlb_set_state(self.ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().hlb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

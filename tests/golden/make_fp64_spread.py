@@ -1,0 +1,68 @@
+"""Write tests/golden/fp64_spread.json: how far two valid FP64 evaluations of
+the same 32^3 helix run drift apart per step when only the rounding order
+differs (the oracle built as usual vs the same source built with FMA
+contraction).  The velocity is a small difference of O(1e-4) stresses, so its
+relative spread sits well above 1e-12; the GPU bound for u is stated relative
+to this spread.  Calls only the oracle."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+
+def run(libpath, nsteps):
+    code = f"""
+import os, sys, numpy as np
+os.environ['HLB_ORACLE_LIB'] = {libpath!r}
+sys.path.insert(0, {ROOT!r})
+import oracle
+from paper_0901_3293_amd import inputs as I
+p, Q, u, rho = I.helix_case()
+st = oracle.State(oracle.params(**p.as_dict()), Q, u, rho)
+for n in range({nsteps}):
+    st.step(1)
+    q, uu, r = st.fields()
+    np.save({libpath!r} + f'.{{n}}.npy', np.concatenate([q.ravel(), uu.ravel(), r.ravel()]))
+"""
+    subprocess.check_call([sys.executable, "-c", code])
+
+
+def main(nsteps=100):
+    import oracle
+    tmp = os.path.join(ROOT, "oracle", "_spread")
+    os.makedirs(tmp, exist_ok=True)
+    plain = os.path.join(tmp, "plain.so")
+    fma = os.path.join(tmp, "fma.so")
+    src = os.path.join(ROOT, "oracle", "hlb_oracle.c")
+    base = [f for f in oracle.CFLAGS if f != "-ffp-contract=off"]
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", plain, src, "-lm"])
+    subprocess.check_call(["gcc", *base, "-ffp-contract=fast", "-mfma", "-o", fma, src, "-lm"])
+    run(plain, nsteps)
+    run(fma, nsteps)
+    N = 32 ** 3
+    spread = {"Q": [], "u": [], "rho": []}
+    for n in range(nsteps):
+        a = np.load(plain + f".{n}.npy")
+        b = np.load(fma + f".{n}.npy")
+        for k, sl in (("Q", slice(0, 5 * N)), ("u", slice(5 * N, 8 * N)), ("rho", slice(8 * N, 9 * N))):
+            spread[k].append(float(np.abs(a[sl] - b[sl]).max() / np.abs(a[sl]).max()))
+    for f in os.listdir(tmp):
+        os.remove(os.path.join(tmp, f))
+    os.rmdir(tmp)
+    out = {"workload": "32^3 helix, q0 = 2 pi/16, kappa = 1, tau = 0, noise 1e-4 seed 1, FP64",
+           "what": "max|a-b|/max|a| per step between the oracle built -ffp-contract=off and "
+                   "built with FMA contraction",
+           "spread": spread}
+    with open(os.path.join(HERE, "fp64_spread.json"), "w") as fh:
+        json.dump(out, fh)
+    print({k: (v[0], v[9], v[-1]) for k, v in spread.items()})
+
+
+if __name__ == "__main__":
+    main()
