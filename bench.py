@@ -126,6 +126,10 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
+                    help="time one form only (profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (the step is single-device; --gpus {a.gpus} is not "
@@ -134,8 +138,17 @@ def main():
     import torch
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if a.copy_probe:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy probe 512 MiB x3 done")
+        del src, dst
     res = {}
-    for prec in ("fp32", "fp64"):
+    forms = (a.only,) if a.only else ("fp32", "fp64")
+    for prec in forms:
         log(f"bench: {prec} {a.n}^3, warmup {a.warmup}, steps {a.steps}")
         res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps)
         log(f"bench: {prec} {res[prec]['mlups']:.1f} MLUPS, kernels {res[prec]['kernel_ms_per_launch']}")
@@ -143,6 +156,9 @@ def main():
     if not a.no_cpu:
         log("bench: cpu baseline (oracle)")
         cpu = cpu_baseline(a.n, a.cpu_budget)
+    if a.only:
+        print(json.dumps({"profiling_run": a.only, **res[a.only]}), flush=True)
+        return
     r32, r64 = res["fp32"], res["fp64"]
     line = {
         "metric": "coupled-step MLUPS (FP32 form; FP64 alongside) + % HBM roofline",

@@ -1,0 +1,83 @@
+"""Summarise rocprofv3 result databases (kernel trace + FETCH_SIZE/WRITE_SIZE
+passes) into a short text table: per kernel, average duration, HBM bytes per
+dispatch (counter KiB scaled by the reading of a plain copy of known size),
+and the algorithmic bytes the kernel has to move.
+
+usage: python -m paper_0901_3293_amd.profsum TRACE_DB FETCH_DB WRITE_DB
+       --copy-bytes 536870912 --alg k_lb=VALUES ... --esz 4 --sites N
+"""
+from __future__ import annotations
+
+import argparse
+import re
+import sqlite3
+from collections import defaultdict
+
+
+def short(name):
+    m = re.search(r"(k_\w+|__amd_rocclr_copyBuffer)", name)
+    return m.group(1) if m else name[:40]
+
+
+def trace(db):
+    con = sqlite3.connect(db)
+    d = defaultdict(list)
+    for name, dur in con.execute("select name, duration from kernels"):
+        d[short(name)].append(dur)
+    return {k: (len(v), sum(v) / len(v) / 1e3) for k, v in d.items()}  # us
+
+
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def counter(db, cname):
+    """KiB per dispatch, averaged per kernel.  For the runtime's copy kernel
+    only the dispatches of the calibration copy (the largest ones) count."""
+    con = sqlite3.connect(db)
+    d = defaultdict(list)
+    for name, v in con.execute("select name, counter_value from pmc_events where counter_name = ?", (cname,)):
+        d[short(name)].append(v)
+    if COPY in d:
+        top = max(d[COPY])
+        d[COPY] = [v for v in d[COPY] if v > 0.5 * top]
+    return {k: sum(v) / len(v) for k, v in d.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("trace_db")
+    ap.add_argument("fetch_db")
+    ap.add_argument("write_db")
+    ap.add_argument("--copy-bytes", type=float, default=512 * 2 ** 20)
+    ap.add_argument("--sites", type=int, required=True)
+    ap.add_argument("--esz", type=int, required=True)
+    ap.add_argument("--alg", nargs="*", default=[], help="kernel=values_per_site")
+    ap.add_argument("--title", default="")
+    ap.add_argument("--command", default="")
+    a = ap.parse_args()
+    alg = {k: float(v) for k, v in (x.split("=") for x in a.alg)}
+    t = trace(a.trace_db)
+    fe = counter(a.fetch_db, "FETCH_SIZE")
+    wr = counter(a.write_db, "WRITE_SIZE")
+    cname = COPY
+    fscale = a.copy_bytes / (fe[cname] * 1024)
+    wscale = a.copy_bytes / (wr[cname] * 1024)
+    print(f"# {a.title}")
+    if a.command:
+        print(f"command: {a.command}")
+    print(f"copy calibration: {a.copy_bytes / 2**20:.0f} MiB copy reads FETCH_SIZE {fe[cname]:.0f} KiB, "
+          f"WRITE_SIZE {wr[cname]:.0f} KiB -> scale fetch x{fscale:.3f}, write x{wscale:.3f}")
+    print(f"{'kernel':12s} {'calls':>5s} {'avg_us':>9s} {'fetch_MB':>9s} {'write_MB':>9s} {'hbm_MB':>8s} "
+          f"{'alg_MB':>8s} {'hbm/alg':>7s} {'alg_GB/s':>9s} {'hbm_GB/s':>9s}")
+    for k, (n, us) in sorted(t.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+        if k == cname:
+            continue
+        f = fe.get(k, float("nan")) * 1024 * fscale / 1e6
+        w = wr.get(k, float("nan")) * 1024 * wscale / 1e6
+        al = alg.get(k, float("nan")) * a.esz * a.sites / 1e6
+        print(f"{k:12s} {n:5d} {us:9.2f} {f:9.1f} {w:9.1f} {f + w:8.1f} {al:8.1f} {(f + w) / al:7.2f} "
+              f"{al / us * 1e3:9.0f} {(f + w) / us * 1e3:9.0f}")
+
+
+if __name__ == "__main__":
+    main()
