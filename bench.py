@@ -30,10 +30,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Algorithmic values moved per site per launch (each array read or written
 # once): reads + writes.
 KERNEL_VALUES = {
+    # per-site schedule (95 values per site per step)
     "k_stress": 5 + 9,            # Q -> Pi
     "k_lb": (19 + 9) + (19 + 3),  # g, Pi -> g', u
     "k_qpred": (5 + 3) + 5,       # Q, u -> Q*
     "k_qcorr": (5 + 5 + 3) + 5,   # Q, Q*, u -> Q
+    # tiled schedule (65 values per site per step)
+    "k_qforce": 5 + 3,            # Q -> F
+    "k_lbf": (19 + 3) + (19 + 3),  # g, F -> g', u
+    "k_qupdate": (5 + 3) + 5,     # Q, u -> Q'
 }
 STATE_VALUES = 48  # f (19) and Q (5) read and written once
 
@@ -42,7 +47,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(prec, n, steps, warmup, prof_steps):
+def run_form(prec, n, steps, warmup, prof_steps, schedule="auto"):
     import torch
 
     from paper_0901_3293_amd import hlb
@@ -52,6 +57,11 @@ def run_form(prec, n, steps, warmup, prof_steps):
     s = hlb.Solver((n, n, n), prec)
     s.set_params(p)
     s.set_fields(Q, u, rho)
+    if schedule == "auto":
+        sched, tz, _ = s.autotune(10)
+    else:
+        s.set_schedule(schedule, 0)
+        sched, tz = s.schedule()
     stream = s.stream
     s.step(warmup)
     torch.cuda.synchronize()
@@ -69,13 +79,14 @@ def run_form(prec, n, steps, warmup, prof_steps):
     N = n ** 3
     ms_step = ms / steps
     mlups = N * steps / (ms / 1e3) / 1e6
-    per_launch = {k: v / prof_steps for k, v in kern.items()}
+    per_launch = {k: v / prof_steps for k, v in kern.items() if v > 0}
     dom = max(per_launch, key=per_launch.get)
     alg_bytes = KERNEL_VALUES[dom] * esz * N
     achieved = alg_bytes / (per_launch[dom] / 1e3) / 1e9
     step_values = sum(KERNEL_VALUES[k] for k in per_launch)
     out = {
         "mlups": mlups,
+        "schedule": {"name": sched, "tz": tz},
         "ms_per_step": ms_step,
         "kernel_ms_per_launch": per_launch,
         "dominant_kernel": dom,
@@ -128,6 +139,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
                     help="time one form only (profiling runs)")
+    ap.add_argument("--schedule", choices=["auto", "sites", "tiled"], default="auto",
+                    help="step schedule (auto: the library's autotuner picks)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -150,7 +163,7 @@ def main():
     forms = (a.only,) if a.only else ("fp32", "fp64")
     for prec in forms:
         log(f"bench: {prec} {a.n}^3, warmup {a.warmup}, steps {a.steps}")
-        res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps)
+        res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps, a.schedule)
         log(f"bench: {prec} {res[prec]['mlups']:.1f} MLUPS, kernels {res[prec]['kernel_ms_per_launch']}")
     cpu = None
     if not a.no_cpu:
@@ -179,7 +192,9 @@ def main():
         "roofline": r32["roofline"],
         "step_roofline": r32["step_roofline"],
         "kernel_ms_per_launch": r32["kernel_ms_per_launch"],
+        "schedule": r32["schedule"],
         "fp64": {"value": r64["mlups"], "unit": "MLUPS", "dtype": "f64", "ms_per_step": r64["ms_per_step"],
+                 "schedule": r64["schedule"],
                  "roofline": r64["roofline"], "step_roofline": r64["step_roofline"],
                  "kernel_ms_per_launch": r64["kernel_ms_per_launch"]},
         "checks": {"fp32": r32["checks"], "fp64": r64["checks"]},

@@ -134,6 +134,23 @@ size_t hlb_state_bytes(hlb_ctx *ctx);
 int hlb_get_state(hlb_ctx *ctx, void *host_buf, size_t nbytes);
 int hlb_set_state(hlb_ctx *ctx, const void *host_buf, size_t nbytes);
 
+/* Step schedules.  HLB_SCHED_SITES: four sweeps with one lattice site per
+ * thread (stress to HBM, LB with its divergence, predictor, corrector in
+ * place).  HLB_SCHED_TILED: three sweeps in which 2.5D z-marching LDS tiles
+ * hold the stress and the predictor stage (recomputed on a one-site halo
+ * ring), tz planes per tile column (0: 16).  Both give the same step to
+ * rounding.  The default is HLB_SCHED_SITES. */
+enum { HLB_SCHED_SITES = 0, HLB_SCHED_TILED = 1 };
+int hlb_set_schedule(hlb_ctx *ctx, int schedule, int tz);
+int hlb_get_schedule(const hlb_ctx *ctx, int *schedule, int *tz);
+
+/* Autotuner: time trial_steps steps of every candidate schedule (per-site;
+ * tiled with tz = 8, 16, 32) on this context's lattice and precision with HIP
+ * events on its stream, keep the fastest, and put the state back as it was
+ * (through a host copy of hlb_state_bytes bytes).  *best_ms_per_step (may be
+ * NULL) receives the winner's time per step.  Synchronises the stream. */
+int hlb_autotune(hlb_ctx *ctx, int trial_steps, double *best_ms_per_step);
+
 /* Diagnostics: enqueue nsteps steps with a HIP event pair recorded on the
  * context's stream around every kernel launch, wait for them, and add each
  * kernel kind's elapsed milliseconds into kernel_ms[k] (zeroed first;

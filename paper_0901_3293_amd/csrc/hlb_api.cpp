@@ -16,7 +16,6 @@
 struct hlb_ctx {
     hlb::Device D;
     hlb::PhysParams p;
-    int cur;
     bool have_params;
     bool have_fields;
     int status;
@@ -29,7 +28,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, Q, Qs, u, Pi, part, res, total;
+    size_t g, Q, u, Pi, part, res, total;
 };
 
 bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
@@ -42,12 +41,11 @@ bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
     const size_t e = precision == HLB_FP64 ? 8 : 4;
     L.g = align256(19 * N * e);
     L.Q = align256(5 * N * e);
-    L.Qs = L.Q;
     L.u = align256(3 * N * e);
     L.Pi = align256(9 * N * e);
-    L.part = align256(hlb::partial_doubles(int(N)) * 8);
+    L.part = align256(hlb::partial_doubles(nx, ny, nz) * 8);
     L.res = 256;
-    L.total = 2 * L.g + L.Q + L.Qs + L.u + L.Pi + L.part + L.res;
+    L.total = 2 * L.g + 2 * L.Q + L.u + L.Pi + L.part + L.res;
     return true;
 }
 
@@ -79,7 +77,9 @@ int hip_fail(hlb_ctx *c, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
     } while (0)
 
-double *stage_of(hlb_ctx *c) { return static_cast<double *>(c->D.g[c->cur ^ 1]); }
+// FP64 staging area for host transfers: the population buffer that does not
+// hold the state (19 x N x 4 bytes >= 9 x N doubles in both precisions).
+double *stage_of(hlb_ctx *c) { return static_cast<double *>(c->D.g[c->D.gcur ^ 1]); }
 
 }  // namespace
 
@@ -108,8 +108,8 @@ int hlb_create(int nx, int ny, int nz, int precision, void *ws, size_t ws_bytes,
     c->D.fp32 = precision == HLB_FP32;
     c->D.g[0] = p; p += L.g;
     c->D.g[1] = p; p += L.g;
-    c->D.Q = p; p += L.Q;
-    c->D.Qs = p; p += L.Qs;
+    c->D.Q[0] = p; p += L.Q;
+    c->D.Q[1] = p; p += L.Q;
     c->D.u = p; p += L.u;
     c->D.Pi = p; p += L.Pi;
     c->D.part = reinterpret_cast<double *>(p); p += L.part;
@@ -169,7 +169,7 @@ int hlb_set_fields(hlb_ctx *c, const double *Q5, const double *u3, const double 
     std::memcpy(host.data() + 4 * N, Q5, 5 * N * sizeof(double));
     double *stage = stage_of(c);
     HIP_TRY(c, hipMemcpyAsync(stage, host.data(), 9 * N * sizeof(double), hipMemcpyHostToDevice, c->D.stream));
-    HIP_TRY(c, hlb::run_init(c->D, c->p, stage, c->cur));
+    HIP_TRY(c, hlb::run_init(c->D, c->p, stage));
     HIP_TRY(c, hipStreamSynchronize(c->D.stream));
     c->have_fields = true;
     return HLB_OK;
@@ -180,7 +180,7 @@ int hlb_step(hlb_ctx *c, int nsteps)
     HLB_GUARD(c);
     if (nsteps < 0) return set_error(c, HLB_ERR_ARG, "nsteps = %d", nsteps);
     if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "hlb_set_fields must come first");
-    HIP_TRY(c, hlb::run_steps(c->D, c->p, nsteps, c->cur));
+    HIP_TRY(c, hlb::run_steps(c->D, c->p, nsteps));
     return HLB_OK;
 }
 
@@ -190,7 +190,7 @@ int hlb_get_fields(hlb_ctx *c, double *Q5, double *u3, double *rho)
     if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
     const size_t N = c->D.G.N;
     double *stage = stage_of(c);
-    HIP_TRY(c, hlb::run_readout(c->D, c->p, c->cur, stage, nullptr));
+    HIP_TRY(c, hlb::run_readout(c->D, c->p, stage, nullptr));
     if (rho) HIP_TRY(c, hipMemcpyAsync(rho, stage, N * 8, hipMemcpyDeviceToHost, c->D.stream));
     if (u3) HIP_TRY(c, hipMemcpyAsync(u3, stage + N, 3 * N * 8, hipMemcpyDeviceToHost, c->D.stream));
     if (Q5) HIP_TRY(c, hipMemcpyAsync(Q5, stage + 4 * N, 5 * N * 8, hipMemcpyDeviceToHost, c->D.stream));
@@ -203,7 +203,7 @@ int hlb_get_totals(hlb_ctx *c, double *mass, double *mom3, double *free_energy)
     HLB_GUARD(c);
     if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
     double r[5];
-    HIP_TRY(c, hlb::run_readout(c->D, c->p, c->cur, nullptr, c->D.res));
+    HIP_TRY(c, hlb::run_readout(c->D, c->p, nullptr, c->D.res));
     HIP_TRY(c, hipMemcpyAsync(r, c->D.res, sizeof(r), hipMemcpyDeviceToHost, c->D.stream));
     HIP_TRY(c, hipStreamSynchronize(c->D.stream));
     const double m = double(c->D.G.N) * c->p.rho0 + r[0];
@@ -216,6 +216,77 @@ int hlb_get_totals(hlb_ctx *c, double *mass, double *mom3, double *free_energy)
     return HLB_OK;
 }
 
+int hlb_set_schedule(hlb_ctx *c, int schedule, int tz)
+{
+    HLB_GUARD(c);
+    if ((schedule != HLB_SCHED_SITES && schedule != HLB_SCHED_TILED) || tz < 0)
+        return set_error(c, HLB_ERR_ARG, "schedule %d / tz %d", schedule, tz);
+    c->D.sched = schedule;
+    c->D.tz = tz;
+    return HLB_OK;
+}
+
+int hlb_get_schedule(const hlb_ctx *c, int *schedule, int *tz)
+{
+    if (!c || !schedule || !tz) return HLB_ERR_ARG;
+    *schedule = c->D.sched;
+    *tz = c->D.tz;
+    return HLB_OK;
+}
+
+int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
+{
+    HLB_GUARD(c);
+    if (trial_steps < 1) return set_error(c, HLB_ERR_ARG, "trial_steps = %d", trial_steps);
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "hlb_set_fields must come first");
+    // the trials advance the state: keep a host copy and put it back after
+    std::vector<char> saved(c->state_bytes);
+    const int g0 = c->D.gcur, q0 = c->D.qcur;
+    int rc = hlb_get_state(c, saved.data(), saved.size());
+    if (rc) return rc;
+    struct Cand {
+        int sched, tz;
+    };
+    const Cand cands[] = {{HLB_SCHED_SITES, 0}, {HLB_SCHED_TILED, 8}, {HLB_SCHED_TILED, 16},
+                          {HLB_SCHED_TILED, 32}};
+    hipEvent_t a, b;
+    HIP_TRY(c, hipEventCreate(&a));
+    HIP_TRY(c, hipEventCreate(&b));
+    double best = 1e300;
+    Cand pick = cands[0];
+    for (const Cand &k : cands) {
+        if (k.sched == HLB_SCHED_TILED && k.tz > c->D.G.nz && k.tz != 8) continue;
+        c->D.sched = k.sched;
+        c->D.tz = k.tz;
+        hipError_t e = hlb::run_steps(c->D, c->p, 2);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(a, c->D.stream);
+        if (e == hipSuccess) e = hlb::run_steps(c->D, c->p, trial_steps);
+        if (e == hipSuccess) e = hipEventRecord(b, c->D.stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return hip_fail(c, e, "hlb_autotune trial");
+        }
+        if (ms / trial_steps < best) {
+            best = ms / trial_steps;
+            pick = k;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    c->D.sched = pick.sched;
+    c->D.tz = pick.tz;
+    c->D.gcur = g0;
+    c->D.qcur = q0;
+    rc = hlb_set_state(c, saved.data(), saved.size());
+    if (rc) return rc;
+    if (best_ms_per_step) *best_ms_per_step = best;
+    return HLB_OK;
+}
+
 int hlb_step_timed(hlb_ctx *c, int nsteps, double *kernel_ms, int nkernels)
 {
     HLB_GUARD(c);
@@ -223,7 +294,7 @@ int hlb_step_timed(hlb_ctx *c, int nsteps, double *kernel_ms, int nkernels)
         return set_error(c, HLB_ERR_ARG, "hlb_step_timed: bad arguments");
     if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "hlb_set_fields must come first");
     hlb::KernelTimer t;
-    hipError_t e = hlb::run_steps(c->D, c->p, nsteps, c->cur, &t);
+    hipError_t e = hlb::run_steps(c->D, c->p, nsteps, &t);
     if (e == hipSuccess) e = hipStreamSynchronize(c->D.stream);
     for (int k = 0; k < nkernels; ++k) kernel_ms[k] = 0.0;
     for (auto &m : t.events) {
@@ -252,8 +323,8 @@ int hlb_get_state(hlb_ctx *c, void *buf, size_t nbytes)
     if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
     const size_t e = c->D.fp32 ? 4 : 8, N = c->D.G.N;
     char *b = static_cast<char *>(buf);
-    HIP_TRY(c, hipMemcpyAsync(b, c->D.g[c->cur], 19 * N * e, hipMemcpyDeviceToHost, c->D.stream));
-    HIP_TRY(c, hipMemcpyAsync(b + 19 * N * e, c->D.Q, 5 * N * e, hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipMemcpyAsync(b, c->D.g[c->D.gcur], 19 * N * e, hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipMemcpyAsync(b + 19 * N * e, c->D.Q[c->D.qcur], 5 * N * e, hipMemcpyDeviceToHost, c->D.stream));
     HIP_TRY(c, hipStreamSynchronize(c->D.stream));
     return HLB_OK;
 }
@@ -265,8 +336,8 @@ int hlb_set_state(hlb_ctx *c, const void *buf, size_t nbytes)
     if (!c->have_params) return set_error(c, HLB_ERR_STATE, "hlb_set_params must come first");
     const size_t e = c->D.fp32 ? 4 : 8, N = c->D.G.N;
     const char *b = static_cast<const char *>(buf);
-    HIP_TRY(c, hipMemcpyAsync(c->D.g[c->cur], b, 19 * N * e, hipMemcpyHostToDevice, c->D.stream));
-    HIP_TRY(c, hipMemcpyAsync(c->D.Q, b + 19 * N * e, 5 * N * e, hipMemcpyHostToDevice, c->D.stream));
+    HIP_TRY(c, hipMemcpyAsync(c->D.g[c->D.gcur], b, 19 * N * e, hipMemcpyHostToDevice, c->D.stream));
+    HIP_TRY(c, hipMemcpyAsync(c->D.Q[c->D.qcur], b + 19 * N * e, 5 * N * e, hipMemcpyHostToDevice, c->D.stream));
     HIP_TRY(c, hipStreamSynchronize(c->D.stream));
     c->have_fields = true;
     return HLB_OK;

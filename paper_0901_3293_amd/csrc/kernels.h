@@ -21,24 +21,34 @@ struct PhysParams {
     int flow;
 };
 
-// Device buffers of one context (all inside the caller's workspace).
+// Step schedules (see kernels.hip).
+enum Schedule { SCHED_SITES = 0, SCHED_TILED = 1 };
+
+// Device buffers of one context (all inside the caller's workspace) and the
+// ping-pong state indices.
 struct Device {
     Geom G;
     bool fp32;
-    void *g[2];    // 19 x N each
-    void *Q;       // 5 x N
-    void *Qs;      // 5 x N
+    void *g[2];    // 19 x N each; g[gcur] holds the state
+    void *Q[2];    // 5 x N each; Q[qcur] holds the state
     void *u;       // 3 x N
-    void *Pi;      // 9 x N
-    double *part;  // partial_doubles(N)
+    void *Pi;      // 9 x N (stress; F in its first 3 x N for the tiled schedule)
+    double *part;  // partial_doubles(nx, ny, nz)
     double *res;   // 16 doubles of reduced totals
+    int gcur, qcur;
+    int sched;     // Schedule
+    int tz;        // z-chunk of the tiled kernels (0: default)
     hipStream_t stream;
 };
 
-size_t partial_doubles(int N);
+size_t partial_doubles(int nx, int ny, int nz);
 
 // Kernel kinds of one step, for per-kernel event timing.
-enum KernelKind { K_STRESS = 0, K_LB = 1, K_QPRED = 2, K_QCORR = 3, K_COUNT = 4 };
+enum KernelKind {
+    K_STRESS = 0, K_LB = 1, K_QPRED = 2, K_QCORR = 3,  // per-site schedule
+    K_QFORCE = 4, K_LBF = 5, K_QUPDATE = 6,            // tiled schedule
+    K_COUNT = 7
+};
 const char *kernel_name(int k);
 
 struct KernelTimer {
@@ -49,18 +59,17 @@ struct KernelTimer {
     std::vector<Mark> events;
 };
 
-// Enqueue nsteps coupled steps; cur is the index of the g buffer holding the
-// state and is flipped by every LB step.  With a timer, an event pair is
-// recorded on the stream around every launch.
-hipError_t run_steps(const Device &D, const PhysParams &p, int nsteps, int &cur,
-                     KernelTimer *timer = nullptr);
+// Enqueue nsteps coupled steps (flips D.gcur and D.qcur).  With a timer, an
+// event pair is recorded on the stream around every launch.
+hipError_t run_steps(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer = nullptr);
 
-// stage: device FP64 [rho N][u 3N][Q 5N]; writes g[cur] and Q, zeroes u.
-hipError_t run_init(const Device &D, const PhysParams &p, const double *stage, int cur);
+// stage: device FP64 [rho N][u 3N][Q 5N] (must not alias g[gcur] or Q[qcur]);
+// writes g[gcur] and Q[qcur], zeroes u.
+hipError_t run_init(Device &D, const PhysParams &p, const double *stage);
 
 // Current-level readout into device FP64 stage [rho N][u 3N][Q 5N] (may be
 // null) and, if totals is non-null, the reductions into D.res:
 // res[0] = sum (rho - rho0), res[1..3] = sum rho u, res[4] = sum f.
-hipError_t run_readout(const Device &D, const PhysParams &p, int cur, double *stage, double *totals);
+hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *totals);
 
 }  // namespace hlb

@@ -1,127 +1,51 @@
 // kernels.hip -- HIP kernels of the hybrid step for gfx950 and their launchers.
 //
-// Data layout in HBM (all structure-of-arrays, component-major, x fastest):
+// Data layout in HBM (structure-of-arrays, component-major, x fastest):
 //   g[2]  19 x N  deviation populations g_i = f_i - w_i rho0 (ping-pong, pull)
-//   Q      5 x N  order parameter (xx, xy, xz, yy, yz)
-//   Qs     5 x N  predictor stage Q*
+//   Q[2]   5 x N  order parameter (xx, xy, xz, yy, yz); Q[qcur] is the state,
+//                 the other copy holds the predictor stage or the next Q
 //   u      3 x N  velocity of the last LB step
-//   Pi     9 x N  chemical stress (row-major a*3+b)
-// Scalars of one run are passed by value (Coef<T>); no constant memory.
+//   Pi     9 x N  chemical stress (its first 3 x N hold F in the tiled schedule)
+// Scalars of one run are passed by value (Coef<T>).
 //
-// Step schedule (Sec. 2.2): stress(Q^n) -> lb(g, div Pi) -> pred(Q^n, u^n)
-// -> corr(Q^n, Q*, u^n).  Each kernel maps one thread to one lattice site;
-// neighbour values come through the L2 of the XCD that owns the block (block
-// ids are remapped so each of the 8 XCDs sweeps a contiguous slab).
+// Two schedules of one step (Sec. 2.2), chosen per lattice and precision by
+// the autotuner:
+//  SITES (4 sweeps, one site per thread, neighbours through L2; 95 values
+//  per site cross HBM):
+//   k_stress  Q^n -> Pi;  k_lb  g, div Pi -> g', u^n;
+//   k_qpred   Q^n, u^n -> Q*;  k_qcorr  Q*, u^n -> Q^{n+1} (in place)
+//  TILED (3 sweeps; the stress and the predictor stage live in LDS of 2.5D
+//  z-marching tiles and are recomputed on a one-site halo ring; 65 values):
+//   k_qforce  Q^n -> F^n;  k_lbf  g, F^n -> g', u^n;  k_qupdate  Q^n, u^n -> Q^{n+1}
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
 #include "site.h"
+#include "sitekern.h"
+#include "tiles.h"
 
 namespace hlb {
 
 namespace {
 
-constexpr int BLK = 256;
+constexpr int BLK = 256;  // per-site kernels
+constexpr int TX = 32, TY = 8;
+using Shape = TileShape<TX, TY>;
 
-// Hardware hands consecutive workgroups to the 8 XCDs in turn; remap so XCD k
-// sweeps blocks [k*per, (k+1)*per) of the domain and its L2 sees the stencil
-// neighbours of its own sites.  gridDim.x is a multiple of 8.
-__device__ __forceinline__ int logical_block()
-{
-    const int per = gridDim.x >> 3;
-    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-}
+// ---------------------------------------------------------------- helpers
 
-struct Site {
-    int s;       // linear index
-    int nb[6];   // x+1, x-1, y+1, y-1, z+1, z-1 (periodic)
-};
-
-__device__ __forceinline__ bool site_of(const Geom &G, Site &S)
-{
-    const int s = logical_block() * BLK + threadIdx.x;
-    if (s >= G.N) return false;
-    const int x = s % G.nx;
-    const int yz = s / G.nx;
-    const int y = yz % G.ny;
-    const int z = yz / G.ny;
-    const int sxy = G.nx * G.ny;
-    S.s = s;
-    S.nb[0] = (x == G.nx - 1) ? s - (G.nx - 1) : s + 1;
-    S.nb[1] = (x == 0) ? s + (G.nx - 1) : s - 1;
-    S.nb[2] = (y == G.ny - 1) ? s - G.nx * (G.ny - 1) : s + G.nx;
-    S.nb[3] = (y == 0) ? s + G.nx * (G.ny - 1) : s - G.nx;
-    S.nb[4] = (z == G.nz - 1) ? s - sxy * (G.nz - 1) : s + sxy;
-    S.nb[5] = (z == 0) ? s + sxy * (G.nz - 1) : s - sxy;
-    return true;
-}
-
-// Pulled source of population i arriving at (x,y,z): site (x,y,z) - e_i.
-__device__ __forceinline__ int pull_src(const Geom &G, int x, int y, int z, int cx, int cy, int cz)
-{
-    int xs = x - cx, ys = y - cy, zs = z - cz;
-    xs += (xs < 0) ? G.nx : ((xs >= G.nx) ? -G.nx : 0);
-    ys += (ys < 0) ? G.ny : ((ys >= G.ny) ? -G.ny : 0);
-    zs += (zs < 0) ? G.nz : ((zs >= G.nz) ? -G.nz : 0);
-    return xs + G.nx * (ys + G.ny * zs);
-}
-
-template <typename T>
-__device__ __forceinline__ void gather_q(const T *__restrict__ Q, size_t N, const Site &S, T q[5],
-                                         T d[3][5], T lap[5])
-{
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        const T *P = Q + c * N;
-        const T v = P[S.s];
-        const T xp = P[S.nb[0]], xm = P[S.nb[1]];
-        const T yp = P[S.nb[2]], ym = P[S.nb[3]];
-        const T zp = P[S.nb[4]], zm = P[S.nb[5]];
-        q[c] = v;
-        d[0][c] = T(0.5) * (xp - xm);
-        d[1][c] = T(0.5) * (yp - ym);
-        d[2][c] = T(0.5) * (zp - zm);
-        lap[c] = ((xp + xm) + (yp + ym)) + (zp + zm) - T(6) * v;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void gather_u(const T *__restrict__ u, size_t N, const Site &S, T uc[3],
-                                         T W[3][3])
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const T *P = u + a * N;
-        uc[a] = P[S.s];
-        W[a][0] = T(0.5) * (P[S.nb[0]] - P[S.nb[1]]);
-        W[a][1] = T(0.5) * (P[S.nb[2]] - P[S.nb[3]]);
-        W[a][2] = T(0.5) * (P[S.nb[4]] - P[S.nb[5]]);
-    }
-}
-
-// Body force F_a = sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2 (Eq. (19)).
-template <typename T>
-__device__ __forceinline__ void divergence(const T *__restrict__ Pi, size_t N, const Site &S, T F[3])
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const T *Px = Pi + (3 * a + 0) * N;
-        const T *Py = Pi + (3 * a + 1) * N;
-        const T *Pz = Pi + (3 * a + 2) * N;
-        F[a] = T(0.5) * ((Px[S.nb[0]] - Px[S.nb[1]]) + (Py[S.nb[2]] - Py[S.nb[3]]) + (Pz[S.nb[4]] - Pz[S.nb[5]]));
-    }
-}
+__device__ __forceinline__ int logical_block() { return xcd_logical_block(); }
 
 // Fixed-order block reduction of NV doubles per thread into out[NV].
-template <int NV>
+template <int NV, int NTH>
 __device__ __forceinline__ void block_sum(double v[NV], double *out)
 {
-    __shared__ double buf[NV][BLK];
+    __shared__ double buf[NV][NTH];
 #pragma unroll
     for (int k = 0; k < NV; ++k) buf[k][threadIdx.x] = v[k];
     __syncthreads();
-    for (int w = BLK / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+    for (int w = NTH / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w)
 #pragma unroll
             for (int k = 0; k < NV; ++k) buf[k][threadIdx.x] += buf[k][threadIdx.x + w];
         __syncthreads();
@@ -131,81 +55,416 @@ __device__ __forceinline__ void block_sum(double v[NV], double *out)
         for (int k = 0; k < NV; ++k) out[k] = buf[k][0];
 }
 
-// ---------------------------------------------------------------- kernels
+// Staging of one z-plane of an NC-component field into an LDS ring slot with
+// a two-site halo in x and y (periodic wrap of the global coordinates).  The
+// element -> (component, in-plane offset) assignment is computed once per
+// block.
+template <int NC>
+struct PlaneLoader {
+    static constexpr int NE = NC * Shape::RN;
+    static constexpr int NL = (NE + Shape::NT - 1) / Shape::NT;
+    int comp[NL];
+    int off[NL];
+
+    __device__ __forceinline__ void init(const Geom &G, int x0, int y0)
+    {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = int(threadIdx.x) + k * Shape::NT;
+            if (e < NE) {
+                const int cc = e / Shape::RN, r = e - cc * Shape::RN;
+                const int ri = r % Shape::RX, rj = r / Shape::RX;
+                comp[k] = cc;
+                off[k] = wrapi(x0 - 2 + ri, G.nx) + G.nx * wrapi(y0 - 2 + rj, G.ny);
+            } else {
+                comp[k] = -1;
+                off[k] = 0;
+            }
+        }
+    }
+
+    template <typename T>
+    __device__ __forceinline__ void load(const T *__restrict__ src, size_t N, int plane_off,
+                                         T *__restrict__ slot) const
+    {
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+            if (comp[k] >= 0)
+                slot[int(threadIdx.x) + k * Shape::NT] = src[size_t(comp[k]) * N + plane_off + off[k]];
+    }
+
+    // Software pipelining: issue the global loads of a plane into registers
+    // now, park them in LDS after the compute of the current plane.
+    template <typename T>
+    __device__ __forceinline__ void fetch(const T *__restrict__ src, size_t N, int plane_off, T reg[NL]) const
+    {
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+            reg[k] = comp[k] >= 0 ? src[size_t(comp[k]) * N + plane_off + off[k]] : T(0);
+    }
+
+    template <typename T>
+    __device__ __forceinline__ void store(const T reg[NL], T *__restrict__ slot) const
+    {
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+            if (comp[k] >= 0) slot[int(threadIdx.x) + k * Shape::NT] = reg[k];
+    }
+};
+
+// Derivatives of an NC=5 field staged with a two-site halo, at staged
+// coordinate r of the middle plane.
+template <typename T>
+__device__ __forceinline__ void stencil_ring(const T *lo, const T *mid, const T *hi, int r, T q[5],
+                                             T d[3][5], T lap[5])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int o = k * Shape::RN + r;
+        const T v = mid[o];
+        const T xp = mid[o + 1], xm = mid[o - 1];
+        const T yp = mid[o + Shape::RX], ym = mid[o - Shape::RX];
+        const T zp = hi[o], zm = lo[o];
+        q[k] = v;
+        d[0][k] = T(0.5) * (xp - xm);
+        d[1][k] = T(0.5) * (yp - ym);
+        d[2][k] = T(0.5) * (zp - zm);
+        lap[k] = ((xp + xm) + (yp + ym)) + (zp + zm) - T(6) * v;
+    }
+}
+
+// Same for a field staged on the halo-1 plane layout (PX x PY).
+template <typename T>
+__device__ __forceinline__ void stencil_p(const T *lo, const T *mid, const T *hi, int r, T q[5],
+                                          T d[3][5], T lap[5])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int o = k * Shape::PN + r;
+        const T v = mid[o];
+        const T xp = mid[o + 1], xm = mid[o - 1];
+        const T yp = mid[o + Shape::PX], ym = mid[o - Shape::PX];
+        const T zp = hi[o], zm = lo[o];
+        q[k] = v;
+        d[0][k] = T(0.5) * (xp - xm);
+        d[1][k] = T(0.5) * (yp - ym);
+        d[2][k] = T(0.5) * (zp - zm);
+        lap[k] = ((xp + xm) + (yp + ym)) + (zp + zm) - T(6) * v;
+    }
+}
+
+// u and its centred gradient W_ab = d_b u_a at staged coordinate r.
+template <typename T>
+__device__ __forceinline__ void velocity_ring(const T *lo, const T *mid, const T *hi, int r, T uc[3],
+                                              T W[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int o = a * Shape::RN + r;
+        uc[a] = mid[o];
+        W[a][0] = T(0.5) * (mid[o + 1] - mid[o - 1]);
+        W[a][1] = T(0.5) * (mid[o + Shape::RX] - mid[o - Shape::RX]);
+        W[a][2] = T(0.5) * (hi[o] - lo[o]);
+    }
+}
+
+struct Block {
+    int x0, y0, z0, z1;
+    bool ok;
+};
+
+__device__ __forceinline__ Block block_of(const Geom &G, const TileGrid &tg)
+{
+    Block b;
+    const int lb = logical_block();
+    b.ok = lb < tg.total;
+    const int bx = lb % tg.tiles_x;
+    const int by = (lb / tg.tiles_x) % tg.tiles_y;
+    const int bz = lb / (tg.tiles_x * tg.tiles_y);
+    b.x0 = bx * Shape::TX;
+    b.y0 = by * Shape::TY;
+    b.z0 = bz * tg.tz;
+    b.z1 = min(b.z0 + tg.tz, G.nz);
+    return b;
+}
+
+// ---------------------------------------------------------------- k_qforce
+// F = div Pi(Q) (Eqs. (6)-(8), (19)).  Per plane p: stage Q(p+1); evaluate
+// the stress on the tile and its one-site halo ring (x and y columns of Pi
+// kept in LDS, the z column of the thread's own site in registers); finish
+// F(p-1) with the z-difference and start F(p) with the in-plane differences.
+// With WITH_F the block also sums the free-energy density of its sites.
+template <typename T, bool WITH_F>
+__global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGrid tg,
+                                                      const T *__restrict__ Q, T *__restrict__ F,
+                                                      double *__restrict__ fpart)
+{
+    __shared__ T sQ[3][5 * Shape::RN];
+    __shared__ T sP[6 * Shape::PN];
+    const Block B = block_of(G, tg);
+    if (!B.ok) return;
+    const size_t N = G.N;
+    const int sxy = G.nx * G.ny;
+    const int tx = int(threadIdx.x) % Shape::TX, ty = int(threadIdx.x) / Shape::TX;
+    const int gx = B.x0 + tx, gy = B.y0 + ty;
+    const bool mine = gx < G.nx && gy < G.ny;
+
+    PlaneLoader<5> L;
+    L.init(G, B.x0, B.y0);
+    int sb = 0, sm = 1, st = 2;  // ring slots of planes p-1, p, p+1
+    L.load(Q, N, wrapi(B.z0 - 2, G.nz) * sxy, sQ[sb]);
+    L.load(Q, N, wrapi(B.z0 - 1, G.nz) * sxy, sQ[sm]);
+    L.load(Q, N, wrapi(B.z0, G.nz) * sxy, sQ[st]);
+    __syncthreads();
+
+    // own site in halo-1 coordinates and in staged coordinates
+    const int pc = (ty + 1) * Shape::PX + (tx + 1);
+    const int rc = (ty + 2) * Shape::RX + (tx + 2);
+    int hp = -1, hr = -1;
+    if (int(threadIdx.x) < Shape::NH) {
+        int i, j;
+        Shape::halo_point(threadIdx.x, i, j);
+        hp = j * Shape::PX + i;
+        hr = (j + 1) * Shape::RX + (i + 1);
+    }
+
+    T Fin[3] = {T(0), T(0), T(0)}, Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
+    double facc = 0.0;
+    T pre[PlaneLoader<5>::NL];
+    for (int p = B.z0 - 1; p <= B.z1; ++p) {
+        const bool more = p + 2 <= B.z1 + 1;
+        if (more) L.fetch(Q, N, wrapi(p + 2, G.nz) * sxy, pre);
+        T Pz[3];
+        {
+            T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
+            stencil_ring(sQ[sb], sQ[sm], sQ[st], rc, q, d, lap);
+            site_stress(c, q, d, lap, P, fd, H);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sP[a * Shape::PN + pc] = P[a][0];
+                sP[(3 + a) * Shape::PN + pc] = P[a][1];
+                Pz[a] = P[a][2];
+            }
+            if (WITH_F && mine && p >= B.z0 && p < B.z1) facc += double(fd);
+        }
+        if (hp >= 0) {
+            T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
+            stencil_ring(sQ[sb], sQ[sm], sQ[st], hr, q, d, lap);
+            site_stress(c, q, d, lap, P, fd, H);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sP[a * Shape::PN + hp] = P[a][0];
+                sP[(3 + a) * Shape::PN + hp] = P[a][1];
+            }
+        }
+        __syncthreads();
+        if (mine && p - 1 >= B.z0) {
+            const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) F[a * N + o] = T(0.5) * (Fin[a] + (Pz[a] - Pz2[a]));
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Fin[a] = (sP[a * Shape::PN + pc + 1] - sP[a * Shape::PN + pc - 1])
+                   + (sP[(3 + a) * Shape::PN + pc + Shape::PX] - sP[(3 + a) * Shape::PN + pc - Shape::PX]);
+            Pz2[a] = Pz1[a];
+            Pz1[a] = Pz[a];
+        }
+        if (more) L.store(pre, sQ[sb]);  // plane p-1 is no longer read: it becomes p+2
+        __syncthreads();
+        const int o = sb;
+        sb = sm;
+        sm = st;
+        st = o;
+    }
+    if (WITH_F) {
+        double v[1] = {facc};
+        block_sum<1, Shape::NT>(v, fpart + logical_block());
+    }
+}
+
+// ---------------------------------------------------------------- k_qupdate
+// Predictor-corrector for the Q equation with u held at u^n (Eqs. (2)-(4)):
+//   Q* = Q + R(Q, u),  Q' = [Q + Q* + R(Q*, u)] / 2   (= Q + [R(Q) + R(Q*)]/2).
+// Per plane p: stage Q(p+1), u(p+1); evaluate Q*(p) on the tile and its halo
+// ring into a three-plane LDS ring; then apply the corrector to plane p-1.
+template <typename T>
+__global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGrid tg,
+                                                       const T *__restrict__ Qin, const T *__restrict__ u,
+                                                       T *__restrict__ Qout)
+{
+    __shared__ T sQ[3][5 * Shape::RN];
+    __shared__ T sU[3][3 * Shape::RN];
+    __shared__ T sS[3][5 * Shape::PN];
+    const Block B = block_of(G, tg);
+    if (!B.ok) return;
+    const size_t N = G.N;
+    const int sxy = G.nx * G.ny;
+    const int tx = int(threadIdx.x) % Shape::TX, ty = int(threadIdx.x) / Shape::TX;
+    const int gx = B.x0 + tx, gy = B.y0 + ty;
+    const bool mine = gx < G.nx && gy < G.ny;
+
+    PlaneLoader<5> LQ;
+    PlaneLoader<3> LU;
+    LQ.init(G, B.x0, B.y0);
+    LU.init(G, B.x0, B.y0);
+    int sb = 0, sm = 1, st = 2;     // staged planes p-1, p, p+1
+    int q2 = 0, q1 = 1, q0 = 2;     // Q* planes p-2, p-1, p
+    LQ.load(Qin, N, wrapi(B.z0 - 2, G.nz) * sxy, sQ[sb]);
+    LQ.load(Qin, N, wrapi(B.z0 - 1, G.nz) * sxy, sQ[sm]);
+    LQ.load(Qin, N, wrapi(B.z0, G.nz) * sxy, sQ[st]);
+    LU.load(u, N, wrapi(B.z0 - 2, G.nz) * sxy, sU[sb]);
+    LU.load(u, N, wrapi(B.z0 - 1, G.nz) * sxy, sU[sm]);
+    LU.load(u, N, wrapi(B.z0, G.nz) * sxy, sU[st]);
+    __syncthreads();
+
+    const int pc = (ty + 1) * Shape::PX + (tx + 1);
+    const int rc = (ty + 2) * Shape::RX + (tx + 2);
+    int hp = -1, hr = -1;
+    if (int(threadIdx.x) < Shape::NH) {
+        int i, j;
+        Shape::halo_point(threadIdx.x, i, j);
+        hp = j * Shape::PX + i;
+        hr = (j + 1) * Shape::RX + (i + 1);
+    }
+
+    T qprev[5] = {T(0), T(0), T(0), T(0), T(0)};  // Q^n at the own site of plane p-1
+    T up1[3] = {T(0), T(0), T(0)};                 // u at the own site, plane p-1
+    T up2[3] = {T(0), T(0), T(0)};                 // u at the own site, plane p-2
+    T preQ[PlaneLoader<5>::NL], preU[PlaneLoader<3>::NL];
+    for (int p = B.z0 - 1; p <= B.z1; ++p) {
+        const bool more = p + 2 <= B.z1 + 1;
+        if (more) {
+            LQ.fetch(Qin, N, wrapi(p + 2, G.nz) * sxy, preQ);
+            LU.fetch(u, N, wrapi(p + 2, G.nz) * sxy, preU);
+        }
+        T qcur[5], ucur[3];
+        {
+            T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
+            stencil_ring(sQ[sb], sQ[sm], sQ[st], rc, q, d, lap);
+            velocity_ring(sU[sb], sU[sm], sU[st], rc, uc, W);
+            site_rhs(c, q, d, lap, uc, W, R);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                sS[q0][k * Shape::PN + pc] = q[k] + R[k];
+                qcur[k] = q[k];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ucur[a] = uc[a];
+        }
+        if (hp >= 0) {
+            T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
+            stencil_ring(sQ[sb], sQ[sm], sQ[st], hr, q, d, lap);
+            velocity_ring(sU[sb], sU[sm], sU[st], hr, uc, W);
+            site_rhs(c, q, d, lap, uc, W, R);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sS[q0][k * Shape::PN + hp] = q[k] + R[k];
+        }
+        __syncthreads();
+        if (p - 1 >= B.z0) {
+            // corrector at plane p-1: Q* stencil from the LDS ring, u of plane
+            // p-1 in-plane from the staged slot sb, z-neighbours from registers
+            T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
+            stencil_p(sS[q2], sS[q1], sS[q0], pc, q, d, lap);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int o = a * Shape::RN + rc;
+                uc[a] = up1[a];
+                W[a][0] = T(0.5) * (sU[sb][o + 1] - sU[sb][o - 1]);
+                W[a][1] = T(0.5) * (sU[sb][o + Shape::RX] - sU[sb][o - Shape::RX]);
+                W[a][2] = T(0.5) * (ucur[a] - up2[a]);
+            }
+            site_rhs(c, q, d, lap, uc, W, R);
+            if (mine) {
+                const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) Qout[k * N + o] = T(0.5) * (qprev[k] + q[k] + R[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) qprev[k] = qcur[k];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            up2[a] = up1[a];
+            up1[a] = ucur[a];
+        }
+        __syncthreads();  // slot sb (plane p-1) and the Q* slot q2 are free now
+        if (more) {
+            LQ.store(preQ, sQ[sb]);
+            LU.store(preU, sU[sb]);
+        }
+        __syncthreads();
+        int o = sb;
+        sb = sm;
+        sm = st;
+        st = o;
+        o = q2;
+        q2 = q1;
+        q1 = q0;
+        q0 = o;
+    }
+}
+
+// ---------------------------------------------------------------- per-site kernels
+
+__device__ __forceinline__ int site_index() { return logical_block() * BLK + int(threadIdx.x); }
 
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_stress(Geom G, Coef<T> c, const T *__restrict__ Q,
                                                 T *__restrict__ Pi, double *__restrict__ fpart)
 {
-    Site S;
-    const bool ok = site_of(G, S);
+    const int s = site_index();
     double fsum = 0.0;
-    if (ok) {
-        const size_t N = G.N;
-        T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
-        gather_q(Q, N, S, q, d, lap);
-        site_stress(c, q, d, lap, P, fd, H);
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) Pi[(3 * a + b) * N + S.s] = P[a][b];
-        fsum = double(fd);
-    }
+    if (s < G.N) fsum = double(stress_at(G, c, Q, Pi, s));
     if (fpart) {
         double v[1] = {fsum};
-        block_sum<1>(v, fpart + logical_block());
+        block_sum<1, BLK>(v, fpart + logical_block());
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_lb(Geom G, Coef<T> c, const T *__restrict__ gin,
-                                            const T *__restrict__ Pi, T *__restrict__ gout,
-                                            T *__restrict__ u)
+                                            const T *__restrict__ Pi, T *__restrict__ gout, T *__restrict__ u)
 {
-    Site S;
-    if (!site_of(G, S)) return;
-    const size_t N = G.N;
-    const int x = S.s % G.nx, y = (S.s / G.nx) % G.ny, z = S.s / (G.nx * G.ny);
-    T g[19], F[3], uu[3], rho;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = gin[i * N + pull_src(G, x, y, z, CX[i], CY[i], CZ[i])];
-    divergence(Pi, N, S, F);
-    lb_collide(c, g, F, uu, rho);
-#pragma unroll
-    for (int i = 0; i < 19; ++i) gout[i * N + S.s] = g[i];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) u[a * N + S.s] = uu[a];
+    const int s = site_index();
+    if (s < G.N) lb_at(G, c, gin, Pi, gout, u, s);
 }
 
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_qpred(Geom G, Coef<T> c, const T *__restrict__ Q,
                                                const T *__restrict__ u, T *__restrict__ Qs)
 {
-    Site S;
-    if (!site_of(G, S)) return;
-    const size_t N = G.N;
-    T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
-    gather_q(Q, N, S, q, d, lap);
-    gather_u(u, N, S, uc, W);
-    site_rhs(c, q, d, lap, uc, W, R);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) Qs[k * N + S.s] = q[k] + R[k];
+    const int s = site_index();
+    if (s < G.N) pred_at(G, c, Q, u, Qs, s);
 }
 
-// Q^{n+1} = Q^n + [R(Q^n) + R(Q*)]/2 = [Q^n + Q* + R(Q*)]/2, written in place.
 template <typename T>
-__global__ __launch_bounds__(BLK) void k_qcorr(Geom G, Coef<T> c, T *__restrict__ Q,
-                                               const T *__restrict__ Qs, const T *__restrict__ u)
+__global__ __launch_bounds__(BLK) void k_qcorr(Geom G, Coef<T> c, T *__restrict__ Q, const T *__restrict__ Qs,
+                                               const T *__restrict__ u)
 {
-    Site S;
-    if (!site_of(G, S)) return;
+    const int s = site_index();
+    if (s < G.N) corr_at(G, c, Q, Qs, u, s);
+}
+
+// LB with a precomputed body force (tiled schedule).
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_lbf(Geom G, Coef<T> c, const T *__restrict__ gin,
+                                             const T *__restrict__ F, T *__restrict__ gout, T *__restrict__ u)
+{
+    const int s = site_index();
+    if (s >= G.N) return;
     const size_t N = G.N;
-    T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
-    gather_q(Qs, N, S, q, d, lap);
-    gather_u(u, N, S, uc, W);
-    site_rhs(c, q, d, lap, uc, W, R);
+    const Nbr S = nbr_of(G, s);
+    T g[19], f[3], uu[3], rho;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Q[k * N + S.s] = T(0.5) * (Q[k * N + S.s] + q[k] + R[k]);
+    for (int i = 0; i < 19; ++i) g[i] = gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[a] = F[a * N + s];
+    lb_collide(c, g, f, uu, rho);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) gout[i * N + s] = g[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
 }
 
 // Populations such that the first pull returns g^eq(rho(x), u(x)):
@@ -216,22 +475,22 @@ __global__ __launch_bounds__(BLK) void k_init(Geom G, Coef<T> c, const double *_
                                               const double *__restrict__ Q_in, T *__restrict__ g,
                                               T *__restrict__ Q)
 {
-    Site S;
-    if (!site_of(G, S)) return;
+    const int s = site_index();
+    if (s >= G.N) return;
     const size_t N = G.N;
-    const int x = S.s % G.nx, y = (S.s / G.nx) % G.ny, z = S.s / (G.nx * G.ny);
+    const Nbr S = nbr_of(G, s);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        const int t = pull_src(G, x, y, z, -CX[i], -CY[i], -CZ[i]);
+        const int t = pull_from(G, S, -CX[i], -CY[i], -CZ[i]);
         const T uu[3] = {T(u_in[t]), T(u_in[N + t]), T(u_in[2 * N + t])};
-        g[i * N + S.s] = lb_geq(c, i, T(rho_in[t]), uu);
+        g[i * N + s] = lb_geq(c, i, T(rho_in[t]), uu);
     }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Q[k * N + S.s] = T(Q_in[k * N + S.s]);
+    for (int k = 0; k < 5; ++k) Q[k * N + s] = T(Q_in[k * N + s]);
 }
 
-// Current-level readout: rho, u = (j + F/2)/rho (F from the current stress,
-// zero when Pi is null) and Q in FP64; FP64 block partials of
+// Current-level readout: rho, u = (j + F/2)/rho with F = div Pi (u == 0 when
+// Pi is null, i.e. flow off) and Q in FP64; FP64 block partials of
 // (rho - rho0, rho u_x, rho u_y, rho u_z).
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_readout(Geom G, Coef<T> c, const T *__restrict__ g,
@@ -239,37 +498,36 @@ __global__ __launch_bounds__(BLK) void k_readout(Geom G, Coef<T> c, const T *__r
                                                  double *__restrict__ rho_out, double *__restrict__ u_out,
                                                  double *__restrict__ Q_out, double *__restrict__ part)
 {
-    Site S;
-    const bool ok = site_of(G, S);
+    const int s = site_index();
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (ok) {
+    if (s < G.N) {
         const size_t N = G.N;
-        const int x = S.s % G.nx, y = (S.s / G.nx) % G.ny, z = S.s / (G.nx * G.ny);
-        T gg[19], drho, j[3], F[3] = {T(0), T(0), T(0)};
+        const Nbr S = nbr_of(G, s);
+        T gg[19], drho, j[3], f[3] = {T(0), T(0), T(0)};
 #pragma unroll
-        for (int i = 0; i < 19; ++i) gg[i] = g[i * N + pull_src(G, x, y, z, CX[i], CY[i], CZ[i])];
+        for (int i = 0; i < 19; ++i) gg[i] = g[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
         lb_moments(gg, drho, j);
-        if (Pi) divergence(Pi, N, S, F);
+        if (Pi) divergence(Pi, N, S, f);
         const T rho = c.rho0 + drho;
         T uu[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) uu[a] = Pi ? (j[a] + T(0.5) * F[a]) / rho : T(0);
-        if (rho_out) rho_out[S.s] = double(rho);
+        for (int a = 0; a < 3; ++a) uu[a] = Pi ? (j[a] + T(0.5) * f[a]) / rho : T(0);
+        if (rho_out) rho_out[s] = double(rho);
         if (u_out)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) u_out[a * N + S.s] = double(uu[a]);
+            for (int a = 0; a < 3; ++a) u_out[a * N + s] = double(uu[a]);
         if (Q_out)
 #pragma unroll
-            for (int k = 0; k < 5; ++k) Q_out[k * N + S.s] = double(Q[k * N + S.s]);
+            for (int k = 0; k < 5; ++k) Q_out[k * N + s] = double(Q[k * N + s]);
         v[0] = double(drho);
         if (Pi)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) v[1 + a] = double(j[a]) + 0.5 * double(F[a]);
+            for (int a = 0; a < 3; ++a) v[1 + a] = double(j[a]) + 0.5 * double(f[a]);
     }
-    if (part) block_sum<4>(v, part + 4 * logical_block());
+    if (part) block_sum<4, BLK>(v, part + 4 * logical_block());
 }
 
-// Second stage: out[k] = sum_b part[b*nv + k], fixed order, one block.
+// Second stage: out[k] = sum_b part[b*stride + k], fixed order, one block.
 __global__ __launch_bounds__(BLK) void k_reduce(const double *__restrict__ part, int nblk, int nv,
                                                 int stride, double *__restrict__ out)
 {
@@ -280,7 +538,7 @@ __global__ __launch_bounds__(BLK) void k_reduce(const double *__restrict__ part,
         buf[threadIdx.x] = s;
         __syncthreads();
         for (int w = BLK / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+            if (int(threadIdx.x) < w) buf[threadIdx.x] += buf[threadIdx.x + w];
             __syncthreads();
         }
         if (threadIdx.x == 0) out[k] = buf[0];
@@ -296,32 +554,16 @@ __global__ __launch_bounds__(BLK) void k_fill(T *__restrict__ p, size_t n, T v)
     for (; i < n; i += stride) p[i] = v;
 }
 
-inline int grid_blocks(int N) { return ((N + BLK - 1) / BLK + 7) / 8 * 8; }
+// ---------------------------------------------------------------- launchers
 
-template <typename T>
-Coef<T> make_coef(const PhysParams &p)
-{
-    Coef<T> c;
-    c.a = T(p.A0 * (1.0 - p.gamma / 3.0));
-    c.bg = T(p.A0 * p.gamma);
-    c.K = T(p.K);
-    c.q0x2 = T(2.0 * p.q0);
-    c.Kq0x2 = T(2.0 * p.K * p.q0);
-    c.Kq0sq4 = T(4.0 * p.K * p.q0 * p.q0);
-    c.xi = T(p.xi);
-    c.Gamma = T(p.Gamma);
-    c.rho0 = T(p.rho0);
-    c.omega = T(1.0 / p.tau);
-    c.pref = T(1.0 - 0.5 / p.tau);
-    return c;
-}
+inline int site_blocks(int N) { return ((N + BLK - 1) / BLK + 7) / 8 * 8; }
 
 // Records an event pair around each launch when a timer is attached.
 struct Marks {
     KernelTimer *t;
     hipStream_t s;
-    template <typename F>
-    hipError_t operator()(int kind, F &&launch)
+    template <typename Fn>
+    hipError_t operator()(int kind, Fn &&launch)
     {
         if (!t) {
             launch();
@@ -339,63 +581,89 @@ struct Marks {
     }
 };
 
+int tile_tz(const Device &D) { return D.tz > 0 ? D.tz : 16; }
+
 template <typename T>
-hipError_t steps_t(const Device &D, const PhysParams &p, int nsteps, int &cur, KernelTimer *timer)
+hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer)
 {
     const Geom G = D.G;
     const Coef<T> c = make_coef<T>(p);
-    const int nb = grid_blocks(G.N);
-    T *Q = static_cast<T *>(D.Q), *Qs = static_cast<T *>(D.Qs), *u = static_cast<T *>(D.u);
-    T *Pi = static_cast<T *>(D.Pi);
+    const int nb = site_blocks(G.N);
+    T *u = static_cast<T *>(D.u), *Pi = static_cast<T *>(D.Pi);
     Marks mark{timer, D.stream};
     hipError_t e = hipSuccess;
     if (!p.flow && nsteps > 0)  // pure relaxation: u == 0 (Sec. 2.1)
         k_fill<T><<<1024, BLK, 0, D.stream>>>(u, 3 * size_t(G.N), T(0));
-    for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
-        if (p.flow) {
-            T *gin = static_cast<T *>(D.g[cur]);
-            T *gout = static_cast<T *>(D.g[cur ^ 1]);
-            e = mark(K_STRESS, [&] { k_stress<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr); });
-            if (e == hipSuccess)
-                e = mark(K_LB, [&] { k_lb<T><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
-            cur ^= 1;
+    if (D.sched == SCHED_SITES) {
+        for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+            T *Q = static_cast<T *>(D.Q[D.qcur]);
+            T *Qs = static_cast<T *>(D.Q[D.qcur ^ 1]);
+            if (p.flow) {
+                T *gin = static_cast<T *>(D.g[D.gcur]);
+                T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
+                e = mark(K_STRESS, [&] { k_stress<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr); });
+                if (e == hipSuccess)
+                    e = mark(K_LB, [&] { k_lb<T><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
+                D.gcur ^= 1;
+            }
+            if (e == hipSuccess) e = mark(K_QPRED, [&] { k_qpred<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, u, Qs); });
+            if (e == hipSuccess) e = mark(K_QCORR, [&] { k_qcorr<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Qs, u); });
         }
-        if (e == hipSuccess) e = mark(K_QPRED, [&] { k_qpred<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, u, Qs); });
-        if (e == hipSuccess) e = mark(K_QCORR, [&] { k_qcorr<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Qs, u); });
+    } else {
+        const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, TX, TY, tile_tz(D));
+        for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+            T *Qn = static_cast<T *>(D.Q[D.qcur]);
+            T *Qn1 = static_cast<T *>(D.Q[D.qcur ^ 1]);
+            if (p.flow) {
+                T *gin = static_cast<T *>(D.g[D.gcur]);
+                T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
+                e = mark(K_QFORCE, [&] {
+                    k_qforce<T, false><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Qn, Pi, nullptr);
+                });
+                if (e == hipSuccess)
+                    e = mark(K_LBF, [&] { k_lbf<T><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
+                D.gcur ^= 1;
+            }
+            if (e == hipSuccess)
+                e = mark(K_QUPDATE, [&] {
+                    k_qupdate<T><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Qn, u, Qn1);
+                });
+            D.qcur ^= 1;
+        }
     }
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t init_t(const Device &D, const PhysParams &p, const double *stage, int cur)
+hipError_t init_t(Device &D, const PhysParams &p, const double *stage)
 {
     const Geom G = D.G;
     const Coef<T> c = make_coef<T>(p);
     const size_t N = G.N;
-    const int nb = grid_blocks(G.N);
-    k_init<T><<<nb, BLK, 0, D.stream>>>(G, c, stage, stage + N, stage + 4 * N, static_cast<T *>(D.g[cur]),
-                                        static_cast<T *>(D.Q));
+    const int nb = site_blocks(G.N);
+    k_init<T><<<nb, BLK, 0, D.stream>>>(G, c, stage, stage + N, stage + 4 * N, static_cast<T *>(D.g[D.gcur]),
+                                        static_cast<T *>(D.Q[D.qcur]));
     // u of the last LB step: zero until the first step (and for good with flow off)
     k_fill<T><<<1024, BLK, 0, D.stream>>>(static_cast<T *>(D.u), 3 * N, T(0));
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t readout_t(const Device &D, const PhysParams &p, int cur, double *stage, double *totals)
+hipError_t readout_t(Device &D, const PhysParams &p, double *stage, double *totals)
 {
     const Geom G = D.G;
     const Coef<T> c = make_coef<T>(p);
     const size_t N = G.N;
-    const int nb = grid_blocks(G.N);
+    const int nb = site_blocks(G.N);
     T *Pi = static_cast<T *>(D.Pi);
-    const bool need_stress = p.flow || totals;
-    if (need_stress)
-        k_stress<T><<<nb, BLK, 0, D.stream>>>(G, c, static_cast<const T *>(D.Q), Pi,
-                                              totals ? D.part + 4 * nb : nullptr);
-    k_readout<T><<<nb, BLK, 0, D.stream>>>(G, c, static_cast<const T *>(D.g[cur]), p.flow ? Pi : nullptr,
-                                           static_cast<const T *>(D.Q), stage ? stage : nullptr,
-                                           stage ? stage + N : nullptr, stage ? stage + 4 * N : nullptr,
+    const T *Q = static_cast<const T *>(D.Q[D.qcur]);
+    if (totals)
+        k_stress<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, D.part + 4 * nb);
+    else if (p.flow)
+        k_stress<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr);
+    k_readout<T><<<nb, BLK, 0, D.stream>>>(G, c, static_cast<const T *>(D.g[D.gcur]), p.flow ? Pi : nullptr, Q,
+                                           stage, stage ? stage + N : nullptr, stage ? stage + 4 * N : nullptr,
                                            totals ? D.part : nullptr);
     if (totals) {
         k_reduce<<<1, BLK, 0, D.stream>>>(D.part, nb, 4, 4, D.res);
@@ -406,27 +674,32 @@ hipError_t readout_t(const Device &D, const PhysParams &p, int cur, double *stag
 
 }  // namespace
 
-size_t partial_doubles(int N) { return size_t(5) * grid_blocks(N) + 16; }
+size_t partial_doubles(int nx, int ny, int nz)
+{
+    // per-site blocks x 4 (readout moments) + per-site blocks (free energy)
+    return size_t(5) * site_blocks(nx * ny * nz) + 16;
+}
 
 const char *kernel_name(int k)
 {
-    static const char *names[K_COUNT] = {"k_stress", "k_lb", "k_qpred", "k_qcorr"};
+    static const char *names[K_COUNT] = {"k_stress", "k_lb", "k_qpred", "k_qcorr", "k_qforce", "k_lbf",
+                                         "k_qupdate"};
     return (k >= 0 && k < K_COUNT) ? names[k] : nullptr;
 }
 
-hipError_t run_steps(const Device &D, const PhysParams &p, int nsteps, int &cur, KernelTimer *timer)
+hipError_t run_steps(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer)
 {
-    return D.fp32 ? steps_t<float>(D, p, nsteps, cur, timer) : steps_t<double>(D, p, nsteps, cur, timer);
+    return D.fp32 ? steps_t<float>(D, p, nsteps, timer) : steps_t<double>(D, p, nsteps, timer);
 }
 
-hipError_t run_init(const Device &D, const PhysParams &p, const double *stage, int cur)
+hipError_t run_init(Device &D, const PhysParams &p, const double *stage)
 {
-    return D.fp32 ? init_t<float>(D, p, stage, cur) : init_t<double>(D, p, stage, cur);
+    return D.fp32 ? init_t<float>(D, p, stage) : init_t<double>(D, p, stage);
 }
 
-hipError_t run_readout(const Device &D, const PhysParams &p, int cur, double *stage, double *totals)
+hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *totals)
 {
-    return D.fp32 ? readout_t<float>(D, p, cur, stage, totals) : readout_t<double>(D, p, cur, stage, totals);
+    return D.fp32 ? readout_t<float>(D, p, stage, totals) : readout_t<double>(D, p, stage, totals);
 }
 
 }  // namespace hlb

@@ -1,0 +1,180 @@
+// sitekern.h -- one-site-per-thread work of the step, as device functions
+// over a linear site index of one periodic box.  The plain kernels and the
+// batched persistent kernel both call these; neighbour values come straight
+// from global memory through the L1/L2 of the executing CU.
+//
+// Buffers of one box (structure-of-arrays, component stride N, x fastest):
+//   g 19 x N, Q 5 x N, Qs (predictor stage) 5 x N, u 3 x N, Pi 9 x N.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "site.h"
+
+namespace hlb {
+
+struct Nbr {
+    int s, x, y, z;
+    int nb[6];  // x+1, x-1, y+1, y-1, z+1, z-1 (periodic)
+};
+
+__device__ __forceinline__ Nbr nbr_of(const Geom &G, int s)
+{
+    Nbr S;
+    S.s = s;
+    S.x = s % G.nx;
+    const int yz = s / G.nx;
+    S.y = yz % G.ny;
+    S.z = yz / G.ny;
+    const int sxy = G.nx * G.ny;
+    S.nb[0] = (S.x == G.nx - 1) ? s - (G.nx - 1) : s + 1;
+    S.nb[1] = (S.x == 0) ? s + (G.nx - 1) : s - 1;
+    S.nb[2] = (S.y == G.ny - 1) ? s - G.nx * (G.ny - 1) : s + G.nx;
+    S.nb[3] = (S.y == 0) ? s + G.nx * (G.ny - 1) : s - G.nx;
+    S.nb[4] = (S.z == G.nz - 1) ? s - sxy * (G.nz - 1) : s + sxy;
+    S.nb[5] = (S.z == 0) ? s + sxy * (G.nz - 1) : s - sxy;
+    return S;
+}
+
+// Pulled source of population i arriving at (x,y,z): site (x,y,z) - e_i.
+__device__ __forceinline__ int pull_from(const Geom &G, const Nbr &S, int cx, int cy, int cz)
+{
+    int xs = S.x - cx, ys = S.y - cy, zs = S.z - cz;
+    xs += (xs < 0) ? G.nx : ((xs >= G.nx) ? -G.nx : 0);
+    ys += (ys < 0) ? G.ny : ((ys >= G.ny) ? -G.ny : 0);
+    zs += (zs < 0) ? G.nz : ((zs >= G.nz) ? -G.nz : 0);
+    return xs + G.nx * (ys + G.ny * zs);
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_q(const T *__restrict__ Q, size_t N, const Nbr &S, T q[5], T d[3][5],
+                                         T lap[5])
+{
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const T *P = Q + c * N;
+        const T v = P[S.s];
+        const T xp = P[S.nb[0]], xm = P[S.nb[1]];
+        const T yp = P[S.nb[2]], ym = P[S.nb[3]];
+        const T zp = P[S.nb[4]], zm = P[S.nb[5]];
+        q[c] = v;
+        d[0][c] = T(0.5) * (xp - xm);
+        d[1][c] = T(0.5) * (yp - ym);
+        d[2][c] = T(0.5) * (zp - zm);
+        lap[c] = ((xp + xm) + (yp + ym)) + (zp + zm) - T(6) * v;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_u(const T *__restrict__ u, size_t N, const Nbr &S, T uc[3], T W[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T *P = u + a * N;
+        uc[a] = P[S.s];
+        W[a][0] = T(0.5) * (P[S.nb[0]] - P[S.nb[1]]);
+        W[a][1] = T(0.5) * (P[S.nb[2]] - P[S.nb[3]]);
+        W[a][2] = T(0.5) * (P[S.nb[4]] - P[S.nb[5]]);
+    }
+}
+
+// Body force F_a = sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2 (Eq. (19)).
+template <typename T>
+__device__ __forceinline__ void divergence(const T *__restrict__ Pi, size_t N, const Nbr &S, T F[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T *Px = Pi + (3 * a + 0) * N;
+        const T *Py = Pi + (3 * a + 1) * N;
+        const T *Pz = Pi + (3 * a + 2) * N;
+        F[a] = T(0.5) * ((Px[S.nb[0]] - Px[S.nb[1]]) + (Py[S.nb[2]] - Py[S.nb[3]]) + (Pz[S.nb[4]] - Pz[S.nb[5]]));
+    }
+}
+
+// Stress Pi(Q) at one site (Eqs. (6)-(8)); returns the free-energy density.
+template <typename T>
+__device__ __forceinline__ T stress_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q,
+                                       T *__restrict__ Pi, int s)
+{
+    const size_t N = G.N;
+    const Nbr S = nbr_of(G, s);
+    T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
+    gather_q(Q, N, S, q, d, lap);
+    site_stress(c, q, d, lap, P, fd, H);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Pi[(3 * a + b) * N + s] = P[a][b];
+    return fd;
+}
+
+// Pull-stream, BGK collision with the body force div Pi (Eqs. (14), (16),
+// (19)) at one site; writes g' and u.
+template <typename T>
+__device__ __forceinline__ void lb_at(const Geom &G, const Coef<T> &c, const T *__restrict__ gin,
+                                      const T *__restrict__ Pi, T *__restrict__ gout, T *__restrict__ u, int s)
+{
+    const size_t N = G.N;
+    const Nbr S = nbr_of(G, s);
+    T g[19], F[3], uu[3], rho;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) g[i] = gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
+    divergence(Pi, N, S, F);
+    lb_collide(c, g, F, uu, rho);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) gout[i * N + s] = g[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
+}
+
+// Predictor Q* = Q + R(Q, u) at one site (Eqs. (2)-(4)).
+template <typename T>
+__device__ __forceinline__ void pred_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q,
+                                        const T *__restrict__ u, T *__restrict__ Qs, int s)
+{
+    const size_t N = G.N;
+    const Nbr S = nbr_of(G, s);
+    T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
+    gather_q(Q, N, S, q, d, lap);
+    gather_u(u, N, S, uc, W);
+    site_rhs(c, q, d, lap, uc, W, R);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Qs[k * N + s] = q[k] + R[k];
+}
+
+// Corrector Q^{n+1} = Q^n + [R(Q^n) + R(Q*)]/2 = [Q^n + Q* + R(Q*)]/2, in
+// place over Q (each site reads only its own Q^n).
+template <typename T>
+__device__ __forceinline__ void corr_at(const Geom &G, const Coef<T> &c, T *__restrict__ Q,
+                                        const T *__restrict__ Qs, const T *__restrict__ u, int s)
+{
+    const size_t N = G.N;
+    const Nbr S = nbr_of(G, s);
+    T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
+    gather_q(Qs, N, S, q, d, lap);
+    gather_u(u, N, S, uc, W);
+    site_rhs(c, q, d, lap, uc, W, R);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Q[k * N + s] = T(0.5) * (Q[k * N + s] + q[k] + R[k]);
+}
+
+template <typename T>
+Coef<T> make_coef(const PhysParams &p)
+{
+    Coef<T> c;
+    c.a = T(p.A0 * (1.0 - p.gamma / 3.0));
+    c.bg = T(p.A0 * p.gamma);
+    c.K = T(p.K);
+    c.q0x2 = T(2.0 * p.q0);
+    c.Kq0x2 = T(2.0 * p.K * p.q0);
+    c.Kq0sq4 = T(4.0 * p.K * p.q0 * p.q0);
+    c.xi = T(p.xi);
+    c.Gamma = T(p.Gamma);
+    c.rho0 = T(p.rho0);
+    c.omega = T(1.0 / p.tau);
+    c.pref = T(1.0 - 0.5 / p.tau);
+    return c;
+}
+
+}  // namespace hlb

@@ -17,6 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhlb.so")
 
 HLB_FP64, HLB_FP32 = 0, 1
+SCHED_SITES, SCHED_TILED = 0, 1
+SCHEDULES = {"sites": SCHED_SITES, "tiled": SCHED_TILED}
 STATUS = {0: "HLB_OK", -1: "HLB_ERR_ARG", -2: "HLB_ERR_PARAM", -3: "HLB_ERR_HIP",
           -4: "HLB_ERR_NONFINITE", -5: "HLB_ERR_STATE", -6: "HLB_ERR_NOMEM"}
 
@@ -65,6 +67,9 @@ def lib():
         L.hlb_state_bytes.restype = sz
         L.hlb_get_state.argtypes = [vp, vp, sz]
         L.hlb_set_state.argtypes = [vp, vp, sz]
+        L.hlb_set_schedule.argtypes = [vp, I, I]
+        L.hlb_get_schedule.argtypes = [vp, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.hlb_autotune.argtypes = [vp, I, dp]
         L.hlb_step_timed.argtypes = [vp, I, dp, I]
         L.hlb_kernel_name.argtypes = [I]
         L.hlb_kernel_name.restype = ctypes.c_char_p
@@ -147,6 +152,22 @@ class Solver:
 
     def step(self, n=1):
         self._check(lib().hlb_step(self.ctx, int(n)))
+
+    def set_schedule(self, schedule="sites", tz=0):
+        self._check(lib().hlb_set_schedule(self.ctx, SCHEDULES[schedule], int(tz)))
+
+    def schedule(self):
+        sc, tz = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().hlb_get_schedule(self.ctx, ctypes.byref(sc), ctypes.byref(tz)))
+        name = {v: k for k, v in SCHEDULES.items()}[sc.value]
+        return name, tz.value
+
+    def autotune(self, trial_steps=10):
+        """Pick the fastest step schedule for this lattice and precision (the
+        state is left as it was); returns (schedule, tz, ms per step)."""
+        ms = np.zeros(1)
+        self._check(lib().hlb_autotune(self.ctx, int(trial_steps), _dp(ms)))
+        return (*self.schedule(), float(ms[0]))
 
     def step_timed(self, n=1):
         """Advance n steps timing every kernel with HIP events on the solver's

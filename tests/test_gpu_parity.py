@@ -28,19 +28,24 @@ def H():
     return hlb
 
 
-def make(H, p, Q, u, rho, prec="fp64"):
+SCHEDS = [("sites", 0), ("tiled", 8), ("tiled", 16)]
+
+
+def make(H, p, Q, u, rho, prec="fp64", sched=("sites", 0)):
     s = H.Solver((Q.shape[3], Q.shape[2], Q.shape[1]), prec)
     s.set_params(p)
     s.set_fields(Q, u, rho)
+    s.set_schedule(*sched)
     return s
 
 
-def test_fp64_helix_32cubed_every_step(H, orc):
+@pytest.mark.parametrize("sched", SCHEDS[:2])
+def test_fp64_helix_32cubed_every_step(H, orc, sched):
     """32^3 helix (q0 = 2 pi/16, kappa = 1, tau = 0, noise 1e-4, seed 1), 100
-    steps: Q, u, rho and F_total at every step."""
-    say("case: fp64 helix 32^3, 100 steps")
+    steps: Q, u, rho and F_total at every step, both schedules."""
+    say("case: fp64 helix 32^3, 100 steps", sched)
     p, Q, u, rho = I.helix_case()
-    gpu = make(H, p, Q, u, rho)
+    gpu = make(H, p, Q, u, rho, sched=sched)
     ref = orc.State(oracle_params(orc, p), Q, u, rho)
     spread = fp64_spread()["u"]
     worst = {"Q": 0.0, "u": 0.0, "rho": 0.0, "F": 0.0, "u/spread": 0.0}
@@ -63,11 +68,12 @@ def test_fp64_helix_32cubed_every_step(H, orc):
     say("fp64 32^3 worst relative errors:", worst)
 
 
-def test_fp32_helix_1000_steps(H, orc):
+@pytest.mark.parametrize("sched", SCHEDS[:2])
+def test_fp32_helix_1000_steps(H, orc, sched):
     """FP32 form vs FP64 oracle after 1000 steps: Q within 1e-5 relative."""
-    say("case: fp32 helix 32^3, 1000 steps")
+    say("case: fp32 helix 32^3, 1000 steps", sched)
     p, Q, u, rho = I.helix_case()
-    gpu = make(H, p, Q, u, rho, "fp32")
+    gpu = make(H, p, Q, u, rho, "fp32", sched)
     ref = orc.State(oracle_params(orc, p), Q, u, rho)
     gpu.step(1000)
     ref.step(1000)
@@ -80,18 +86,19 @@ def test_fp32_helix_1000_steps(H, orc):
     assert eQ <= 1e-5
 
 
+@pytest.mark.parametrize("sched", SCHEDS)
 @pytest.mark.parametrize("shape", [(13, 7, 9), (37, 5, 6), (4, 4, 4), (70, 3 + 2, 11)])
-def test_fp64_ragged_shapes(H, orc, shape):
+def test_fp64_ragged_shapes(H, orc, shape, sched):
     """Odd, non-cubic and minimum-size lattices (several blocks plus a ragged
     tail) with a strongly perturbed state, flow coupled."""
-    say("case: fp64 ragged", shape)
+    say("case: fp64 ragged", shape, sched)
     rng = np.random.default_rng(sum(shape))
     nx, ny, nz = shape
     p = I.PhysParams(K=0.02, q0=0.35, gamma=3.1)
     Q = I.smooth_field(shape, amp=0.2, seed=5) + rng.uniform(-0.02, 0.02, size=(5, nz, ny, nx))
     u = rng.uniform(-1e-3, 1e-3, size=(3, nz, ny, nx))
     rho = 1 + rng.uniform(-1e-3, 1e-3, size=(nz, ny, nx))
-    gpu = make(H, p, Q, u, rho)
+    gpu = make(H, p, Q, u, rho, sched=sched)
     ref = orc.State(oracle_params(orc, p), Q, u, rho)
     for n in (1, 4, 15):
         gpu.step(n)
@@ -104,12 +111,13 @@ def test_fp64_ragged_shapes(H, orc, shape):
         assert abs(gpu.totals()[2] - ref.totals()[2]) <= 1e-12 * abs(ref.totals()[2])
 
 
-def test_fp64_flow_off(H, orc):
+@pytest.mark.parametrize("sched", SCHEDS[:2])
+def test_fp64_flow_off(H, orc, sched):
     """Pure relaxation (u == 0, populations untouched)."""
-    say("case: fp64 flow off 24x20x16")
+    say("case: fp64 flow off 24x20x16", sched)
     p, Q, _, _ = I.helix_case(n=24, q0=2 * math.pi / 12, flow=False)
     Q = Q[:, :16, :20, :24].copy()
-    gpu = make(H, p, Q, None, None)
+    gpu = make(H, p, Q, None, None, sched=sched)
     ref = orc.State(oracle_params(orc, p), Q)
     gpu.step(30)
     ref.step(30)
@@ -120,28 +128,30 @@ def test_fp64_flow_off(H, orc):
     assert np.abs(rg - 1).max() == 0.0
 
 
-def test_checkpoint_restart_bitwise(H):
-    say("case: checkpoint 16^3")
+@pytest.mark.parametrize("sched", SCHEDS[:2])
+def test_checkpoint_restart_bitwise(H, sched):
+    say("case: checkpoint 16^3", sched)
     p, Q, u, rho = I.helix_case(n=16, q0=2 * math.pi / 8)
-    a = make(H, p, Q, u, rho)
+    a = make(H, p, Q, u, rho, sched=sched)
     a.step(20)
     snap = a.get_state()
     a.step(20)
     Qa, ua, ra = a.fields()
-    b = make(H, p, np.zeros_like(Q), None, None)
+    b = make(H, p, np.zeros_like(Q), None, None, sched=sched)
     b.set_state(snap)
     b.step(20)
     Qb, ub, rb = b.fields()
     assert np.array_equal(Qa, Qb) and np.array_equal(ua, ub) and np.array_equal(ra, rb)
 
 
-def test_deterministic(H):
-    say("case: determinism 20^3 fp64+fp32")
+@pytest.mark.parametrize("sched", SCHEDS[:2])
+def test_deterministic(H, sched):
+    say("case: determinism 20^3 fp64+fp32", sched)
     p, Q, u, rho = I.helix_case(n=20, q0=2 * math.pi / 10)
     for prec in ("fp64", "fp32"):
         runs = []
         for _ in range(2):
-            s = make(H, p, Q, u, rho, prec)
+            s = make(H, p, Q, u, rho, prec, sched)
             s.step(25)
             runs.append((s.fields(), s.totals()))
         (f1, t1), (f2, t2) = runs
@@ -174,12 +184,13 @@ def test_conservation_fp32_long(H):
 
 
 def test_full_size_128_fp64_every_site(H, orc):
-    """The 128^3 benchmark workload in the benchmark's launch configuration:
-    FP64 GPU vs the oracle on every site after 5 steps; then the FP32 form's
-    conservation laws over 200 steps."""
+    """The 128^3 benchmark workload in the benchmark's launch configuration
+    (the schedule the autotuner picks): FP64 GPU vs the oracle on every site
+    after 5 steps; then the FP32 form's conservation laws over 200 steps."""
     say("case: 128^3 O2 fp64 5 steps vs oracle")
     p, Q, u, rho = I.bpii_case(n=128)
     gpu = make(H, p, Q, u, rho)
+    say("autotuned:", gpu.autotune(5))
     ref = orc.State(oracle_params(orc, p), Q, u, rho)
     gpu.step(5)
     ref.step(5)
@@ -193,8 +204,44 @@ def test_full_size_128_fp64_every_site(H, orc):
     del gpu
     say("case: 128^3 O2 fp32 conservation")
     s = make(H, p, Q, u, rho, "fp32")
+    say("autotuned:", s.autotune(5))
     m0, mom0, _ = s.totals()
     s.step(200)
     m1, mom1, _ = s.totals()
     assert abs(m1 - m0) / m0 < 1e-6
     assert np.abs(mom1 - mom0).max() < 1e-4
+
+
+def test_autotune_keeps_state(H):
+    """The autotuner's trial steps leave the state untouched."""
+    say("case: autotune keeps state 24^3")
+    p, Q, u, rho = I.helix_case(n=24, q0=2 * math.pi / 12)
+    a = make(H, p, Q, u, rho)
+    a.step(3)
+    before = a.fields()
+    sched = a.autotune(3)
+    after = a.fields()
+    say("autotuned:", sched)
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    b = make(H, p, Q, u, rho, sched=sched[:2])
+    b.step(3)
+    a.step(4)
+    b.step(4)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+
+
+def test_schedules_agree_fp32(H):
+    """Per-site and tiled schedules give the same FP32 step to rounding."""
+    say("case: schedules agree fp32 40x24x20")
+    p, Q, u, rho = I.helix_case(n=40, q0=2 * math.pi / 10)
+    Q = Q[:, :20, :24, :40].copy()
+    u, rho = u[:, :20, :24, :40].copy(), rho[:20, :24, :40].copy()
+    a = make(H, p, Q, u, rho, "fp32", ("sites", 0))
+    b = make(H, p, Q, u, rho, "fp32", ("tiled", 8))
+    a.step(50)
+    b.step(50)
+    Qa, ua, ra = a.fields()
+    Qb, ub, rb = b.fields()
+    assert rel(Qb, Qa) < 1e-5 and rel(rb, ra) < 1e-6
