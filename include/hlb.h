@@ -160,6 +160,53 @@ int hlb_autotune(hlb_ctx *ctx, int trial_steps, double *best_ms_per_step);
 int hlb_step_timed(hlb_ctx *ctx, int nsteps, double *kernel_ms, int nkernels);
 const char *hlb_kernel_name(int k);
 
+/* ------------------------------------------------------------------------
+ * Batched form: n periodic boxes of uneven size, each with its own
+ * parameters (e.g. a scan of chirality kappa and reduced temperature tau,
+ * Sec. 2.1, Eqs. (9)-(10)), advanced by one persistent kernel launch per
+ * call.  The step of every box is the per-site schedule above (same device
+ * code), so a box gives the same result as a single context on it.  Each box
+ * is cut into work items of `chunk` sites; items of all boxes are spread over
+ * the co-resident blocks and the four phases of a step are separated by grid
+ * barriers whose waits are bounded (a stall ends the launch with an error,
+ * reported by the next hlb_batch_sync / readout as HLB_ERR_HIP).
+ * ------------------------------------------------------------------------ */
+typedef struct hlb_batch hlb_batch;
+
+/* dims: n triples (nx, ny, nz), each >= 4.  Returns 0 for invalid input. */
+size_t hlb_batch_workspace_bytes(int n, const int *dims, int precision);
+int hlb_batch_create(int n, const int *dims, int precision, void *device_workspace, size_t workspace_bytes,
+                     void *hip_stream, hlb_batch **out);
+/* Per box i in [0, n): same validation as hlb_set_params / hlb_set_fields. */
+int hlb_batch_set_params(hlb_batch *b, int i, const hlb_lb_params *lb, const hlb_fe_params *fe,
+                         const hlb_be_params *be);
+int hlb_batch_set_fields(hlb_batch *b, int i, const double *Q5, const double *u3, const double *rho);
+/* Sites per work item for boxes of `sites_of_box` sites (multiple of 256;
+ * default 1024). */
+int hlb_batch_set_chunk(hlb_batch *b, int sites_of_box, int chunk);
+/* Autotuner: for each distinct box size, time trial_steps batched steps with
+ * chunks of 256, 1024, 4096 and 16384 sites (HIP events on the batch stream)
+ * and keep the fastest; the states are put back afterwards (host copies).
+ * Writes up to max_out (size, chunk) pairs; returns the number of sizes. */
+int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunks_out, int max_out);
+/* Enqueue nsteps steps of every box as one persistent launch. */
+int hlb_batch_step(hlb_batch *b, int nsteps);
+/* Capture one persistent launch of nsteps steps into a HIP graph;
+ * hlb_batch_launch replays it (nsteps more steps per replay).  Changing any
+ * box's parameters or chunk afterwards requires a new capture.  Capture needs
+ * a non-null stream (HLB_ERR_ARG otherwise). */
+int hlb_batch_capture(hlb_batch *b, int nsteps);
+int hlb_batch_launch(hlb_batch *b);
+/* Wait for the batch stream and check the barrier error flag. */
+int hlb_batch_sync(hlb_batch *b);
+/* Readout of box i at the current level (as hlb_get_fields / hlb_get_totals). */
+int hlb_batch_get_fields(hlb_batch *b, int i, double *Q5, double *u3, double *rho);
+int hlb_batch_get_totals(hlb_batch *b, int i, double *mass, double *mom3, double *free_energy);
+/* Grid size of the persistent launch and number of work items. */
+int hlb_batch_info(const hlb_batch *b, int *grid, int *n_items);
+const char *hlb_batch_last_error(const hlb_batch *b);
+void hlb_batch_destroy(hlb_batch *b);
+
 /* Message of the last error on this context ("" if none). Never NULL. */
 const char *hlb_last_error(const hlb_ctx *ctx);
 

@@ -1,0 +1,28 @@
+// batch.h -- internal interface of the batched persistent kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "kernels.h"
+
+namespace hlb {
+
+// Size of one box descriptor on the device and packing of the descriptor
+// table (box views, parameters, population ping-pong indices).
+size_t batch_rep_bytes(bool fp32);
+void batch_pack_reps(bool fp32, const std::vector<Device> &box, const std::vector<PhysParams> &par,
+                     const std::vector<int> &gcur, std::vector<char> &blob);
+
+// Largest grid (multiple of 8, at most n_items) whose blocks are all
+// co-resident on the current device.
+hipError_t batch_grid(bool fp32, int n_items, int *grid);
+
+// Enqueue: reset the barrier counter (a one-block kernel, so the pair can be
+// captured in a graph) and run the persistent kernel for nsteps steps.
+// d_items holds int4 {box, first site, site count, 0} per work item.
+hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items, int n_items, unsigned *d_bar,
+                        int *d_err, int nsteps, int grid, hipStream_t stream);
+
+}  // namespace hlb

@@ -73,6 +73,26 @@ def lib():
         L.hlb_step_timed.argtypes = [vp, I, dp, I]
         L.hlb_kernel_name.argtypes = [I]
         L.hlb_kernel_name.restype = ctypes.c_char_p
+        ip = ctypes.POINTER(I)
+        L.hlb_batch_workspace_bytes.argtypes = [I, ip, I]
+        L.hlb_batch_workspace_bytes.restype = sz
+        L.hlb_batch_create.argtypes = [I, ip, I, vp, sz, vp, ctypes.POINTER(vp)]
+        L.hlb_batch_set_params.argtypes = [vp, I, ctypes.POINTER(LbParams), ctypes.POINTER(FeParams),
+                                           ctypes.POINTER(BeParams)]
+        L.hlb_batch_set_fields.argtypes = [vp, I, dp, dp, dp]
+        L.hlb_batch_set_chunk.argtypes = [vp, I, I]
+        L.hlb_batch_autotune.argtypes = [vp, I, ip, ip, I]
+        L.hlb_batch_step.argtypes = [vp, I]
+        L.hlb_batch_capture.argtypes = [vp, I]
+        L.hlb_batch_launch.argtypes = [vp]
+        L.hlb_batch_sync.argtypes = [vp]
+        L.hlb_batch_get_fields.argtypes = [vp, I, dp, dp, dp]
+        L.hlb_batch_get_totals.argtypes = [vp, I, dp, dp, dp]
+        L.hlb_batch_info.argtypes = [vp, ip, ip]
+        L.hlb_batch_last_error.argtypes = [vp]
+        L.hlb_batch_last_error.restype = ctypes.c_char_p
+        L.hlb_batch_destroy.argtypes = [vp]
+        L.hlb_batch_destroy.restype = None
         L.hlb_last_error.argtypes = [vp]
         L.hlb_last_error.restype = ctypes.c_char_p
         L.hlb_destroy.argtypes = [vp]
@@ -207,6 +227,106 @@ class Solver:
         if getattr(self, "ctx", None):
             lib().hlb_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many periodic boxes of uneven size advanced by one persistent launch.
+
+    ``shapes``: list of (nx, ny, nz).  Arrays per box are float64 [c][z][y][x].
+    """
+
+    def __init__(self, shapes, precision="fp32", device="cuda", stream=None):
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.n = len(self.shapes)
+        self.prec = {"fp64": HLB_FP64, "fp32": HLB_FP32}[precision]
+        dims = (ctypes.c_int * (3 * self.n))(*[v for s in self.shapes for v in s])
+        self._dims = dims
+        L = lib()
+        nbytes = L.hlb_batch_workspace_bytes(self.n, dims, self.prec)
+        if nbytes == 0:
+            raise HlbError(-1, "invalid batch shapes")
+        self.device = torch.device(device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        # graph capture needs a stream of its own (the legacy null stream cannot
+        # be captured); default priority
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        b = ctypes.c_void_p()
+        rc = L.hlb_batch_create(self.n, dims, self.prec, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(b))
+        if rc:
+            raise HlbError(rc, "hlb_batch_create")
+        self.b = b
+
+    def _check(self, rc):
+        if rc < 0:
+            raise HlbError(rc, lib().hlb_batch_last_error(self.b).decode())
+        return rc
+
+    def set_params(self, i, p):
+        lb = LbParams(p.tau, p.rho0)
+        fe = FeParams(p.A0, p.gamma, p.K, p.q0)
+        be = BeParams(p.Gamma, p.xi, 1 if p.flow else 0)
+        self._check(lib().hlb_batch_set_params(self.b, i, ctypes.byref(lb), ctypes.byref(fe), ctypes.byref(be)))
+
+    def set_fields(self, i, Q5, u3=None, rho=None):
+        Q5 = np.ascontiguousarray(Q5, dtype=np.float64)
+        u3 = None if u3 is None else np.ascontiguousarray(u3, dtype=np.float64)
+        rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+        nx, ny, nz = self.shapes[i]
+        assert Q5.shape == (5, nz, ny, nx)
+        self._check(lib().hlb_batch_set_fields(self.b, i, _dp(Q5), _dp(u3), _dp(rho)))
+
+    def set_chunk(self, sites_of_box, chunk):
+        self._check(lib().hlb_batch_set_chunk(self.b, int(sites_of_box), int(chunk)))
+
+    def autotune(self, trial_steps=3):
+        """{box size in sites: chosen chunk}; the states are left as they were."""
+        n = 64
+        sizes = (ctypes.c_int * n)()
+        chunks = (ctypes.c_int * n)()
+        k = self._check(lib().hlb_batch_autotune(self.b, int(trial_steps), sizes, chunks, n))
+        return {sizes[j]: chunks[j] for j in range(min(k, n))}
+
+    def step(self, n=1):
+        self._check(lib().hlb_batch_step(self.b, int(n)))
+
+    def capture(self, n):
+        self._check(lib().hlb_batch_capture(self.b, int(n)))
+
+    def launch(self):
+        self._check(lib().hlb_batch_launch(self.b))
+
+    def sync(self):
+        self._check(lib().hlb_batch_sync(self.b))
+
+    def info(self):
+        g, n = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().hlb_batch_info(self.b, ctypes.byref(g), ctypes.byref(n)))
+        return g.value, n.value
+
+    def fields(self, i):
+        nx, ny, nz = self.shapes[i]
+        Q5 = np.empty((5, nz, ny, nx))
+        u3 = np.empty((3, nz, ny, nx))
+        rho = np.empty((nz, ny, nx))
+        self._check(lib().hlb_batch_get_fields(self.b, i, _dp(Q5), _dp(u3), _dp(rho)))
+        return Q5, u3, rho
+
+    def totals(self, i):
+        m, mom, f = np.zeros(1), np.zeros(3), np.zeros(1)
+        self._check(lib().hlb_batch_get_totals(self.b, i, _dp(m), _dp(mom), _dp(f)))
+        return float(m[0]), mom, float(f[0])
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().hlb_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:
