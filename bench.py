@@ -107,6 +107,46 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto"):
     return out
 
 
+def run_batched(steps, graph_steps=50):
+    """96 uneven periodic boxes (sizes 24/32/48/64, per-box kappa and tau) in
+    one persistent launch per graph replay, FP32.  Aggregate MLUPS."""
+    import torch
+
+    from paper_0901_3293_amd import hlb
+    from paper_0901_3293_amd import inputs as I
+
+    rs = I.replica_set()
+    shapes = [(r["L"],) * 3 for r in rs]
+    b = hlb.Batch(shapes, "fp32")
+    for i, r in enumerate(rs):
+        b.set_params(i, r["params"])
+        b.set_fields(i, r["Q"], r["u"], r["rho"])
+    chunks = b.autotune(3)
+    b.capture(graph_steps)
+    b.launch()
+    b.sync()
+    reps = max(1, steps // graph_steps)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(b.stream)
+    for _ in range(reps):
+        b.launch()
+    ev1.record(b.stream)
+    b.sync()
+    ms = ev0.elapsed_time(ev1)
+    sites = sum(L ** 3 for L in (r["L"] for r in rs))
+    grid, items = b.info()
+    masses = [b.totals(i)[0] for i in range(len(rs))]
+    out = {"mlups": sites * reps * graph_steps / (ms / 1e3) / 1e6, "boxes": len(rs), "sites": sites,
+           "steps": reps * graph_steps, "ms_per_step": ms / (reps * graph_steps), "grid": grid,
+           "work_items": items, "chunk_by_box_sites": chunks,
+           "sizes": {str(L): sum(1 for r in rs if r["L"] == L) for L in (24, 32, 48, 64)},
+           "finite": bool(all(math.isfinite(m) for m in masses))}
+    b.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n, budget_s=15.0):
     """The FP64 oracle (test infrastructure) on the host: steps of the same
     128^3 workload until the time budget is spent (at least one step)."""
@@ -141,6 +181,8 @@ def main():
                     help="time one form only (profiling runs)")
     ap.add_argument("--schedule", choices=["auto", "sites", "tiled"], default="auto",
                     help="step schedule (auto: the library's autotuner picks)")
+    ap.add_argument("--batch-steps", type=int, default=1000,
+                    help="steps of the 96-box batched FP32 run (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -165,6 +207,11 @@ def main():
         log(f"bench: {prec} {a.n}^3, warmup {a.warmup}, steps {a.steps}")
         res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps, a.schedule)
         log(f"bench: {prec} {res[prec]['mlups']:.1f} MLUPS, kernels {res[prec]['kernel_ms_per_launch']}")
+    batched = None
+    if a.batch_steps > 0 and not a.only:
+        log(f"bench: batched 96 boxes fp32, {a.batch_steps} steps")
+        batched = run_batched(a.batch_steps)
+        log(f"bench: batched {batched['mlups']:.1f} MLUPS aggregate")
     cpu = None
     if not a.no_cpu:
         log("bench: cpu baseline (oracle)")
@@ -197,6 +244,7 @@ def main():
                  "schedule": r64["schedule"],
                  "roofline": r64["roofline"], "step_roofline": r64["step_roofline"],
                  "kernel_ms_per_launch": r64["kernel_ms_per_launch"]},
+        "batched": batched,
         "checks": {"fp32": r32["checks"], "fp64": r64["checks"]},
         "cpu_baseline": cpu,
     }

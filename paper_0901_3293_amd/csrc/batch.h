@@ -16,8 +16,9 @@ void batch_pack_reps(bool fp32, const std::vector<Device> &box, const std::vecto
                      const std::vector<int> &gcur, std::vector<char> &blob);
 
 // Largest grid (multiple of 8, at most n_items) whose blocks are all
-// co-resident on the current device.
-hipError_t batch_grid(bool fp32, int n_items, int *grid);
+// co-resident on the current device, with at most blocks_per_cu blocks per
+// compute unit (0: as many as fit).
+hipError_t batch_grid(bool fp32, int n_items, int blocks_per_cu, int *grid);
 
 // Enqueue: reset the barrier counter (a one-block kernel, so the pair can be
 // captured in a graph) and run the persistent kernel for nsteps steps.

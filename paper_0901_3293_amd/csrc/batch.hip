@@ -30,22 +30,24 @@ struct Rep {
     int gcur;  // ping-pong index of the populations, advanced on the device
 };
 
-// Grid-wide barrier over a monotonically increasing arrival counter.  Every
-// thread publishes its writes at device scope before arriving; thread 0 polls
-// with a bounded number of sleeps; afterwards every wave invalidates its
-// caches so the next phase reads what other XCDs wrote.  Returns false (in
-// every thread of the block) if the wait ran out or another block failed.
+// Grid-wide barrier over a monotonically increasing arrival counter.  The
+// block's stores are complete at the workgroup barrier; thread 0 then
+// publishes them at device scope (one L2 write-back per block), arrives,
+// polls with a bounded number of sleeps, and acquires at device scope (one
+// cache invalidation per block, shared by the CU's waves) so the next phase
+// reads what other XCDs wrote.  Returns false (in every thread of the block)
+// if the wait ran out or another block failed.
 __device__ __forceinline__ bool grid_sync(unsigned *bar, int *err, unsigned &target, unsigned spin_limit)
 {
-    __threadfence();
     __syncthreads();
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         target += gridDim.x;
         atomicAdd(bar, 1u);
         int ok = 1;
         unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > spin_limit) {
                 atomicMax(err, 1);
                 ok = 0;
@@ -53,14 +55,53 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, int *err, unsigned &tar
             }
             __builtin_amdgcn_s_sleep(2);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return s_ok != 0;
 }
 
 enum Phase { PH_STRESS, PH_LB, PH_PRED, PH_CORR };
+
+// The work item and its box descriptor are the same for the whole block;
+// moving them into scalar registers keeps the stencil addressing at one VGPR
+// per access (base in SGPRs) instead of 64-bit per-lane addresses.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ double uni(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b & 0xffffffffll)));
+    const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(b >> 32)));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <typename P>
+__device__ __forceinline__ P *uni(P *p)
+{
+    const unsigned long long b = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b & 0xffffffffull)));
+    const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(b >> 32)));
+    return reinterpret_cast<P *>(((unsigned long long)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ Coef<T> uni(const Coef<T> &c)
+{
+    Coef<T> r;
+    r.a = uni(c.a);
+    r.bg = uni(c.bg);
+    r.K = uni(c.K);
+    r.q0x2 = uni(c.q0x2);
+    r.Kq0x2 = uni(c.Kq0x2);
+    r.Kq0sq4 = uni(c.Kq0sq4);
+    r.xi = uni(c.xi);
+    r.Gamma = uni(c.Gamma);
+    r.rho0 = uni(c.rho0);
+    r.omega = uni(c.omega);
+    r.pref = uni(c.pref);
+    return r;
+}
 
 template <typename T, int PH>
 __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 *__restrict__ items,
@@ -70,20 +111,31 @@ __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 
     const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
     const int seg = (n_items + 7) >> 3;
     const int lo = xcd * seg, hi = min(n_items, lo + seg);
+#pragma unroll 1
     for (int it = lo + local; it < hi; it += per) {
-        const int4 w = items[it];
-        Rep<T> &R = reps[w.x];
-        if ((PH == PH_STRESS || PH == PH_LB) && !R.flow) continue;
-        const int gc = R.gcur ^ (step & 1);
-        for (int s = w.y + int(threadIdx.x); s < w.y + w.z; s += BLK) {
+        const int4 w4 = items[it];
+        const int box = uni(w4.x), first = uni(w4.y), count = uni(w4.z);
+        const Rep<T> &R = reps[box];
+        if ((PH == PH_STRESS || PH == PH_LB) && !uni(R.flow)) continue;
+        const int gc = uni(R.gcur) ^ (step & 1);
+        const Geom G = {uni(R.G.nx), uni(R.G.ny), uni(R.G.nz), uni(R.G.N)};
+        const Coef<T> c = uni(R.c);
+        T *__restrict__ Q = uni(R.Q);
+        T *__restrict__ Qs = uni(R.Qs);
+        T *__restrict__ u = uni(R.u);
+        T *__restrict__ Pi = uni(R.Pi);
+        const T *__restrict__ gin = uni(R.g[gc]);
+        T *__restrict__ gout = uni(R.g[gc ^ 1]);
+#pragma unroll 1
+        for (int s = first + int(threadIdx.x); s < first + count; s += BLK) {
             if (PH == PH_STRESS)
-                stress_at(R.G, R.c, R.Q, R.Pi, s);
+                stress_at(G, c, Q, Pi, s);
             else if (PH == PH_LB)
-                lb_at(R.G, R.c, R.g[gc], R.Pi, R.g[gc ^ 1], R.u, s);
+                lb_at(G, c, gin, Pi, gout, u, s);
             else if (PH == PH_PRED)
-                pred_at(R.G, R.c, R.Q, R.u, R.Qs, s);
+                pred_at(G, c, Q, u, Qs, s);
             else
-                corr_at(R.G, R.c, R.Q, R.Qs, R.u, s);
+                corr_at(G, c, Q, Qs, u, s);
         }
     }
 }
@@ -152,7 +204,7 @@ void batch_pack_reps(bool fp32, const std::vector<Device> &box, const std::vecto
         fill_reps<double>(box, par, gcur, blob);
 }
 
-hipError_t batch_grid(bool fp32, int n_items, int *grid)
+hipError_t batch_grid(bool fp32, int n_items, int blocks_per_cu, int *grid)
 {
     int dev = 0, per_cu = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -161,6 +213,7 @@ hipError_t batch_grid(bool fp32, int n_items, int *grid)
         e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float>, BLK, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double>, BLK, 0);
     if (e != hipSuccess) return e;
+    if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
     int g = per_cu * cus;
     if (g > n_items) g = n_items;
     g = g / 8 * 8;

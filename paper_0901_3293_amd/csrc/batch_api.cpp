@@ -32,6 +32,7 @@ struct hlb_batch {
     unsigned *d_bar;
     int *d_err;
     int grid;
+    int bpc;                         // blocks per compute unit of the persistent grid (0: max)
     bool dirty;                      // descriptor table / work list must be rebuilt
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -124,7 +125,7 @@ int rebuild(hlb_batch *b)
     B_TRY(b, hipMemcpyAsync(b->d_reps, blob.data(), blob.size(), hipMemcpyHostToDevice, b->stream));
     B_TRY(b, hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
     B_TRY(b, hipStreamSynchronize(b->stream));
-    B_TRY(b, hlb::batch_grid(b->fp32, b->n_items, &b->grid));
+    B_TRY(b, hlb::batch_grid(b->fp32, b->n_items, b->bpc, &b->grid));
     b->dirty = false;
     drop_graph(b);
     return HLB_OK;
@@ -367,12 +368,21 @@ int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunk
     B_TRY(b, hipEventCreate(&ea));
     B_TRY(b, hipEventCreate(&eb));
     int rc = HLB_OK;
-    for (int N : sizes) {  // coordinate descent, one box size at a time
+    // coordinate descent: blocks per CU first (key 0 below), then the chunk
+    // of each box size in turn
+    std::vector<int> keys(1, 0);
+    keys.insert(keys.end(), sizes.begin(), sizes.end());
+    for (int N : keys) {
         double best = 1e300;
-        int pick = chunk_for(b, N);
-        for (int ch : cands) {
-            if (ch > N && ch != 256) continue;
-            b->chunk_of_n[N] = ch;
+        int pick = N == 0 ? b->bpc : chunk_for(b, N);
+        const std::vector<int> opts = N == 0 ? std::vector<int>{1, 2, 3, 4}
+                                             : std::vector<int>(std::begin(cands), std::end(cands));
+        for (int ch : opts) {
+            if (N != 0 && ch > N && ch != 256) continue;
+            if (N == 0)
+                b->bpc = ch;
+            else
+                b->chunk_of_n[N] = ch;
             if ((rc = rebuild(b))) break;
             hipError_t e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->n_items, b->d_bar, b->d_err, 1,
                                              b->grid, b->stream);
@@ -397,7 +407,10 @@ int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunk
             }
         }
         if (rc) break;
-        b->chunk_of_n[N] = pick;
+        if (N == 0)
+            b->bpc = pick;
+        else
+            b->chunk_of_n[N] = pick;
     }
     (void)hipEventDestroy(ea);
     (void)hipEventDestroy(eb);
