@@ -128,6 +128,12 @@ int hlb_get_fields(hlb_ctx *ctx, double *Q5, double *u3, double *rho);
  * HLB_ERR_NONFINITE if any total is NaN or Inf.  Synchronises the stream. */
 int hlb_get_totals(hlb_ctx *ctx, double *mass, double *mom3, double *free_energy);
 
+/* Free-energy profile along z: fz[z] = sum over the plane z of the
+ * free-energy density (Eq. (1)) of the current Q, FP64, fixed-order per-plane
+ * reduction; the domain-wall position of a slab run is read off this profile.
+ * fz: host array of nz doubles.  Synchronises the stream. */
+int hlb_get_fz(hlb_ctx *ctx, double *fz);
+
 /* Raw checkpoint of the state (populations and Q in the context's precision).
  * hlb_state_bytes gives the size; get/set copy exactly that many bytes. */
 size_t hlb_state_bytes(hlb_ctx *ctx);

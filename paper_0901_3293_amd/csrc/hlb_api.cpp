@@ -314,6 +314,20 @@ const char *hlb_kernel_name(int k)
     return n ? n : "";
 }
 
+int hlb_get_fz(hlb_ctx *c, double *fz)
+{
+    HLB_GUARD(c);
+    if (!fz) return set_error(c, HLB_ERR_ARG, "fz is null");
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
+    const int nz = c->D.G.nz;
+    HIP_TRY(c, hlb::run_fz(c->D, c->p, c->D.part));
+    HIP_TRY(c, hipMemcpyAsync(fz, c->D.part, nz * sizeof(double), hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
+    for (int z = 0; z < nz; ++z)
+        if (!std::isfinite(fz[z])) return set_error(c, HLB_ERR_NONFINITE, "non-finite f(z) at z = %d", z);
+    return HLB_OK;
+}
+
 size_t hlb_state_bytes(hlb_ctx *c) { return c ? c->state_bytes : 0; }
 
 int hlb_get_state(hlb_ctx *c, void *buf, size_t nbytes)

@@ -72,4 +72,7 @@ hipError_t run_init(Device &D, const PhysParams &p, const double *stage);
 // res[0] = sum (rho - rho0), res[1..3] = sum rho u, res[4] = sum f.
 hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *totals);
 
+// Plane sums of the free-energy density of the current Q into device fz[nz].
+hipError_t run_fz(Device &D, const PhysParams &p, double *fz);
+
 }  // namespace hlb

@@ -546,6 +546,19 @@ __global__ __launch_bounds__(BLK) void k_reduce(const double *__restrict__ part,
     }
 }
 
+// Plane sums of the free-energy density: block z sums plane z in a fixed
+// order (FP64), so the profile f(z) is deterministic.
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_fz(Geom G, Coef<T> c, const T *__restrict__ Q, double *__restrict__ fz)
+{
+    const int z = blockIdx.x;
+    const int sxy = G.nx * G.ny;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < sxy; k += BLK) acc += double(fdens_at(G, c, Q, z * sxy + k));
+    double v[1] = {acc};
+    block_sum<1, BLK>(v, fz + z);
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_fill(T *__restrict__ p, size_t n, T v)
 {
@@ -672,12 +685,25 @@ hipError_t readout_t(Device &D, const PhysParams &p, double *stage, double *tota
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t fz_t(Device &D, const PhysParams &p, double *fz)
+{
+    k_fz<T><<<D.G.nz, BLK, 0, D.stream>>>(D.G, make_coef<T>(p), static_cast<const T *>(D.Q[D.qcur]), fz);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t run_fz(Device &D, const PhysParams &p, double *fz)
+{
+    return D.fp32 ? fz_t<float>(D, p, fz) : fz_t<double>(D, p, fz);
+}
 
 size_t partial_doubles(int nx, int ny, int nz)
 {
-    // per-site blocks x 4 (readout moments) + per-site blocks (free energy)
-    return size_t(5) * site_blocks(nx * ny * nz) + 16;
+    // per-site blocks x 4 (readout moments) + per-site blocks (free energy),
+    // or one value per z-plane (free-energy profile)
+    return size_t(5) * site_blocks(nx * ny * nz) + size_t(nz) + 16;
 }
 
 const char *kernel_name(int k)

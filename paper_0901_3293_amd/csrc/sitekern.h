@@ -159,6 +159,28 @@ __device__ __forceinline__ void corr_at(const Geom &G, const Coef<T> &c, T *__re
     for (int k = 0; k < 5; ++k) Q[k * N + s] = T(0.5) * (Q[k * N + s] + q[k] + R[k]);
 }
 
+// Free-energy density at one site (Eq. (1) with the divergence term).
+template <typename T>
+__device__ __forceinline__ T fdens_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q, int s)
+{
+    const Nbr S = nbr_of(G, s);
+    T q[5], d[3][5], lap[5], Qf[3][3], dQ[3][3][3], CQ[3][3], Q2[3][3], M[3][3], div[3];
+    gather_q(Q, size_t(G.N), S, q, d, lap);
+    full3(q, Qf);
+    full_grad(d, dQ);
+    curl(dQ, CQ);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            Q2[a][b] = Qf[a][0] * Qf[0][b] + Qf[a][1] * Qf[1][b] + Qf[a][2] * Qf[2][b];
+            M[a][b] = CQ[a][b] + c.q0x2 * Qf[a][b];
+        }
+        div[a] = dQ[0][a][0] + dQ[1][a][1] + dQ[2][a][2];
+    }
+    return free_energy(c, Qf, Q2, Q2[0][0] + Q2[1][1] + Q2[2][2], div, M);
+}
+
 template <typename T>
 Coef<T> make_coef(const PhysParams &p)
 {

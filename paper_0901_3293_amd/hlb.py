@@ -67,6 +67,7 @@ def lib():
         L.hlb_state_bytes.restype = sz
         L.hlb_get_state.argtypes = [vp, vp, sz]
         L.hlb_set_state.argtypes = [vp, vp, sz]
+        L.hlb_get_fz.argtypes = [vp, dp]
         L.hlb_set_schedule.argtypes = [vp, I, I]
         L.hlb_get_schedule.argtypes = [vp, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.hlb_autotune.argtypes = [vp, I, dp]
@@ -205,6 +206,12 @@ class Solver:
         rho = np.empty((nz, ny, nx))
         self._check(lib().hlb_get_fields(self.ctx, _dp(Q5), _dp(u3), _dp(rho)))
         return Q5, u3, rho
+
+    def fz(self):
+        """Plane sums of the free-energy density, one per z (FP64)."""
+        out = np.zeros(self.shape[2])
+        self._check(lib().hlb_get_fz(self.ctx, _dp(out)))
+        return out
 
     def totals(self):
         m = np.zeros(1)

@@ -245,3 +245,22 @@ def test_schedules_agree_fp32(H):
     Qa, ua, ra = a.fields()
     Qb, ub, rb = b.fields()
     assert rel(Qb, Qa) < 1e-5 and rel(rb, ra) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_free_energy_profile(H, orc, prec):
+    """Plane sums of f on the domain-growth slab (O2 seed in an x-helix),
+    against the oracle's free-energy density summed per plane."""
+    say("case: f(z) slab 32x24x40", prec)
+    p, Q, u, rho = I.slab_case(nx=32, ny=24, nz=40, cell=16, seed_depth=16)
+    s = make(H, p, Q, u, rho, prec)
+    s.step(5)
+    fz = s.fz()
+    ref = orc.State(oracle_params(orc, p), Q, u, rho)
+    ref.step(5)
+    _, f, _ = orc.chem(oracle_params(orc, p), ref.Q9)
+    fz_ref = np.array([orc.psum(f[z]) for z in range(f.shape[0])])
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel(fz, fz_ref) <= tol
+    # the seeded blue-phase slab and the helix have different plateaus
+    assert abs(fz[:8].mean() - fz[-8:].mean()) > 1e-3 * np.abs(fz).max()
