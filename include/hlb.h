@@ -213,6 +213,72 @@ int hlb_batch_info(const hlb_batch *b, int *grid, int *n_items);
 const char *hlb_batch_last_error(const hlb_batch *b);
 void hlb_batch_destroy(hlb_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate: a 3D convolutional network that maps the state
+ * (Q, u) of a lattice to the increment of Q over k steps.  Four 3x3x3
+ * convolutions with periodic padding, channels 8 -> 32 -> 32 -> 32 -> 5,
+ * bias, ReLU after the first three; bfloat16 operands on the matrix cores,
+ * FP32 accumulation; inputs and targets standardised per channel.
+ * Parameters: one flat FP32 vector, layer by layer, each layer's weights
+ * W[c_out][c_in][kz][ky][kx] (tap kz*9+ky*3+kx reads offset (kx-1,ky-1,kz-1))
+ * followed by its bias; hlbnn_param_count() values (66629).
+ * Device arrays handed to these calls are FP32 structure-of-arrays
+ * [c][z][y][x]: network inputs x [8][N] = (Q xx, xy, xz, yy, yz, u x, y, z),
+ * increments dq [5][N].  All calls use the network's stream.
+ * ------------------------------------------------------------------------ */
+typedef struct hlbnn hlbnn;
+
+int hlbnn_param_count(void);
+size_t hlbnn_workspace_bytes(int nx, int ny, int nz);
+int hlbnn_create(int nx, int ny, int nz, void *device_workspace, size_t workspace_bytes, void *hip_stream,
+                 hlbnn **out);
+/* Host FP32 parameters in / out (setting them resets the Adam moments). */
+int hlbnn_set_params(hlbnn *nn, const float *params);
+int hlbnn_get_params(hlbnn *nn, float *params);
+/* Host FP32 gradient of the last training step (same layout as the parameters). */
+int hlbnn_get_grads(hlbnn *nn, float *grads);
+/* Standardisation: norm[0..7] input means, [8..15] input stds (> 0),
+ * [16..20] output means, [21..25] output stds (> 0). */
+int hlbnn_set_norm(hlbnn *nn, const float *norm26);
+/* Per-channel mean and standard deviation of nsamples device arrays
+ * [nsamples][nch][N] (FP64 sums). */
+int hlbnn_channel_stats(hlbnn *nn, const float *data_dev, int nch, int nsamples, double *mean, double *std_out);
+/* Inputs of the network from a solver context on the same lattice: its
+ * current Q and the velocity of its last LB step, into x_dev [8][N]. */
+int hlbnn_sample(hlbnn *nn, hlb_ctx *solver, float *x_dev_out);
+/* dq_dev = network(x_dev) in raw (de-standardised) units. */
+int hlbnn_predict(hlbnn *nn, const float *x_dev, float *dq_dev);
+/* One training step on one sample: mean-squared error between the network
+ * output and the standardised target dq_dev, backward pass (bfloat16
+ * operands, FP32 accumulation, FP64 fixed-order reduction of the weight
+ * gradient), Adam (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr.
+ * *loss (may be NULL; reading it synchronises) receives the loss before the
+ * update. */
+int hlbnn_train_step(hlbnn *nn, const float *x_dev, const float *dq_dev, float lr, double *loss);
+/* Single-layer entry points (host arrays) used to check the kernels layer by
+ * layer: x_bf16 [N][cin_padded] bfloat16 bits (cin_padded 16 for the first
+ * layer, 32 otherwise); z [N][c_out] FP32 = conv + bias;
+ * dz_bf16 [N][cout_padded] (32, or 16 for the last layer); dx [N][cin_padded]
+ * FP32 = transposed convolution of dz (may be NULL); grad = the layer's flat
+ * weight and bias gradient. */
+int hlbnn_layer_forward(hlbnn *nn, int layer, const unsigned short *x_bf16, float *z);
+int hlbnn_layer_backward(hlbnn *nn, int layer, const unsigned short *x_bf16, const unsigned short *dz_bf16,
+                         float *dx, float *grad);
+const char *hlbnn_last_error(const hlbnn *nn);
+void hlbnn_destroy(hlbnn *nn);
+
+/* One surrogate cycle on the solver's stream (same lattice as the network):
+ * keep a checkpoint of the state; take M-1 jumps Q += network(Q, u) (the
+ * populations and u are held fixed during a jump); for the M-th jump take the
+ * network's prediction and, from the same state, k plain steps; residual r =
+ * ||Q_pre + dq - Q_plain|| / ||Q_plain|| over the five stored components.
+ * r <= threshold: the cycle is accepted and the state is the plain result of
+ * the last jump.  Otherwise (*fell_back = 1) the state is rolled back to the
+ * checkpoint and the whole cycle is taken with M*k plain steps.  Either way
+ * the simulated time advances by M*k steps.  Errors are reported on nn. */
+int hlb_surrogate_advance(hlb_ctx *solver, hlbnn *nn, int k, int M, double threshold, int *fell_back,
+                          double *residual);
+
 /* Message of the last error on this context ("" if none). Never NULL. */
 const char *hlb_last_error(const hlb_ctx *ctx);
 

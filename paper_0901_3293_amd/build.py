@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhlb.so")
 
-SOURCES = ["kernels.hip", "batch.hip", "hlb_api.cpp", "batch_api.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "nn.hip", "hlb_api.cpp", "batch_api.cpp", "nn_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -11,17 +11,8 @@
 #include <vector>
 
 #include "../../include/hlb.h"
+#include "ctx.h"
 #include "kernels.h"
-
-struct hlb_ctx {
-    hlb::Device D;
-    hlb::PhysParams p;
-    bool have_params;
-    bool have_fields;
-    int status;
-    char msg[512];
-    size_t state_bytes;
-};
 
 namespace {
 

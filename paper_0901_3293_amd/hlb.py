@@ -340,3 +340,163 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _nn_lib():
+    L = lib()
+    if not getattr(L, "_nn_ready", False):
+        vp, dp, I, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_size_t
+        fp = ctypes.POINTER(ctypes.c_float)
+        up = ctypes.POINTER(ctypes.c_uint16)
+        L.hlbnn_param_count.restype = I
+        L.hlbnn_workspace_bytes.argtypes = [I, I, I]
+        L.hlbnn_workspace_bytes.restype = sz
+        L.hlbnn_create.argtypes = [I, I, I, vp, sz, vp, ctypes.POINTER(vp)]
+        L.hlbnn_set_params.argtypes = [vp, fp]
+        L.hlbnn_get_params.argtypes = [vp, fp]
+        L.hlbnn_get_grads.argtypes = [vp, fp]
+        L.hlbnn_set_norm.argtypes = [vp, fp]
+        L.hlbnn_channel_stats.argtypes = [vp, vp, I, I, dp, dp]
+        L.hlbnn_sample.argtypes = [vp, vp, vp]
+        L.hlbnn_predict.argtypes = [vp, vp, vp]
+        L.hlbnn_train_step.argtypes = [vp, vp, vp, ctypes.c_float, dp]
+        L.hlbnn_layer_forward.argtypes = [vp, I, up, fp]
+        L.hlbnn_layer_backward.argtypes = [vp, I, up, up, fp, fp]
+        L.hlbnn_last_error.argtypes = [vp]
+        L.hlbnn_last_error.restype = ctypes.c_char_p
+        L.hlbnn_destroy.argtypes = [vp]
+        L.hlbnn_destroy.restype = None
+        L.hlb_surrogate_advance.argtypes = [vp, vp, I, I, ctypes.c_double, ctypes.POINTER(I), dp]
+        L._nn_ready = True
+    return L
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _up(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))
+
+
+class Net:
+    """The convolutional surrogate on one lattice (see include/hlb.h, hlbnn_*).
+
+    Device tensors passed in are torch float32 CUDA tensors shaped [C, nz, ny, nx]
+    (or any contiguous tensor of that many elements)."""
+
+    def __init__(self, shape, device="cuda", stream=None):
+        L = _nn_lib()
+        self.shape = tuple(int(v) for v in shape)
+        nbytes = L.hlbnn_workspace_bytes(*self.shape)
+        if nbytes == 0:
+            raise HlbError(-1, f"invalid lattice {self.shape}")
+        self.device = torch.device(device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = L.hlbnn_create(*self.shape, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc:
+            raise HlbError(rc, "hlbnn_create")
+        self.h = h
+        self.n_params = L.hlbnn_param_count()
+
+    @property
+    def N(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+    def _check(self, rc):
+        if rc < 0:
+            raise HlbError(rc, _nn_lib().hlbnn_last_error(self.h).decode())
+        return rc
+
+    @staticmethod
+    def _ptr(t):
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params
+        self._check(_nn_lib().hlbnn_set_params(self.h, _fp(p)))
+
+    def params(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(_nn_lib().hlbnn_get_params(self.h, _fp(p)))
+        return p
+
+    def grads(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(_nn_lib().hlbnn_get_grads(self.h, _fp(p)))
+        return p
+
+    def set_norm(self, in_mean, in_std, out_mean, out_std):
+        v = np.concatenate([in_mean, in_std, out_mean, out_std]).astype(np.float32)
+        assert v.size == 26
+        self._check(_nn_lib().hlbnn_set_norm(self.h, _fp(v)))
+
+    def channel_stats(self, data, nch):
+        """data: CUDA float32 tensor of nsamples*nch*N values."""
+        ns = data.numel() // (nch * self.N)
+        mean, std = np.zeros(nch), np.zeros(nch)
+        self._check(_nn_lib().hlbnn_channel_stats(self.h, self._ptr(data), nch, ns, _dp(mean), _dp(std)))
+        return mean, std
+
+    def sample(self, solver, out=None):
+        if out is None:
+            out = torch.empty((8,) + self.shape[::-1], dtype=torch.float32, device=self.device)
+        self._check(_nn_lib().hlbnn_sample(self.h, solver.ctx, self._ptr(out)))
+        return out
+
+    def predict(self, x, out=None):
+        if out is None:
+            out = torch.empty((5,) + self.shape[::-1], dtype=torch.float32, device=self.device)
+        self._check(_nn_lib().hlbnn_predict(self.h, self._ptr(x), self._ptr(out)))
+        return out
+
+    def train_step(self, x, dq, lr, want_loss=True):
+        loss = np.zeros(1)
+        self._check(_nn_lib().hlbnn_train_step(self.h, self._ptr(x), self._ptr(dq), float(lr),
+                                                _dp(loss) if want_loss else None))
+        return float(loss[0]) if want_loss else None
+
+    def layer_forward(self, layer, x_bf16):
+        co = (32, 32, 32, 5)[layer]
+        x = np.ascontiguousarray(x_bf16, dtype=np.uint16)
+        z = np.empty((self.N, co), dtype=np.float32)
+        self._check(_nn_lib().hlbnn_layer_forward(self.h, layer, _up(x), _fp(z)))
+        return z
+
+    def layer_backward(self, layer, x_bf16, dz_bf16):
+        cip = 16 if layer == 0 else 32
+        ci, co = (8, 32, 32, 32)[layer], (32, 32, 32, 5)[layer]
+        x = np.ascontiguousarray(x_bf16, dtype=np.uint16)
+        dz = np.ascontiguousarray(dz_bf16, dtype=np.uint16)
+        dx = np.empty((self.N, cip), dtype=np.float32)
+        g = np.empty(co * ci * 27 + co, dtype=np.float32)
+        self._check(_nn_lib().hlbnn_layer_backward(self.h, layer, _up(x), _up(dz), _fp(dx), _fp(g)))
+        return dx, g
+
+    def close(self):
+        if getattr(self, "h", None):
+            _nn_lib().hlbnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def surrogate_advance(solver, net, k=8, M=4, threshold=1e-3):
+    """One surrogate cycle (M jumps of k steps, the last one checked against k
+    plain steps).  Returns (fell_back, residual)."""
+    fb = ctypes.c_int()
+    r = np.zeros(1)
+    rc = _nn_lib().hlb_surrogate_advance(solver.ctx, net.h, int(k), int(M), float(threshold), ctypes.byref(fb),
+                                         _dp(r))
+    net._check(rc)
+    return bool(fb.value), float(r[0])

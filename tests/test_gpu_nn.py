@@ -1,0 +1,158 @@
+"""Surrogate kernels against the CNN oracle, through the C-ABI.
+
+Per layer, on the same bfloat16 operands: forward pre-activation, weight and
+bias gradients and the backward-data convolution within 1e-5 relative of the
+FP64 oracle (FP32 accumulation of at most 864 exact bf16 products).  Whole
+network: the bfloat16 rounding of intermediate activations can flip at ties
+between the two sides, so the end-to-end output and gradient are held to
+looser bars derived from that rounding (stated per test)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn
+from tests.hlbtest import rel, say
+
+pytestmark = pytest.mark.gpu
+
+CIP = (16, 32, 32, 32)
+COP = (32, 32, 32, 16)
+CI = (8, 32, 32, 32)
+CO = (32, 32, 32, 5)
+
+
+@pytest.fixture(scope="module")
+def H():
+    assert torch.cuda.is_available()
+    from paper_0901_3293_amd import hlb
+
+    return hlb
+
+
+def to_bf16_bits(a):
+    """float array -> bfloat16 bit patterns (RNE), same shape."""
+    t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().view(np.uint16)
+
+
+def channels_last(a, cpad):
+    """[C][z][y][x] -> [N][cpad] (zero padded)."""
+    C = a.shape[0]
+    out = np.zeros((a[0].size, cpad))
+    out[:, :C] = np.asarray(a).reshape(C, -1).T
+    return out
+
+
+def from_channels_last(a, C, shape):
+    nx, ny, nz = shape
+    return np.asarray(a)[:, :C].T.reshape(C, nz, ny, nx)
+
+
+SHAPES = [(16, 8, 8), (20, 6, 9)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("layer", [0, 1, 3])
+def test_layer_forward(H, shape, layer):
+    say("case: nn layer forward", shape, layer)
+    rng = np.random.default_rng(10 + layer)
+    net = H.Net(shape)
+    p = cnn.init_params(seed=layer)
+    p[-(5 + 1):] = 0
+    p = (p + rng.normal(0, 0.02, size=p.size)).astype(np.float32)
+    net.set_params(p)
+    x = rng.normal(size=(CI[layer],) + shape[::-1])
+    xb = to_bf16_bits(channels_last(x, CIP[layer]))
+    z = net.layer_forward(layer, xb)
+    W, b = cnn.unflatten(p)[layer]
+    xr = cnn.bf16(torch.tensor(x))
+    ref = cnn.conv(xr, cnn.bf16(W), b).numpy()
+    got = from_channels_last(z, CO[layer], shape)
+    e = rel(got, ref)
+    say("rel err", e)
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("layer", [0, 2, 3])
+def test_layer_backward(H, shape, layer):
+    say("case: nn layer backward", shape, layer)
+    rng = np.random.default_rng(20 + layer)
+    net = H.Net(shape)
+    p = (cnn.init_params(seed=5) + rng.normal(0, 0.02, size=cnn.param_count())).astype(np.float32)
+    net.set_params(p)
+    x = rng.normal(size=(CI[layer],) + shape[::-1])
+    dz = rng.normal(size=(CO[layer],) + shape[::-1]) * 1e-3
+    xb = to_bf16_bits(channels_last(x, CIP[layer]))
+    dzb = to_bf16_bits(channels_last(dz, COP[layer]))
+    dx, g = net.layer_backward(layer, xb, dzb)
+    W, _ = cnn.unflatten(p)[layer]
+    dW, db, dxr = cnn.layer_backward(cnn.bf16(torch.tensor(x)), cnn.bf16(torch.tensor(dz)), cnn.bf16(W))
+    gref = torch.cat([dW.reshape(-1), db]).numpy()
+    e_w = rel(g[:-CO[layer]], gref[:-CO[layer]])
+    e_b = rel(g[-CO[layer]:], gref[-CO[layer]:])
+    e_x = rel(from_channels_last(dx, CI[layer], shape), dxr.numpy())
+    say("rel err dW, db, dx", e_w, e_b, e_x)
+    assert e_w <= 1e-5 and e_b <= 1e-5 and e_x <= 1e-5
+
+
+def norm_for(x, dq):
+    return (x.reshape(8, -1).mean(1), x.reshape(8, -1).std(1) + 1e-12,
+            dq.reshape(5, -1).mean(1), dq.reshape(5, -1).std(1) + 1e-12)
+
+
+def test_network_forward_and_training_step(H):
+    """Whole network and one Adam step on a 24x12x16 lattice.  Bars: output
+    dq within 2e-2 (max) and 1e-3 (mean) relative; gradient within 5e-2 (max
+    norm) relative; loss within 1e-4; Adam update exactly the textbook step
+    on the GPU's own gradient (1e-6)."""
+    say("case: nn network forward + train step")
+    shape = (24, 12, 16)
+    rng = np.random.default_rng(3)
+    net = H.Net(shape)
+    p0 = (cnn.init_params(seed=7) + rng.normal(0, 0.01, size=cnn.param_count())).astype(np.float32)
+    net.set_params(p0)
+    x = rng.normal(size=(8,) + shape[::-1]) * np.linspace(0.1, 1.0, 8)[:, None, None, None]
+    dq = rng.normal(size=(5,) + shape[::-1]) * 1e-3
+    im, isd, om, osd = norm_for(x, dq)
+    net.set_norm(im, isd, om, osd)
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    dqd = torch.tensor(dq, dtype=torch.float32, device="cuda")
+    out = net.predict(xd).cpu().numpy()
+    x32 = x.astype(np.float32)
+    xs = (x32 - im.astype(np.float32)[:, None, None, None]) / isd.astype(np.float32)[:, None, None, None]
+    acts, z = cnn.forward(p0, xs)
+    ref = z.numpy() * osd.astype(np.float32)[:, None, None, None] + om.astype(np.float32)[:, None, None, None]
+    d = np.abs(out - ref)
+    say("forward rel max, mean:", d.max() / np.abs(ref).max(), d.mean() / np.abs(ref).mean())
+    assert d.max() / np.abs(ref).max() <= 2e-2 and d.mean() / np.abs(ref).mean() <= 1e-3
+    loss = net.train_step(xd, dqd, lr=1e-3)
+    t = (dq.astype(np.float32) - om.astype(np.float32)[:, None, None, None]) / osd.astype(np.float32)[:, None, None, None]
+    loss_ref = cnn.mse(z, t)
+    say("loss gpu, oracle:", loss, loss_ref)
+    assert abs(loss - loss_ref) <= 1e-4 * loss_ref
+    g = net.grads()
+    gref = cnn.backward(p0, acts, z, t).numpy()
+    eg = rel(g, gref)
+    say("grad rel err", eg)
+    assert eg <= 5e-2
+    p1 = net.params()
+    p_ref, _, _ = cnn.adam(p0, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    assert np.abs(p1 - p_ref).max() <= 1e-6 * max(1.0, np.abs(p_ref).max())
+
+
+def test_training_is_deterministic(H):
+    say("case: nn training determinism")
+    shape = (16, 8, 12)
+    rng = np.random.default_rng(4)
+    x = torch.tensor(rng.normal(size=(8,) + shape[::-1]), dtype=torch.float32, device="cuda")
+    dq = torch.tensor(rng.normal(size=(5,) + shape[::-1]) * 1e-3, dtype=torch.float32, device="cuda")
+    res = []
+    for _ in range(2):
+        net = H.Net(shape)
+        net.set_params(cnn.init_params(seed=1))
+        net.set_norm(np.zeros(8), np.ones(8), np.zeros(5), np.full(5, 1e-3))
+        for _ in range(3):
+            net.train_step(x, dq, 1e-3, want_loss=False)
+        res.append(net.params())
+    assert np.array_equal(res[0], res[1])
