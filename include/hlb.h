@@ -246,6 +246,9 @@ int hlbnn_channel_stats(hlbnn *nn, const float *data_dev, int nch, int nsamples,
 /* Inputs of the network from a solver context on the same lattice: its
  * current Q and the velocity of its last LB step, into x_dev [8][N]. */
 int hlbnn_sample(hlbnn *nn, hlb_ctx *solver, float *x_dev_out);
+/* One training pair from a solver on the same lattice: x_dev [8][N] = its
+ * inputs now, then k solver steps on its stream, dq_dev [5][N] = Q(t+k) - Q(t). */
+int hlbnn_make_pair(hlbnn *nn, hlb_ctx *solver, int k, float *x_dev, float *dq_dev);
 /* dq_dev = network(x_dev) in raw (de-standardised) units. */
 int hlbnn_predict(hlbnn *nn, const float *x_dev, float *dq_dev);
 /* One training step on one sample: mean-squared error between the network

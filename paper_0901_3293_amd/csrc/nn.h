@@ -37,6 +37,7 @@ hipError_t adam(int n, float *p, const float *g, float *m, float *v, float lr, f
 hipError_t stats(const float *data, int nch, int N, int nsamples, double *part, int nblk, hipStream_t st);
 hipError_t sample(bool fp32, int N, const void *Q, const void *u, float *x, hipStream_t st);
 hipError_t apply(bool fp32, int N, const float *Y, const float *norm, float *dq, void *Q, hipStream_t st);
+hipError_t diff(int N, const float *x0, const float *x1, float *dq, hipStream_t st);
 hipError_t resid(bool fp32, int N, const void *Qa, const float *dq, const void *Qb, double *part, int nblk,
                  hipStream_t st);
 

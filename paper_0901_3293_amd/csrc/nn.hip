@@ -435,6 +435,14 @@ __global__ __launch_bounds__(BLK) void k_resid(int N, const T *__restrict__ Qa, 
     }
 }
 
+// dq = Q(t+k) - Q(t) from two network-input arrays (their first 5 planes).
+__global__ __launch_bounds__(BLK) void k_diff(int N, const float *__restrict__ x0, const float *__restrict__ x1,
+                                              float *__restrict__ dq)
+{
+    const size_t i = size_t(blockIdx.x) * BLK + threadIdx.x;
+    if (i < size_t(5) * N) dq[i] = x1[i] - x0[i];
+}
+
 inline int blocks(size_t n) { return int((n + BLK - 1) / BLK); }
 
 }  // namespace
@@ -546,6 +554,12 @@ hipError_t apply(bool fp32, int N, const float *Y, const float *norm, float *dq,
         k_apply<float><<<blocks(N), BLK, 0, st>>>(N, Y, norm, dq, static_cast<float *>(Q));
     else
         k_apply<double><<<blocks(N), BLK, 0, st>>>(N, Y, norm, dq, static_cast<double *>(Q));
+    return hipGetLastError();
+}
+
+hipError_t diff(int N, const float *x0, const float *x1, float *dq, hipStream_t st)
+{
+    k_diff<<<blocks(size_t(5) * N), BLK, 0, st>>>(N, x0, x1, dq);
     return hipGetLastError();
 }
 

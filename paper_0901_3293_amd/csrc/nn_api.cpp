@@ -363,6 +363,22 @@ int hlbnn_sample(hlbnn *n, hlb_ctx *c, float *x_dev)
     return HLB_OK;
 }
 
+int hlbnn_make_pair(hlbnn *n, hlb_ctx *c, int k, float *x_dev, float *dq_dev)
+{
+    N_GUARD(n);
+    if (!c || !x_dev || !dq_dev || k < 1) return nerr(n, HLB_ERR_ARG, "hlbnn_make_pair arguments");
+    if (c->status) return nerr(n, c->status, "solver context in error: %s", c->msg);
+    if (c->D.G.nx != n->g.nx || c->D.G.ny != n->g.ny || c->D.G.nz != n->g.nz)
+        return nerr(n, HLB_ERR_ARG, "solver and network lattices differ");
+    if (!c->have_fields) return nerr(n, HLB_ERR_STATE, "solver has no fields");
+    hlb::Device &D = c->D;
+    N_TRY(n, hlb::nn::sample(D.fp32, n->g.N, D.Q[D.qcur], D.u, x_dev, D.stream));
+    N_TRY(n, hlb::run_steps(D, c->p, k));
+    N_TRY(n, hlb::nn::sample(D.fp32, n->g.N, D.Q[D.qcur], D.u, n->xraw, D.stream));
+    N_TRY(n, hlb::nn::diff(n->g.N, x_dev, n->xraw, dq_dev, D.stream));
+    return HLB_OK;
+}
+
 const char *hlbnn_last_error(const hlbnn *n) { return n ? n->msg : "null network"; }
 
 void hlbnn_destroy(hlbnn *n) { delete n; }

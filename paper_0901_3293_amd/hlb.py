@@ -359,6 +359,7 @@ def _nn_lib():
         L.hlbnn_channel_stats.argtypes = [vp, vp, I, I, dp, dp]
         L.hlbnn_sample.argtypes = [vp, vp, vp]
         L.hlbnn_predict.argtypes = [vp, vp, vp]
+        L.hlbnn_make_pair.argtypes = [vp, vp, I, vp, vp]
         L.hlbnn_train_step.argtypes = [vp, vp, vp, ctypes.c_float, dp]
         L.hlbnn_layer_forward.argtypes = [vp, I, up, fp]
         L.hlbnn_layer_backward.argtypes = [vp, I, up, up, fp, fp]
@@ -449,6 +450,10 @@ class Net:
             out = torch.empty((8,) + self.shape[::-1], dtype=torch.float32, device=self.device)
         self._check(_nn_lib().hlbnn_sample(self.h, solver.ctx, self._ptr(out)))
         return out
+
+    def make_pair(self, solver, k, x_out, dq_out):
+        """x_out <- inputs of the solver now; k solver steps; dq_out <- Q(t+k) - Q(t)."""
+        self._check(_nn_lib().hlbnn_make_pair(self.h, solver.ctx, int(k), self._ptr(x_out), self._ptr(dq_out)))
 
     def predict(self, x, out=None):
         if out is None:
