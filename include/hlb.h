@@ -214,22 +214,42 @@ const char *hlb_batch_last_error(const hlb_batch *b);
 void hlb_batch_destroy(hlb_batch *b);
 
 /* ------------------------------------------------------------------------
- * Learned surrogate: a 3D convolutional network that maps the state
- * (Q, u) of a lattice to the increment of Q over k steps.  Four 3x3x3
- * convolutions with periodic padding, channels 8 -> 32 -> 32 -> 32 -> 5,
- * bias, ReLU after the first three; bfloat16 operands on the matrix cores,
- * FP32 accumulation; inputs and targets standardised per channel.
+ * Learned surrogate: a 3D convolutional network that advances Q by k solver
+ * steps in one application.  Four 3x3x3 convolutions with periodic padding,
+ * channels 18 -> 32 -> 32 -> 32 -> 5, bias, ReLU after the first three;
+ * bfloat16 operands on the matrix cores, FP32 accumulation.
+ *
+ * Inputs per site (NIN = 18, FP32): Q (xx, xy, xz, yy, yz), u (x, y, z) of
+ * the last LB step, the last increment d1 = Q(t) - Q(t-k) and its change
+ * s2 = Q(t) - 2 Q(t-k) + Q(t-2k).  Output: the standardised correction c of
+ * the increment over the next k steps with respect to the extrapolation base,
+ *     dQ = d1 + beta s2 + (c std_out + mean_out),
+ * beta = 0 (linear extrapolation base) or 1 (quadratic).  The history (d1,
+ * s2) is kept by the network object for one solver context; it is recorded
+ * from plain steps (hlbnn_warmup, fallbacks, checked jumps) and advanced by
+ * the network's own jumps.  Any call that changes the solver's state or
+ * parameters from outside (hlb_set_fields, hlb_step, ...) invalidates it.
+ *
  * Parameters: one flat FP32 vector, layer by layer, each layer's weights
  * W[c_out][c_in][kz][ky][kx] (tap kz*9+ky*3+kx reads offset (kx-1,ky-1,kz-1))
- * followed by its bias; hlbnn_param_count() values (66629).
- * Device arrays handed to these calls are FP32 structure-of-arrays
- * [c][z][y][x]: network inputs x [8][N] = (Q xx, xy, xz, yy, yz, u x, y, z),
- * increments dq [5][N].  All calls use the network's stream.
+ * followed by its bias; hlbnn_param_count() values (75269).
+ * Standardisation block (hlbnn_norm_size() = 47 floats): [0..17] input
+ * means, [18..35] input stds (> 0), [36..40] target means, [41..45] target
+ * stds (> 0), [46] beta.
+ * Device arrays are FP32 structure-of-arrays [c][z][y][x]: inputs x [18][N],
+ * increments dq [5][N].  Training and inference calls use the network's
+ * stream; calls that take a solver context run on the solver's stream.
+ * Errors are reported on the network (hlbnn_last_error) and are sticky.
  * ------------------------------------------------------------------------ */
 typedef struct hlbnn hlbnn;
 
 int hlbnn_param_count(void);
+int hlbnn_input_channels(void);
+int hlbnn_norm_size(void);
 size_t hlbnn_workspace_bytes(int nx, int ny, int nz);
+/* device_workspace: caller-owned, 256-byte aligned, at least
+ * hlbnn_workspace_bytes(); HLB_ERR_NOMEM if smaller, HLB_ERR_ARG for a bad
+ * lattice or a misaligned or null workspace. */
 int hlbnn_create(int nx, int ny, int nz, void *device_workspace, size_t workspace_bytes, void *hip_stream,
                  hlbnn **out);
 /* Host FP32 parameters in / out (setting them resets the Adam moments). */
@@ -237,48 +257,64 @@ int hlbnn_set_params(hlbnn *nn, const float *params);
 int hlbnn_get_params(hlbnn *nn, float *params);
 /* Host FP32 gradient of the last training step (same layout as the parameters). */
 int hlbnn_get_grads(hlbnn *nn, float *grads);
-/* Standardisation: norm[0..7] input means, [8..15] input stds (> 0),
- * [16..20] output means, [21..25] output stds (> 0). */
-int hlbnn_set_norm(hlbnn *nn, const float *norm26);
+/* Standardisation block in / out (host, hlbnn_norm_size() floats); stds
+ * must be positive and all values finite (HLB_ERR_PARAM). */
+int hlbnn_set_norm(hlbnn *nn, const float *norm);
+int hlbnn_get_norm(hlbnn *nn, float *norm);
 /* Per-channel mean and standard deviation of nsamples device arrays
  * [nsamples][nch][N] (FP64 sums). */
 int hlbnn_channel_stats(hlbnn *nn, const float *data_dev, int nch, int nsamples, double *mean, double *std_out);
-/* Inputs of the network from a solver context on the same lattice: its
- * current Q and the velocity of its last LB step, into x_dev [8][N]. */
-int hlbnn_sample(hlbnn *nn, hlb_ctx *solver, float *x_dev_out);
-/* One training pair from a solver on the same lattice: x_dev [8][N] = its
- * inputs now, then k solver steps on its stream, dq_dev [5][N] = Q(t+k) - Q(t). */
+/* Standardisation from nsamples training pairs x [nsamples][18][N] and dq
+ * [nsamples][5][N]: input statistics of x, target statistics of
+ * dq - d1 - beta s2; sets it on the network and copies it to norm_out
+ * (host, may be NULL). */
+int hlbnn_fit_norm(hlbnn *nn, const float *x_dev, const float *dq_dev, int nsamples, float beta, float *norm_out);
+/* 2k plain steps of the solver (same lattice), recording the history for
+ * jumps of k steps. */
+int hlbnn_warmup(hlbnn *nn, hlb_ctx *solver, int k);
+/* Host copies of the history d1, s2 ([5][N] FP32 each) for the solver's
+ * current state; HLB_ERR_STATE if there is none. */
+int hlbnn_history(hlbnn *nn, const hlb_ctx *solver, float *d1, float *s2);
+/* One training pair: x_dev [18][N] = the inputs at the solver's current
+ * state (after a warm-up of 2k steps when there is no valid history), then k
+ * plain steps, dq_dev [5][N] = Q(t+k) - Q(t).  The history stays valid. */
 int hlbnn_make_pair(hlbnn *nn, hlb_ctx *solver, int k, float *x_dev, float *dq_dev);
-/* dq_dev = network(x_dev) in raw (de-standardised) units. */
+/* dq_dev = predicted increment for raw inputs x_dev. */
 int hlbnn_predict(hlbnn *nn, const float *x_dev, float *dq_dev);
-/* One training step on one sample: mean-squared error between the network
- * output and the standardised target dq_dev, backward pass (bfloat16
- * operands, FP32 accumulation, FP64 fixed-order reduction of the weight
- * gradient), Adam (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr.
- * *loss (may be NULL; reading it synchronises) receives the loss before the
- * update. */
+/* One unchecked network jump on the solver: Q += dQ, history advanced
+ * (s2 = dQ - d1, d1 = dQ); populations and u untouched. */
+int hlbnn_jump(hlbnn *nn, hlb_ctx *solver);
+/* One training step on one pair: mean-squared error between the network
+ * output and the standardised target (dq - d1 - beta s2 - mean) / std,
+ * backward pass (bfloat16 operands, FP32 accumulation, FP64 fixed-order
+ * reduction of the weight gradient), Adam (beta1 0.9, beta2 0.999, eps
+ * 1e-8) with learning rate lr.  *loss (may be NULL; reading it
+ * synchronises) receives the loss before the update. */
 int hlbnn_train_step(hlbnn *nn, const float *x_dev, const float *dq_dev, float lr, double *loss);
 /* Single-layer entry points (host arrays) used to check the kernels layer by
- * layer: x_bf16 [N][cin_padded] bfloat16 bits (cin_padded 16 for the first
- * layer, 32 otherwise); z [N][c_out] FP32 = conv + bias;
- * dz_bf16 [N][cout_padded] (32, or 16 for the last layer); dx [N][cin_padded]
- * FP32 = transposed convolution of dz (may be NULL); grad = the layer's flat
- * weight and bias gradient. */
+ * layer: x_bf16 [N][32] bfloat16 bits (channels beyond the layer's inputs
+ * zero); z [N][c_out] FP32 = conv + bias; dz_bf16 [N][cout_padded] (32, or 16
+ * for the last layer); dx [N][32] FP32 = transposed convolution of dz (may
+ * be NULL); grad = the layer's flat weight and bias gradient. */
 int hlbnn_layer_forward(hlbnn *nn, int layer, const unsigned short *x_bf16, float *z);
 int hlbnn_layer_backward(hlbnn *nn, int layer, const unsigned short *x_bf16, const unsigned short *dz_bf16,
                          float *dx, float *grad);
 const char *hlbnn_last_error(const hlbnn *nn);
 void hlbnn_destroy(hlbnn *nn);
 
-/* One surrogate cycle on the solver's stream (same lattice as the network):
- * keep a checkpoint of the state; take M-1 jumps Q += network(Q, u) (the
- * populations and u are held fixed during a jump); for the M-th jump take the
- * network's prediction and, from the same state, k plain steps; residual r =
- * ||Q_pre + dq - Q_plain|| / ||Q_plain|| over the five stored components.
- * r <= threshold: the cycle is accepted and the state is the plain result of
- * the last jump.  Otherwise (*fell_back = 1) the state is rolled back to the
- * checkpoint and the whole cycle is taken with M*k plain steps.  Either way
- * the simulated time advances by M*k steps.  Errors are reported on nn. */
+/* One surrogate cycle of M >= 2 jumps of k steps on the solver's stream,
+ * the network holding a valid history for this solver and k (HLB_ERR_STATE
+ * otherwise).  Keeps a checkpoint of the state; takes M-1 network jumps (the
+ * populations and u are held during a jump); for the M-th jump takes the
+ * network's increment dq and, from the same state, k plain steps; residual
+ * r = ||Q_pre + dq - Q_plain|| / ||Q_plain|| over the five stored components
+ * (FP64 sums).  r < threshold: the cycle is accepted, the state is the plain
+ * result of the last jump and the history its increment.  Otherwise
+ * (*fell_back = 1) the state is rolled back to the checkpoint and the whole
+ * cycle is taken with M*k plain steps, the history recorded over its last
+ * two jumps.  threshold = 0 therefore reproduces the plain run bit for bit.
+ * Either way the simulated time advances by M*k steps.  Synchronises once
+ * (to read r).  Errors are reported on nn. */
 int hlb_surrogate_advance(hlb_ctx *solver, hlbnn *nn, int k, int M, double threshold, int *fell_back,
                           double *residual);
 

@@ -1,10 +1,11 @@
 """FP64 CPU oracle of the 3D convolutional surrogate (test infrastructure only).
 
-Network: four 3x3x3 convolutions with periodic padding, channels 8 -> 32 -> 32
--> 32 -> 5, bias, ReLU after the first three.  Input channels: the five
-stored Q components and the three velocity components, standardised per
-channel; output: the standardised increment of the five Q components over k
-solver steps.
+Network: four 3x3x3 convolutions with periodic padding, channels 18 -> 32 ->
+32 -> 32 -> 5, bias, ReLU after the first three.  Input channels: the five
+stored Q components, the three velocity components, the last increment of Q
+over k solver steps (d1) and the change of that increment (s2), standardised
+per channel; output: the standardised correction of the next k-step
+increment with respect to the extrapolation d1 + beta s2.
 
 Numerics of the GPU kernels that the oracle reproduces: operands (weights
 and input activations of every layer, and upstream gradients in the backward
@@ -23,7 +24,7 @@ import numpy as np
 import torch
 import torch.nn.functional as F
 
-CHANNELS = (8, 32, 32, 32, 5)
+CHANNELS = (18, 32, 32, 32, 5)
 N_LAYERS = 4
 
 
@@ -50,17 +51,6 @@ def unflatten(params):
     return out
 
 
-def init_params(seed=0, scale=1.0):
-    """He-style initialisation (seeded), as a flat FP32 vector."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    parts = []
-    for co, ci, *_ in layer_shapes():
-        std = scale * np.sqrt(2.0 / (ci * 27))
-        parts.append(rng.normal(0.0, std, size=co * ci * 27))
-        parts.append(np.zeros(co))
-    return np.concatenate(parts).astype(np.float32)
-
-
 def bf16(x):
     """Round to the nearest bfloat16 (ties to even), returned as float64."""
     x = torch.as_tensor(x)
@@ -77,7 +67,7 @@ def conv(x, W, b=None):
 
 
 def forward(params, x_std, rounding=True):
-    """Full network on standardised inputs x_std [8, z, y, x].
+    """Full network on standardised inputs x_std [18, z, y, x].
 
     Returns (activations, z_last): activations[l] is the (rounded) input of
     layer l, z_last the FP64 output of the last layer (standardised dQ)."""
@@ -140,3 +130,38 @@ def adam(params, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# Layout of the standardisation block: input means and stds, target means and
+# stds, and beta.
+NIN = CHANNELS[0]
+IN_MEAN, IN_STD, OUT_MEAN, OUT_STD, BETA = 0, NIN, 2 * NIN, 2 * NIN + 5, 2 * NIN + 10
+NORM_SIZE = 2 * NIN + 11
+
+
+def standardise(x, norm):
+    """Raw inputs x [18, ...] -> (x - mean) / std, in FP32 as the GPU does."""
+    x = np.asarray(x, dtype=np.float32)
+    m = np.asarray(norm[IN_MEAN:IN_MEAN + NIN], dtype=np.float32).reshape((NIN,) + (1,) * (x.ndim - 1))
+    s = np.asarray(norm[IN_STD:IN_STD + NIN], dtype=np.float32).reshape((NIN,) + (1,) * (x.ndim - 1))
+    return (x - m) / s
+
+
+def increment(params, norm, Q, u, d1, s2):
+    """Increment of Q over the next k steps predicted from the state (Q, u)
+    and the history (d1, s2), all [c, z, y, x]: the extrapolation
+    d1 + beta s2 plus the de-standardised network output.  FP64."""
+    x = np.concatenate([np.asarray(Q, dtype=np.float32), np.asarray(u, dtype=np.float32),
+                        np.asarray(d1, dtype=np.float32), np.asarray(s2, dtype=np.float32)])
+    _, z = forward(params, standardise(x, norm))
+    sd = np.asarray(norm[OUT_STD:OUT_STD + 5], dtype=np.float64)[:, None, None, None]
+    mu = np.asarray(norm[OUT_MEAN:OUT_MEAN + 5], dtype=np.float64)[:, None, None, None]
+    beta = float(norm[BETA])
+    return np.asarray(d1, dtype=np.float64) + beta * np.asarray(s2, dtype=np.float64) + z.numpy() * sd + mu
+
+
+def jump(params, norm, Q, u, d1, s2):
+    """One surrogate jump: Q += dq with the history advanced (s2 = dq - d1,
+    d1 = dq).  Returns (Q, d1, s2) in FP64."""
+    dq = increment(params, norm, Q, u, d1, s2)
+    return np.asarray(Q, dtype=np.float64) + dq, dq, dq - np.asarray(d1, dtype=np.float64)

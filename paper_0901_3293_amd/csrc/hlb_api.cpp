@@ -142,6 +142,7 @@ int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe,
     c->p = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi,
             be->flow_coupling ? 1 : 0};
     c->have_params = true;
+    ++c->version;
     return HLB_OK;
 }
 
@@ -163,6 +164,7 @@ int hlb_set_fields(hlb_ctx *c, const double *Q5, const double *u3, const double 
     HIP_TRY(c, hlb::run_init(c->D, c->p, stage));
     HIP_TRY(c, hipStreamSynchronize(c->D.stream));
     c->have_fields = true;
+    ++c->version;
     return HLB_OK;
 }
 
@@ -172,6 +174,7 @@ int hlb_step(hlb_ctx *c, int nsteps)
     if (nsteps < 0) return set_error(c, HLB_ERR_ARG, "nsteps = %d", nsteps);
     if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "hlb_set_fields must come first");
     HIP_TRY(c, hlb::run_steps(c->D, c->p, nsteps));
+    if (nsteps) ++c->version;
     return HLB_OK;
 }
 
@@ -296,6 +299,7 @@ int hlb_step_timed(hlb_ctx *c, int nsteps, double *kernel_ms, int nkernels)
         (void)hipEventDestroy(m.stop);
     }
     if (e != hipSuccess) return hip_fail(c, e, "hlb_step_timed");
+    if (nsteps) ++c->version;
     return hlb::K_COUNT;
 }
 
@@ -345,6 +349,7 @@ int hlb_set_state(hlb_ctx *c, const void *buf, size_t nbytes)
     HIP_TRY(c, hipMemcpyAsync(c->D.Q[c->D.qcur], b + 19 * N * e, 5 * N * e, hipMemcpyHostToDevice, c->D.stream));
     HIP_TRY(c, hipStreamSynchronize(c->D.stream));
     c->have_fields = true;
+    ++c->version;
     return HLB_OK;
 }
 

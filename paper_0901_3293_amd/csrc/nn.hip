@@ -1,22 +1,23 @@
 // nn.hip -- kernels of the 3D convolutional surrogate on BF16 matrix cores.
 //
 // Activations are channels-last bfloat16, act[site][C] with C padded to 16 or
-// 32; weights of a layer are bfloat16 [tap][C_out][C_in] (tap = kz*9 + ky*3 +
-// kx reads the input at offset (kx-1, ky-1, kz-1), periodic).  A 3x3x3
-// convolution is an implicit GEMM per tile of 16x4x4 output sites:
-// M = 16 sites of one x-row, N = 16 output channels, K = 16 input channels of
-// one tap, on v_mfma_f32_16x16x16_bf16 with FP32 accumulation.  The input
-// brick of the tile (18x6x6 sites, periodic wrap) and the layer's weights are
-// staged in LDS; each of the 4 waves owns one z-plane of the tile.
+// 32.  tap = kz*9 + ky*3 + kx of a 3x3x3 kernel reads the input at offset
+// (kx-1, ky-1, kz-1), periodic.  The convolutions are implicit GEMMs on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (k_conv); the weight
+// gradient is a GEMM over sites (k_wgrad) with a deterministic FP64 reduction
+// of per-block partials.
 #include <hip/hip_runtime.h>
 
 #include "nn.h"
+#include "tiles.h"
 
 namespace hlb {
 namespace nn {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -39,6 +40,15 @@ __device__ __forceinline__ int wrap(int v, int n)
 {
     v %= n;
     return v < 0 ? v + n : v;
+}
+
+// Periodic wrap for an index that is at most one period out of range (the
+// general modulo only when it is not, i.e. on lattices smaller than a tile).
+__device__ __forceinline__ int wrap_near(int v, int n)
+{
+    v += v < 0 ? n : 0;
+    v -= v >= n ? n : 0;
+    return (v >= 0 && v < n) ? v : wrap(v, n);
 }
 
 __device__ __forceinline__ void tile_origin(const Grid3 &g, int t, int &x0, int &y0, int &z0)
@@ -67,89 +77,186 @@ __device__ __forceinline__ void stage_brick(const Grid3 &g, const unsigned short
     }
 }
 
-template <int CIP, int COP>
-__device__ __forceinline__ void stage_weights(const unsigned short *__restrict__ W, unsigned short *sW)
-{
-    constexpr int WP = CIP + 8, V = CIP / 8;
-    for (int e = threadIdx.x; e < 27 * COP * V; e += BLK) {
-        const int row = e / V, v = e - row * V;
-        *reinterpret_cast<uint4 *>(sW + row * WP + v * 8) = *reinterpret_cast<const uint4 *>(W + row * CIP + v * 8);
-    }
-}
-
-// Forward-style convolution with an epilogue:
+// Forward-style periodic 3x3x3 convolution of a CIN-channel activation into
+// COUT channels, as an implicit GEMM on v_mfma_f32_16x16x32_bf16: M = 16
+// output channels, N = 16 sites of one x-row, K = 32 (the CIN = 32 channels of
+// one tap, or the 16 channels of two taps when CIN = 16).
+//
+// A block owns a tile of 16 x (WY RY) x (WZ RZ) output sites; its input brick
+// (tile plus a one-site periodic halo) is staged in LDS, and the brick of the
+// block's next tile is fetched into registers while the current one is
+// computed.  Each wave owns 16 x RY x RZ output sites with all COUT channels
+// in its accumulators; for each x-offset of the stencil it reads the
+// (RY+2)(RZ+2) brick rows it needs into registers once and runs all nine
+// (y, z) taps of that offset against them.  The weights, pre-arranged in MFMA
+// fragment order (k_wprep), are staged once per block.  Blocks take
+// contiguous runs of tiles, and the block index is remapped so that each XCD
+// (with its own L2) works on one contiguous part of the lattice.
+//
+// Epilogues:
 //  MODE_RELU:   out_bf16[s][co] = bf16(relu(acc + b[co])), 0 for co >= co_valid
 //  MODE_LINEAR: out_f32[s][co]  = acc + b[co] for co < co_valid (row stride co_valid)
 //  MODE_MASK:   out_bf16[s][co] = mask[s][co] > 0 ? bf16(acc) : 0   (backward through ReLU)
-//  MODE_RAW:    out_f32[s][co]  = acc (row stride COP)
-template <int CIP, int COP, int MODE>
-__global__ __launch_bounds__(BLK) void k_conv(Grid3 g, const unsigned short *__restrict__ X,
-                                              const unsigned short *__restrict__ Wg, const float *__restrict__ bias,
-                                              void *__restrict__ out, const unsigned short *__restrict__ mask,
-                                              int co_valid)
+//  MODE_RAW:    out_f32[s][co]  = acc (row stride COUT)
+constexpr int nksteps(int cin) { return cin == 32 ? 27 : 15; }
+
+template <int CIN, int COUT, int RY, int RZ, int WY, int WZ>
+struct ConvShape {
+    static constexpr int NS = COUT / 16, NKS = nksteps(CIN), KPD = NKS / 3;
+    static constexpr int TY = WY * RY, TZ = WZ * RZ;              // block tile: 16 x TY x TZ
+    static constexpr int BX = 18, BY = TY + 2, BZ = TZ + 2;       // brick
+    static constexpr int BN = BX * BY * BZ;
+    static constexpr int V = CIN / 8;                             // 16-byte chunks per site
+    static constexpr int NCH = (BN * V + BLK - 1) / BLK;          // chunks staged per thread
+    static constexpr size_t lds_bytes = size_t(BN) * CIN * 2;
+};
+
+// LDS position (in 16-byte chunks) of chunk v of brick site `site`: sites
+// are unpadded and the chunk index is XOR-swizzled with the site so that the
+// 16 lanes of a quarter-wave reading one chunk of 16 consecutive sites hit
+// 16 different bank groups.
+template <int V>
+__device__ __forceinline__ int brick_chunk(int site, int v)
 {
-    constexpr int SP = CIP + 8, WP = CIP + 8, NS = COP / 16, KC = CIP / 16;
-    __shared__ __attribute__((aligned(16))) unsigned short sB[BN * SP];
-    __shared__ __attribute__((aligned(16))) unsigned short sW[27 * COP * WP];
-    stage_weights<CIP, COP>(Wg, sW);
+    return site * V + (v ^ ((site / (16 / V)) % V));
+}
+
+template <int CIN, int COUT, int MODE, int RY, int RZ, int WY, int WZ>
+__global__ __launch_bounds__(BLK, 2) void k_conv(Grid3 g, int ctx, int cty, int ntiles, int per_block,
+                                                 const unsigned short *__restrict__ X, const u32x4 *__restrict__ Wfrag,
+                                                 const float *__restrict__ bias, void *__restrict__ out,
+                                                 const unsigned short *__restrict__ mask, int co_valid)
+{
+    using S = ConvShape<CIN, COUT, RY, RZ, WY, WZ>;
+    constexpr int NS = S::NS, KPD = S::KPD, V = S::V;
+    static_assert(WY * WZ == BLK / 64, "one wave per sub-tile");
+    extern __shared__ __attribute__((aligned(16))) unsigned short smem[];
+    u32x4 *sB = reinterpret_cast<u32x4 *>(smem);
+
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lg = l >> 4;
-    for (int t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
-        int x0, y0, z0;
-        tile_origin(g, t, x0, y0, z0);
+    const int wy = w % WY, wz = w / WY;
+    const int cv = CIN == 32 ? lg : (lg & 1);  // chunk of the site this lane feeds to the MFMA
+    const bool upper = lg >= 2;                // CIN == 16: this lane feeds the second tap of a pair
+    float bv[NS][4];
+#pragma unroll
+    for (int ns = 0; ns < NS; ++ns)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = ns * 16 + 4 * lg + r;
+            bv[ns][r] = ((MODE == MODE_RELU || MODE == MODE_LINEAR) && co < co_valid) ? bias[co] : 0.f;
+        }
+    const int b = xcd_logical_block();
+    const int t_begin = b * per_block;
+    const int t_end = min(ntiles, t_begin + per_block);
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+
+    for (int t = t_begin; t < t_end; ++t) {
+        const int x0 = (t % ctx) * 16, rr = t / ctx;
+        const int yb = (rr % cty) * S::TY, zb = (rr / cty) * S::TZ;
+        // stage the brick of this tile (global -> LDS); a second resident
+        // block overlaps its own compute with this
         __syncthreads();
-        stage_brick<CIP>(g, X, x0, y0, z0, sB);
-        __syncthreads();
-        f32x4 acc[4][NS];
 #pragma unroll
-        for (int ms = 0; ms < 4; ++ms)
-#pragma unroll
-            for (int ns = 0; ns < NS; ++ns) acc[ms][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int tap = 0; tap < 27; ++tap) {
-            const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                bf16x4 b[NS];
-#pragma unroll
-                for (int ns = 0; ns < NS; ++ns)
-                    b[ns] = *reinterpret_cast<const bf16x4 *>(sW + (tap * COP + ns * 16 + li) * WP + kc * 16 + lg * 4);
-#pragma unroll
-                for (int ms = 0; ms < 4; ++ms) {
-                    const int site = ((w + dz) * BY + (ms + dy)) * BX + (li + dx);
-                    const bf16x4 a = *reinterpret_cast<const bf16x4 *>(sB + site * SP + kc * 16 + lg * 4);
-#pragma unroll
-                    for (int ns = 0; ns < NS; ++ns)
-                        acc[ms][ns] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[ns], acc[ms][ns], 0, 0, 0);
-                }
+        for (int k = 0; k < S::NCH; ++k) {
+            const int e = threadIdx.x + k * BLK;
+            if (e < S::BN * V) {
+                const int site = e / V, v = e - site * V;
+                const int bx = site % S::BX, r2 = site / S::BX, by = r2 % S::BY, bz = r2 / S::BY;
+                const int x = wrap_near(x0 - 1 + bx, g.nx), y = wrap_near(yb - 1 + by, g.ny),
+                          z = wrap_near(zb - 1 + bz, g.nz);
+                const size_t gs = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
+                sB[brick_chunk<V>(site, v)] = *reinterpret_cast<const u32x4 *>(X + gs * CIN + v * 8);
             }
         }
-        // D[row][col]: row = site x within the x-row (4*lg + r), col = channel (li)
-        const int z = z0 + w;
+        __syncthreads();
+        f32x4 acc[RZ * RY][NS];
 #pragma unroll
-        for (int ms = 0; ms < 4; ++ms) {
-            const int y = y0 + ms;
+        for (int m = 0; m < RZ * RY; ++m)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int x = x0 + lg * 4 + r;
-                if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
-                const size_t s = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
+            for (int ns = 0; ns < NS; ++ns) acc[m][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // weight fragments straight from global memory (L1/L2-resident), one
+        // kstep ahead
+        u32x4 a[NS], an[NS];
+#pragma unroll
+        for (int ns = 0; ns < NS; ++ns) a[ns] = Wfrag[ns * 64 + l];
+#pragma unroll 1
+        for (int dx = 0; dx < 3; ++dx) {
+            u32x4 f[RZ + 2][RY + 2];
+#pragma unroll
+            for (int zz = 0; zz < RZ + 2; ++zz)
+#pragma unroll
+                for (int yy = 0; yy < RY + 2; ++yy) {
+                    const int site = ((wz * RZ + zz) * S::BY + (wy * RY + yy)) * S::BX + li + dx;
+                    f[zz][yy] = sB[brick_chunk<V>(site, cv)];
+                }
+#pragma unroll
+            for (int k = 0; k < KPD; ++k) {
+                const int ks = dx * KPD + k;
+                if (ks + 1 < S::NKS) {
+#pragma unroll
+                    for (int ns = 0; ns < NS; ++ns) an[ns] = Wfrag[((ks + 1) * NS + ns) * 64 + l];
+                }
+#pragma unroll
+                for (int zz = 0; zz < RZ; ++zz)
+#pragma unroll
+                    for (int yy = 0; yy < RY; ++yy) {
+                        u32x4 bop;
+                        if (CIN == 32) {
+                            bop = f[zz + k / 3][yy + k % 3];
+                        } else {
+                            const int qa = 2 * k, qb = 2 * k + 1 < 9 ? 2 * k + 1 : 0;
+                            const u32x4 lo = f[zz + qa / 3][yy + qa % 3];
+                            const u32x4 hi = 2 * k + 1 < 9 ? f[zz + qb / 3][yy + qb % 3] : zero;
+                            bop = upper ? hi : lo;
+                        }
+#pragma unroll
+                        for (int ns = 0; ns < NS; ++ns)
+                            acc[zz * RY + yy][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf16x8, a[ns]), __builtin_bit_cast(bf16x8, bop),
+                                acc[zz * RY + yy][ns], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int ns = 0; ns < NS; ++ns) a[ns] = an[ns];
+            }
+        }
+        // D[r] of lane (li, lg): output channel 16 ns + 4 lg + r of site x0 + li
+        const int xo = x0 + li, y0 = yb + wy * RY, z0 = zb + wz * RZ;
+#pragma unroll
+        for (int zz = 0; zz < RZ; ++zz)
+#pragma unroll
+            for (int yy = 0; yy < RY; ++yy) {
+                const int yo = y0 + yy, zo = z0 + zz;
+                if (xo >= g.nx || yo >= g.ny || zo >= g.nz) continue;
+                const size_t s = size_t(xo) + size_t(g.nx) * (size_t(yo) + size_t(g.ny) * zo);
 #pragma unroll
                 for (int ns = 0; ns < NS; ++ns) {
-                    const int co = ns * 16 + li;
-                    const float v = acc[ms][ns][r];
+                    const f32x4 v = acc[zz * RY + yy][ns];
+                    const int co = ns * 16 + 4 * lg;
                     if (MODE == MODE_RELU) {
-                        const float y1 = co < co_valid ? fmaxf(v + bias[co], 0.f) : 0.f;
-                        static_cast<unsigned short *>(out)[s * COP + co] = f2bf(y1);
+                        unsigned short h[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h[r] = co + r < co_valid ? f2bf(fmaxf(v[r] + bv[ns][r], 0.f)) : 0;
+                        *reinterpret_cast<uint2 *>(static_cast<unsigned short *>(out) + s * COUT + co) =
+                            make_uint2(unsigned(h[0]) | (unsigned(h[1]) << 16), unsigned(h[2]) | (unsigned(h[3]) << 16));
                     } else if (MODE == MODE_LINEAR) {
-                        if (co < co_valid) static_cast<float *>(out)[s * co_valid + co] = v + bias[co];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (co + r < co_valid) static_cast<float *>(out)[s * co_valid + co + r] = v[r] + bv[ns][r];
                     } else if (MODE == MODE_MASK) {
-                        const bool on = bf2f(mask[s * COP + co]) > 0.f;
-                        static_cast<unsigned short *>(out)[s * COP + co] = on ? f2bf(v) : (unsigned short)0;
+                        const uint2 mk = *reinterpret_cast<const uint2 *>(mask + s * COUT + co);
+                        const unsigned short mh[4] = {(unsigned short)(mk.x & 0xffffu), (unsigned short)(mk.x >> 16),
+                                                      (unsigned short)(mk.y & 0xffffu), (unsigned short)(mk.y >> 16)};
+                        unsigned short h[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h[r] = bf2f(mh[r]) > 0.f ? f2bf(v[r]) : (unsigned short)0;
+                        *reinterpret_cast<uint2 *>(static_cast<unsigned short *>(out) + s * COUT + co) =
+                            make_uint2(unsigned(h[0]) | (unsigned(h[1]) << 16), unsigned(h[2]) | (unsigned(h[3]) << 16));
                     } else {
-                        static_cast<float *>(out)[s * COP + co] = v;
+                        *reinterpret_cast<float4 *>(static_cast<float *>(out) + s * COUT + co) =
+                            make_float4(v[0], v[1], v[2], v[3]);
                     }
                 }
             }
-        }
     }
 }
 
@@ -228,19 +335,22 @@ __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__
 }
 
 // Sum the per-block partials (FP64, block order) into the flat gradient of
-// one layer: W[co][ci][tap] (ci < CI, co < CO) then b[co].
+// one layer: W[co][ci][tap] (ci < CI, co < CO) then b[co].  Threads walk the
+// partial layout contiguously, so every block's partials are read coalesced.
 __global__ __launch_bounds__(BLK) void k_wgrad_reduce(const float *__restrict__ part, int nblk, int CIP, int COP,
                                                       int CI, int CO, float *__restrict__ grad)
 {
     const int PS = 27 * CIP * COP + COP;
-    const int total = CO * CI * 27 + CO;
-    for (int e = blockIdx.x * BLK + threadIdx.x; e < total; e += gridDim.x * BLK) {
-        int idx;
-        if (e < CO * CI * 27) {
-            const int co = e / (CI * 27), ci = (e / 27) % CI, tap = e % 27;
-            idx = (tap * CIP + ci) * COP + co;
+    for (int idx = blockIdx.x * BLK + threadIdx.x; idx < PS; idx += gridDim.x * BLK) {
+        int e;
+        if (idx < 27 * CIP * COP) {
+            const int co = idx % COP, ci = (idx / COP) % CIP, tap = idx / (COP * CIP);
+            if (co >= CO || ci >= CI) continue;
+            e = (co * CI + ci) * 27 + tap;
         } else {
-            idx = 27 * CIP * COP + (e - CO * CI * 27);
+            const int co = idx - 27 * CIP * COP;
+            if (co >= CO) continue;
+            e = CO * CI * 27 + co;
         }
         double s = 0.0;
         for (int b = 0; b < nblk; ++b) s += double(part[size_t(b) * PS + idx]);
@@ -248,42 +358,194 @@ __global__ __launch_bounds__(BLK) void k_wgrad_reduce(const float *__restrict__ 
     }
 }
 
-// Layer weights from the flat FP32 parameters: forward layout [tap][COP][CIP]
-// and, for the backward-data convolution, the transposed layout with the
-// taps reversed (offset -> -offset): [26 - tap][CIP][COP].
-__global__ __launch_bounds__(BLK) void k_wprep(const float *__restrict__ W, int CI, int CO, int CIP, int COP,
-                                               unsigned short *__restrict__ Wf, unsigned short *__restrict__ Wt)
+// Weights of one layer in MFMA fragment order for k_conv, from the flat FP32
+// parameters W[co][ci][tap].  A convolution as run maps CIN input channels to
+// COUT output channels; its fragment array is [kstep][COUT/16][lane][8] bf16,
+// lane = 16 lg + i holding output channel 16 ns + i and the 8 input channels
+// that lane group lg contributes to the K = 32 slice of the kstep.  Ksteps run
+// x-offset major: for CIN = 32 kstep dx*9 + (dz*3 + dy) is one tap; for
+// CIN = 16 kstep dx*5 + p pairs the (dz, dy) positions 2p (lane groups 0-1)
+// and 2p + 1 (lane groups 2-3; zero past the ninth).
+// Forward (transposed = 0): out channel co, in channel ci, tap as stored.
+// Backward-data (transposed = 1): out channel ci, in channel co, tap reversed
+// (offset -> -offset), i.e. the adjoint convolution.
+__global__ __launch_bounds__(BLK) void k_wprep(const float *__restrict__ W, int CI, int CO, int cin, int cout,
+                                               int transposed, unsigned short *__restrict__ F)
 {
-    const int total = 27 * COP * CIP;
+    const int nks = nksteps(cin), ns_n = cout / 16;
+    const int total = nks * ns_n * 64 * 8;
     for (int e = blockIdx.x * BLK + threadIdx.x; e < total; e += gridDim.x * BLK) {
-        const int tap = e / (COP * CIP), co = (e / CIP) % COP, ci = e % CIP;
-        const float v = (co < CO && ci < CI) ? W[(co * CI + ci) * 27 + tap] : 0.f;
-        const unsigned short h = f2bf(v);
-        Wf[e] = h;
-        Wt[((26 - tap) * CIP + ci) * COP + co] = h;
+        const int j = e & 7, lane = (e >> 3) & 63, rest = e >> 9;
+        const int ns = rest % ns_n, ks = rest / ns_n;
+        const int lg = lane >> 4, i = lane & 15;
+        int dx, q, c;
+        if (cin == 32) {
+            dx = ks / 9;
+            q = ks % 9;
+            c = 8 * lg + j;
+        } else {
+            dx = ks / 5;
+            q = 2 * (ks % 5) + (lg >= 2 ? 1 : 0);
+            c = 8 * (lg & 1) + j;
+        }
+        const int o = 16 * ns + i;
+        float v = 0.f;
+        if (q < 9) {
+            const int tap = (q / 3) * 9 + (q % 3) * 3 + dx;
+            if (!transposed) {
+                if (o < CO && c < CI) v = W[(o * CI + c) * 27 + tap];
+            } else {
+                if (o < CI && c < CO) v = W[(c * CI + o) * 27 + (26 - tap)];
+            }
+        }
+        F[e] = f2bf(v);
     }
 }
 
-// Standardised input activations: raw [8][N] FP32 -> bf16 [N][16].
+// Network inputs (NIN = 18 channels): Q (5 stored components), u (3), the
+// last increment d1 = Q(t) - Q(t-k) (5) and its change s2 = Q(t) - 2 Q(t-k) +
+// Q(t-2k) (5).  Standardised with norm and rounded to bf16 into the first
+// layer's [N][32] activation (channels 18..31 zero).
+__device__ __forceinline__ void store_input_row(int N, int s, const float v[NIN], const float *__restrict__ norm,
+                                                unsigned short *__restrict__ A0)
+{
+    alignas(16) unsigned short h[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) h[c] = c < NIN ? f2bf((v[c] - norm[NORM_IN_MEAN + c]) / norm[NORM_IN_STD + c]) : 0;
+    uint4 *dst = reinterpret_cast<uint4 *>(A0 + size_t(s) * 32);
+    const uint4 *src = reinterpret_cast<const uint4 *>(h);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[k] = src[k];
+}
+
+// From raw inputs x [NIN][N] FP32.
 __global__ __launch_bounds__(BLK) void k_pack(int N, const float *__restrict__ x, const float *__restrict__ norm,
                                               unsigned short *__restrict__ A0)
 {
     const int s = blockIdx.x * BLK + threadIdx.x;
     if (s >= N) return;
-    alignas(16) unsigned short h[16];
+    float v[NIN];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) h[c] = c < 8 ? f2bf((x[size_t(c) * N + s] - norm[c]) / norm[8 + c]) : 0;
-    uint4 *dst = reinterpret_cast<uint4 *>(A0 + size_t(s) * 16);
-    const uint4 *src = reinterpret_cast<const uint4 *>(h);
-    dst[0] = src[0];
-    dst[1] = src[1];
+    for (int c = 0; c < NIN; ++c) v[c] = x[size_t(c) * N + s];
+    store_input_row(N, s, v, norm, A0);
 }
 
-// Loss and its gradient: target t = (dq_raw - mean)/std, d = y - t,
-// dZ = bf16(2 d / (5 N)), block partials of sum d^2 (FP64).
+// From a solver state (Q, u of type T) and the history (d1, s2 FP32 [5][N]).
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_pack_state(int N, const T *__restrict__ Q, const T *__restrict__ u,
+                                                    const float *__restrict__ d1, const float *__restrict__ s2,
+                                                    const float *__restrict__ norm, unsigned short *__restrict__ A0)
+{
+    const int s = blockIdx.x * BLK + threadIdx.x;
+    if (s >= N) return;
+    float v[NIN];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = float(Q[size_t(c) * N + s]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[5 + c] = float(u[size_t(c) * N + s]);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        v[8 + c] = d1[size_t(c) * N + s];
+        v[13 + c] = s2[size_t(c) * N + s];
+    }
+    store_input_row(N, s, v, norm, A0);
+}
+
+// Raw inputs [NIN][N] from a solver state and the history.
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_inputs(int N, const T *__restrict__ Q, const T *__restrict__ u,
+                                                const float *__restrict__ d1, const float *__restrict__ s2,
+                                                float *__restrict__ x)
+{
+    const int s = blockIdx.x * BLK + threadIdx.x;
+    if (s >= N) return;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) x[size_t(c) * N + s] = float(Q[size_t(c) * N + s]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[size_t(5 + c) * N + s] = float(u[size_t(c) * N + s]);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        x[size_t(8 + c) * N + s] = d1[size_t(c) * N + s];
+        x[size_t(13 + c) * N + s] = s2[size_t(c) * N + s];
+    }
+}
+
+// History from three snapshots of Q (type T) k steps apart, oldest A, then
+// B, then the current Q: d1 = Q - B, s2 = Q - 2B + A (in T, then FP32).
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_hist3(int N, const T *__restrict__ Q, const T *__restrict__ B,
+                                               const T *__restrict__ A, float *__restrict__ d1,
+                                               float *__restrict__ s2)
+{
+    const size_t i = size_t(blockIdx.x) * BLK + threadIdx.x;
+    if (i >= size_t(5) * N) return;
+    const T q = Q[i], b = B[i], a = A[i];
+    d1[i] = float(q - b);
+    s2[i] = float((q - b) - (b - a));
+}
+
+// History after k plain steps from the snapshot P: dq = Q - P, s2 = dq - d1, d1 = dq.
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_hist_step(int N, const T *__restrict__ Q, const T *__restrict__ P,
+                                                   float *__restrict__ d1, float *__restrict__ s2)
+{
+    const size_t i = size_t(blockIdx.x) * BLK + threadIdx.x;
+    if (i >= size_t(5) * N) return;
+    const float dq = float(Q[i] - P[i]);
+    s2[i] = dq - d1[i];
+    d1[i] = dq;
+}
+
+// Increment predicted by the network: dq = d1 + beta s2 + (y std + mean), y
+// the standardised network output [N][5].
+__device__ __forceinline__ float predicted(const float *__restrict__ Y, const float *__restrict__ norm, int N, int s,
+                                           int k, float d1, float s2)
+{
+    return d1 + norm[NORM_BETA] * s2 + (Y[size_t(s) * 5 + k] * norm[NORM_OUT_STD + k] + norm[NORM_OUT_MEAN + k]);
+}
+
+// dq [5][N] from raw inputs x (history in its channels 8..17).
+__global__ __launch_bounds__(BLK) void k_predict_out(int N, const float *__restrict__ Y, const float *__restrict__ norm,
+                                                     const float *__restrict__ x, float *__restrict__ dq)
+{
+    const int s = blockIdx.x * BLK + threadIdx.x;
+    if (s >= N) return;
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        dq[size_t(k) * N + s] =
+            predicted(Y, norm, N, s, k, x[size_t(8 + k) * N + s], x[size_t(13 + k) * N + s]);
+}
+
+// One network jump on a solver state: dq from the history; either written
+// out (dq != nullptr) or applied: Q += dq, s2 = dq - d1, d1 = dq.
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_jump(int N, const float *__restrict__ Y, const float *__restrict__ norm,
+                                              float *__restrict__ d1, float *__restrict__ s2, T *__restrict__ Q,
+                                              float *__restrict__ dq)
+{
+    const int s = blockIdx.x * BLK + threadIdx.x;
+    if (s >= N) return;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const size_t i = size_t(k) * N + s;
+        const float a = d1[i], b = s2[i];
+        const float d = predicted(Y, norm, N, s, k, a, b);
+        if (dq) {
+            dq[i] = d;
+        } else {
+            Q[i] = T(Q[i] + T(d));
+            s2[i] = d - a;
+            d1[i] = d;
+        }
+    }
+}
+
+// Loss and its gradient: target t = (dq - d1 - beta s2 - mean) / std with the
+// history from x, d = y - t, dZ = bf16(2 d / (5 N)), block partials of
+// sum d^2 (FP64).
 __global__ __launch_bounds__(BLK) void k_lossgrad(int N, const float *__restrict__ Y, const float *__restrict__ dq,
-                                                  const float *__restrict__ norm, unsigned short *__restrict__ dZ,
-                                                  double *__restrict__ part)
+                                                  const float *__restrict__ x, const float *__restrict__ norm,
+                                                  unsigned short *__restrict__ dZ, double *__restrict__ part)
 {
     const int s = blockIdx.x * BLK + threadIdx.x;
     double acc = 0.0;
@@ -293,7 +555,9 @@ __global__ __launch_bounds__(BLK) void k_lossgrad(int N, const float *__restrict
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (k < 5) {
-                const float t = (dq[size_t(k) * N + s] - norm[16 + k]) / norm[21 + k];
+                const float c = dq[size_t(k) * N + s] - x[size_t(8 + k) * N + s] -
+                                norm[NORM_BETA] * x[size_t(13 + k) * N + s];
+                const float t = (c - norm[NORM_OUT_MEAN + k]) / norm[NORM_OUT_STD + k];
                 const float d = Y[size_t(s) * 5 + k] - t;
                 acc += double(d) * double(d);
                 h[k] = f2bf(d * sc);
@@ -376,33 +640,35 @@ __global__ __launch_bounds__(BLK) void k_stats(const float *__restrict__ data, i
     }
 }
 
-// Raw network inputs from a solver state: Q (5 x N) and u (3 x N) of type T
-// -> [8][N] FP32.
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_sample(int N, const T *__restrict__ Q, const T *__restrict__ u,
-                                                float *__restrict__ x)
+// Per-channel sums of the training target c = dq - d1 - beta s2 over
+// nsamples pairs (x [ns][NIN][N], dq [ns][5][N]); FP64 partials, grid 5 x B.
+__global__ __launch_bounds__(BLK) void k_stats_target(const float *__restrict__ x, const float *__restrict__ dq,
+                                                      int N, int nsamples, float beta, double *__restrict__ part)
 {
-    const int s = blockIdx.x * BLK + threadIdx.x;
-    if (s >= N) return;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) x[size_t(c) * N + s] = float(Q[size_t(c) * N + s]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) x[size_t(5 + c) * N + s] = float(u[size_t(c) * N + s]);
-}
-
-// Network output (standardised, [N][5]) -> raw increment; either written as
-// [5][N] FP32 (dq) or added to a Q field of type T (5 x N).
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_apply(int N, const float *__restrict__ Y, const float *__restrict__ norm,
-                                               float *__restrict__ dq, T *__restrict__ Q)
-{
-    const int s = blockIdx.x * BLK + threadIdx.x;
-    if (s >= N) return;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const float d = Y[size_t(s) * 5 + k] * norm[21 + k] + norm[16 + k];
-        if (dq) dq[size_t(k) * N + s] = d;
-        if (Q) Q[size_t(k) * N + s] = T(Q[size_t(k) * N + s] + T(d));
+    const int c = blockIdx.y;
+    double s1 = 0.0, s2 = 0.0;
+    const size_t per = size_t(nsamples) * N;
+    for (size_t k = size_t(blockIdx.x) * BLK + threadIdx.x; k < per; k += size_t(gridDim.x) * BLK) {
+        const size_t smp = k / N, s = k - smp * N;
+        const float t = dq[(smp * 5 + c) * N + s] - x[(smp * NIN + 8 + c) * N + s] -
+                        beta * x[(smp * NIN + 13 + c) * N + s];
+        s1 += double(t);
+        s2 += double(t) * double(t);
+    }
+    __shared__ double b1[BLK], b2[BLK];
+    b1[threadIdx.x] = s1;
+    b2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int w = BLK / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            b1[threadIdx.x] += b1[threadIdx.x + w];
+            b2[threadIdx.x] += b2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * (c * gridDim.x + blockIdx.x)] = b1[0];
+        part[2 * (c * gridDim.x + blockIdx.x) + 1] = b2[0];
     }
 }
 
@@ -435,14 +701,6 @@ __global__ __launch_bounds__(BLK) void k_resid(int N, const T *__restrict__ Qa, 
     }
 }
 
-// dq = Q(t+k) - Q(t) from two network-input arrays (their first 5 planes).
-__global__ __launch_bounds__(BLK) void k_diff(int N, const float *__restrict__ x0, const float *__restrict__ x1,
-                                              float *__restrict__ dq)
-{
-    const size_t i = size_t(blockIdx.x) * BLK + threadIdx.x;
-    if (i < size_t(5) * N) dq[i] = x1[i] - x0[i];
-}
-
 inline int blocks(size_t n) { return int((n + BLK - 1) / BLK); }
 
 }  // namespace
@@ -461,30 +719,69 @@ Grid3 make_grid(int nx, int ny, int nz)
     return g;
 }
 
-int conv_grid(const Grid3 &g) { return g.ntiles < 4096 ? g.ntiles : 4096; }
 int wgrad_grid(const Grid3 &g) { return g.ntiles < WGRAD_BLOCKS ? g.ntiles : WGRAD_BLOCKS; }
 
-hipError_t conv(const Grid3 &g, int cip, int cop, int mode, const unsigned short *X, const unsigned short *W,
+size_t frag_bytes(int cin, int cout) { return size_t(nksteps(cin)) * (cout / 16) * 64 * 16; }
+
+namespace {
+
+int device_cus()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    return cus;
+}
+
+template <int CIN, int COUT, int MODE>
+hipError_t conv_launch(const Grid3 &g, const unsigned short *X, const unsigned short *W, const float *bias, void *out,
+                       const unsigned short *mask, int co_valid, hipStream_t st)
+{
+    constexpr int RY = 4, RZ = 2, WY = 2, WZ = 2;
+    using S = ConvShape<CIN, COUT, RY, RZ, WY, WZ>;
+    auto kern = k_conv<CIN, COUT, MODE, RY, RZ, WY, WZ>;
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(S::lds_bytes));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int ctx = (g.nx + 15) / 16, cty = (g.ny + S::TY - 1) / S::TY, ctz = (g.nz + S::TZ - 1) / S::TZ;
+    const int ntiles = ctx * cty * ctz;
+    // two resident blocks per CU (the LDS bound), a multiple of the 8 XCDs
+    int grid = 2 * device_cus();
+    grid = ntiles < grid ? ntiles : grid;
+    grid = (grid + 7) & ~7;
+    const int per_block = (ntiles + grid - 1) / grid;
+    kern<<<grid, BLK, S::lds_bytes, st>>>(g, ctx, cty, ntiles, per_block, X, reinterpret_cast<const u32x4 *>(W), bias,
+                                          out, mask, co_valid);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t conv(const Grid3 &g, int cin, int cout, int mode, const unsigned short *X, const unsigned short *W,
                 const float *bias, void *out, const unsigned short *mask, int co_valid, hipStream_t st)
 {
-    const int gr = conv_grid(g);
 #define HLB_CONV(CI_, CO_, M_) \
-    k_conv<CI_, CO_, M_><<<gr, BLK, 0, st>>>(g, X, W, bias, out, mask, co_valid)
-    if (cip == 16 && cop == 32 && mode == MODE_RELU) HLB_CONV(16, 32, MODE_RELU);
-    else if (cip == 32 && cop == 32 && mode == MODE_RELU) HLB_CONV(32, 32, MODE_RELU);
-    else if (cip == 32 && cop == 16 && mode == MODE_LINEAR) HLB_CONV(32, 16, MODE_LINEAR);
-    else if (cip == 16 && cop == 32 && mode == MODE_LINEAR) HLB_CONV(16, 32, MODE_LINEAR);
-    else if (cip == 32 && cop == 32 && mode == MODE_LINEAR) HLB_CONV(32, 32, MODE_LINEAR);
-    else if (cip == 16 && cop == 32 && mode == MODE_MASK) HLB_CONV(16, 32, MODE_MASK);
-    else if (cip == 32 && cop == 32 && mode == MODE_MASK) HLB_CONV(32, 32, MODE_MASK);
-    else if (cip == 16 && cop == 32 && mode == MODE_RAW) HLB_CONV(16, 32, MODE_RAW);
-    else if (cip == 32 && cop == 32 && mode == MODE_RAW) HLB_CONV(32, 32, MODE_RAW);
-    else if (cip == 32 && cop == 16 && mode == MODE_RAW) HLB_CONV(32, 16, MODE_RAW);
-    else if (cip == 32 && cop == 16 && mode == MODE_RELU) HLB_CONV(32, 16, MODE_RELU);
-    else
-        return hipErrorInvalidValue;
+    if (cin == CI_ && cout == CO_ && mode == M_) return conv_launch<CI_, CO_, M_>(g, X, W, bias, out, mask, co_valid, st)
+    HLB_CONV(16, 32, MODE_RELU);
+    HLB_CONV(32, 32, MODE_RELU);
+    HLB_CONV(32, 16, MODE_LINEAR);
+    HLB_CONV(16, 32, MODE_LINEAR);
+    HLB_CONV(32, 32, MODE_LINEAR);
+    HLB_CONV(16, 32, MODE_MASK);
+    HLB_CONV(32, 32, MODE_MASK);
+    HLB_CONV(16, 32, MODE_RAW);
+    HLB_CONV(32, 32, MODE_RAW);
+    HLB_CONV(32, 16, MODE_RAW);
 #undef HLB_CONV
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 hipError_t wgrad(const Grid3 &g, int cip, int cop, const unsigned short *X, const unsigned short *dZ, float *part,
@@ -499,14 +796,15 @@ hipError_t wgrad(const Grid3 &g, int cip, int cop, const unsigned short *X, cons
         k_wgrad<32, 16><<<gr, BLK, 0, st>>>(g, X, dZ, part);
     else
         return hipErrorInvalidValue;
-    k_wgrad_reduce<<<64, BLK, 0, st>>>(part, gr, cip, cop, ci, co, grad);
+    k_wgrad_reduce<<<(27 * cip * cop + cop + BLK - 1) / BLK, BLK, 0, st>>>(part, gr, cip, cop, ci, co, grad);
     return hipGetLastError();
 }
 
 hipError_t wprep(const float *W, int ci, int co, int cip, int cop, unsigned short *Wf, unsigned short *Wt,
                  hipStream_t st)
 {
-    k_wprep<<<64, BLK, 0, st>>>(W, ci, co, cip, cop, Wf, Wt);
+    k_wprep<<<64, BLK, 0, st>>>(W, ci, co, cip, cop, 0, Wf);
+    k_wprep<<<64, BLK, 0, st>>>(W, ci, co, cop, cip, 1, Wt);
     return hipGetLastError();
 }
 
@@ -516,10 +814,74 @@ hipError_t pack(int N, const float *x, const float *norm, unsigned short *A0, hi
     return hipGetLastError();
 }
 
-hipError_t lossgrad(int N, const float *Y, const float *dq, const float *norm, unsigned short *dZ, double *part,
-                    double *out, hipStream_t st)
+hipError_t pack_state(bool fp32, int N, const void *Q, const void *u, const float *d1, const float *s2,
+                      const float *norm, unsigned short *A0, hipStream_t st)
 {
-    k_lossgrad<<<blocks(N), BLK, 0, st>>>(N, Y, dq, norm, dZ, part);
+    if (fp32)
+        k_pack_state<float><<<blocks(N), BLK, 0, st>>>(N, static_cast<const float *>(Q),
+                                                       static_cast<const float *>(u), d1, s2, norm, A0);
+    else
+        k_pack_state<double><<<blocks(N), BLK, 0, st>>>(N, static_cast<const double *>(Q),
+                                                        static_cast<const double *>(u), d1, s2, norm, A0);
+    return hipGetLastError();
+}
+
+hipError_t inputs(bool fp32, int N, const void *Q, const void *u, const float *d1, const float *s2, float *x,
+                  hipStream_t st)
+{
+    if (fp32)
+        k_inputs<float><<<blocks(N), BLK, 0, st>>>(N, static_cast<const float *>(Q), static_cast<const float *>(u),
+                                                   d1, s2, x);
+    else
+        k_inputs<double><<<blocks(N), BLK, 0, st>>>(N, static_cast<const double *>(Q),
+                                                    static_cast<const double *>(u), d1, s2, x);
+    return hipGetLastError();
+}
+
+hipError_t hist3(bool fp32, int N, const void *Q, const void *B, const void *A, float *d1, float *s2, hipStream_t st)
+{
+    if (fp32)
+        k_hist3<float><<<blocks(size_t(5) * N), BLK, 0, st>>>(N, static_cast<const float *>(Q),
+                                                              static_cast<const float *>(B),
+                                                              static_cast<const float *>(A), d1, s2);
+    else
+        k_hist3<double><<<blocks(size_t(5) * N), BLK, 0, st>>>(N, static_cast<const double *>(Q),
+                                                               static_cast<const double *>(B),
+                                                               static_cast<const double *>(A), d1, s2);
+    return hipGetLastError();
+}
+
+hipError_t hist_step(bool fp32, int N, const void *Q, const void *P, float *d1, float *s2, hipStream_t st)
+{
+    if (fp32)
+        k_hist_step<float><<<blocks(size_t(5) * N), BLK, 0, st>>>(N, static_cast<const float *>(Q),
+                                                                  static_cast<const float *>(P), d1, s2);
+    else
+        k_hist_step<double><<<blocks(size_t(5) * N), BLK, 0, st>>>(N, static_cast<const double *>(Q),
+                                                                   static_cast<const double *>(P), d1, s2);
+    return hipGetLastError();
+}
+
+hipError_t predict_out(int N, const float *Y, const float *norm, const float *x, float *dq, hipStream_t st)
+{
+    k_predict_out<<<blocks(N), BLK, 0, st>>>(N, Y, norm, x, dq);
+    return hipGetLastError();
+}
+
+hipError_t jump(bool fp32, int N, const float *Y, const float *norm, float *d1, float *s2, void *Q, float *dq,
+                hipStream_t st)
+{
+    if (fp32)
+        k_jump<float><<<blocks(N), BLK, 0, st>>>(N, Y, norm, d1, s2, static_cast<float *>(Q), dq);
+    else
+        k_jump<double><<<blocks(N), BLK, 0, st>>>(N, Y, norm, d1, s2, static_cast<double *>(Q), dq);
+    return hipGetLastError();
+}
+
+hipError_t lossgrad(int N, const float *Y, const float *dq, const float *x, const float *norm, unsigned short *dZ,
+                    double *part, double *out, hipStream_t st)
+{
+    k_lossgrad<<<blocks(N), BLK, 0, st>>>(N, Y, dq, x, norm, dZ, part);
     k_sum<<<1, BLK, 0, st>>>(part, blocks(N), out);
     return hipGetLastError();
 }
@@ -538,28 +900,10 @@ hipError_t stats(const float *data, int nch, int N, int nsamples, double *part, 
     return hipGetLastError();
 }
 
-hipError_t sample(bool fp32, int N, const void *Q, const void *u, float *x, hipStream_t st)
+hipError_t stats_target(const float *x, const float *dq, int N, int nsamples, float beta, double *part, int nblk,
+                        hipStream_t st)
 {
-    if (fp32)
-        k_sample<float><<<blocks(N), BLK, 0, st>>>(N, static_cast<const float *>(Q), static_cast<const float *>(u), x);
-    else
-        k_sample<double><<<blocks(N), BLK, 0, st>>>(N, static_cast<const double *>(Q), static_cast<const double *>(u),
-                                                    x);
-    return hipGetLastError();
-}
-
-hipError_t apply(bool fp32, int N, const float *Y, const float *norm, float *dq, void *Q, hipStream_t st)
-{
-    if (fp32)
-        k_apply<float><<<blocks(N), BLK, 0, st>>>(N, Y, norm, dq, static_cast<float *>(Q));
-    else
-        k_apply<double><<<blocks(N), BLK, 0, st>>>(N, Y, norm, dq, static_cast<double *>(Q));
-    return hipGetLastError();
-}
-
-hipError_t diff(int N, const float *x0, const float *x1, float *dq, hipStream_t st)
-{
-    k_diff<<<blocks(size_t(5) * N), BLK, 0, st>>>(N, x0, x1, dq);
+    k_stats_target<<<dim3(nblk, 5), BLK, 0, st>>>(x, dq, N, nsamples, beta, part);
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // nn_api.cpp -- C-ABI of the convolutional surrogate (include/hlb.h,
 // hlbnn_* and hlb_surrogate_advance): buffers, forward, training step with
-// Adam, per-layer entry points for the parity tests, and the surrogate-with-
-// fallback driver.  All arithmetic runs in the kernels of nn.hip/kernels.hip.
+// Adam, the Q history the network reads, per-layer entry points for the
+// parity tests, and the surrogate-with-fallback driver.  All arithmetic runs
+// in the kernels of nn.hip/kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,10 +19,13 @@
 
 namespace {
 
+using hlb::nn::NIN;
+using hlb::nn::NORM_SIZE;
+
 constexpr int NL = 4;
-constexpr int CI[NL] = {8, 32, 32, 32};
+constexpr int CI[NL] = {NIN, 32, 32, 32};
 constexpr int CO[NL] = {32, 32, 32, 5};
-constexpr int CIP[NL] = {16, 32, 32, 32};
+constexpr int CIP[NL] = {32, 32, 32, 32};
 constexpr int COP[NL] = {32, 32, 32, 16};
 
 int layer_params(int l) { return CO[l] * CI[l] * 27 + CO[l]; }
@@ -41,7 +45,7 @@ int layer_offset(int l)
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Sizes {
-    size_t params, wbf, act0, act, y, dz, part, red, xraw, dq, ckpt, total;
+    size_t params, wbf, act, y, dz, part, red, f5, ckpt, qsnap, norm, total;
 };
 
 Sizes sizes_for(const hlb::nn::Grid3 &g)
@@ -50,19 +54,20 @@ Sizes sizes_for(const hlb::nn::Grid3 &g)
     const size_t N = g.N;
     z.params = a256(size_t(param_total()) * 4);
     size_t wb = 0;
-    for (int l = 0; l < NL; ++l) wb += 2 * a256(size_t(27) * CIP[l] * COP[l] * 2);
+    for (int l = 0; l < NL; ++l)
+        wb += a256(hlb::nn::frag_bytes(CIP[l], COP[l])) + a256(hlb::nn::frag_bytes(COP[l], CIP[l]));
     z.wbf = wb;
-    z.act0 = a256(N * 16 * 2);
     z.act = a256(N * 32 * 2);
     z.y = a256(N * 5 * 4);
     z.dz = a256(N * 32 * 2);
     z.part = a256(size_t(hlb::nn::wgrad_grid(g)) * (27 * 32 * 32 + 32) * 4);
-    z.red = a256((size_t((N + 255) / 256) + 64 * 2 * 16 + 4096) * 8);
-    z.xraw = a256(N * 8 * 4);
-    z.dq = a256(N * 5 * 4);
-    z.ckpt = a256(N * 24 * 8) + a256(N * 5 * 8);  // full state + one Q snapshot, FP64 worst case
-    z.total = 4 * z.params /* params, grads, m, v */ + z.wbf + z.act0 + 3 * z.act + z.y + 2 * z.dz + z.part + z.red +
-              z.xraw + z.dq + z.ckpt + 256 /* norm */;
+    z.red = a256((size_t((N + 255) / 256) + 64 * 2 * NIN + 4096) * 8);
+    z.f5 = a256(N * 5 * 4);
+    z.ckpt = a256(N * 24 * 8);  // populations + Q of an FP64 state; also two Q snapshots
+    z.qsnap = a256(N * 5 * 8);
+    z.norm = a256(NORM_SIZE * 4);
+    z.total = 4 * z.params /* params, grads, m, v */ + z.wbf + NL * z.act + z.y + 2 * z.dz + z.part + z.red +
+              3 * z.f5 /* dq, d1, s2 */ + z.ckpt + z.qsnap + z.norm;
     return z;
 }
 
@@ -73,15 +78,19 @@ struct hlbnn {
     hipStream_t stream;
     float *params, *grads, *m, *v;
     unsigned short *Wf[NL], *Wt[NL];
-    unsigned short *A[NL];  // inputs of the layers: A[0] [N][16], A[1..3] [N][32]
-    float *Y;               // [N][5]
+    unsigned short *A[NL];  // inputs of the layers, [N][32] bf16
+    float *Y;               // [N][5] standardised output of the last layer
     unsigned short *dZ[2];  // [N][32]
     float *part;
     double *red;
-    float *xraw, *dq;
+    float *dq, *d1, *s2;    // [5][N]: predicted increment; history d1, s2
     char *ckpt, *qsnap;
-    float *norm;  // in_mean 8, in_std 8, out_mean 5, out_std 5
+    float *norm;            // NORM_SIZE floats (layout in nn.h)
     bool have_params, have_norm;
+    // the history belongs to one solver context at one state version and k
+    const hlb_ctx *hist_ctx;
+    unsigned long long hist_version;
+    int hist_k;
     int adam_t;
     int status;
     char msg[512];
@@ -151,11 +160,61 @@ int backward(hlbnn *n)
     return HLB_OK;
 }
 
+int check_solver(hlbnn *n, const hlb_ctx *c)
+{
+    if (!c) return nerr(n, HLB_ERR_ARG, "solver context is null");
+    if (c->status) return nerr(n, c->status, "solver context in error: %s", c->msg);
+    if (c->D.G.nx != n->g.nx || c->D.G.ny != n->g.ny || c->D.G.nz != n->g.nz)
+        return nerr(n, HLB_ERR_ARG, "solver and network lattices differ");
+    if (!c->have_fields) return nerr(n, HLB_ERR_STATE, "solver has no fields");
+    return HLB_OK;
+}
+
+bool history_valid(const hlbnn *n, const hlb_ctx *c, int k)
+{
+    return n->hist_ctx == c && n->hist_version == c->version && n->hist_k == k;
+}
+
+// After steps_before plain steps, 2k more recording Q every k steps; the
+// history from the three snapshots (the oldest two in the checkpoint area).
+int record_history(hlbnn *n, hlb_ctx *c, int k, int steps_before)
+{
+    hlb::Device &D = c->D;
+    const size_t N = D.G.N, e = D.fp32 ? 4 : 8;
+    char *A = n->ckpt, *B = n->ckpt + a256(5 * N * e);
+    if (steps_before > 0) N_TRY(n, hlb::run_steps(D, c->p, steps_before));
+    N_TRY(n, hipMemcpyAsync(A, D.Q[D.qcur], 5 * N * e, hipMemcpyDeviceToDevice, D.stream));
+    N_TRY(n, hlb::run_steps(D, c->p, k));
+    N_TRY(n, hipMemcpyAsync(B, D.Q[D.qcur], 5 * N * e, hipMemcpyDeviceToDevice, D.stream));
+    N_TRY(n, hlb::run_steps(D, c->p, k));
+    N_TRY(n, hlb::nn::hist3(D.fp32, int(N), D.Q[D.qcur], B, A, n->d1, n->s2, D.stream));
+    n->hist_ctx = c;
+    n->hist_version = c->version;
+    n->hist_k = k;
+    return HLB_OK;
+}
+
+// Network prediction of the next increment from the solver state and the
+// history: applied to Q with the history advanced (dq_out == nullptr), or
+// written to dq_out.
+int network_jump(hlbnn *n, hlb_ctx *c, float *dq_out)
+{
+    hlb::Device &D = c->D;
+    const int N = int(D.G.N);
+    N_TRY(n, hlb::nn::pack_state(D.fp32, N, D.Q[D.qcur], D.u, n->d1, n->s2, n->norm, n->A[0], D.stream));
+    int rc = forward(n, D.stream);
+    if (rc) return rc;
+    N_TRY(n, hlb::nn::jump(D.fp32, N, n->Y, n->norm, n->d1, n->s2, D.Q[D.qcur], dq_out, D.stream));
+    return HLB_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 int hlbnn_param_count(void) { return param_total(); }
+int hlbnn_input_channels(void) { return NIN; }
+int hlbnn_norm_size(void) { return NORM_SIZE; }
 
 size_t hlbnn_workspace_bytes(int nx, int ny, int nz)
 {
@@ -181,12 +240,10 @@ int hlbnn_create(int nx, int ny, int nz, void *ws, size_t ws_bytes, void *stream
     n->m = reinterpret_cast<float *>(p); p += z.params;
     n->v = reinterpret_cast<float *>(p); p += z.params;
     for (int l = 0; l < NL; ++l) {
-        const size_t wb = a256(size_t(27) * CIP[l] * COP[l] * 2);
-        n->Wf[l] = reinterpret_cast<unsigned short *>(p); p += wb;
-        n->Wt[l] = reinterpret_cast<unsigned short *>(p); p += wb;
+        n->Wf[l] = reinterpret_cast<unsigned short *>(p); p += a256(hlb::nn::frag_bytes(CIP[l], COP[l]));
+        n->Wt[l] = reinterpret_cast<unsigned short *>(p); p += a256(hlb::nn::frag_bytes(COP[l], CIP[l]));
     }
-    n->A[0] = reinterpret_cast<unsigned short *>(p); p += z.act0;
-    for (int l = 1; l < NL; ++l) {
+    for (int l = 0; l < NL; ++l) {
         n->A[l] = reinterpret_cast<unsigned short *>(p);
         p += z.act;
     }
@@ -195,10 +252,11 @@ int hlbnn_create(int nx, int ny, int nz, void *ws, size_t ws_bytes, void *stream
     n->dZ[1] = reinterpret_cast<unsigned short *>(p); p += z.dz;
     n->part = reinterpret_cast<float *>(p); p += z.part;
     n->red = reinterpret_cast<double *>(p); p += z.red;
-    n->xraw = reinterpret_cast<float *>(p); p += z.xraw;
-    n->dq = reinterpret_cast<float *>(p); p += z.dq;
-    n->ckpt = p; p += a256(size_t(n->g.N) * 24 * 8);
-    n->qsnap = p; p += a256(size_t(n->g.N) * 5 * 8);
+    n->dq = reinterpret_cast<float *>(p); p += z.f5;
+    n->d1 = reinterpret_cast<float *>(p); p += z.f5;
+    n->s2 = reinterpret_cast<float *>(p); p += z.f5;
+    n->ckpt = p; p += z.ckpt;
+    n->qsnap = p; p += z.qsnap;
     n->norm = reinterpret_cast<float *>(p);
     *out = n;
     return HLB_OK;
@@ -238,17 +296,29 @@ int hlbnn_get_grads(hlbnn *n, float *host)
     return HLB_OK;
 }
 
-int hlbnn_set_norm(hlbnn *n, const float *norm26)
+int hlbnn_set_norm(hlbnn *n, const float *norm)
 {
+    using namespace hlb::nn;
     N_GUARD(n);
-    if (!norm26) return nerr(n, HLB_ERR_ARG, "norm is null");
-    for (int k = 0; k < 8; ++k)
-        if (!(norm26[8 + k] > 0.f)) return nerr(n, HLB_ERR_PARAM, "input std %d must be positive", k);
+    if (!norm) return nerr(n, HLB_ERR_ARG, "norm is null");
+    for (int k = 0; k < NORM_SIZE; ++k)
+        if (!std::isfinite(norm[k])) return nerr(n, HLB_ERR_PARAM, "norm[%d] not finite", k);
+    for (int k = 0; k < NIN; ++k)
+        if (!(norm[NORM_IN_STD + k] > 0.f)) return nerr(n, HLB_ERR_PARAM, "input std %d must be positive", k);
     for (int k = 0; k < 5; ++k)
-        if (!(norm26[21 + k] > 0.f)) return nerr(n, HLB_ERR_PARAM, "output std %d must be positive", k);
-    N_TRY(n, hipMemcpyAsync(n->norm, norm26, 26 * 4, hipMemcpyHostToDevice, n->stream));
+        if (!(norm[NORM_OUT_STD + k] > 0.f)) return nerr(n, HLB_ERR_PARAM, "output std %d must be positive", k);
+    N_TRY(n, hipMemcpyAsync(n->norm, norm, NORM_SIZE * 4, hipMemcpyHostToDevice, n->stream));
     N_TRY(n, hipStreamSynchronize(n->stream));
     n->have_norm = true;
+    return HLB_OK;
+}
+
+int hlbnn_get_norm(hlbnn *n, float *norm)
+{
+    N_GUARD(n);
+    if (!norm || !n->have_norm) return nerr(n, HLB_ERR_STATE, "no normalisation");
+    N_TRY(n, hipMemcpyAsync(norm, n->norm, NORM_SIZE * 4, hipMemcpyDeviceToHost, n->stream));
+    N_TRY(n, hipStreamSynchronize(n->stream));
     return HLB_OK;
 }
 
@@ -275,6 +345,41 @@ int hlbnn_channel_stats(hlbnn *n, const float *data_dev, int nch, int nsamples, 
     return HLB_OK;
 }
 
+int hlbnn_fit_norm(hlbnn *n, const float *x_dev, const float *dq_dev, int nsamples, float beta, float *norm_out)
+{
+    using namespace hlb::nn;
+    N_GUARD(n);
+    if (!x_dev || !dq_dev || nsamples < 1 || !std::isfinite(beta))
+        return nerr(n, HLB_ERR_ARG, "hlbnn_fit_norm arguments");
+    double mean[NIN], sd[NIN];
+    int rc = hlbnn_channel_stats(n, x_dev, NIN, nsamples, mean, sd);
+    if (rc) return rc;
+    const int nblk = 64;
+    std::vector<double> h(size_t(2) * 5 * nblk);
+    N_TRY(n, stats_target(x_dev, dq_dev, n->g.N, nsamples, beta, n->red, nblk, n->stream));
+    N_TRY(n, hipMemcpyAsync(h.data(), n->red, h.size() * 8, hipMemcpyDeviceToHost, n->stream));
+    N_TRY(n, hipStreamSynchronize(n->stream));
+    float norm[NORM_SIZE];
+    for (int c = 0; c < NIN; ++c) {
+        norm[NORM_IN_MEAN + c] = float(mean[c]);
+        norm[NORM_IN_STD + c] = sd[c] > 0.0 ? float(sd[c]) : 1.f;
+    }
+    const double cnt = double(n->g.N) * nsamples;
+    for (int c = 0; c < 5; ++c) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+            s1 += h[2 * (c * nblk + b)];
+            s2 += h[2 * (c * nblk + b) + 1];
+        }
+        const double m = s1 / cnt, v = std::sqrt(std::fmax(s2 / cnt - m * m, 0.0));
+        norm[NORM_OUT_MEAN + c] = float(m);
+        norm[NORM_OUT_STD + c] = v > 0.0 ? float(v) : 1.f;
+    }
+    norm[NORM_BETA] = beta;
+    if (norm_out) std::memcpy(norm_out, norm, sizeof(norm));
+    return hlbnn_set_norm(n, norm);
+}
+
 int hlbnn_predict(hlbnn *n, const float *x_dev, float *dq_dev)
 {
     N_GUARD(n);
@@ -283,7 +388,7 @@ int hlbnn_predict(hlbnn *n, const float *x_dev, float *dq_dev)
     N_TRY(n, hlb::nn::pack(n->g.N, x_dev, n->norm, n->A[0], n->stream));
     int rc = forward(n, n->stream);
     if (rc) return rc;
-    N_TRY(n, hlb::nn::apply(true, n->g.N, n->Y, n->norm, dq_dev, nullptr, n->stream));
+    N_TRY(n, hlb::nn::predict_out(n->g.N, n->Y, n->norm, x_dev, dq_dev, n->stream));
     return HLB_OK;
 }
 
@@ -295,7 +400,7 @@ int hlbnn_train_step(hlbnn *n, const float *x_dev, const float *dq_dev, float lr
     N_TRY(n, hlb::nn::pack(n->g.N, x_dev, n->norm, n->A[0], n->stream));
     int rc = forward(n, n->stream);
     if (rc) return rc;
-    N_TRY(n, hlb::nn::lossgrad(n->g.N, n->Y, dq_dev, n->norm, n->dZ[0], n->red, n->red + 4096, n->stream));
+    N_TRY(n, hlb::nn::lossgrad(n->g.N, n->Y, dq_dev, x_dev, n->norm, n->dZ[0], n->red, n->red + 4096, n->stream));
     if ((rc = backward(n))) return rc;
     n->adam_t += 1;
     N_TRY(n, hlb::nn::adam(param_total(), n->params, n->grads, n->m, n->v, lr, 0.9f, 0.999f, 1e-8f, n->adam_t,
@@ -352,31 +457,52 @@ int hlbnn_layer_backward(hlbnn *n, int l, const unsigned short *x_host, const un
     return HLB_OK;
 }
 
-int hlbnn_sample(hlbnn *n, hlb_ctx *c, float *x_dev)
+int hlbnn_warmup(hlbnn *n, hlb_ctx *c, int k)
 {
     N_GUARD(n);
-    if (!c || !x_dev) return nerr(n, HLB_ERR_ARG, "null argument");
-    if (c->D.G.nx != n->g.nx || c->D.G.ny != n->g.ny || c->D.G.nz != n->g.nz)
-        return nerr(n, HLB_ERR_ARG, "solver and network lattices differ");
-    if (!c->have_fields) return nerr(n, HLB_ERR_STATE, "solver has no fields");
-    N_TRY(n, hlb::nn::sample(c->D.fp32, n->g.N, c->D.Q[c->D.qcur], c->D.u, x_dev, c->D.stream));
+    if (k < 1) return nerr(n, HLB_ERR_ARG, "k = %d", k);
+    int rc = check_solver(n, c);
+    if (rc) return rc;
+    return record_history(n, c, k, 0);
+}
+
+int hlbnn_history(hlbnn *n, const hlb_ctx *c, float *d1_host, float *s2_host)
+{
+    N_GUARD(n);
+    if (!d1_host || !s2_host) return nerr(n, HLB_ERR_ARG, "null argument");
+    if (!c || !history_valid(n, c, n->hist_k)) return nerr(n, HLB_ERR_STATE, "no history for this solver state");
+    const size_t N = n->g.N;
+    N_TRY(n, hipMemcpyAsync(d1_host, n->d1, 5 * N * 4, hipMemcpyDeviceToHost, c->D.stream));
+    N_TRY(n, hipMemcpyAsync(s2_host, n->s2, 5 * N * 4, hipMemcpyDeviceToHost, c->D.stream));
+    N_TRY(n, hipStreamSynchronize(c->D.stream));
     return HLB_OK;
 }
 
 int hlbnn_make_pair(hlbnn *n, hlb_ctx *c, int k, float *x_dev, float *dq_dev)
 {
     N_GUARD(n);
-    if (!c || !x_dev || !dq_dev || k < 1) return nerr(n, HLB_ERR_ARG, "hlbnn_make_pair arguments");
-    if (c->status) return nerr(n, c->status, "solver context in error: %s", c->msg);
-    if (c->D.G.nx != n->g.nx || c->D.G.ny != n->g.ny || c->D.G.nz != n->g.nz)
-        return nerr(n, HLB_ERR_ARG, "solver and network lattices differ");
-    if (!c->have_fields) return nerr(n, HLB_ERR_STATE, "solver has no fields");
+    if (!x_dev || !dq_dev || k < 1) return nerr(n, HLB_ERR_ARG, "hlbnn_make_pair arguments");
+    int rc = check_solver(n, c);
+    if (rc) return rc;
     hlb::Device &D = c->D;
-    N_TRY(n, hlb::nn::sample(D.fp32, n->g.N, D.Q[D.qcur], D.u, x_dev, D.stream));
+    const size_t N = D.G.N, e = D.fp32 ? 4 : 8;
+    if (!history_valid(n, c, k) && (rc = record_history(n, c, k, 0))) return rc;
+    N_TRY(n, hlb::nn::inputs(D.fp32, int(N), D.Q[D.qcur], D.u, n->d1, n->s2, x_dev, D.stream));
+    N_TRY(n, hipMemcpyAsync(n->qsnap, D.Q[D.qcur], 5 * N * e, hipMemcpyDeviceToDevice, D.stream));
     N_TRY(n, hlb::run_steps(D, c->p, k));
-    N_TRY(n, hlb::nn::sample(D.fp32, n->g.N, D.Q[D.qcur], D.u, n->xraw, D.stream));
-    N_TRY(n, hlb::nn::diff(n->g.N, x_dev, n->xraw, dq_dev, D.stream));
+    N_TRY(n, hlb::nn::hist_step(D.fp32, int(N), D.Q[D.qcur], n->qsnap, n->d1, n->s2, D.stream));
+    N_TRY(n, hipMemcpyAsync(dq_dev, n->d1, 5 * N * 4, hipMemcpyDeviceToDevice, D.stream));
     return HLB_OK;
+}
+
+int hlbnn_jump(hlbnn *n, hlb_ctx *c)
+{
+    N_GUARD(n);
+    int rc = check_solver(n, c);
+    if (rc) return rc;
+    if (!n->have_params || !n->have_norm) return nerr(n, HLB_ERR_STATE, "parameters and normalisation first");
+    if (!history_valid(n, c, n->hist_k)) return nerr(n, HLB_ERR_STATE, "no history for this solver state");
+    return network_jump(n, c, nullptr);
 }
 
 const char *hlbnn_last_error(const hlbnn *n) { return n ? n->msg : "null network"; }
@@ -387,11 +513,11 @@ void hlbnn_destroy(hlbnn *n) { delete n; }
 int hlb_surrogate_advance(hlb_ctx *c, hlbnn *n, int k, int M, double threshold, int *fell_back, double *residual)
 {
     N_GUARD(n);
-    if (!c || k < 1 || M < 1 || !(threshold >= 0.0)) return nerr(n, HLB_ERR_ARG, "hlb_surrogate_advance arguments");
-    if (c->status) return nerr(n, c->status, "solver context in error: %s", c->msg);
-    if (c->D.G.nx != n->g.nx || c->D.G.ny != n->g.ny || c->D.G.nz != n->g.nz)
-        return nerr(n, HLB_ERR_ARG, "solver and network lattices differ");
-    if (!c->have_fields || !n->have_params || !n->have_norm) return nerr(n, HLB_ERR_STATE, "not initialised");
+    if (k < 1 || M < 2 || !(threshold >= 0.0)) return nerr(n, HLB_ERR_ARG, "hlb_surrogate_advance arguments");
+    int rc = check_solver(n, c);
+    if (rc) return rc;
+    if (!n->have_params || !n->have_norm) return nerr(n, HLB_ERR_STATE, "parameters and normalisation first");
+    if (!history_valid(n, c, k)) return nerr(n, HLB_ERR_STATE, "no history for this solver state and k (warm up)");
     hlb::Device &D = c->D;
     const size_t N = D.G.N, e = D.fp32 ? 4 : 8;
     const hipStream_t st = D.stream;
@@ -399,26 +525,18 @@ int hlb_surrogate_advance(hlb_ctx *c, hlbnn *n, int k, int M, double threshold, 
     const int g0 = D.gcur, q0 = D.qcur;
     N_TRY(n, hipMemcpyAsync(n->ckpt, D.g[D.gcur], 19 * N * e, hipMemcpyDeviceToDevice, st));
     N_TRY(n, hipMemcpyAsync(n->ckpt + 19 * N * e, D.Q[D.qcur], 5 * N * e, hipMemcpyDeviceToDevice, st));
-    // M-1 unchecked jumps: Q += network(Q, u); populations and u held
-    for (int j = 0; j < M - 1; ++j) {
-        N_TRY(n, hlb::nn::sample(D.fp32, int(N), D.Q[D.qcur], D.u, n->xraw, st));
-        N_TRY(n, hlb::nn::pack(int(N), n->xraw, n->norm, n->A[0], st));
-        int rc = forward(n, st);
-        if (rc) return rc;
-        N_TRY(n, hlb::nn::apply(D.fp32, int(N), n->Y, n->norm, nullptr, D.Q[D.qcur], st));
-    }
-    // checked jump: network prediction from the pre-jump state, then k plain steps
-    N_TRY(n, hlb::nn::sample(D.fp32, int(N), D.Q[D.qcur], D.u, n->xraw, st));
+    // M-1 unchecked jumps; the populations and u are held
+    for (int j = 0; j < M - 1; ++j)
+        if ((rc = network_jump(n, c, nullptr))) return rc;
+    // checked jump: the network's increment and, from the same state, k plain steps
+    if ((rc = network_jump(n, c, n->dq))) return rc;
     N_TRY(n, hipMemcpyAsync(n->qsnap, D.Q[D.qcur], 5 * N * e, hipMemcpyDeviceToDevice, st));
-    N_TRY(n, hlb::nn::pack(int(N), n->xraw, n->norm, n->A[0], st));
-    int rc = forward(n, st);
-    if (rc) return rc;
-    N_TRY(n, hlb::nn::apply(true, int(N), n->Y, n->norm, n->dq, nullptr, st));
     N_TRY(n, hlb::run_steps(D, c->p, k));
     // residual || (Q_pre + dq) - Q_plain || / || Q_plain || over the five stored components
     const int nblk = 256;
     double h[2 * nblk];
     N_TRY(n, hlb::nn::resid(D.fp32, int(N), n->qsnap, n->dq, D.Q[D.qcur], n->red, nblk, st));
+    N_TRY(n, hlb::nn::hist_step(D.fp32, int(N), D.Q[D.qcur], n->qsnap, n->d1, n->s2, st));
     N_TRY(n, hipMemcpyAsync(h, n->red, sizeof(h), hipMemcpyDeviceToHost, st));
     N_TRY(n, hipStreamSynchronize(st));
     double s1 = 0.0, s2 = 0.0;
@@ -428,15 +546,16 @@ int hlb_surrogate_advance(hlb_ctx *c, hlbnn *n, int k, int M, double threshold, 
     }
     const double r = s2 > 0.0 ? std::sqrt(s1 / s2) : std::sqrt(s1);
     if (residual) *residual = r;
-    const bool bad = !(r <= threshold);
+    const bool bad = !(r < threshold);  // threshold 0 always falls back
     if (fell_back) *fell_back = bad ? 1 : 0;
     if (bad) {
-        // roll back to the cycle start and take the whole cycle with plain steps
+        // roll back to the cycle start and take the whole cycle with plain
+        // steps, recording the history over its last two jumps
         D.gcur = g0;
         D.qcur = q0;
         N_TRY(n, hipMemcpyAsync(D.g[D.gcur], n->ckpt, 19 * N * e, hipMemcpyDeviceToDevice, st));
         N_TRY(n, hipMemcpyAsync(D.Q[D.qcur], n->ckpt + 19 * N * e, 5 * N * e, hipMemcpyDeviceToDevice, st));
-        N_TRY(n, hlb::run_steps(D, c->p, M * k));
+        if ((rc = record_history(n, c, k, (M - 2) * k))) return rc;
     }
     return HLB_OK;
 }

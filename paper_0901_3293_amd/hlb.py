@@ -349,6 +349,8 @@ def _nn_lib():
         fp = ctypes.POINTER(ctypes.c_float)
         up = ctypes.POINTER(ctypes.c_uint16)
         L.hlbnn_param_count.restype = I
+        L.hlbnn_input_channels.restype = I
+        L.hlbnn_norm_size.restype = I
         L.hlbnn_workspace_bytes.argtypes = [I, I, I]
         L.hlbnn_workspace_bytes.restype = sz
         L.hlbnn_create.argtypes = [I, I, I, vp, sz, vp, ctypes.POINTER(vp)]
@@ -356,10 +358,14 @@ def _nn_lib():
         L.hlbnn_get_params.argtypes = [vp, fp]
         L.hlbnn_get_grads.argtypes = [vp, fp]
         L.hlbnn_set_norm.argtypes = [vp, fp]
+        L.hlbnn_get_norm.argtypes = [vp, fp]
         L.hlbnn_channel_stats.argtypes = [vp, vp, I, I, dp, dp]
-        L.hlbnn_sample.argtypes = [vp, vp, vp]
-        L.hlbnn_predict.argtypes = [vp, vp, vp]
+        L.hlbnn_fit_norm.argtypes = [vp, vp, vp, I, ctypes.c_float, fp]
+        L.hlbnn_warmup.argtypes = [vp, vp, I]
+        L.hlbnn_history.argtypes = [vp, vp, fp, fp]
         L.hlbnn_make_pair.argtypes = [vp, vp, I, vp, vp]
+        L.hlbnn_predict.argtypes = [vp, vp, vp]
+        L.hlbnn_jump.argtypes = [vp, vp]
         L.hlbnn_train_step.argtypes = [vp, vp, vp, ctypes.c_float, dp]
         L.hlbnn_layer_forward.argtypes = [vp, I, up, fp]
         L.hlbnn_layer_backward.argtypes = [vp, I, up, up, fp, fp]
@@ -383,8 +389,9 @@ def _up(a):
 class Net:
     """The convolutional surrogate on one lattice (see include/hlb.h, hlbnn_*).
 
-    Device tensors passed in are torch float32 CUDA tensors shaped [C, nz, ny, nx]
-    (or any contiguous tensor of that many elements)."""
+    Device tensors passed in are torch float32 CUDA tensors, contiguous, laid
+    out [C, nz, ny, nx] (or flat with that many elements): inputs x have 18
+    channels (Q, u, d1, s2), increments dq have 5."""
 
     def __init__(self, shape, device="cuda", stream=None):
         L = _nn_lib()
@@ -402,6 +409,8 @@ class Net:
             raise HlbError(rc, "hlbnn_create")
         self.h = h
         self.n_params = L.hlbnn_param_count()
+        self.n_in = L.hlbnn_input_channels()
+        self.n_norm = L.hlbnn_norm_size()
 
     @property
     def N(self):
@@ -433,10 +442,15 @@ class Net:
         self._check(_nn_lib().hlbnn_get_grads(self.h, _fp(p)))
         return p
 
-    def set_norm(self, in_mean, in_std, out_mean, out_std):
-        v = np.concatenate([in_mean, in_std, out_mean, out_std]).astype(np.float32)
-        assert v.size == 26
+    def set_norm(self, norm):
+        v = np.ascontiguousarray(norm, dtype=np.float32)
+        assert v.size == self.n_norm
         self._check(_nn_lib().hlbnn_set_norm(self.h, _fp(v)))
+
+    def norm(self):
+        v = np.empty(self.n_norm, dtype=np.float32)
+        self._check(_nn_lib().hlbnn_get_norm(self.h, _fp(v)))
+        return v
 
     def channel_stats(self, data, nch):
         """data: CUDA float32 tensor of nsamples*nch*N values."""
@@ -445,11 +459,23 @@ class Net:
         self._check(_nn_lib().hlbnn_channel_stats(self.h, self._ptr(data), nch, ns, _dp(mean), _dp(std)))
         return mean, std
 
-    def sample(self, solver, out=None):
-        if out is None:
-            out = torch.empty((8,) + self.shape[::-1], dtype=torch.float32, device=self.device)
-        self._check(_nn_lib().hlbnn_sample(self.h, solver.ctx, self._ptr(out)))
+    def fit_norm(self, X, Y, beta):
+        """Standardisation from pairs X [P, 18, N], Y [P, 5, N] (set and returned)."""
+        ns = X.numel() // (self.n_in * self.N)
+        assert Y.numel() == ns * 5 * self.N
+        out = np.empty(self.n_norm, dtype=np.float32)
+        self._check(_nn_lib().hlbnn_fit_norm(self.h, self._ptr(X), self._ptr(Y), ns, float(beta), _fp(out)))
         return out
+
+    def warmup(self, solver, k):
+        self._check(_nn_lib().hlbnn_warmup(self.h, solver.ctx, int(k)))
+
+    def history(self, solver):
+        nx, ny, nz = self.shape
+        d1 = np.empty((5, nz, ny, nx), dtype=np.float32)
+        s2 = np.empty((5, nz, ny, nx), dtype=np.float32)
+        self._check(_nn_lib().hlbnn_history(self.h, solver.ctx, _fp(d1), _fp(s2)))
+        return d1, s2
 
     def make_pair(self, solver, k, x_out, dq_out):
         """x_out <- inputs of the solver now; k solver steps; dq_out <- Q(t+k) - Q(t)."""
@@ -461,6 +487,9 @@ class Net:
         self._check(_nn_lib().hlbnn_predict(self.h, self._ptr(x), self._ptr(out)))
         return out
 
+    def jump(self, solver):
+        self._check(_nn_lib().hlbnn_jump(self.h, solver.ctx))
+
     def train_step(self, x, dq, lr, want_loss=True):
         loss = np.zeros(1)
         self._check(_nn_lib().hlbnn_train_step(self.h, self._ptr(x), self._ptr(dq), float(lr),
@@ -470,16 +499,18 @@ class Net:
     def layer_forward(self, layer, x_bf16):
         co = (32, 32, 32, 5)[layer]
         x = np.ascontiguousarray(x_bf16, dtype=np.uint16)
+        assert x.size == self.N * 32
         z = np.empty((self.N, co), dtype=np.float32)
         self._check(_nn_lib().hlbnn_layer_forward(self.h, layer, _up(x), _fp(z)))
         return z
 
     def layer_backward(self, layer, x_bf16, dz_bf16):
-        cip = 16 if layer == 0 else 32
-        ci, co = (8, 32, 32, 32)[layer], (32, 32, 32, 5)[layer]
+        ci, co = (self.n_in, 32, 32, 32)[layer], (32, 32, 32, 5)[layer]
+        cop = 16 if layer == 3 else 32
         x = np.ascontiguousarray(x_bf16, dtype=np.uint16)
         dz = np.ascontiguousarray(dz_bf16, dtype=np.uint16)
-        dx = np.empty((self.N, cip), dtype=np.float32)
+        assert x.size == self.N * 32 and dz.size == self.N * cop
+        dx = np.empty((self.N, 32), dtype=np.float32)
         g = np.empty(co * ci * 27 + co, dtype=np.float32)
         self._check(_nn_lib().hlbnn_layer_backward(self.h, layer, _up(x), _up(dz), _fp(dx), _fp(g)))
         return dx, g
@@ -498,7 +529,8 @@ class Net:
 
 def surrogate_advance(solver, net, k=8, M=4, threshold=1e-3):
     """One surrogate cycle (M jumps of k steps, the last one checked against k
-    plain steps).  Returns (fell_back, residual)."""
+    plain steps); the network must hold a history for this solver and k
+    (Net.warmup).  Returns (fell_back, residual)."""
     fb = ctypes.c_int()
     r = np.zeros(1)
     rc = _nn_lib().hlb_surrogate_advance(solver.ctx, net.h, int(k), int(M), float(threshold), ctypes.byref(fb),

@@ -229,3 +229,23 @@ def smooth_field(shape, amp=0.1, seed=7, modes=2):
             v += a * np.cos(2 * math.pi * (m[0] * x / nx + m[1] * y / ny + m[2] * z / nz) + ph)
         comps.append(amp * v / modes)
     return np.stack(comps)
+
+
+# --------------------------------------------------------------------------
+# Surrogate network
+# --------------------------------------------------------------------------
+
+CNN_CHANNELS = (18, 32, 32, 32, 5)
+
+
+def cnn_params(seed=0, scale=1.0):
+    """Seeded He-style initial weights of the 3x3x3 convolutional surrogate as
+    one flat FP32 vector, layer by layer: W [co][ci][kz][ky][kx] drawn from
+    N(0, scale^2 * 2 / (27 ci)), then a zero bias [co]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for ci, co in zip(CNN_CHANNELS[:-1], CNN_CHANNELS[1:]):
+        std = scale * math.sqrt(2.0 / (ci * 27))
+        parts.append(rng.normal(0.0, std, size=co * ci * 27))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)

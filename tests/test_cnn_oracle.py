@@ -6,6 +6,7 @@ import pytest
 import torch
 
 from oracle import cnn
+from paper_0901_3293_amd import inputs
 
 
 def brute_conv(x, W, b):
@@ -56,16 +57,16 @@ def test_bf16_round_to_nearest_even():
 
 
 def test_param_count():
-    assert cnn.param_count() == 8 * 32 * 27 + 32 + 2 * (32 * 32 * 27 + 32) + 32 * 5 * 27 + 5 == 66629
+    assert cnn.param_count() == 18 * 32 * 27 + 32 + 2 * (32 * 32 * 27 + 32) + 32 * 5 * 27 + 5 == 75269
 
 
 def test_backward_matches_finite_differences():
     """Gradient of the MSE loss (no rounding) against central differences on
     a random subset of parameters of every layer."""
     rng = np.random.default_rng(2)
-    p = cnn.init_params(seed=3).astype(np.float64)
+    p = inputs.cnn_params(seed=3).astype(np.float64)
     p += rng.normal(0, 0.01, size=p.size)  # non-zero biases too
-    x = rng.normal(size=(8, 4, 4, 4))
+    x = rng.normal(size=(18, 4, 4, 4))
     t = rng.normal(size=(5, 4, 4, 4))
     acts, z = cnn.forward(p, x, rounding=False)
     g = cnn.backward(p, acts, z, t, rounding=False).numpy()

@@ -11,13 +11,14 @@ import pytest
 import torch
 
 from oracle import cnn
+from paper_0901_3293_amd import inputs
 from tests.hlbtest import rel, say
 
 pytestmark = pytest.mark.gpu
 
-CIP = (16, 32, 32, 32)
+CIP = (32, 32, 32, 32)
 COP = (32, 32, 32, 16)
-CI = (8, 32, 32, 32)
+CI = (18, 32, 32, 32)
 CO = (32, 32, 32, 5)
 
 
@@ -57,7 +58,7 @@ def test_layer_forward(H, shape, layer):
     say("case: nn layer forward", shape, layer)
     rng = np.random.default_rng(10 + layer)
     net = H.Net(shape)
-    p = cnn.init_params(seed=layer)
+    p = inputs.cnn_params(seed=layer)
     p[-(5 + 1):] = 0
     p = (p + rng.normal(0, 0.02, size=p.size)).astype(np.float32)
     net.set_params(p)
@@ -79,7 +80,7 @@ def test_layer_backward(H, shape, layer):
     say("case: nn layer backward", shape, layer)
     rng = np.random.default_rng(20 + layer)
     net = H.Net(shape)
-    p = (cnn.init_params(seed=5) + rng.normal(0, 0.02, size=cnn.param_count())).astype(np.float32)
+    p = (inputs.cnn_params(seed=5) + rng.normal(0, 0.02, size=cnn.param_count())).astype(np.float32)
     net.set_params(p)
     x = rng.normal(size=(CI[layer],) + shape[::-1])
     dz = rng.normal(size=(CO[layer],) + shape[::-1]) * 1e-3
@@ -96,38 +97,55 @@ def test_layer_backward(H, shape, layer):
     assert e_w <= 1e-5 and e_b <= 1e-5 and e_x <= 1e-5
 
 
-def norm_for(x, dq):
-    return (x.reshape(8, -1).mean(1), x.reshape(8, -1).std(1) + 1e-12,
-            dq.reshape(5, -1).mean(1), dq.reshape(5, -1).std(1) + 1e-12)
+def norm_block(x, dq, beta):
+    """Standardisation block (47 floats) from one raw input x [18, ...] and
+    target dq [5, ...]."""
+    c = dq - x[8:13] - beta * x[13:18]
+    v = np.zeros(cnn.NORM_SIZE)
+    v[cnn.IN_MEAN:cnn.IN_MEAN + 18] = x.reshape(18, -1).mean(1)
+    v[cnn.IN_STD:cnn.IN_STD + 18] = x.reshape(18, -1).std(1) + 1e-12
+    v[cnn.OUT_MEAN:cnn.OUT_MEAN + 5] = c.reshape(5, -1).mean(1)
+    v[cnn.OUT_STD:cnn.OUT_STD + 5] = c.reshape(5, -1).std(1) + 1e-12
+    v[cnn.BETA] = beta
+    return v.astype(np.float32)
+
+
+def random_inputs(rng, shape):
+    """Raw inputs with the scales of a solver state: Q ~ 0.1, u ~ 1e-4, d1 ~
+    1e-3, s2 ~ 1e-5."""
+    sc = np.array([0.1] * 5 + [1e-4] * 3 + [1e-3] * 5 + [1e-5] * 5)
+    return rng.normal(size=(18,) + shape[::-1]) * sc[:, None, None, None]
 
 
 def test_network_forward_and_training_step(H):
-    """Whole network and one Adam step on a 24x12x16 lattice.  Bars: output
-    dq within 2e-2 (max) and 1e-3 (mean) relative; gradient within 5e-2 (max
+    """Whole network and one Adam step on a 24x12x16 lattice, extrapolation
+    weight beta = 1.  Bars: predicted increment within 2e-2 (max) and 1e-3
+    (mean) relative to the network's share of it; gradient within 5e-2 (max
     norm) relative; loss within 1e-4; Adam update exactly the textbook step
     on the GPU's own gradient (1e-6)."""
     say("case: nn network forward + train step")
     shape = (24, 12, 16)
     rng = np.random.default_rng(3)
     net = H.Net(shape)
-    p0 = (cnn.init_params(seed=7) + rng.normal(0, 0.01, size=cnn.param_count())).astype(np.float32)
+    p0 = (inputs.cnn_params(seed=7) + rng.normal(0, 0.01, size=cnn.param_count())).astype(np.float32)
     net.set_params(p0)
-    x = rng.normal(size=(8,) + shape[::-1]) * np.linspace(0.1, 1.0, 8)[:, None, None, None]
-    dq = rng.normal(size=(5,) + shape[::-1]) * 1e-3
-    im, isd, om, osd = norm_for(x, dq)
-    net.set_norm(im, isd, om, osd)
+    x = random_inputs(rng, shape)
+    dq = x[8:13] + x[13:18] + rng.normal(size=(5,) + shape[::-1]) * 1e-6
+    norm = norm_block(x, dq, 1.0)
+    net.set_norm(norm)
     xd = torch.tensor(x, dtype=torch.float32, device="cuda")
     dqd = torch.tensor(dq, dtype=torch.float32, device="cuda")
-    out = net.predict(xd).cpu().numpy()
+    out = net.predict(xd).cpu().numpy().astype(np.float64)
     x32 = x.astype(np.float32)
-    xs = (x32 - im.astype(np.float32)[:, None, None, None]) / isd.astype(np.float32)[:, None, None, None]
-    acts, z = cnn.forward(p0, xs)
-    ref = z.numpy() * osd.astype(np.float32)[:, None, None, None] + om.astype(np.float32)[:, None, None, None]
+    ref = cnn.increment(p0, norm, x32[:5], x32[5:8], x32[8:13], x32[13:18])
+    share = ref - x32[8:13].astype(np.float64) - x32[13:18].astype(np.float64)
     d = np.abs(out - ref)
-    say("forward rel max, mean:", d.max() / np.abs(ref).max(), d.mean() / np.abs(ref).mean())
-    assert d.max() / np.abs(ref).max() <= 2e-2 and d.mean() / np.abs(ref).mean() <= 1e-3
+    say("forward rel max, mean:", d.max() / np.abs(share).max(), d.mean() / np.abs(share).mean())
+    assert d.max() / np.abs(share).max() <= 2e-2 and d.mean() / np.abs(share).mean() <= 1e-3
     loss = net.train_step(xd, dqd, lr=1e-3)
-    t = (dq.astype(np.float32) - om.astype(np.float32)[:, None, None, None]) / osd.astype(np.float32)[:, None, None, None]
+    acts, z = cnn.forward(p0, cnn.standardise(x32, norm))
+    c = dq.astype(np.float32) - x32[8:13] - np.float32(1.0) * x32[13:18]
+    t = (c - norm[cnn.OUT_MEAN:cnn.OUT_MEAN + 5, None, None, None]) / norm[cnn.OUT_STD:cnn.OUT_STD + 5, None, None, None]
     loss_ref = cnn.mse(z, t)
     say("loss gpu, oracle:", loss, loss_ref)
     assert abs(loss - loss_ref) <= 1e-4 * loss_ref
@@ -145,13 +163,15 @@ def test_training_is_deterministic(H):
     say("case: nn training determinism")
     shape = (16, 8, 12)
     rng = np.random.default_rng(4)
-    x = torch.tensor(rng.normal(size=(8,) + shape[::-1]), dtype=torch.float32, device="cuda")
-    dq = torch.tensor(rng.normal(size=(5,) + shape[::-1]) * 1e-3, dtype=torch.float32, device="cuda")
+    xh = random_inputs(rng, shape)
+    dqh = xh[8:13] + rng.normal(size=(5,) + shape[::-1]) * 1e-5
+    x = torch.tensor(xh, dtype=torch.float32, device="cuda")
+    dq = torch.tensor(dqh, dtype=torch.float32, device="cuda")
     res = []
     for _ in range(2):
         net = H.Net(shape)
-        net.set_params(cnn.init_params(seed=1))
-        net.set_norm(np.zeros(8), np.ones(8), np.zeros(5), np.full(5, 1e-3))
+        net.set_params(inputs.cnn_params(seed=1))
+        net.set_norm(norm_block(xh, dqh, 0.0))
         for _ in range(3):
             net.train_step(x, dq, 1e-3, want_loss=False)
         res.append(net.params())
