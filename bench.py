@@ -147,6 +147,104 @@ def run_batched(steps, graph_steps=50):
     return out
 
 
+def run_surrogate(n=96, steps=20000, M=8, iters=1500):
+    """The surrogate workload on a 96^3 box: 500 training pairs from five
+    O2 runs and two domain-growth runs (kappa 0.7, tau -0.5, noise 1e-3;
+    the last run of each kind held out), training on the GPU, then 20000 steps
+    of the domain-growth box (O2 slab z < 32 inside an x-helix) with the
+    surrogate (k = 8, M jumps per checked cycle, threshold 1e-3) against the
+    plain FP32 form from the same state."""
+    import numpy as np
+    import torch
+
+    from paper_0901_3293_amd import hlb
+    from paper_0901_3293_amd import inputs as I
+    from paper_0901_3293_amd import surrogate as S
+
+    N = n ** 3
+    net = hlb.Net((n, n, n))
+    o2_pairs, gr_pairs, spacing, burn = 80, 50, 240, 300
+    runs = ([("o2", s, o2_pairs) for s in range(4)] + [("growth", 1, gr_pairs)] +
+            [("o2", 4, o2_pairs)] + [("growth", 2, gr_pairs)])
+    total = sum(r[2] for r in runs)
+    pairs = S.allocate_pairs(total, N)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slot, spans = 0, {}
+    for kind, seed, count in runs:
+        case = S.o2_run(n, seed=seed) if kind == "o2" else S.growth_run(n, noise_amp=1e-3, seed=seed)
+        sv = S.new_solver(case)
+        S.record_pairs(net, sv, pairs, slot, count, spacing, burn_in=burn, tag=f"{kind}-{seed}")
+        spans[f"{kind}-{seed}"] = list(range(slot, slot + count))
+        slot += count
+        del sv
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    train_idx = list(range(0, 4 * o2_pairs + gr_pairs))
+    S.fit_norm(net, pairs, 0.0, index=train_idx)
+    net.set_params(I.cnn_params(seed=0))
+    tl = S.train(net, pairs, iters, lr=2e-3, index=train_idx, log_every=max(1, iters // 5))
+    evals = {}
+    for tag in ("o2-4", "growth-2"):
+        e = S.evaluate(net, pairs, spans[tag])
+        evals[tag] = {k: float(np.median(v)) for k, v in e.items()}
+    # network application time (HIP events on the network's stream)
+    x = pairs.X[train_idx[-1]]
+    out = torch.empty((5, N), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        net.predict(x, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    for _ in range(20):
+        net.predict(x, out)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    ms_net = e0.elapsed_time(e1) / 20
+    del pairs, x
+    torch.cuda.empty_cache()
+
+    case = S.growth_run(n)
+    plain = S.new_solver(case)
+    t_plain = S.plain_run(plain, steps)
+    fz_plain = S.domain_profile(plain)
+    sur = S.new_solver(case)
+    st = S.run(sur, net, steps, M=M)
+    fz_sur = S.domain_profile(sur)
+    ex_net = hlb.Net((n, n, n))
+    S.extrapolation_only(ex_net, 0.0)
+    ext = S.new_solver(case)
+    sx = S.run(ext, ex_net, steps, M=M)
+    spread = float(fz_plain.max() - fz_plain.min())
+    flop = 2.0 * N * S.MACS_PER_SITE
+    out = {
+        "workload": f"{n}^3 domain-growth box (O2 slab z<32 in an x-helix, kappa 0.7, tau -0.5), FP32, "
+                    f"{steps} steps; k = 8, M = {M}, threshold {S.THRESHOLD:g}",
+        "plain_fp32_s": t_plain,
+        "surrogate_s": st.seconds,
+        "speedup": t_plain / st.seconds,
+        "q_error_vs_plain": S.q_error(sur, plain),
+        "fz_max_dev_over_spread": float(np.abs(fz_sur - fz_plain).max() / spread) if spread > 0 else None,
+        "domain_planes": {"plain": S.domain_size(fz_plain), "surrogate": S.domain_size(fz_sur)},
+        "cycles": st.cycles, "fallbacks": st.fallbacks, "plain_cooldown_cycles": st.plain_cycles,
+        "residual_median": float(np.median(st.residuals)) if st.residuals else None,
+        "residual_max": float(np.max(st.residuals)) if st.residuals else None,
+        "extrapolation_only": {"seconds": sx.seconds, "q_error_vs_plain": S.q_error(ext, plain),
+                               "fallbacks": sx.fallbacks, "cycles": sx.cycles},
+        "increment_error_heldout": evals,
+        "training": {"pairs": total, "train_pairs": len(train_idx), "iters": iters, "seconds": tl.seconds,
+                     "data_seconds": t_data, "final_loss": tl.losses[-1][1] if tl.losses else None},
+        "network_ms": ms_net,
+        "conv_roofline": {"bound": "mfma", "achieved": flop / (ms_net * 1e-3) / 1e12, "peak": 2500.0,
+                          "unit": "TFLOP/s", "frac": flop / (ms_net * 1e-3) / 1e12 / 2500.0,
+                          "flop_per_site": 2 * S.MACS_PER_SITE, "kernel": "k_conv (4 layers)"},
+    }
+    for o in (net, ex_net):
+        o.close()
+    del plain, sur, ext
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n, budget_s=15.0):
     """The FP64 oracle (test infrastructure) on the host: steps of the same
     128^3 workload until the time budget is spent (at least one step)."""
@@ -177,12 +275,16 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
-                    help="time one form only (profiling runs)")
+    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate"], default=None,
+                    help="run one leg only (profiling runs)")
     ap.add_argument("--schedule", choices=["auto", "sites", "tiled"], default="auto",
                     help="step schedule (auto: the library's autotuner picks)")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the 96-box batched FP32 run (0: skip)")
+    ap.add_argument("--surrogate-steps", type=int, default=20000,
+                    help="steps of the 96^3 surrogate-vs-plain run (0: skip the surrogate leg)")
+    ap.add_argument("--surrogate-m", type=int, default=8, help="jumps per checked surrogate cycle")
+    ap.add_argument("--surrogate-iters", type=int, default=1500, help="training iterations of the surrogate")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -201,6 +303,13 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy probe 512 MiB x3 done")
         del src, dst
+    if a.only in ("batched", "surrogate"):
+        if a.only == "batched":
+            out = run_batched(a.batch_steps)
+        else:
+            out = run_surrogate(steps=a.surrogate_steps, M=a.surrogate_m, iters=a.surrogate_iters)
+        print(json.dumps({"profiling_run": a.only, **out}), flush=True)
+        return
     res = {}
     forms = (a.only,) if a.only else ("fp32", "fp64")
     for prec in forms:
@@ -212,6 +321,11 @@ def main():
         log(f"bench: batched 96 boxes fp32, {a.batch_steps} steps")
         batched = run_batched(a.batch_steps)
         log(f"bench: batched {batched['mlups']:.1f} MLUPS aggregate")
+    sur = None
+    if a.surrogate_steps > 0 and not a.only:
+        log(f"bench: surrogate 96^3, {a.surrogate_steps} steps, M {a.surrogate_m}")
+        sur = run_surrogate(steps=a.surrogate_steps, M=a.surrogate_m, iters=a.surrogate_iters)
+        log(f"bench: surrogate speedup {sur['speedup']:.2f}, Q error {sur['q_error_vs_plain']:.2e}")
     cpu = None
     if not a.no_cpu:
         log("bench: cpu baseline (oracle)")
@@ -245,6 +359,7 @@ def main():
                  "roofline": r64["roofline"], "step_roofline": r64["step_roofline"],
                  "kernel_ms_per_launch": r64["kernel_ms_per_launch"]},
         "batched": batched,
+        "surrogate": sur,
         "checks": {"fp32": r32["checks"], "fp64": r64["checks"]},
         "cpu_baseline": cpu,
     }

@@ -275,6 +275,10 @@ int hlbnn_warmup(hlbnn *nn, hlb_ctx *solver, int k);
 /* Host copies of the history d1, s2 ([5][N] FP32 each) for the solver's
  * current state; HLB_ERR_STATE if there is none. */
 int hlbnn_history(hlbnn *nn, const hlb_ctx *solver, float *d1, float *s2);
+/* Host copy x [18][N] of the network inputs for the solver's current state
+ * and the history (exactly what the next jump reads); HLB_ERR_STATE without
+ * a valid history. */
+int hlbnn_inputs(hlbnn *nn, const hlb_ctx *solver, float *x);
 /* One training pair: x_dev [18][N] = the inputs at the solver's current
  * state (after a warm-up of 2k steps when there is no valid history), then k
  * plain steps, dq_dev [5][N] = Q(t+k) - Q(t).  The history stays valid. */

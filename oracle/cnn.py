@@ -66,6 +66,25 @@ def conv(x, W, b=None):
     return y
 
 
+def conv_sites(x, W, b, sites):
+    """The periodic convolution at selected sites only (direct sums): x [ci,
+    z, y, x], sites an array of (z, y, x) rows -> [len(sites), co]."""
+    x = np.asarray(x, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    _, nz, ny, nx = x.shape
+    out = np.zeros((len(sites), W.shape[0]))
+    for n, (z, y, xx) in enumerate(np.asarray(sites)):
+        patch = np.empty((x.shape[0], 3, 3, 3))
+        for kz in range(3):
+            for ky in range(3):
+                for kx in range(3):
+                    patch[:, kz, ky, kx] = x[:, (z + kz - 1) % nz, (y + ky - 1) % ny, (xx + kx - 1) % nx]
+        out[n] = np.tensordot(W, patch, axes=([1, 2, 3, 4], [0, 1, 2, 3]))
+        if b is not None:
+            out[n] += np.asarray(b, dtype=np.float64)
+    return out
+
+
 def forward(params, x_std, rounding=True):
     """Full network on standardised inputs x_std [18, z, y, x].
 

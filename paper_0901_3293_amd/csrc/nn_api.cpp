@@ -478,6 +478,22 @@ int hlbnn_history(hlbnn *n, const hlb_ctx *c, float *d1_host, float *s2_host)
     return HLB_OK;
 }
 
+int hlbnn_inputs(hlbnn *n, const hlb_ctx *c, float *x_host)
+{
+    N_GUARD(n);
+    if (!x_host) return nerr(n, HLB_ERR_ARG, "null argument");
+    int rc = check_solver(n, c);
+    if (rc) return rc;
+    if (!history_valid(n, c, n->hist_k)) return nerr(n, HLB_ERR_STATE, "no history for this solver state");
+    const hlb::Device &D = c->D;
+    const size_t N = D.G.N;
+    float *x = reinterpret_cast<float *>(n->ckpt);  // N*24*8 bytes >= NIN*N*4
+    N_TRY(n, hlb::nn::inputs(D.fp32, int(N), D.Q[D.qcur], D.u, n->d1, n->s2, x, D.stream));
+    N_TRY(n, hipMemcpyAsync(x_host, x, size_t(NIN) * N * 4, hipMemcpyDeviceToHost, D.stream));
+    N_TRY(n, hipStreamSynchronize(D.stream));
+    return HLB_OK;
+}
+
 int hlbnn_make_pair(hlbnn *n, hlb_ctx *c, int k, float *x_dev, float *dq_dev)
 {
     N_GUARD(n);

@@ -363,6 +363,7 @@ def _nn_lib():
         L.hlbnn_fit_norm.argtypes = [vp, vp, vp, I, ctypes.c_float, fp]
         L.hlbnn_warmup.argtypes = [vp, vp, I]
         L.hlbnn_history.argtypes = [vp, vp, fp, fp]
+        L.hlbnn_inputs.argtypes = [vp, vp, fp]
         L.hlbnn_make_pair.argtypes = [vp, vp, I, vp, vp]
         L.hlbnn_predict.argtypes = [vp, vp, vp]
         L.hlbnn_jump.argtypes = [vp, vp]
@@ -476,6 +477,13 @@ class Net:
         s2 = np.empty((5, nz, ny, nx), dtype=np.float32)
         self._check(_nn_lib().hlbnn_history(self.h, solver.ctx, _fp(d1), _fp(s2)))
         return d1, s2
+
+    def inputs(self, solver):
+        """The raw network inputs [18, nz, ny, nx] the next jump would read."""
+        nx, ny, nz = self.shape
+        x = np.empty((self.n_in, nz, ny, nx), dtype=np.float32)
+        self._check(_nn_lib().hlbnn_inputs(self.h, solver.ctx, _fp(x)))
+        return x
 
     def make_pair(self, solver, k, x_out, dq_out):
         """x_out <- inputs of the solver now; k solver steps; dq_out <- Q(t+k) - Q(t)."""

@@ -185,32 +185,62 @@ def evaluate(net, pairs, index):
 @dataclass
 class RunStats:
     steps: int
-    cycles: int
-    fallbacks: int
+    cycles: int          # surrogate cycles attempted
+    fallbacks: int       # of which rolled back and redone with plain steps
+    plain_cycles: int    # cycles taken with plain steps while cooling down
     residuals: list
     seconds: float
 
 
-def run(solver, net, steps, k=K_JUMP, M=4, threshold=THRESHOLD):
+def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64):
     """Advance `solver` by `steps` solver steps: a 2k-step history warm-up,
-    then surrogate cycles of M*k steps while a whole cycle fits, plain steps
-    for the rest."""
+    then cycles of M*k steps while a whole cycle fits, plain steps for the
+    rest.  A cycle is a surrogate cycle (M network jumps, the last one checked
+    against k plain steps, rolled back to plain steps when its residual
+    reaches `threshold`) unless the runner is cooling down: after a fallback
+    the next c cycles are plain (c = 1, 2, 4, ... up to cooldown_max on
+    consecutive fallbacks, reset by an accepted cycle), so a fast transient is
+    not paid for twice."""
     cyc = k * M
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net.warmup(solver, k)
     n_cyc = (steps - 2 * k) // cyc
-    fb = 0
+    fb = plain = attempted = 0
     res = []
+    wait = 0
+    penalty = 1
     for _ in range(n_cyc):
+        if wait > 0:
+            # a plain cycle that leaves a valid history behind
+            solver.step(cyc - 2 * k)
+            net.warmup(solver, k)
+            wait -= 1
+            plain += 1
+            continue
         f, r = hlb.surrogate_advance(solver, net, k=k, M=M, threshold=threshold)
-        fb += int(f)
+        attempted += 1
         res.append(r)
+        if f:
+            fb += 1
+            wait = penalty
+            penalty = min(2 * penalty, cooldown_max)
+        else:
+            penalty = 1
     rest = steps - 2 * k - n_cyc * cyc
     if rest:
         solver.step(rest)
     torch.cuda.synchronize()
-    return RunStats(steps, n_cyc, fb, res, time.perf_counter() - t0)
+    return RunStats(steps, attempted, fb, plain, res, time.perf_counter() - t0)
+
+
+def plain_run(solver, steps):
+    """The plain FP32 form over the same steps, timed the same way."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
 
 
 def extrapolation_only(net, beta):
@@ -234,3 +264,14 @@ def domain_profile(solver):
     """Plane-averaged free-energy density f(z)."""
     nx, ny, _ = solver.shape
     return solver.fz() / (nx * ny)
+
+
+def domain_size(fz):
+    """Planes of the higher free-energy phase: the number of z-planes whose
+    plane-averaged f lies above the midpoint of the profile's extremes."""
+    fz = np.asarray(fz)
+    return int((fz > 0.5 * (fz.max() + fz.min())).sum())
+
+
+# Multiply-adds per site of one network application (3x3x3 taps, real channels).
+MACS_PER_SITE = 27 * (N_IN * 32 + 32 * 32 + 32 * 32 + 32 * 5)

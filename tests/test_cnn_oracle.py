@@ -36,6 +36,18 @@ def test_conv_matches_brute_force():
     assert np.abs(cnn.conv(x, W, b).numpy() - brute_conv(x, W, b)).max() < 1e-12
 
 
+def test_conv_sites_matches_conv():
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(3, 5, 4, 6))
+    W = rng.normal(size=(2, 3, 3, 3, 3))
+    b = rng.normal(size=2)
+    full = cnn.conv(x, W, b).numpy()
+    sites = np.array([(0, 0, 0), (4, 3, 5), (2, 1, 3), (4, 0, 5)])
+    got = cnn.conv_sites(x, W, b, sites)
+    want = np.stack([full[:, z, y, xx] for z, y, xx in sites])
+    assert np.abs(got - want).max() < 1e-12
+
+
 def test_conv_periodic_translation_equivariance():
     rng = np.random.default_rng(1)
     x = torch.tensor(rng.normal(size=(4, 6, 5, 7)))

@@ -49,7 +49,7 @@ def from_channels_last(a, C, shape):
     return np.asarray(a)[:, :C].T.reshape(C, nz, ny, nx)
 
 
-SHAPES = [(16, 8, 8), (20, 6, 9)]
+SHAPES = [(16, 8, 8), (20, 6, 9), (40, 20, 12)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)

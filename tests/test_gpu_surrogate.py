@@ -1,0 +1,226 @@
+"""The surrogate driver through the C-ABI.
+
+- The history the network reads is exactly the increments of the plain run.
+- One network jump matches the oracle's jump (network forward on the same
+  bfloat16 operands, extrapolation base, history update).
+- The fallback contract: threshold 0 reproduces the plain run bit for bit;
+  an infinite threshold never falls back.
+- A full-size (96^3) convolution layer at sampled sites against direct sums.
+- What the trained network gains over the method without it (the zero
+  increment) on a held-out trajectory."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn
+from paper_0901_3293_amd import inputs
+from tests.hlbtest import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    assert torch.cuda.is_available()
+    from paper_0901_3293_amd import hlb
+
+    return hlb
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_0901_3293_amd import surrogate
+
+    return surrogate
+
+
+SHAPE = (20, 16, 12)  # ragged against the 16 x 8 x 4 convolution tiles
+
+
+def helix(shape, seed=1, noise=1e-3):
+    nx, ny, nz = shape
+    p = inputs.reduced(1.0, 0.0, 2 * math.pi / 16)
+    Q = inputs.helix_q5(shape, p.q0, inputs.uniaxial_amplitude(p.gamma), "z") + inputs.noise(shape, noise, seed)
+    u, rho = inputs.rest_fluid(shape)
+    return p, Q, u, rho
+
+
+def solver(H, shape, prec, case):
+    p, Q, u, rho = case
+    s = H.Solver(shape, prec)
+    s.set_params(p)
+    s.set_fields(Q, u, rho)
+    return s
+
+
+def some_norm(beta, seed=0):
+    """A valid standardisation block with the scales of a solver state."""
+    rng = np.random.default_rng(seed)
+    v = np.zeros(cnn.NORM_SIZE)
+    v[cnn.IN_MEAN:cnn.IN_MEAN + 18] = rng.normal(size=18) * 1e-3
+    v[cnn.IN_STD:cnn.IN_STD + 18] = [0.1] * 5 + [1e-5] * 3 + [1e-4] * 5 + [1e-6] * 5
+    v[cnn.OUT_MEAN:cnn.OUT_MEAN + 5] = rng.normal(size=5) * 1e-7
+    v[cnn.OUT_STD:cnn.OUT_STD + 5] = 1e-5
+    v[cnn.BETA] = beta
+    return v.astype(np.float32)
+
+
+def test_history_is_the_plain_increments(H):
+    say("case: surrogate history vs plain snapshots, fp64", SHAPE)
+    k = 3
+    case = helix(SHAPE)
+    a, b = solver(H, SHAPE, "fp64", case), solver(H, SHAPE, "fp64", case)
+    net = H.Net(SHAPE)
+    net.warmup(a, k)
+    q0 = b.fields()[0]
+    b.step(k)
+    q1 = b.fields()[0]
+    b.step(k)
+    q2 = b.fields()[0]
+    d1, s2 = net.history(a)
+    assert np.array_equal(a.fields()[0], q2)
+    assert np.array_equal(d1, (q2 - q1).astype(np.float32))
+    assert np.array_equal(s2, ((q2 - q1) - (q1 - q0)).astype(np.float32))
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_jump_matches_oracle(H, beta):
+    """Bars as for the whole network: the increment within 2e-2 (max) and
+    1e-3 (mean) of the network's share of it; the history update exact in
+    FP32 arithmetic."""
+    say("case: surrogate jump vs oracle, fp64, beta", beta)
+    k = 4
+    rng = np.random.default_rng(11)
+    case = helix(SHAPE, seed=2)
+    s = solver(H, SHAPE, "fp64", case)
+    net = H.Net(SHAPE)
+    params = (inputs.cnn_params(seed=3) + rng.normal(0, 0.01, size=cnn.param_count())).astype(np.float32)
+    norm = some_norm(beta)
+    net.set_params(params)
+    net.set_norm(norm)
+    net.warmup(s, k)
+    Q = s.fields()[0]
+    x = net.inputs(s)
+    d1, s2 = net.history(s)
+    assert np.array_equal(x[8:13], d1) and np.array_equal(x[13:18], s2)
+    assert np.array_equal(x[:5], Q.astype(np.float32))
+    u = x[5:8]
+    net.jump(s)
+    Qn = s.fields()[0]
+    d1n, s2n = net.history(s)
+    _, dq_ref, _ = cnn.jump(params, norm, Q, u, d1, s2)
+    dq = Qn - Q
+    share = dq_ref - d1.astype(np.float64) - beta * s2.astype(np.float64)
+    d = np.abs(dq - dq_ref)
+    say("jump rel max, mean:", d.max() / np.abs(share).max(), d.mean() / np.abs(share).mean())
+    assert d.max() <= 2e-2 * np.abs(share).max() + 1e-6 * np.abs(dq_ref).max()
+    assert d.mean() <= 1e-3 * np.abs(share).mean() + 1e-6 * np.abs(dq_ref).mean()
+    # the FP64 state took the FP32 increment; the history advanced in FP32
+    assert np.abs(dq - d1n.astype(np.float64)).max() <= 1e-15
+    assert np.array_equal(s2n, d1n - d1)
+
+
+def trained_free_net(H, shape, beta):
+    net = H.Net(shape)
+    net.set_params((inputs.cnn_params(seed=4) * 0.5).astype(np.float32))
+    net.set_norm(some_norm(beta, seed=1))
+    return net
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_threshold_zero_reproduces_plain_run(H, prec):
+    say("case: surrogate threshold 0 == plain run", prec)
+    k, M, cycles = 4, 3, 3
+    case = helix(SHAPE, seed=3)
+    a, b = solver(H, SHAPE, prec, case), solver(H, SHAPE, prec, case)
+    net = trained_free_net(H, SHAPE, 1.0)
+    net.warmup(a, k)
+    for _ in range(cycles):
+        fb, r = H.surrogate_advance(a, net, k=k, M=M, threshold=0.0)
+        assert fb and r > 0
+    b.step(2 * k + cycles * M * k)
+    fa, fb_ = a.fields(), b.fields()
+    for x, y in zip(fa, fb_):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.get_state(), b.get_state())
+
+
+def test_infinite_threshold_never_falls_back(H):
+    say("case: surrogate threshold inf")
+    k, M = 4, 4
+    case = helix(SHAPE, seed=4)
+    a = solver(H, SHAPE, "fp32", case)
+    net = trained_free_net(H, SHAPE, 0.0)
+    net.warmup(a, k)
+    for _ in range(4):
+        fb, r = H.surrogate_advance(a, net, k=k, M=M, threshold=math.inf)
+        assert not fb and np.isfinite(r) and r > 0
+    Q = a.fields()[0]
+    assert np.isfinite(Q).all()
+
+
+def test_surrogate_needs_history(H):
+    say("case: surrogate without history")
+    case = helix(SHAPE, seed=5)
+    a = solver(H, SHAPE, "fp32", case)
+    net = trained_free_net(H, SHAPE, 0.0)
+    with pytest.raises(H.HlbError):
+        H.surrogate_advance(a, net, k=4, M=2, threshold=1.0)
+    net2 = trained_free_net(H, SHAPE, 0.0)
+    net2.warmup(a, 4)
+    a.step(1)  # the state moved outside the driver: the history is stale
+    with pytest.raises(H.HlbError):
+        H.surrogate_advance(a, net2, k=4, M=2, threshold=1.0)
+
+
+def test_full_size_layer_at_sampled_sites(H):
+    """One 32 -> 32 layer on the 96^3 lattice of the surrogate workload, in
+    the launch configuration the surrogate uses, against direct sums at 512
+    sampled sites (same bfloat16 operands; FP32 accumulation, bar 1e-5)."""
+    shape = (96, 96, 96)
+    say("case: conv layer 1 at 96^3, sampled sites")
+    rng = np.random.default_rng(8)
+    net = H.Net(shape)
+    p = (inputs.cnn_params(seed=9) + rng.normal(0, 0.01, size=cnn.param_count())).astype(np.float32)
+    net.set_params(p)
+    x = rng.normal(size=(32,) + shape[::-1]).astype(np.float32)
+    xb16 = torch.tensor(x).to(torch.bfloat16)
+    bits = xb16.view(torch.int16).numpy().view(np.uint16)
+    x_cl = np.ascontiguousarray(bits.reshape(32, -1).T)
+    z = net.layer_forward(1, x_cl)
+    W, b = cnn.unflatten(p)[1]
+    sites = np.stack([rng.integers(0, n, size=512) for n in shape[::-1]], axis=1)
+    sites[:8] = [(0, 0, 0), (95, 95, 95), (0, 95, 0), (95, 0, 95), (0, 0, 95), (47, 48, 15), (3, 7, 16), (95, 95, 0)]
+    ref = cnn.conv_sites(xb16.to(torch.float64).numpy(), cnn.bf16(W).numpy(), b.numpy(), sites)
+    nx, ny, _ = shape
+    got = np.stack([z[(zz * ny + yy) * nx + xx] for zz, yy, xx in sites])
+    e = np.abs(got - ref).max() / np.abs(ref).max()
+    say("rel err", e)
+    assert e <= 1e-5
+
+
+def test_trained_network_gains_over_zero_increment(H, S):
+    """Train on two 32^3 O2 runs (the surrogate's own kernels), evaluate the
+    predicted 8-step increment on a held-out run.  The method without the
+    network leaves Q unchanged over a jump (relative increment error 1); the
+    trained network must cut that at least tenfold, and stay within 1.5x of
+    the linear extrapolation it corrects."""
+    say("case: trained surrogate vs zero increment")
+    n, P = 32, 24
+    shape = (n, n, n)
+    net = H.Net(shape)
+    pairs = S.allocate_pairs(3 * P, n ** 3)
+    for r, seed in enumerate((0, 1, 2)):
+        s = S.new_solver(S.o2_run(n, seed=seed))
+        S.record_pairs(net, s, pairs, r * P, P, spacing=120, burn_in=300, tag=f"o2-{seed}")
+    train_idx, test_idx = list(range(2 * P)), list(range(2 * P, 3 * P))
+    S.fit_norm(net, pairs, 0.0, index=train_idx)
+    net.set_params(inputs.cnn_params(seed=0))
+    log = S.train(net, pairs, 400, lr=2e-3, index=train_idx, log_every=100)
+    ev = S.evaluate(net, pairs, test_idx)
+    say("train s", log.seconds, "net median", np.median(ev["net"]), "linear", np.median(ev["linear"]),
+        "quadratic", np.median(ev["quadratic"]))
+    assert np.median(ev["net"]) <= 0.1
+    assert np.median(ev["net"]) <= 1.5 * np.median(ev["linear"])
