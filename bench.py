@@ -277,7 +277,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate"], default=None,
                     help="run one leg only (profiling runs)")
-    ap.add_argument("--schedule", choices=["auto", "sites", "tiled"], default="auto",
+    ap.add_argument("--schedule", choices=["auto", "sites", "tiled", "mixed"], default="auto",
                     help="step schedule (auto: the library's autotuner picks)")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the 96-box batched FP32 run (0: skip)")

@@ -144,9 +144,10 @@ int hlb_set_state(hlb_ctx *ctx, const void *host_buf, size_t nbytes);
  * thread (stress to HBM, LB with its divergence, predictor, corrector in
  * place).  HLB_SCHED_TILED: three sweeps in which 2.5D z-marching LDS tiles
  * hold the stress and the predictor stage (recomputed on a one-site halo
- * ring), tz planes per tile column (0: 16).  Both give the same step to
- * rounding.  The default is HLB_SCHED_SITES. */
-enum { HLB_SCHED_SITES = 0, HLB_SCHED_TILED = 1 };
+ * ring), tz planes per tile column (0: 16).  HLB_SCHED_MIXED: the per-site
+ * stress and LB sweeps, then the tiled predictor-corrector.  All give the
+ * same step to rounding.  The default is HLB_SCHED_SITES. */
+enum { HLB_SCHED_SITES = 0, HLB_SCHED_TILED = 1, HLB_SCHED_MIXED = 2 };
 int hlb_set_schedule(hlb_ctx *ctx, int schedule, int tz);
 int hlb_get_schedule(const hlb_ctx *ctx, int *schedule, int *tz);
 

@@ -213,7 +213,7 @@ int hlb_get_totals(hlb_ctx *c, double *mass, double *mom3, double *free_energy)
 int hlb_set_schedule(hlb_ctx *c, int schedule, int tz)
 {
     HLB_GUARD(c);
-    if ((schedule != HLB_SCHED_SITES && schedule != HLB_SCHED_TILED) || tz < 0)
+    if ((schedule != HLB_SCHED_SITES && schedule != HLB_SCHED_TILED && schedule != HLB_SCHED_MIXED) || tz < 0)
         return set_error(c, HLB_ERR_ARG, "schedule %d / tz %d", schedule, tz);
     c->D.sched = schedule;
     c->D.tz = tz;
@@ -241,15 +241,16 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
     struct Cand {
         int sched, tz;
     };
-    const Cand cands[] = {{HLB_SCHED_SITES, 0}, {HLB_SCHED_TILED, 8}, {HLB_SCHED_TILED, 16},
-                          {HLB_SCHED_TILED, 32}};
+    const Cand cands[] = {{HLB_SCHED_SITES, 0}, {HLB_SCHED_TILED, 8},  {HLB_SCHED_TILED, 16},
+                          {HLB_SCHED_TILED, 32}, {HLB_SCHED_MIXED, 8}, {HLB_SCHED_MIXED, 16},
+                          {HLB_SCHED_MIXED, 32}};
     hipEvent_t a, b;
     HIP_TRY(c, hipEventCreate(&a));
     HIP_TRY(c, hipEventCreate(&b));
     double best = 1e300;
     Cand pick = cands[0];
     for (const Cand &k : cands) {
-        if (k.sched == HLB_SCHED_TILED && k.tz > c->D.G.nz && k.tz != 8) continue;
+        if (k.sched != HLB_SCHED_SITES && k.tz > c->D.G.nz && k.tz != 8) continue;
         c->D.sched = k.sched;
         c->D.tz = k.tz;
         hipError_t e = hlb::run_steps(c->D, c->p, 2);  // warm-up

@@ -22,7 +22,7 @@ struct PhysParams {
 };
 
 // Step schedules (see kernels.hip).
-enum Schedule { SCHED_SITES = 0, SCHED_TILED = 1 };
+enum Schedule { SCHED_SITES = 0, SCHED_TILED = 1, SCHED_MIXED = 2 };
 
 // Device buffers of one context (all inside the caller's workspace) and the
 // ping-pong state indices.

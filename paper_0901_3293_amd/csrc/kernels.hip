@@ -17,6 +17,8 @@
 //  TILED (3 sweeps; the stress and the predictor stage live in LDS of 2.5D
 //  z-marching tiles and are recomputed on a one-site halo ring; 65 values):
 //   k_qforce  Q^n -> F^n;  k_lbf  g, F^n -> g', u^n;  k_qupdate  Q^n, u^n -> Q^{n+1}
+//  MIXED (3 sweeps: the per-site stress and LB, then the tiled Q update;
+//  77 values):  k_stress, k_lb, k_qupdate
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -607,7 +609,9 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
     hipError_t e = hipSuccess;
     if (!p.flow && nsteps > 0)  // pure relaxation: u == 0 (Sec. 2.1)
         k_fill<T><<<1024, BLK, 0, D.stream>>>(u, 3 * size_t(G.N), T(0));
-    if (D.sched == SCHED_SITES) {
+    if (D.sched == SCHED_SITES || D.sched == SCHED_MIXED) {
+        const bool fused_q = D.sched == SCHED_MIXED;
+        const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, TX, TY, tile_tz(D));
         for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
             T *Q = static_cast<T *>(D.Q[D.qcur]);
             T *Qs = static_cast<T *>(D.Q[D.qcur ^ 1]);
@@ -619,8 +623,18 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
                     e = mark(K_LB, [&] { k_lb<T><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
                 D.gcur ^= 1;
             }
-            if (e == hipSuccess) e = mark(K_QPRED, [&] { k_qpred<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, u, Qs); });
-            if (e == hipSuccess) e = mark(K_QCORR, [&] { k_qcorr<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Qs, u); });
+            if (fused_q) {
+                if (e == hipSuccess)
+                    e = mark(K_QUPDATE, [&] {
+                        k_qupdate<T><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Q, u, Qs);
+                    });
+                D.qcur ^= 1;
+            } else {
+                if (e == hipSuccess)
+                    e = mark(K_QPRED, [&] { k_qpred<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, u, Qs); });
+                if (e == hipSuccess)
+                    e = mark(K_QCORR, [&] { k_qcorr<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Qs, u); });
+            }
         }
     } else {
         const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, TX, TY, tile_tz(D));

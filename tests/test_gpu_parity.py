@@ -28,7 +28,7 @@ def H():
     return hlb
 
 
-SCHEDS = [("sites", 0), ("tiled", 8), ("tiled", 16)]
+SCHEDS = [("sites", 0), ("tiled", 8), ("mixed", 8), ("tiled", 16)]
 
 
 def make(H, p, Q, u, rho, prec="fp64", sched=("sites", 0)):
@@ -39,7 +39,7 @@ def make(H, p, Q, u, rho, prec="fp64", sched=("sites", 0)):
     return s
 
 
-@pytest.mark.parametrize("sched", SCHEDS[:2])
+@pytest.mark.parametrize("sched", SCHEDS[:3])
 def test_fp64_helix_32cubed_every_step(H, orc, sched):
     """32^3 helix (q0 = 2 pi/16, kappa = 1, tau = 0, noise 1e-4, seed 1), 100
     steps: Q, u, rho and F_total at every step, both schedules."""
@@ -68,7 +68,7 @@ def test_fp64_helix_32cubed_every_step(H, orc, sched):
     say("fp64 32^3 worst relative errors:", worst)
 
 
-@pytest.mark.parametrize("sched", SCHEDS[:2])
+@pytest.mark.parametrize("sched", SCHEDS[:3])
 def test_fp32_helix_1000_steps(H, orc, sched):
     """FP32 form vs FP64 oracle after 1000 steps: Q within 1e-5 relative."""
     say("case: fp32 helix 32^3, 1000 steps", sched)
