@@ -47,7 +47,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(prec, n, steps, warmup, prof_steps, schedule="auto"):
+def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0):
     import torch
 
     from paper_0901_3293_amd import hlb
@@ -60,7 +60,7 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto"):
     if schedule == "auto":
         sched, tz, _ = s.autotune(10)
     else:
-        s.set_schedule(schedule, 0)
+        s.set_schedule(schedule, tz)
         sched, tz = s.schedule()
     stream = s.stream
     s.step(warmup)
@@ -245,6 +245,46 @@ def run_surrogate(n=96, steps=20000, M=8, iters=1500):
     return out
 
 
+def run_network(n=96, predicts=20, train_steps=10):
+    """The surrogate network alone on an n^3 lattice with seeded random
+    inputs: `predicts` forward applications, then `train_steps` training
+    steps (forward, backward, Adam).  For kernel profiles."""
+    import numpy as np
+    import torch
+
+    from paper_0901_3293_amd import hlb
+    from paper_0901_3293_amd import inputs as I
+
+    N = n ** 3
+    net = hlb.Net((n, n, n))
+    net.set_params(I.cnn_params(seed=0))
+    norm = np.zeros(net.n_norm, dtype=np.float32)
+    norm[net.n_in:2 * net.n_in] = 1.0
+    norm[2 * net.n_in + 5:2 * net.n_in + 10] = 1.0
+    net.set_norm(norm)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((net.n_in, N), device="cuda", generator=g)
+    y = torch.randn((5, N), device="cuda", generator=g) * 0.1
+    out = torch.empty((5, N), device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    net.predict(x, out)
+    e0.record(net.stream)
+    for _ in range(predicts):
+        net.predict(x, out)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    ms_pred = e0.elapsed_time(e1) / predicts
+    net.train_step(x, y, 1e-5, want_loss=False)
+    e0.record(net.stream)
+    for _ in range(train_steps):
+        net.train_step(x, y, 1e-5, want_loss=False)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    ms_train = e0.elapsed_time(e1) / train_steps
+    net.close()
+    return {"lattice": n, "predict_ms": ms_pred, "train_step_ms": ms_train}
+
+
 def cpu_baseline(n, budget_s=15.0):
     """The FP64 oracle (test infrastructure) on the host: steps of the same
     128^3 workload until the time budget is spent (at least one step)."""
@@ -275,10 +315,11 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate"], default=None,
+    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "network"], default=None,
                     help="run one leg only (profiling runs)")
     ap.add_argument("--schedule", choices=["auto", "sites", "tiled", "mixed"], default="auto",
                     help="step schedule (auto: the library's autotuner picks)")
+    ap.add_argument("--tz", type=int, default=0, help="planes per tile column for a fixed tiled/mixed schedule")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the 96-box batched FP32 run (0: skip)")
     ap.add_argument("--surrogate-steps", type=int, default=20000,
@@ -303,9 +344,11 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy probe 512 MiB x3 done")
         del src, dst
-    if a.only in ("batched", "surrogate"):
+    if a.only in ("batched", "surrogate", "network"):
         if a.only == "batched":
             out = run_batched(a.batch_steps)
+        elif a.only == "network":
+            out = run_network()
         else:
             out = run_surrogate(steps=a.surrogate_steps, M=a.surrogate_m, iters=a.surrogate_iters)
         print(json.dumps({"profiling_run": a.only, **out}), flush=True)
@@ -314,7 +357,7 @@ def main():
     forms = (a.only,) if a.only else ("fp32", "fp64")
     for prec in forms:
         log(f"bench: {prec} {a.n}^3, warmup {a.warmup}, steps {a.steps}")
-        res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps, a.schedule)
+        res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps, a.schedule, a.tz)
         log(f"bench: {prec} {res[prec]['mlups']:.1f} MLUPS, kernels {res[prec]['kernel_ms_per_launch']}")
     batched = None
     if a.batch_steps > 0 and not a.only:

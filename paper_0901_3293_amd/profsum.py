@@ -5,6 +5,8 @@ and the algorithmic bytes the kernel has to move.
 
 usage: python -m paper_0901_3293_amd.profsum TRACE_DB FETCH_DB WRITE_DB
        --copy-bytes 536870912 --alg k_lb=VALUES ... --esz 4 --sites N
+       [--mfma]   (convolution kernels: padded MFMA flops per dispatch from the
+                   channel counts in the kernel name, TFLOP/s against 2.5 PFLOP/s)
 """
 from __future__ import annotations
 
@@ -15,8 +17,18 @@ from collections import defaultdict
 
 
 def short(name):
+    m = re.search(r"k_(conv|wgrad)<(\d+), (\d+)(, (\d+))?", name)
+    if m:  # keep the channel counts (and epilogue mode) of the surrogate kernels
+        return f"k_{m.group(1)}<{m.group(2)},{m.group(3)}" + (f",{m.group(5)}>" if m.group(5) else ">")
     m = re.search(r"(k_\w+|__amd_rocclr_copyBuffer)", name)
     return m.group(1) if m else name[:40]
+
+
+def conv_flops(k, sites):
+    """Padded multiply-adds x 2 of one dispatch of a 3x3x3 convolution (or its
+    weight gradient) over `sites` sites, from the channel counts in its name."""
+    m = re.match(r"k_(conv|wgrad)<(\d+),(\d+)", k)
+    return 2.0 * sites * 27 * int(m.group(2)) * int(m.group(3)) if m else float("nan")
 
 
 def trace(db):
@@ -54,6 +66,7 @@ def main():
     ap.add_argument("--alg", nargs="*", default=[], help="kernel=values_per_site")
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default="")
+    ap.add_argument("--mfma", action="store_true")
     a = ap.parse_args()
     alg = {k: float(v) for k, v in (x.split("=") for x in a.alg)}
     t = trace(a.trace_db)
@@ -67,6 +80,18 @@ def main():
         print(f"command: {a.command}")
     print(f"copy calibration: {a.copy_bytes / 2**20:.0f} MiB copy reads FETCH_SIZE {fe[cname]:.0f} KiB, "
           f"WRITE_SIZE {wr[cname]:.0f} KiB -> scale fetch x{fscale:.3f}, write x{wscale:.3f}")
+    if a.mfma:
+        print(f"{'kernel':18s} {'calls':>5s} {'avg_us':>9s} {'fetch_MB':>9s} {'write_MB':>9s} {'hbm_GB/s':>9s} "
+              f"{'GFLOP':>8s} {'TFLOP/s':>8s} {'of_2.5P':>8s}")
+        for k, (n, us) in sorted(t.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+            if k == cname:
+                continue
+            f = fe.get(k, float("nan")) * 1024 * fscale / 1e6
+            w = wr.get(k, float("nan")) * 1024 * wscale / 1e6
+            fl = conv_flops(k, a.sites)
+            print(f"{k:18s} {n:5d} {us:9.2f} {f:9.1f} {w:9.1f} {(f + w) / us * 1e3:9.0f} {fl / 1e9:8.1f} "
+                  f"{fl / us / 1e6:8.1f} {fl / us / 1e6 / 2500:8.3f}")
+        return
     print(f"{'kernel':12s} {'calls':>5s} {'avg_us':>9s} {'fetch_MB':>9s} {'write_MB':>9s} {'hbm_MB':>8s} "
           f"{'alg_MB':>8s} {'hbm/alg':>7s} {'alg_GB/s':>9s} {'hbm_GB/s':>9s}")
     for k, (n, us) in sorted(t.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
