@@ -42,6 +42,16 @@ KERNEL_VALUES = {
 }
 STATE_VALUES = 48  # f (19) and Q (5) read and written once
 
+# HBM bytes per launch of the 128^3 kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by a 512 MiB device copy (profiles/*.md); valid
+# while the kernels are unchanged since those counters were taken.
+MEASURED_TRAFFIC = {
+    ("fp32", "k_lb"): (261.3 + 184.5) * 1e6,       # profiles/step_unfused_128cubed.md
+    ("fp64", "k_lb"): (524.7 + 369.1) * 1e6,       # profiles/step_fp64_mixed_128cubed.md
+    ("fp64", "k_qupdate"): (160.7 + 83.9) * 1e6,   # profiles/step_fp64_mixed_128cubed.md
+    ("fp32", "k_qupdate"): (84.1 + 41.9) * 1e6,    # profiles/step_fp32_tiled_128cubed.md
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -91,7 +101,8 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0):
         "kernel_ms_per_launch": per_launch,
         "dominant_kernel": dom,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": MEASURED_TRAFFIC.get((prec, dom)) if n == 128 else None, "kernel": dom,
                      "alg_bytes_per_launch": alg_bytes},
         "step_roofline": {
             "bytes_per_site": step_values * esz,
