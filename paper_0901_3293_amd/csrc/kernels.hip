@@ -232,10 +232,14 @@ __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGri
 
     T Fin[3] = {T(0), T(0), T(0)}, Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
     double facc = 0.0;
-    T pre[PlaneLoader<5>::NL];
-    for (int p = B.z0 - 1; p <= B.z1; ++p) {
-        const bool more = p + 2 <= B.z1 + 1;
-        if (more) L.fetch(Q, N, wrapi(p + 2, G.nz) * sxy, pre);
+    // Planes are fetched into registers two iterations before they are parked
+    // in LDS (two register sets, alternating), so each load has two plane
+    // computations to complete in.
+    constexpr int NL = PlaneLoader<5>::NL;
+    T preA[NL], preB[NL];
+    if (B.z0 + 1 <= B.z1 + 1) L.fetch(Q, N, wrapi(B.z0 + 1, G.nz) * sxy, preA);
+    auto plane = [&](int p, T(&cur)[NL], T(&nxt)[NL]) __attribute__((always_inline)) {
+        if (p + 3 <= B.z1 + 1) L.fetch(Q, N, wrapi(p + 3, G.nz) * sxy, nxt);
         T Pz[3];
         {
             T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
@@ -272,13 +276,19 @@ __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGri
             Pz2[a] = Pz1[a];
             Pz1[a] = Pz[a];
         }
-        if (more) L.store(pre, sQ[sb]);  // plane p-1 is no longer read: it becomes p+2
+        if (p + 2 <= B.z1 + 1) L.store(cur, sQ[sb]);  // plane p-1 is no longer read: it becomes p+2
         __syncthreads();
         const int o = sb;
         sb = sm;
         sm = st;
         st = o;
+    };
+    int p = B.z0 - 1;
+    for (; p + 1 <= B.z1; p += 2) {
+        plane(p, preA, preB);
+        plane(p + 1, preB, preA);
     }
+    if (p <= B.z1) plane(p, preA, preB);
     if (WITH_F) {
         double v[1] = {facc};
         block_sum<1, Shape::NT>(v, fpart + logical_block());
@@ -333,12 +343,18 @@ __global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGr
     T qprev[5] = {T(0), T(0), T(0), T(0), T(0)};  // Q^n at the own site of plane p-1
     T up1[3] = {T(0), T(0), T(0)};                 // u at the own site, plane p-1
     T up2[3] = {T(0), T(0), T(0)};                 // u at the own site, plane p-2
-    T preQ[PlaneLoader<5>::NL], preU[PlaneLoader<3>::NL];
-    for (int p = B.z0 - 1; p <= B.z1; ++p) {
-        const bool more = p + 2 <= B.z1 + 1;
-        if (more) {
-            LQ.fetch(Qin, N, wrapi(p + 2, G.nz) * sxy, preQ);
-            LU.fetch(u, N, wrapi(p + 2, G.nz) * sxy, preU);
+    // Planes are fetched into registers two iterations before they are parked
+    // in LDS (two register sets, alternating).
+    constexpr int NQ = PlaneLoader<5>::NL, NU = PlaneLoader<3>::NL;
+    T preQa[NQ], preUa[NU], preQb[NQ], preUb[NU];
+    if (B.z0 + 1 <= B.z1 + 1) {
+        LQ.fetch(Qin, N, wrapi(B.z0 + 1, G.nz) * sxy, preQa);
+        LU.fetch(u, N, wrapi(B.z0 + 1, G.nz) * sxy, preUa);
+    }
+    auto plane = [&](int p, T(&curQ)[NQ], T(&curU)[NU], T(&nxtQ)[NQ], T(&nxtU)[NU]) __attribute__((always_inline)) {
+        if (p + 3 <= B.z1 + 1) {
+            LQ.fetch(Qin, N, wrapi(p + 3, G.nz) * sxy, nxtQ);
+            LU.fetch(u, N, wrapi(p + 3, G.nz) * sxy, nxtU);
         }
         T qcur[5], ucur[3];
         {
@@ -391,9 +407,9 @@ __global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGr
             up1[a] = ucur[a];
         }
         __syncthreads();  // slot sb (plane p-1) and the Q* slot q2 are free now
-        if (more) {
-            LQ.store(preQ, sQ[sb]);
-            LU.store(preU, sU[sb]);
+        if (p + 2 <= B.z1 + 1) {
+            LQ.store(curQ, sQ[sb]);
+            LU.store(curU, sU[sb]);
         }
         __syncthreads();
         int o = sb;
@@ -404,7 +420,13 @@ __global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGr
         q2 = q1;
         q1 = q0;
         q0 = o;
+    };
+    int p = B.z0 - 1;
+    for (; p + 1 <= B.z1; p += 2) {
+        plane(p, preQa, preUa, preQb, preUb);
+        plane(p + 1, preQb, preUb, preQa, preUa);
     }
+    if (p <= B.z1) plane(p, preQa, preUa, preQb, preUb);
 }
 
 // ---------------------------------------------------------------- per-site kernels
