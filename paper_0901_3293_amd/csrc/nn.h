@@ -33,8 +33,9 @@ size_t frag_bytes(int cin, int cout);
 // supported (cin, cout): (16, 32), (32, 32), (32, 16).
 hipError_t conv(const Grid3 &g, int cip, int cop, int mode, const unsigned short *X, const unsigned short *W,
                 const float *bias, void *out, const unsigned short *mask, int co_valid, hipStream_t st);
-// Weight and bias gradient of one layer into the flat layout W[co][ci][27], b[co].
-// part: wgrad_grid(g) x (27 cip cop + cop) floats of scratch.
+// Weight and bias gradient of one layer into the flat layout W[co][ci][27], b[co]
+// (cip = 32; cop = 32 or 16).  part: wgrad_grid(g) x (27 cip cop + cop) floats
+// of scratch.
 hipError_t wgrad(const Grid3 &g, int cip, int cop, const unsigned short *X, const unsigned short *dZ, float *part,
                  int ci, int co, float *grad, hipStream_t st);
 // Fragment-ordered weights of one layer: Wf for the forward convolution

@@ -22,9 +22,7 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BLK = 256;
-constexpr int TXs = 16, TYs = 4, TZs = 4;               // output tile
-constexpr int BX = TXs + 2, BY = TYs + 2, BZ = TZs + 2;  // staged input brick
-constexpr int BN = BX * BY * BZ;
+constexpr int TXs = 16, TYs = 4, TZs = 4;  // weight-gradient tile (Grid3)
 
 __device__ __forceinline__ unsigned short f2bf(float f)
 {
@@ -57,24 +55,6 @@ __device__ __forceinline__ void tile_origin(const Grid3 &g, int t, int &x0, int 
     const int r = t / g.tx;
     y0 = (r % g.ty) * TYs;
     z0 = (r / g.ty) * TZs;
-}
-
-// Brick of (TX+2)(TY+2)(TZ+2) sites around the tile, CIP channels each, into
-// LDS rows of SP = CIP + 8 (16-byte aligned, no bank conflicts for the
-// fragment reads).
-template <int CIP>
-__device__ __forceinline__ void stage_brick(const Grid3 &g, const unsigned short *__restrict__ act, int x0, int y0,
-                                            int z0, unsigned short *sB)
-{
-    constexpr int SP = CIP + 8, V = CIP / 8;
-    for (int e = threadIdx.x; e < BN * V; e += BLK) {
-        const int site = e / V, v = e - site * V;
-        const int bx = site % BX, r = site / BX, by = r % BY, bz = r / BY;
-        const int x = wrap(x0 - 1 + bx, g.nx), y = wrap(y0 - 1 + by, g.ny), z = wrap(z0 - 1 + bz, g.nz);
-        const size_t gs = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
-        *reinterpret_cast<uint4 *>(sB + site * SP + v * 8) =
-            *reinterpret_cast<const uint4 *>(act + gs * CIP + v * 8);
-    }
 }
 
 // Forward-style periodic 3x3x3 convolution of a CIN-channel activation into
@@ -260,77 +240,122 @@ __global__ __launch_bounds__(BLK, 2) void k_conv(Grid3 g, int ctx, int cty, int 
     }
 }
 
-// Weight gradient dW[tap][ci][co] = sum_s X[s + off(tap)][ci] dZ[s][co] and
-// bias gradient db[co] = sum_s dZ[s][co]: per tile, a GEMM with M = 16 input
-// channels, N = 16 output channels, K = 16 sites of one x-row; each wave owns
-// a fixed set of (tap, ci block, co block) accumulators across all the tiles
-// its block visits.  Per-block FP32 partials; the final sum is FP64 in a fixed
-// order (k_wgrad_reduce), so the result is deterministic.
-template <int CIP, int COP>
+// Weight gradient dW[tap][ci][co] = sum_s dZ[s][co] X[s + off(tap)][ci] and
+// bias gradient db[co] = sum_s dZ[s][co] on v_mfma_f32_16x16x32_bf16: per
+// tile of 16x4x4 sites, M = 16 output channels, N = 16 input channels,
+// K = 32 sites (two x-rows).  The tile's dZ and its input brick (18x6x6
+// sites, periodic wrap) are staged channel-major in LDS (brick rows padded to
+// 24 sites).  An operand of 8 consecutive sites shifted by the tap's
+// x-offset comes from one aligned 16-byte read and one 4-byte read of the
+// brick row, shared by the three x-offsets of a (y, z) offset pair (odd
+// offsets take a 16-bit funnel shift).  With 32 output channels wave w owns
+// the (co block, ci block) pair (w >> 1, w & 1) for all 27 taps; with 16, ci
+// block w & 1 over half the K-chunks, the two halves summed in LDS at the end.
+// Per-block FP32 partials; the final sum is FP64 in a fixed order
+// (k_wgrad_reduce), so the result is deterministic.
+template <int COP>
 __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__restrict__ X,
                                                const unsigned short *__restrict__ dZ, float *__restrict__ part)
 {
-    constexpr int SP = CIP + 8, DP = COP + 8, MS = CIP / 16, NS = COP / 16, NCOMBO = 27 * MS * NS;
-    constexpr int PER = (NCOMBO + 3) / 4;
+    constexpr int CIP = 32;
+    constexpr int XR = 24, BYs = TYs + 2, BZs = TZs + 2, ROWS = BYs * BZs;
+    constexpr int TS = TXs * TYs * TZs;  // 256 sites, 8 K-chunks of 32
     constexpr int PS = 27 * CIP * COP + COP;
-    __shared__ __attribute__((aligned(16))) unsigned short sB[BN * SP];
-    __shared__ __attribute__((aligned(16))) unsigned short sD[TXs * TYs * TZs * DP];
+    constexpr int NBX = (TXs + 2) * ROWS;  // brick sites
+    __shared__ __attribute__((aligned(16))) unsigned short sX[CIP * ROWS * XR];
+    __shared__ __attribute__((aligned(16))) unsigned short sD[COP * TS];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lg = l >> 4;
-    f32x4 acc[PER];
+    const int mt = COP == 32 ? (w >> 1) : 0, nt = w & 1;
+    const int half = COP == 32 ? 0 : (w >> 1);  // COP == 16: which K-chunks this wave takes
+    const int cstep = COP == 32 ? 1 : 2;
+    f32x4 acc[27];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 27; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float dbacc = 0.f;
     for (int t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
         int x0, y0, z0;
         tile_origin(g, t, x0, y0, z0);
         __syncthreads();
-        stage_brick<CIP>(g, X, x0, y0, z0, sB);
-        constexpr int V = COP / 8;
-        for (int e = threadIdx.x; e < TXs * TYs * TZs * V; e += BLK) {
-            const int site = e / V, v = e - site * V;
-            const int tx = site % TXs, r = site / TXs, ty = r % TYs, tz = r / TYs;
+        // input brick, channel-major: sX[ci][bz][by][bx]
+        for (int e = threadIdx.x; e < NBX * 4; e += BLK) {
+            const int site = e >> 2, v = e & 3;
+            const int bx = site % (TXs + 2), r = site / (TXs + 2), by = r % BYs, bz = r / BYs;
+            const int x = wrap(x0 - 1 + bx, g.nx), y = wrap(y0 - 1 + by, g.ny), z = wrap(z0 - 1 + bz, g.nz);
+            const size_t gs = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
+            const u32x4 val = *reinterpret_cast<const u32x4 *>(X + gs * CIP + v * 8);
+            unsigned short *d = sX + ((8 * v) * ROWS + bz * BYs + by) * XR + bx;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                d[(2 * c) * ROWS * XR] = (unsigned short)(val[c] & 0xffffu);
+                d[(2 * c + 1) * ROWS * XR] = (unsigned short)(val[c] >> 16);
+            }
+        }
+        // output gradient of the tile, channel-major: sD[co][site]
+        for (int e = threadIdx.x; e < TS * (COP / 8); e += BLK) {
+            const int si = e / (COP / 8), v = e - si * (COP / 8);
+            const int tx = si % TXs, r = si / TXs, ty = r % TYs, tz = r / TYs;
             const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
-            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            u32x4 val = {0u, 0u, 0u, 0u};
             if (x < g.nx && y < g.ny && z < g.nz) {
                 const size_t gs = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
-                val = *reinterpret_cast<const uint4 *>(dZ + gs * COP + v * 8);
+                val = *reinterpret_cast<const u32x4 *>(dZ + gs * COP + v * 8);
             }
-            *reinterpret_cast<uint4 *>(sD + site * DP + v * 8) = val;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                sD[(8 * v + 2 * c) * TS + si] = (unsigned short)(val[c] & 0xffffu);
+                sD[(8 * v + 2 * c + 1) * TS + si] = (unsigned short)(val[c] >> 16);
+            }
         }
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int combo = w + 4 * j;
-            if (combo < NCOMBO) {
-                const int tap = combo / (MS * NS), rem = combo - tap * (MS * NS), ms = rem / NS, ns = rem - ms * NS;
-                const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+        if (int(threadIdx.x) < COP)
+            for (int si = 0; si < TS; ++si) dbacc += bf2f(sD[threadIdx.x * TS + si]);
 #pragma unroll 1
-                for (int kc = 0; kc < TYs * TZs; ++kc) {
-                    const int yy = kc % TYs, zz = kc / TYs;
-                    bf16x4 a, b;
+        for (int c = half; c < TS / 32; c += cstep) {
+            const int rowk = 2 * c + (lg >> 1), yy = rowk % TYs, zz = rowk / TYs, xo = 8 * (lg & 1);
+            const u32x4 A = *reinterpret_cast<const u32x4 *>(sD + (16 * mt + li) * TS + c * 32 + 8 * lg);
+            const unsigned short *xrow = sX + ((16 * nt + li) * ROWS) * XR + xo;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int x = lg * 4 + q;
-                        a[q] = short(sB[(((zz + dz) * BY + (yy + dy)) * BX + (x + dx)) * SP + ms * 16 + li]);
-                        b[q] = short(sD[((zz * TYs + yy) * TXs + x) * DP + ns * 16 + li]);
-                    }
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
-                }
+            for (int q = 0; q < 9; ++q) {
+                const int dz = q / 3, dy = q % 3;
+                const unsigned short *rp = xrow + ((zz + dz) * BYs + (yy + dy)) * XR;
+                const u32x4 lo = *reinterpret_cast<const u32x4 *>(rp);
+                const unsigned hi = *reinterpret_cast<const unsigned *>(rp + 8);
+                const u32x4 b0 = lo;
+                const u32x4 b1 = {__builtin_amdgcn_alignbit(lo[1], lo[0], 16), __builtin_amdgcn_alignbit(lo[2], lo[1], 16),
+                                  __builtin_amdgcn_alignbit(lo[3], lo[2], 16), __builtin_amdgcn_alignbit(hi, lo[3], 16)};
+                const u32x4 b2 = {lo[1], lo[2], lo[3], hi};
+                const int tap = dz * 9 + dy * 3;
+                acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A),
+                                                                   __builtin_bit_cast(bf16x8, b0), acc[tap], 0, 0, 0);
+                acc[tap + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, A), __builtin_bit_cast(bf16x8, b1), acc[tap + 1], 0, 0, 0);
+                acc[tap + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, A), __builtin_bit_cast(bf16x8, b2), acc[tap + 2], 0, 0, 0);
             }
         }
-        if (int(threadIdx.x) < COP)
-            for (int s = 0; s < TXs * TYs * TZs; ++s) dbacc += bf2f(sD[s * DP + threadIdx.x]);
     }
     float *P = part + size_t(blockIdx.x) * PS;
+    if (COP == 16) {
+        // waves 2 and 3 hand their half-sums to waves 0 and 1 through LDS
+        float *sA = reinterpret_cast<float *>(sX);  // 2 x 27 x 64 x 4 floats == sizeof(sX)
+        __syncthreads();
+        if (half == 1)
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int combo = w + 4 * j;
-        if (combo < NCOMBO) {
-            const int tap = combo / (MS * NS), rem = combo - tap * (MS * NS), ms = rem / NS, ns = rem - ms * NS;
+            for (int j = 0; j < 27; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) P[(tap * CIP + ms * 16 + lg * 4 + r) * COP + ns * 16 + li] = acc[j][r];
-        }
+                for (int r = 0; r < 4; ++r) sA[((nt * 27 + j) * 64 + l) * 4 + r] = acc[j][r];
+        __syncthreads();
+        if (half == 1) return;
+#pragma unroll
+        for (int j = 0; j < 27; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[j][r] += sA[((nt * 27 + j) * 64 + l) * 4 + r];
     }
+    // D[r] of lane (li, lg): output channel 16 mt + 4 lg + r, input channel 16 nt + li
+#pragma unroll
+    for (int j = 0; j < 27; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P[(j * CIP + 16 * nt + li) * COP + 16 * mt + 4 * lg + r] = acc[j][r];
     if (int(threadIdx.x) < COP) P[27 * CIP * COP + threadIdx.x] = dbacc;
 }
 
@@ -352,8 +377,15 @@ __global__ __launch_bounds__(BLK) void k_wgrad_reduce(const float *__restrict__ 
             if (co >= CO) continue;
             e = CO * CI * 27 + co;
         }
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += double(part[size_t(b) * PS + idx]);
+        // eight interleaved partial sums (block b into sum b % 8), combined in a
+        // fixed order: deterministic, with eight loads in flight per thread
+        double acc8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = 0;
+        for (; b + 8 <= nblk; b += 8)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc8[k] += double(part[size_t(b + k) * PS + idx]);
+        for (; b < nblk; ++b) acc8[b & 7] += double(part[size_t(b) * PS + idx]);
+        const double s = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
         grad[e] = float(s);
     }
 }
@@ -788,12 +820,10 @@ hipError_t wgrad(const Grid3 &g, int cip, int cop, const unsigned short *X, cons
                  int ci, int co, float *grad, hipStream_t st)
 {
     const int gr = wgrad_grid(g);
-    if (cip == 16 && cop == 32)
-        k_wgrad<16, 32><<<gr, BLK, 0, st>>>(g, X, dZ, part);
-    else if (cip == 32 && cop == 32)
-        k_wgrad<32, 32><<<gr, BLK, 0, st>>>(g, X, dZ, part);
+    if (cip == 32 && cop == 32)
+        k_wgrad<32><<<gr, BLK, 0, st>>>(g, X, dZ, part);
     else if (cip == 32 && cop == 16)
-        k_wgrad<32, 16><<<gr, BLK, 0, st>>>(g, X, dZ, part);
+        k_wgrad<16><<<gr, BLK, 0, st>>>(g, X, dZ, part);
     else
         return hipErrorInvalidValue;
     k_wgrad_reduce<<<(27 * cip * cop + cop + BLK - 1) / BLK, BLK, 0, st>>>(part, gr, cip, cop, ci, co, grad);
