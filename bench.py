@@ -47,9 +47,8 @@ STATE_VALUES = 48  # f (19) and Q (5) read and written once
 # while the kernels are unchanged since those counters were taken.
 MEASURED_TRAFFIC = {
     ("fp32", "k_lb"): (261.3 + 184.5) * 1e6,       # profiles/step_unfused_128cubed.md
-    ("fp64", "k_lb"): (524.7 + 369.1) * 1e6,       # profiles/step_fp64_mixed_128cubed.md
-    ("fp64", "k_qupdate"): (160.7 + 83.9) * 1e6,   # profiles/step_fp64_mixed_128cubed.md
-    ("fp32", "k_qupdate"): (84.1 + 41.9) * 1e6,    # profiles/step_fp32_tiled_128cubed.md
+    ("fp64", "k_lb"): (524.5 + 369.1) * 1e6,       # profiles/step_fp64_mixed_128cubed.md
+    ("fp64", "k_qupdate"): (160.9 + 83.9) * 1e6,   # profiles/step_fp64_mixed_128cubed.md
 }
 
 
@@ -221,6 +220,13 @@ def run_surrogate(n=96, steps=20000, M=8, iters=1500):
     sur = S.new_solver(case)
     st = S.run(sur, net, steps, M=M)
     fz_sur = S.domain_profile(sur)
+    sweep = {}
+    for m in (16, 32):  # jumps per checked cycle
+        sv = S.new_solver(case)
+        sm = S.run(sv, net, steps, M=m)
+        sweep[str(m)] = {"seconds": sm.seconds, "speedup": t_plain / sm.seconds,
+                         "q_error_vs_plain": S.q_error(sv, plain), "fallbacks": sm.fallbacks, "cycles": sm.cycles}
+        del sv
     ex_net = hlb.Net((n, n, n))
     S.extrapolation_only(ex_net, 0.0)
     ext = S.new_solver(case)
@@ -237,8 +243,10 @@ def run_surrogate(n=96, steps=20000, M=8, iters=1500):
         "fz_max_dev_over_spread": float(np.abs(fz_sur - fz_plain).max() / spread) if spread > 0 else None,
         "domain_planes": {"plain": S.domain_size(fz_plain), "surrogate": S.domain_size(fz_sur)},
         "cycles": st.cycles, "fallbacks": st.fallbacks, "plain_cooldown_cycles": st.plain_cycles,
+        "fallback_steps": st.fallback_steps,
         "residual_median": float(np.median(st.residuals)) if st.residuals else None,
         "residual_max": float(np.max(st.residuals)) if st.residuals else None,
+        "m_sweep": sweep,
         "extrapolation_only": {"seconds": sx.seconds, "q_error_vs_plain": S.q_error(ext, plain),
                                "fallbacks": sx.fallbacks, "cycles": sx.cycles},
         "increment_error_heldout": evals,

@@ -17,9 +17,12 @@ from collections import defaultdict
 
 
 def short(name):
-    m = re.search(r"k_(conv|wgrad)<(\d+), (\d+)(, (\d+))?", name)
-    if m:  # keep the channel counts (and epilogue mode) of the surrogate kernels
-        return f"k_{m.group(1)}<{m.group(2)},{m.group(3)}" + (f",{m.group(5)}>" if m.group(5) else ">")
+    m = re.search(r"k_conv<(\d+), (\d+), (\d+)", name)
+    if m:  # keep the channel counts and epilogue mode of the convolutions
+        return f"k_conv<{m.group(1)},{m.group(2)},{m.group(3)}>"
+    m = re.search(r"k_wgrad<(\d+)>", name)
+    if m:  # weight gradient: 32 input channels, COP output channels
+        return f"k_wgrad<32,{m.group(1)}>"
     m = re.search(r"(k_\w+|__amd_rocclr_copyBuffer)", name)
     return m.group(1) if m else name[:40]
 

@@ -190,6 +190,7 @@ class RunStats:
     plain_cycles: int    # cycles taken with plain steps while cooling down
     residuals: list
     seconds: float
+    fallback_steps: list = field(default_factory=list)  # solver step at which each fallback cycle began
 
 
 def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64):
@@ -208,9 +209,10 @@ def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64)
     n_cyc = (steps - 2 * k) // cyc
     fb = plain = attempted = 0
     res = []
+    fb_at = []
     wait = 0
     penalty = 1
-    for _ in range(n_cyc):
+    for c in range(n_cyc):
         if wait > 0:
             # a plain cycle that leaves a valid history behind
             solver.step(cyc - 2 * k)
@@ -223,6 +225,7 @@ def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64)
         res.append(r)
         if f:
             fb += 1
+            fb_at.append(2 * k + c * cyc)
             wait = penalty
             penalty = min(2 * penalty, cooldown_max)
         else:
@@ -231,7 +234,7 @@ def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64)
     if rest:
         solver.step(rest)
     torch.cuda.synchronize()
-    return RunStats(steps, attempted, fb, plain, res, time.perf_counter() - t0)
+    return RunStats(steps, attempted, fb, plain, res, time.perf_counter() - t0, fb_at)
 
 
 def plain_run(solver, steps):
