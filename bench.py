@@ -117,9 +117,11 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0):
     return out
 
 
-def run_batched(steps, graph_steps=50):
+def run_batched(steps, graph_steps=50, chunk=0, xcd_local=True):
     """96 uneven periodic boxes (sizes 24/32/48/64, per-box kappa and tau) in
-    one persistent launch per graph replay, FP32.  Aggregate MLUPS."""
+    one persistent launch per graph replay, FP32.  Aggregate MLUPS.  With
+    `chunk` > 0 the autotuner is skipped and every box size uses that chunk
+    (profiling runs, where every dispatch must be `graph_steps` steps)."""
     import torch
 
     from paper_0901_3293_amd import hlb
@@ -131,7 +133,13 @@ def run_batched(steps, graph_steps=50):
     for i, r in enumerate(rs):
         b.set_params(i, r["params"])
         b.set_fields(i, r["Q"], r["u"], r["rho"])
-    chunks = b.autotune(3)
+    b.set_xcd_local(xcd_local)
+    if chunk > 0:
+        for L in sorted({r["L"] for r in rs}):
+            b.set_chunk(L ** 3, chunk)
+        chunks = {L ** 3: chunk for L in sorted({r["L"] for r in rs})}
+    else:
+        chunks = b.autotune(3)
     b.capture(graph_steps)
     b.launch()
     b.sync()
@@ -146,10 +154,11 @@ def run_batched(steps, graph_steps=50):
     ms = ev0.elapsed_time(ev1)
     sites = sum(L ** 3 for L in (r["L"] for r in rs))
     grid, items = b.info()
+    xcd_local = b.xcd_local()
     masses = [b.totals(i)[0] for i in range(len(rs))]
     out = {"mlups": sites * reps * graph_steps / (ms / 1e3) / 1e6, "boxes": len(rs), "sites": sites,
            "steps": reps * graph_steps, "ms_per_step": ms / (reps * graph_steps), "grid": grid,
-           "work_items": items, "chunk_by_box_sites": chunks,
+           "work_items": items, "xcd_local_barriers": xcd_local, "chunk_by_box_sites": chunks,
            "sizes": {str(L): sum(1 for r in rs if r["L"] == L) for L in (24, 32, 48, 64)},
            "finite": bool(all(math.isfinite(m) for m in masses))}
     b.close()
@@ -341,6 +350,11 @@ def main():
     ap.add_argument("--tz", type=int, default=0, help="planes per tile column for a fixed tiled/mixed schedule")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the 96-box batched FP32 run (0: skip)")
+    ap.add_argument("--batch-graph-steps", type=int, default=50, help="steps per batched graph replay")
+    ap.add_argument("--batch-chunk", type=int, default=0,
+                    help="fixed chunk for every box size instead of the autotuner (profiling runs)")
+    ap.add_argument("--batch-device-fences", action="store_true",
+                    help="batched run with the fixed work mapping and device-scope barrier fences")
     ap.add_argument("--surrogate-steps", type=int, default=20000,
                     help="steps of the 96^3 surrogate-vs-plain run (0: skip the surrogate leg)")
     ap.add_argument("--surrogate-m", type=int, default=8, help="jumps per checked surrogate cycle")
@@ -365,7 +379,7 @@ def main():
         del src, dst
     if a.only in ("batched", "surrogate", "network"):
         if a.only == "batched":
-            out = run_batched(a.batch_steps)
+            out = run_batched(a.batch_steps, a.batch_graph_steps, a.batch_chunk, not a.batch_device_fences)
         elif a.only == "network":
             out = run_network()
         else:

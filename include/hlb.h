@@ -196,6 +196,12 @@ int hlb_batch_set_chunk(hlb_batch *b, int sites_of_box, int chunk);
  * and keep the fastest; the states are put back afterwards (host copies).
  * Writes up to max_out (size, chunk) pairs; returns the number of sizes. */
 int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunks_out, int max_out);
+/* enable = 1 (default): keep each box on one XCD (boxes packed into 8 groups of
+ * about equal site count; the workgroups on XCD x take group x), so the phase
+ * barriers need not write the XCD's L2 back to memory.  enable = 0: groups
+ * follow blockIdx and every barrier uses device-scope fences.  Results are
+ * identical; drops a captured graph. */
+int hlb_batch_set_xcd_local(hlb_batch *b, int enable);
 /* Enqueue nsteps steps of every box as one persistent launch. */
 int hlb_batch_step(hlb_batch *b, int nsteps);
 /* Capture one persistent launch of nsteps steps into a HIP graph;
@@ -211,6 +217,12 @@ int hlb_batch_get_fields(hlb_batch *b, int i, double *Q5, double *u3, double *rh
 int hlb_batch_get_totals(hlb_batch *b, int i, double *mass, double *mom3, double *free_energy);
 /* Grid size of the persistent launch and number of work items. */
 int hlb_batch_info(const hlb_batch *b, int *grid, int *n_items);
+/* After a launch (synchronises): *local = 1 if the last launch kept every box
+ * on one XCD (workgroups take the group of the XCD they run on), so its phase
+ * barriers skipped the L2 write-back; 0 if some XCD got no workgroup and the
+ * launch fell back to a fixed mapping with device-scope fences.  Results are
+ * identical either way. */
+int hlb_batch_xcd_local(hlb_batch *b, int *local);
 const char *hlb_batch_last_error(const hlb_batch *b);
 void hlb_batch_destroy(hlb_batch *b);
 

@@ -20,10 +20,16 @@ void batch_pack_reps(bool fp32, const std::vector<Device> &box, const std::vecto
 // compute unit (0: as many as fit).
 hipError_t batch_grid(bool fp32, int n_items, int blocks_per_cu, int *grid);
 
-// Enqueue: reset the barrier counter (a one-block kernel, so the pair can be
-// captured in a graph) and run the persistent kernel for nsteps steps.
-// d_items holds int4 {box, first site, site count, 0} per work item.
-hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items, int n_items, unsigned *d_bar,
-                        int *d_err, int nsteps, int grid, hipStream_t stream);
+// Enqueue: reset the barrier counter and flags (a one-block kernel, so the
+// pair can be captured in a graph) and run the persistent kernel for nsteps
+// steps.  d_items holds int4 {box, first site, site count, 0} per work item,
+// grouped by XCD: group x is items [d_xlo[x], d_xlo[x + 1]), and every box
+// lies in one group; the workgroups running on XCD x take group x.  d_xcnt:
+// 8 ints of scratch (workgroups per XCD).  d_misplaced: flag set when some XCD
+// got no workgroup or allow_local is false; that launch then maps groups to
+// blockIdx and uses device-scope fences throughout.
+hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items, const int *d_xlo, unsigned *d_bar,
+                        int *d_err, int *d_misplaced, int *d_xcnt, bool allow_local, int nsteps, int grid,
+                        hipStream_t stream);
 
 }  // namespace hlb

@@ -2,9 +2,12 @@
 // parameters, advanced by ONE persistent kernel launch per call.
 //
 // Work list: every box is cut into chunks of `chunk` consecutive sites; the
-// chunks of all boxes form one list, split into 8 contiguous segments, one
-// per XCD (workgroups reach the XCDs round-robin), and the blocks of an XCD
-// take the items of its segment in turn.  One step is four phases over the
+// boxes are packed into 8 groups of about equal site count, one per XCD.  At
+// the start of a launch every workgroup reads the XCD it runs on and draws a
+// rank among the workgroups of that XCD; the workgroups of an XCD then take
+// the items of its group in turn, so each box is read and written by one XCD
+// only (if some XCD got no workgroup, the launch falls back to a fixed
+// blockIdx mapping and device-scope fences).  One step is four phases over the
 // list (stress, LB, predictor, corrector -- the per-site device functions of
 // sitekern.h), separated by grid barriers.  The grid never exceeds the number
 // of co-resident blocks; every barrier wait is bounded so that a stall ends
@@ -37,12 +40,20 @@ struct Rep {
 // cache invalidation per block, shared by the CU's waves) so the next phase
 // reads what other XCDs wrote.  Returns false (in every thread of the block)
 // if the wait ran out or another block failed.
-__device__ __forceinline__ bool grid_sync(unsigned *bar, int *err, unsigned &target, unsigned spin_limit)
+//
+// With `local` (every block runs on the XCD its work-list group belongs to,
+// checked at the start of the launch) a phase's results only have to reach
+// the L2 of their own XCD, which all its CUs share: each wave waits until its
+// own stores are acknowledged (by that L2) before the workgroup barrier, and
+// the L2 write-back of the device-scope release is skipped.  The acquire
+// stays at device scope: it is what is sure to drop the CU's stale L1 lines.
+__device__ __forceinline__ bool grid_sync(unsigned *bar, int *err, unsigned &target, unsigned spin_limit, bool local)
 {
+    if (local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached L2
     __syncthreads();
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         target += gridDim.x;
         atomicAdd(bar, 1u);
         int ok = 1;
@@ -60,6 +71,14 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, int *err, unsigned &tar
     }
     __syncthreads();
     return s_ok != 0;
+}
+
+// Hardware XCD (XCC) of the executing workgroup.
+__device__ __forceinline__ int xcc_id()
+{
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
+    return int(v);
 }
 
 enum Phase { PH_STRESS, PH_LB, PH_PRED, PH_CORR };
@@ -103,16 +122,14 @@ __device__ __forceinline__ Coef<T> uni(const Coef<T> &c)
     return r;
 }
 
+// The items [lo, hi) of this block's group, taken by its `per` blocks in
+// turn starting at `rank`.
 template <typename T, int PH>
-__device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 *__restrict__ items,
-                                          int n_items, int step)
+__device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 *__restrict__ items, int lo, int hi,
+                                          int rank, int per, int step)
 {
-    const int per = gridDim.x >> 3;
-    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
-    const int seg = (n_items + 7) >> 3;
-    const int lo = xcd * seg, hi = min(n_items, lo + seg);
 #pragma unroll 1
-    for (int it = lo + local; it < hi; it += per) {
+    for (int it = lo + rank; it < hi; it += per) {
         const int4 w4 = items[it];
         const int box = uni(w4.x), first = uni(w4.y), count = uni(w4.z);
         const Rep<T> &R = reps[box];
@@ -142,19 +159,40 @@ __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 
 
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, int n_reps, const int4 *__restrict__ items,
-                                               int n_items, unsigned *bar, int *err, int nsteps,
-                                               unsigned spin_limit)
+                                               const int *__restrict__ xlo, unsigned *bar, int *err, int *misplaced,
+                                               int *xcnt, int allow_local, int nsteps, unsigned spin_limit)
 {
     unsigned target = 0;
+    // Rank of this block among the blocks of its XCD; after one full barrier
+    // every block sees the same per-XCD counts and takes the same decision.
+    __shared__ int s_rank;
+    const int xcd = xcc_id();
+    if (threadIdx.x == 0) s_rank = xcd < 8 ? atomicAdd(&xcnt[xcd], 1) : (atomicOr(misplaced, 1), 0);
+    if (!grid_sync(bar, err, target, spin_limit, false)) return;
+    bool local = allow_local && __hip_atomic_load(misplaced, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    for (int x = 0; x < 8; ++x)
+        if (__hip_atomic_load(&xcnt[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) local = false;
+    int grp, rank, per;
+    if (local) {
+        grp = xcd;
+        rank = s_rank;
+        per = __hip_atomic_load(&xcnt[xcd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        grp = blockIdx.x & 7;
+        rank = blockIdx.x >> 3;
+        per = gridDim.x >> 3;
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(misplaced, 1);  // report the fallback
+    }
+    const int lo = xlo[grp], hi = xlo[grp + 1];
     for (int n = 0; n < nsteps; ++n) {
-        run_phase<T, PH_STRESS>(reps, items, n_items, n);
-        if (!grid_sync(bar, err, target, spin_limit)) return;
-        run_phase<T, PH_LB>(reps, items, n_items, n);
-        if (!grid_sync(bar, err, target, spin_limit)) return;
-        run_phase<T, PH_PRED>(reps, items, n_items, n);
-        if (!grid_sync(bar, err, target, spin_limit)) return;
-        run_phase<T, PH_CORR>(reps, items, n_items, n);
-        if (!grid_sync(bar, err, target, spin_limit)) return;
+        run_phase<T, PH_STRESS>(reps, items, lo, hi, rank, per, n);
+        if (!grid_sync(bar, err, target, spin_limit, local)) return;
+        run_phase<T, PH_LB>(reps, items, lo, hi, rank, per, n);
+        if (!grid_sync(bar, err, target, spin_limit, local)) return;
+        run_phase<T, PH_PRED>(reps, items, lo, hi, rank, per, n);
+        if (!grid_sync(bar, err, target, spin_limit, local)) return;
+        run_phase<T, PH_CORR>(reps, items, lo, hi, rank, per, n);
+        if (!grid_sync(bar, err, target, spin_limit, local)) return;
     }
     // every block has read gcur before the last barrier: advance it once
     if (blockIdx.x == 0 && (nsteps & 1))
@@ -162,12 +200,14 @@ __global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, int n_
             if (reps[r].flow) reps[r].gcur ^= 1;
 }
 
-__global__ void k_batch_reset(unsigned *bar, int *err)
+__global__ void k_batch_reset(unsigned *bar, int *err, int *misplaced, int *xcnt)
 {
     if (threadIdx.x == 0) {
         *bar = 0u;
         *err = 0;
+        *misplaced = 0;
     }
+    if (threadIdx.x < 8) xcnt[threadIdx.x] = 0;
 }
 
 template <typename T>
@@ -223,18 +263,21 @@ hipError_t batch_grid(bool fp32, int n_items, int blocks_per_cu, int *grid)
     return hipSuccess;
 }
 
-hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items, int n_items, unsigned *d_bar,
-                        int *d_err, int nsteps, int grid, hipStream_t stream)
+hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items, const int *d_xlo, unsigned *d_bar,
+                        int *d_err, int *d_misplaced, int *d_xcnt, bool allow_local, int nsteps, int grid,
+                        hipStream_t stream)
 {
     const unsigned spin_limit = 1u << 24;  // ~1 s of polling per barrier
-    k_batch_reset<<<1, 64, 0, stream>>>(d_bar, d_err);
+    k_batch_reset<<<1, 64, 0, stream>>>(d_bar, d_err, d_misplaced, d_xcnt);
     const int4 *items = reinterpret_cast<const int4 *>(d_items);
     if (fp32)
-        k_batch<float><<<grid, BLK, 0, stream>>>(static_cast<Rep<float> *>(d_reps), n_reps, items, n_items, d_bar,
-                                                 d_err, nsteps, spin_limit);
+        k_batch<float><<<grid, BLK, 0, stream>>>(static_cast<Rep<float> *>(d_reps), n_reps, items, d_xlo, d_bar,
+                                                 d_err, d_misplaced, d_xcnt, int(allow_local), nsteps,
+                                                 spin_limit);
     else
-        k_batch<double><<<grid, BLK, 0, stream>>>(static_cast<Rep<double> *>(d_reps), n_reps, items, n_items,
-                                                  d_bar, d_err, nsteps, spin_limit);
+        k_batch<double><<<grid, BLK, 0, stream>>>(static_cast<Rep<double> *>(d_reps), n_reps, items, d_xlo, d_bar,
+                                                  d_err, d_misplaced, d_xcnt, int(allow_local), nsteps,
+                                                 spin_limit);
     return hipGetLastError();
 }
 

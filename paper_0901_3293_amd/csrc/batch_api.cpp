@@ -31,8 +31,13 @@ struct hlb_batch {
     int n_items;
     unsigned *d_bar;
     int *d_err;
+    int *d_misplaced;
+    int *d_xlo;     // item offsets of the 8 XCD groups (9 ints)
+    int *d_xcnt;    // workgroups per XCD of the running launch (8 ints)
+    int xlo[9];
     int grid;
     int bpc;                         // blocks per compute unit of the persistent grid (0: max)
+    bool xcd_local = true;           // keep each box on one XCD when the launch allows it
     bool dirty;                      // descriptor table / work list must be rebuilt
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -110,20 +115,41 @@ int rebuild(hlb_batch *b)
             return bset_error(b, HLB_ERR_STATE, "box %d has no parameters or fields", i);
     std::vector<char> blob;
     hlb::batch_pack_reps(b->fp32, b->box, b->par, b->gcur, blob);
+    // boxes -> 8 XCD groups of about equal site count (largest box first to
+    // the lightest group), each box whole in one group
+    std::vector<int> order(b->n);
+    for (int i = 0; i < b->n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->box[x].G.N > b->box[y].G.N; });
+    std::vector<int> group(b->n);
+    long long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i : order) {
+        int g = 0;
+        for (int k = 1; k < 8; ++k)
+            if (load[k] < load[g]) g = k;
+        group[i] = g;
+        load[g] += b->box[i].G.N;
+    }
     std::vector<int> items;
-    for (int i = 0; i < b->n; ++i) {
-        const int N = b->box[i].G.N, ch = chunk_for(b, N);
-        for (int s = 0; s < N; s += ch) {
-            items.push_back(i);
-            items.push_back(s);
-            items.push_back(std::min(ch, N - s));
-            items.push_back(0);
+    for (int g = 0; g < 8; ++g) {
+        b->xlo[g] = int(items.size() / 4);
+        for (int i = 0; i < b->n; ++i) {
+            if (group[i] != g) continue;
+            const int N = b->box[i].G.N, ch = chunk_for(b, N);
+            for (int s = 0; s < N; s += ch) {
+                items.push_back(i);
+                items.push_back(s);
+                items.push_back(std::min(ch, N - s));
+                items.push_back(0);
+            }
         }
     }
     b->n_items = int(items.size() / 4);
+    b->xlo[8] = b->n_items;
     if (size_t(b->n_items) > b->items_cap) return bset_error(b, HLB_ERR_ARG, "work list overflow");
     B_TRY(b, hipMemcpyAsync(b->d_reps, blob.data(), blob.size(), hipMemcpyHostToDevice, b->stream));
     B_TRY(b, hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    B_TRY(b, hipMemcpyAsync(b->d_xlo, b->xlo, sizeof(b->xlo), hipMemcpyHostToDevice, b->stream));
     B_TRY(b, hipStreamSynchronize(b->stream));
     B_TRY(b, hlb::batch_grid(b->fp32, b->n_items, b->bpc, &b->grid));
     b->dirty = false;
@@ -200,6 +226,9 @@ int hlb_batch_create(int n, const int *dims, int precision, void *ws, size_t ws_
     p += align256(b->items_cap * 16);
     b->d_bar = reinterpret_cast<unsigned *>(p);
     b->d_err = reinterpret_cast<int *>(p + 64);
+    b->d_misplaced = reinterpret_cast<int *>(p + 128);
+    b->d_xlo = reinterpret_cast<int *>(p + 160);   // 9 ints
+    b->d_xcnt = reinterpret_cast<int *>(p + 224);  // 8 ints
     p += 256;
     size_t part_max = 0;
     for (int i = 0; i < n; ++i) {
@@ -284,6 +313,14 @@ int hlb_batch_set_chunk(hlb_batch *b, int sites_of_box, int chunk)
     return HLB_OK;
 }
 
+int hlb_batch_set_xcd_local(hlb_batch *b, int enable)
+{
+    B_GUARD(b);
+    b->xcd_local = enable != 0;
+    drop_graph(b);
+    return HLB_OK;
+}
+
 int hlb_batch_step(hlb_batch *b, int nsteps)
 {
     B_GUARD(b);
@@ -293,8 +330,8 @@ int hlb_batch_step(hlb_batch *b, int nsteps)
         if (rc) return rc;
     }
     if (nsteps == 0) return HLB_OK;
-    B_TRY(b, hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->n_items, b->d_bar, b->d_err, nsteps,
-                               b->grid, b->stream));
+    B_TRY(b, hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err, b->d_misplaced,
+                               b->d_xcnt, b->xcd_local, nsteps, b->grid, b->stream));
     advance_host_gcur(b, nsteps);
     return HLB_OK;
 }
@@ -310,8 +347,8 @@ int hlb_batch_capture(hlb_batch *b, int nsteps)
     }
     drop_graph(b);
     B_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->n_items, b->d_bar, b->d_err, nsteps,
-                                     b->grid, b->stream);
+    hipError_t e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err,
+                                     b->d_misplaced, b->d_xcnt, b->xcd_local, nsteps, b->grid, b->stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -384,13 +421,13 @@ int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunk
             else
                 b->chunk_of_n[N] = ch;
             if ((rc = rebuild(b))) break;
-            hipError_t e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->n_items, b->d_bar, b->d_err, 1,
-                                             b->grid, b->stream);
+            hipError_t e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err,
+                                             b->d_misplaced, b->d_xcnt, b->xcd_local, 1, b->grid, b->stream);
             advance_host_gcur(b, 1);
             if (e == hipSuccess) e = hipEventRecord(ea, b->stream);
             if (e == hipSuccess)
-                e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->n_items, b->d_bar, b->d_err,
-                                      trial_steps, b->grid, b->stream);
+                e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err,
+                                      b->d_misplaced, b->d_xcnt, b->xcd_local, trial_steps, b->grid, b->stream);
             advance_host_gcur(b, trial_steps);
             if (e == hipSuccess) e = hipEventRecord(eb, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(eb);
@@ -481,6 +518,17 @@ int hlb_batch_info(const hlb_batch *b, int *grid, int *n_items)
     if (!b) return HLB_ERR_ARG;
     if (grid) *grid = b->grid;
     if (n_items) *n_items = b->n_items;
+    return HLB_OK;
+}
+
+int hlb_batch_xcd_local(hlb_batch *b, int *local)
+{
+    B_GUARD(b);
+    if (!local) return bset_error(b, HLB_ERR_ARG, "null argument");
+    int mis = 1;
+    B_TRY(b, hipMemcpyAsync(&mis, b->d_misplaced, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    B_TRY(b, hipStreamSynchronize(b->stream));
+    *local = mis == 0 ? 1 : 0;
     return HLB_OK;
 }
 

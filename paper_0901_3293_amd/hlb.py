@@ -82,6 +82,7 @@ def lib():
                                            ctypes.POINTER(BeParams)]
         L.hlb_batch_set_fields.argtypes = [vp, I, dp, dp, dp]
         L.hlb_batch_set_chunk.argtypes = [vp, I, I]
+        L.hlb_batch_set_xcd_local.argtypes = [vp, I]
         L.hlb_batch_autotune.argtypes = [vp, I, ip, ip, I]
         L.hlb_batch_step.argtypes = [vp, I]
         L.hlb_batch_capture.argtypes = [vp, I]
@@ -90,6 +91,7 @@ def lib():
         L.hlb_batch_get_fields.argtypes = [vp, I, dp, dp, dp]
         L.hlb_batch_get_totals.argtypes = [vp, I, dp, dp, dp]
         L.hlb_batch_info.argtypes = [vp, ip, ip]
+        L.hlb_batch_xcd_local.argtypes = [vp, ip]
         L.hlb_batch_last_error.argtypes = [vp]
         L.hlb_batch_last_error.restype = ctypes.c_char_p
         L.hlb_batch_destroy.argtypes = [vp]
@@ -292,6 +294,9 @@ class Batch:
     def set_chunk(self, sites_of_box, chunk):
         self._check(lib().hlb_batch_set_chunk(self.b, int(sites_of_box), int(chunk)))
 
+    def set_xcd_local(self, enable=True):
+        self._check(lib().hlb_batch_set_xcd_local(self.b, int(bool(enable))))
+
     def autotune(self, trial_steps=3):
         """{box size in sites: chosen chunk}; the states are left as they were."""
         n = 64
@@ -316,6 +321,12 @@ class Batch:
         g, n = ctypes.c_int(), ctypes.c_int()
         self._check(lib().hlb_batch_info(self.b, ctypes.byref(g), ctypes.byref(n)))
         return g.value, n.value
+
+    def xcd_local(self):
+        """Whether the last launch kept its phase barriers XCD-local."""
+        v = ctypes.c_int()
+        self._check(lib().hlb_batch_xcd_local(self.b, ctypes.byref(v)))
+        return bool(v.value)
 
     def fields(self, i):
         nx, ny, nz = self.shapes[i]

@@ -51,15 +51,22 @@ def make_batch(H, prec, rs):
     return b
 
 
+@pytest.mark.parametrize("local", [True, False])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_matches_single_boxes(H, prec):
-    say("case: batch vs single", prec)
+def test_batch_matches_single_boxes(H, prec, local):
+    """Both barrier modes: boxes kept on one XCD (XCD-scope release) and the
+    fixed mapping with device-scope fences."""
+    say("case: batch vs single", prec, "xcd-local allowed", local)
     rs = small_set()
     b = make_batch(H, prec, rs)
     b.set_chunk(8 ** 3, 256)
+    b.set_xcd_local(local)
     b.step(7)
     b.step(6)
-    say("grid, items:", b.info())
+    went_local = b.xcd_local()
+    say("grid, items:", b.info(), "xcd-local barriers:", went_local)
+    if not local:
+        assert not went_local
     for i, r in enumerate(rs):
         got = b.fields(i)
         ref = single(H, prec, r, 13)
