@@ -51,9 +51,16 @@ class Params(ctypes.Structure):
     ]
 
 
+def flow_code(flow=True, coupling="force") -> int:
+    """0: u == 0; 1: whole stress as a body force; 2: split coupling."""
+    if coupling not in ("force", "split"):
+        raise ValueError(f"coupling {coupling!r}")
+    return 0 if not flow else (2 if coupling == "split" else 1)
+
+
 def params(tau=2.5, rho0=1.0, A0=0.01, gamma=3.0, K=0.0, q0=0.0, Gamma=0.3, xi=0.7,
-           flow=True) -> Params:
-    return Params(tau, rho0, A0, gamma, K, q0, Gamma, xi, 1 if flow else 0)
+           flow=True, coupling="force") -> Params:
+    return Params(tau, rho0, A0, gamma, K, q0, Gamma, xi, flow_code(flow, coupling))
 
 
 _lib = None
@@ -76,6 +83,8 @@ def lib():
         L.or_rhs.argtypes = [pp, I, I, I, dp, dp, dp]
         L.or_qupdate.argtypes = [pp, I, I, I, dp, dp, dp]
         L.or_lb.argtypes = [pp, I, I, I, dp, dp, dp, dp, dp]
+        L.or_split.argtypes = [pp, I, I, I, dp, dp, dp]
+        L.or_lb_split.argtypes = [pp, I, I, I, dp, dp, dp, dp, dp, dp]
         L.or_init_g.argtypes = [pp, I, I, I, dp, dp, dp]
         L.or_readout.argtypes = [pp, I, I, I, dp, dp, dp, dp]
         L.or_step.argtypes = [pp, I, I, I, dp, dp, I]
@@ -138,6 +147,16 @@ def force(p: Params, Q9):
     return F
 
 
+def split(p: Params, Q9):
+    """Split coupling: (sigma^xi (9 planes), body force b (3))."""
+    Q9 = np.ascontiguousarray(Q9, dtype=np.float64)
+    nx, ny, nz = _shape(Q9)
+    sig = np.empty_like(Q9)
+    b = np.empty((3,) + Q9.shape[1:])
+    lib().or_split(ctypes.byref(p), nx, ny, nz, _p(Q9), _p(sig), _p(b))
+    return sig, b
+
+
 def rhs(p: Params, Q9, u3):
     Q9 = np.ascontiguousarray(Q9, dtype=np.float64)
     u3 = np.ascontiguousarray(u3, dtype=np.float64)
@@ -166,6 +185,19 @@ def lb(p: Params, g, F3=None):
     rho = np.empty(g.shape[1:])
     u = np.empty((3,) + g.shape[1:])
     lib().or_lb(ctypes.byref(p), nx, ny, nz, _p(g), _p(F3), _p(gn), _p(rho), _p(u))
+    return gn, rho, u
+
+
+def lb_split(p: Params, g, b3, sig9):
+    """LB step of the split coupling (body force b3, equilibrium stress sig9)."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    b3 = np.ascontiguousarray(b3, dtype=np.float64)
+    sig9 = np.ascontiguousarray(sig9, dtype=np.float64)
+    nx, ny, nz = _shape(g)
+    gn = np.empty_like(g)
+    rho = np.empty(g.shape[1:])
+    u = np.empty((3,) + g.shape[1:])
+    lib().or_lb_split(ctypes.byref(p), nx, ny, nz, _p(g), _p(b3), _p(sig9), _p(gn), _p(rho), _p(u))
     return gn, rho, u
 
 

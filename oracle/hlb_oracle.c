@@ -25,6 +25,11 @@
  *   body force b_a = d_b Pi_ab ... Sec. 2.2, Eq. (19): the whole chemical
  *                                  stress enters as a force (centred
  *                                  divergence on the second index)
+ *   split coupling ............... Sec. 2.2, Eqs. (17)-(21): the symmetric
+ *                                  xi-stress enters the second moment of the
+ *                                  equilibrium, the body force is the
+ *                                  divergence of the antisymmetric stress
+ *                                  minus H : grad Q
  *   moments ...................... Sec. 2.2, Eq. (14), velocity with +F/2
  *   BGK collision + forcing ...... Sec. 2.2, Eq. (16), on D3Q19 with the
  *                                  second-order (Guo) forcing term
@@ -51,7 +56,8 @@ typedef struct {
     double q0;     /* 2 pi / pitch, Eq. (1)                               */
     double Gamma;  /* collective rotational diffusion constant, Eq. (2)   */
     double xi;     /* flow-aligning parameter, Eqs. (4), (7)              */
-    int flow;      /* 1: hydrodynamics coupled; 0: u == 0 (Sec. 2.1)     */
+    int flow;      /* 0: u == 0 (Sec. 2.1); 1: coupled, whole stress as a
+                    * body force; 2: coupled, split coupling (Sec. 2.2)  */
 } or_params;
 
 /* ------------------------------------------------------------------------ */
@@ -329,6 +335,79 @@ void or_force(const or_params *p, int nx, int ny, int nz, const double *Q9, doub
     free(Pi9);
 }
 
+/* Split coupling, Sec. 2.2.  The stress of Eqs. (6)-(8) is divided as
+ *   sigma^xi_ab = 2 xi A_ab (Q:H) - xi (H A)_ab - xi (A H)_ab   (A = Q + I/3),
+ *   tau_ab      = (Q H - H Q)_ab,
+ * and the remaining gradient and free-energy terms; by the identity of
+ * Eq. (21) the divergence of the remainder equals -H_gn d_a Q_gn.  The
+ * symmetric sigma^xi is carried by the second moment of the equilibrium
+ * (Eq. (17)); the body force of Eq. (19) becomes
+ *   b_a = d_b tau_ab - H_gn d_a Q_gn
+ * with the divergence taken centred on the second index, as for the whole
+ * stress.  sig9 (9 planes) may be NULL. */
+void or_split(const or_params *p, int nx, int ny, int nz, const double *Q9, double *sig9, double *b3)
+{
+    long N = (long)nx * ny * nz;
+    double *tau9 = (double *)malloc(sizeof(double) * 9 * N);
+    double *h3 = (double *)malloc(sizeof(double) * 3 * N);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; z++)
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++) {
+                double Q[3][3], dQ[3][3][3], lap[3][3], H[3][3], A[3][3], HA[3][3], AH[3][3], QH[3][3],
+                    HQ[3][3];
+                long s = site(x, y, z, nx, ny, nz);
+                derivs(Q9, nx, ny, nz, x, y, z, Q, dQ, lap);
+                molecular_field(p, Q, dQ, lap, H);
+                for (int a = 0; a < 3; a++)
+                    for (int b = 0; b < 3; b++) A[a][b] = Q[a][b] + (a == b ? 1.0 / 3.0 : 0.0);
+                matmul(H, A, HA);
+                matmul(A, H, AH);
+                matmul(Q, H, QH);
+                matmul(H, Q, HQ);
+                double QdH = ddot(Q, H);
+                for (int a = 0; a < 3; a++)
+                    for (int b = 0; b < 3; b++) {
+                        if (sig9)
+                            sig9[(3 * a + b) * N + s] =
+                                2.0 * p->xi * A[a][b] * QdH - p->xi * HA[a][b] - p->xi * AH[a][b];
+                        tau9[(3 * a + b) * N + s] = QH[a][b] - HQ[a][b];
+                    }
+                for (int a = 0; a < 3; a++) h3[a * N + s] = -ddot(H, dQ[a]);
+            }
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; z++)
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++) {
+                long s = site(x, y, z, nx, ny, nz);
+                long sp[3] = {site(x + 1, y, z, nx, ny, nz), site(x, y + 1, z, nx, ny, nz),
+                              site(x, y, z + 1, nx, ny, nz)};
+                long sm[3] = {site(x - 1, y, z, nx, ny, nz), site(x, y - 1, z, nx, ny, nz),
+                              site(x, y, z - 1, nx, ny, nz)};
+                for (int a = 0; a < 3; a++) {
+                    double d = 0.0;
+                    for (int b = 0; b < 3; b++) {
+                        const double *T = tau9 + (3 * a + b) * N;
+                        d += 0.5 * (T[sp[b]] - T[sm[b]]);
+                    }
+                    b3[a * N + s] = d + h3[a * N + s];
+                }
+            }
+    free(tau9);
+    free(h3);
+}
+
+/* The force the LB step takes for this coupling: the centred divergence of
+ * the whole stress (flow = 1) or the split body force b (flow = 2). */
+static void coupling_force(const or_params *p, int nx, int ny, int nz, const double *Q9, double *sig9,
+                           double *F3)
+{
+    if (p->flow == 2)
+        or_split(p, nx, ny, nz, Q9, sig9, F3);
+    else
+        or_force(p, nx, ny, nz, Q9, F3);
+}
+
 /* Right-hand side of the Q equation, Eqs. (2)-(4):
  *   dQ/dt = -u.grad Q + S(W,Q) + Gamma H,   W_ab = d_b u_a (centred),
  * projected on symmetric traceless tensors, P_T(X) = sym(X) - tr(X)/3 I. */
@@ -424,6 +503,17 @@ static double geq(int i, double rho0, double rho, const double u[3])
     return w * (rho - rho0) + w * rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
 }
 
+/* Stress part of the equilibrium in the split coupling: the Hermite term
+ * whose second moment is -sigma and whose zeroth and first moments vanish,
+ *   -(9/2) w_i [sigma_ab e_ia e_ib - tr(sigma)/3]   (c_s^2 = 1/3). */
+static double geq_stress(int i, const double sig[3][3])
+{
+    double see = 0.0;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) see += sig[a][b] * E[i][a] * E[i][b];
+    return -4.5 * weight(i) * (see - (sig[0][0] + sig[1][1] + sig[2][2]) / 3.0);
+}
+
 /* Pull the populations arriving at x: g~_i(x) = g_i(x - e_i). */
 static void pull(const double *g, long N, int nx, int ny, int nz, int x, int y, int z,
                  double gt[19])
@@ -435,9 +525,11 @@ static void pull(const double *g, long N, int nx, int ny, int nz, int x, int y, 
 /* One LB step (pull stream, BGK collide, forcing), Eqs. (14), (16):
  *   rho = rho0 + sum g~,  rho u = sum g~ e + F/2,
  *   g' = g~ - (g~ - g^eq)/tau + (1 - 1/(2 tau)) w [3(e - u) + 9 (e.u) e].F
- * Outputs rho and u (may be NULL) are the moments used in the collision. */
-void or_lb(const or_params *p, int nx, int ny, int nz, const double *g_in,
-           const double *F3, double *g_out, double *rho_out, double *u3_out)
+ * with, when sig9 is given (split coupling), the stress term of geq_stress
+ * added to g^eq.  Outputs rho and u (may be NULL) are the moments used in
+ * the collision. */
+static void lb_step(const or_params *p, int nx, int ny, int nz, const double *g_in, const double *F3,
+                    const double *sig9, double *g_out, double *rho_out, double *u3_out)
 {
     long N = (long)nx * ny * nz;
 #pragma omp parallel for schedule(static)
@@ -455,6 +547,9 @@ void or_lb(const or_params *p, int nx, int ny, int nz, const double *g_in,
                 double rho = p->rho0 + drho;
                 for (int a = 0; a < 3; a++) u[a] = (j[a] + 0.5 * F[a]) / rho;
                 double pref = 1.0 - 0.5 / p->tau;
+                double sig[3][3];
+                if (sig9)
+                    for (int a = 0; a < 9; a++) sig[a / 3][a % 3] = sig9[a * N + s];
                 for (int i = 0; i < 19; i++) {
                     double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
                     double src = 0.0;
@@ -462,12 +557,27 @@ void or_lb(const or_params *p, int nx, int ny, int nz, const double *g_in,
                         src += (3.0 * (E[i][a] - u[a]) + 9.0 * eu * E[i][a]) * F[a];
                     double Fi = pref * weight(i) * src;
                     double eq = geq(i, p->rho0, rho, u);
+                    if (sig9) eq += geq_stress(i, sig);
                     g_out[i * N + s] = gt[i] - (gt[i] - eq) / p->tau + Fi;
                 }
                 if (rho_out) rho_out[s] = rho;
                 if (u3_out)
                     for (int a = 0; a < 3; a++) u3_out[a * N + s] = u[a];
             }
+}
+
+void or_lb(const or_params *p, int nx, int ny, int nz, const double *g_in, const double *F3, double *g_out,
+           double *rho_out, double *u3_out)
+{
+    lb_step(p, nx, ny, nz, g_in, F3, NULL, g_out, rho_out, u3_out);
+}
+
+/* The LB step of the split coupling: body force b3 and the symmetric stress
+ * sig9 (9 planes) in the equilibrium. */
+void or_lb_split(const or_params *p, int nx, int ny, int nz, const double *g_in, const double *b3,
+                 const double *sig9, double *g_out, double *rho_out, double *u3_out)
+{
+    lb_step(p, nx, ny, nz, g_in, b3, sig9, g_out, rho_out, u3_out);
 }
 
 /* Populations stored so that the first pull returns g^eq(rho(x), u(x)) at
@@ -496,7 +606,7 @@ void or_readout(const or_params *p, int nx, int ny, int nz, const double *g,
 {
     long N = (long)nx * ny * nz;
     double *F3 = (double *)calloc(3 * N, sizeof(double));
-    if (p->flow) or_force(p, nx, ny, nz, Q9, F3);
+    if (p->flow) coupling_force(p, nx, ny, nz, Q9, NULL, F3);
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; z++)
         for (int y = 0; y < ny; y++)
@@ -517,25 +627,28 @@ void or_readout(const or_params *p, int nx, int ny, int nz, const double *g,
 }
 
 /* One coupled step per iteration (Sec. 2.2):
- *   F^n = div Pi(Q^n); LB step -> g_n, u^n; Q^{n+1} = Heun(Q^n, u^n).
+ *   F^n = div Pi(Q^n) (or b^n and sigma^xi(Q^n) in the split coupling);
+ *   LB step -> g_n, u^n; Q^{n+1} = Heun(Q^n, u^n).
  * With flow off, u == 0 and the populations are left untouched. */
 void or_step(const or_params *p, int nx, int ny, int nz, double *g, double *Q9, int nsteps)
 {
     long N = (long)nx * ny * nz;
     double *F3 = (double *)malloc(sizeof(double) * 3 * N);
+    double *sig9 = p->flow == 2 ? (double *)malloc(sizeof(double) * 9 * N) : NULL;
     double *u3 = (double *)calloc(3 * N, sizeof(double));
     double *g2 = (double *)malloc(sizeof(double) * 19 * N);
     double *Qn = (double *)malloc(sizeof(double) * 9 * N);
     for (int n = 0; n < nsteps; n++) {
         if (p->flow) {
-            or_force(p, nx, ny, nz, Q9, F3);
-            or_lb(p, nx, ny, nz, g, F3, g2, NULL, u3);
+            coupling_force(p, nx, ny, nz, Q9, sig9, F3);
+            lb_step(p, nx, ny, nz, g, F3, sig9, g2, NULL, u3);
             memcpy(g, g2, sizeof(double) * 19 * N);
         }
         or_qupdate(p, nx, ny, nz, Q9, u3, Qn);
         memcpy(Q9, Qn, sizeof(double) * 9 * N);
     }
     free(F3);
+    free(sig9);
     free(u3);
     free(g2);
     free(Qn);

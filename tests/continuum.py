@@ -110,3 +110,22 @@ def body_force(Q5, A0, gamma, K, q0, xi):
         for b in range(3):
             F[a] += spectral_d(T[a, b], b)
     return F
+
+
+def split_terms(Q5, A0, gamma, K, q0, xi):
+    """Continuum split coupling (Eqs. (17)-(21)): the symmetric xi-stress
+    sigma^xi (full 3x3 per point) and the body force
+    b_a = d_b tau_ab - H:d_a Q."""
+    Q, dQ, H = molecular_field(Q5, A0, gamma, K, q0)
+    I = np.eye(3).reshape(3, 3, *([1] * (Q.ndim - 2)))
+    A = Q + I / 3.0
+    mm = lambda X, Y: np.einsum("ac...,cb...->ab...", X, Y)
+    QH = np.einsum("ab...,ab...->...", Q, H)
+    sig = 2 * xi * A * QH - xi * mm(H, A) - xi * mm(A, H)
+    tau = mm(Q, H) - mm(H, Q)
+    b = np.zeros((3,) + Q.shape[2:])
+    for a in range(3):
+        b[a] = -np.einsum("gn...,gn...->...", H, dQ[a])
+        for c in range(3):
+            b[a] += spectral_d(tau[a, c], c)
+    return sig, b
