@@ -40,6 +40,11 @@ KERNEL_VALUES = {
     "k_lbf": (19 + 3) + (19 + 3),  # g, F -> g', u
     "k_qupdate": (5 + 3) + 5,     # Q, u -> Q'
 }
+# split coupling: the stress sweep writes sigma^xi (6), tau (3) and h (3)
+SPLIT_VALUES = {
+    "k_stress": 5 + 12,            # Q -> sigma, tau, h
+    "k_lb": (19 + 12) + (19 + 3),  # g, sigma, tau, h -> g', u
+}
 STATE_VALUES = 48  # f (19) and Q (5) read and written once
 
 # HBM bytes per launch of the 128^3 kernels, from rocprofv3 FETCH_SIZE and
@@ -56,13 +61,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0):
+def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling="force"):
     import torch
 
     from paper_0901_3293_amd import hlb
     from paper_0901_3293_amd import inputs as I
 
     p, Q, u, rho = I.bpii_case(n=n)
+    p.coupling = coupling
+    values = {**KERNEL_VALUES, **(SPLIT_VALUES if coupling == "split" else {})}
     s = hlb.Solver((n, n, n), prec)
     s.set_params(p)
     s.set_fields(Q, u, rho)
@@ -90,18 +97,20 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0):
     mlups = N * steps / (ms / 1e3) / 1e6
     per_launch = {k: v / prof_steps for k, v in kern.items() if v > 0}
     dom = max(per_launch, key=per_launch.get)
-    alg_bytes = KERNEL_VALUES[dom] * esz * N
+    alg_bytes = values[dom] * esz * N
     achieved = alg_bytes / (per_launch[dom] / 1e3) / 1e9
-    step_values = sum(KERNEL_VALUES[k] for k in per_launch)
+    step_values = sum(values[k] for k in per_launch)
+    traffic = MEASURED_TRAFFIC.get((prec, dom)) if (n == 128 and coupling == "force") else None
     out = {
         "mlups": mlups,
+        "coupling": coupling,
         "schedule": {"name": sched, "tz": tz},
         "ms_per_step": ms_step,
         "kernel_ms_per_launch": per_launch,
         "dominant_kernel": dom,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC.get((prec, dom)) if n == 128 else None, "kernel": dom,
+                     "traffic": traffic, "kernel": dom,
                      "alg_bytes_per_launch": alg_bytes},
         "step_roofline": {
             "bytes_per_site": step_values * esz,
@@ -345,6 +354,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "network"], default=None,
                     help="run one leg only (profiling runs)")
+    ap.add_argument("--coupling", choices=["force", "split"], default="force",
+                    help="fluid coupling of the --only fp32/fp64 profiling legs")
+    ap.add_argument("--no-split", action="store_true", help="skip the FP32 split-coupling leg")
     ap.add_argument("--schedule", choices=["auto", "sites", "tiled", "mixed"], default="auto",
                     help="step schedule (auto: the library's autotuner picks)")
     ap.add_argument("--tz", type=int, default=0, help="planes per tile column for a fixed tiled/mixed schedule")
@@ -390,8 +402,16 @@ def main():
     forms = (a.only,) if a.only else ("fp32", "fp64")
     for prec in forms:
         log(f"bench: {prec} {a.n}^3, warmup {a.warmup}, steps {a.steps}")
-        res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps, a.schedule, a.tz)
+        res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps, a.schedule, a.tz,
+                             a.coupling if a.only else "force")
         log(f"bench: {prec} {res[prec]['mlups']:.1f} MLUPS, kernels {res[prec]['kernel_ms_per_launch']}")
+    split = None
+    if not a.only and not a.no_split:
+        log(f"bench: fp32 {a.n}^3 split coupling")
+        r = run_form("fp32", a.n, a.steps, a.warmup, a.prof_steps, "auto", 0, "split")
+        split = {k: r[k] for k in ("mlups", "ms_per_step", "schedule", "kernel_ms_per_launch", "roofline",
+                                   "step_roofline")}
+        log(f"bench: split {split['mlups']:.1f} MLUPS")
     batched = None
     if a.batch_steps > 0 and not a.only:
         log(f"bench: batched 96 boxes fp32, {a.batch_steps} steps")
@@ -434,6 +454,7 @@ def main():
                  "schedule": r64["schedule"],
                  "roofline": r64["roofline"], "step_roofline": r64["step_roofline"],
                  "kernel_ms_per_launch": r64["kernel_ms_per_launch"]},
+        "split_coupling_fp32": split,
         "batched": batched,
         "surrogate": sur,
         "checks": {"fp32": r32["checks"], "fp64": r64["checks"]},

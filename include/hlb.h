@@ -73,8 +73,20 @@ typedef struct {
 
 /* Beris-Edwards kinetics (Sec. 2.1, Eqs. (2)-(4)): rotational diffusion
  * constant Gamma (> 0), flow-aligning parameter xi, and the flow switch of
- * Sec. 2.1: flow_coupling = 0 imposes u == 0 (pure relaxation; the LB state
- * is left untouched), 1 couples the fluid. */
+ * Sec. 2.1 with the choice of coupling:
+ *   HLB_FLOW_OFF   (0) imposes u == 0 (pure relaxation; the LB state is left
+ *                      untouched);
+ *   HLB_FLOW_FORCE (1) couples the fluid through the centred divergence of the
+ *                      whole chemical stress of Eqs. (6)-(8) as a body force;
+ *   HLB_FLOW_SPLIT (2) the split coupling of Sec. 2.2, Eqs. (17)-(21): the
+ *                      symmetric xi-stress sigma^xi enters the second moment
+ *                      of the equilibrium, the body force is
+ *                      b_a = d_b tau_ab - H:d_a Q (tau the antisymmetric
+ *                      stress), which vanishes with H, so an equilibrium
+ *                      structure has no spurious flow.  Single-box contexts
+ *                      with the sites or mixed schedule only.
+ * Other values are rejected with HLB_ERR_PARAM. */
+enum { HLB_FLOW_OFF = 0, HLB_FLOW_FORCE = 1, HLB_FLOW_SPLIT = 2 };
 typedef struct {
     double Gamma;
     double xi;
@@ -102,9 +114,10 @@ int hlb_fe_from_reduced(double kappa, double tau_ldg, double q0, double A0,
                         hlb_fe_params *out);
 
 /* Set all physical parameters.  Rejected with HLB_ERR_PARAM: tau <= 1/2,
- * rho0 <= 0, A0 <= 0, gamma <= 0, K < 0, Gamma <= 0, and the explicit
- * diffusion bound 12 Gamma K >= 2 of the forward-Euler predictor.  Must be
- * called before hlb_set_fields. */
+ * rho0 <= 0, A0 <= 0, gamma <= 0, K < 0, Gamma <= 0, the explicit diffusion
+ * bound 12 Gamma K >= 2 of the forward-Euler predictor, and an unknown
+ * flow_coupling; HLB_ERR_STATE for the split coupling while the tiled
+ * schedule is selected.  Must be called before hlb_set_fields. */
 int hlb_set_params(hlb_ctx *ctx, const hlb_lb_params *lb, const hlb_fe_params *fe,
                    const hlb_be_params *be);
 
@@ -146,13 +159,15 @@ int hlb_set_state(hlb_ctx *ctx, const void *host_buf, size_t nbytes);
  * hold the stress and the predictor stage (recomputed on a one-site halo
  * ring), tz planes per tile column (0: 16).  HLB_SCHED_MIXED: the per-site
  * stress and LB sweeps, then the tiled predictor-corrector.  All give the
- * same step to rounding.  The default is HLB_SCHED_SITES. */
+ * same step to rounding.  The default is HLB_SCHED_SITES.  With the split
+ * coupling, HLB_SCHED_TILED is rejected (HLB_ERR_STATE). */
 enum { HLB_SCHED_SITES = 0, HLB_SCHED_TILED = 1, HLB_SCHED_MIXED = 2 };
 int hlb_set_schedule(hlb_ctx *ctx, int schedule, int tz);
 int hlb_get_schedule(const hlb_ctx *ctx, int *schedule, int *tz);
 
 /* Autotuner: time trial_steps steps of every candidate schedule (per-site;
- * tiled with tz = 8, 16, 32) on this context's lattice and precision with HIP
+ * tiled and mixed with tz = 8, 16, 32; no tiled with the split coupling) on
+ * this context's lattice and precision with HIP
  * events on its stream, keep the fastest, and put the state back as it was
  * (through a host copy of hlb_state_bytes bytes).  *best_ms_per_step (may be
  * NULL) receives the winner's time per step.  Synchronises the stream. */
@@ -184,7 +199,8 @@ typedef struct hlb_batch hlb_batch;
 size_t hlb_batch_workspace_bytes(int n, const int *dims, int precision);
 int hlb_batch_create(int n, const int *dims, int precision, void *device_workspace, size_t workspace_bytes,
                      void *hip_stream, hlb_batch **out);
-/* Per box i in [0, n): same validation as hlb_set_params / hlb_set_fields. */
+/* Per box i in [0, n): same validation as hlb_set_params / hlb_set_fields;
+ * flow_coupling must be HLB_FLOW_OFF or HLB_FLOW_FORCE (HLB_ERR_PARAM). */
 int hlb_batch_set_params(hlb_batch *b, int i, const hlb_lb_params *lb, const hlb_fe_params *fe,
                          const hlb_be_params *be);
 int hlb_batch_set_fields(hlb_batch *b, int i, const double *Q5, const double *u3, const double *rho);

@@ -275,7 +275,9 @@ int hlb_batch_set_params(hlb_batch *b, int i, const hlb_lb_params *lb, const hlb
     if (!(lb->tau > 0.5) || !(lb->rho0 > 0.0) || !(fe->A0 > 0.0) || !(fe->gamma > 0.0) || !(fe->K >= 0.0) ||
         !(be->Gamma > 0.0) || !std::isfinite(fe->q0) || !std::isfinite(be->xi) || !(12.0 * be->Gamma * fe->K < 2.0))
         return bset_error(b, HLB_ERR_PARAM, "box %d: parameters out of range", i);
-    b->par[i] = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi, be->flow_coupling ? 1 : 0};
+    if (be->flow_coupling != HLB_FLOW_OFF && be->flow_coupling != HLB_FLOW_FORCE)
+        return bset_error(b, HLB_ERR_PARAM, "box %d: the batched kernel takes flow_coupling 0 or 1", i);
+    b->par[i] = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi, be->flow_coupling};
     b->have_params[i] = 1;
     b->dirty = true;
     return HLB_OK;

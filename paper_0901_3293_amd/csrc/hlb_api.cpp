@@ -33,7 +33,7 @@ bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
     L.g = align256(19 * N * e);
     L.Q = align256(5 * N * e);
     L.u = align256(3 * N * e);
-    L.Pi = align256(9 * N * e);
+    L.Pi = align256(12 * N * e);
     L.part = align256(hlb::partial_doubles(nx, ny, nz) * 8);
     L.res = 256;
     L.total = 2 * L.g + 2 * L.Q + L.u + L.Pi + L.part + L.res;
@@ -136,11 +136,14 @@ int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe,
     if (!std::isfinite(fe->q0)) return set_error(c, HLB_ERR_PARAM, "q0 not finite");
     if (!(be->Gamma > 0.0)) return set_error(c, HLB_ERR_PARAM, "Gamma = %g must be positive", be->Gamma);
     if (!std::isfinite(be->xi)) return set_error(c, HLB_ERR_PARAM, "xi not finite");
+    if (be->flow_coupling < HLB_FLOW_OFF || be->flow_coupling > HLB_FLOW_SPLIT)
+        return set_error(c, HLB_ERR_PARAM, "flow_coupling = %d is not one of 0, 1, 2", be->flow_coupling);
+    if (be->flow_coupling == HLB_FLOW_SPLIT && c->D.sched == HLB_SCHED_TILED)
+        return set_error(c, HLB_ERR_STATE, "the split coupling needs the sites or mixed schedule");
     if (!(12.0 * be->Gamma * fe->K < 2.0))
         return set_error(c, HLB_ERR_PARAM, "12 Gamma K = %g violates the explicit diffusion bound 2",
                          12.0 * be->Gamma * fe->K);
-    c->p = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi,
-            be->flow_coupling ? 1 : 0};
+    c->p = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi, be->flow_coupling};
     c->have_params = true;
     ++c->version;
     return HLB_OK;
@@ -215,6 +218,8 @@ int hlb_set_schedule(hlb_ctx *c, int schedule, int tz)
     HLB_GUARD(c);
     if ((schedule != HLB_SCHED_SITES && schedule != HLB_SCHED_TILED && schedule != HLB_SCHED_MIXED) || tz < 0)
         return set_error(c, HLB_ERR_ARG, "schedule %d / tz %d", schedule, tz);
+    if (schedule == HLB_SCHED_TILED && c->have_params && c->p.flow == HLB_FLOW_SPLIT)
+        return set_error(c, HLB_ERR_STATE, "the tiled schedule carries the whole-stress force only");
     c->D.sched = schedule;
     c->D.tz = tz;
     return HLB_OK;
@@ -251,6 +256,7 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
     Cand pick = cands[0];
     for (const Cand &k : cands) {
         if (k.sched != HLB_SCHED_SITES && k.tz > c->D.G.nz && k.tz != 8) continue;
+        if (k.sched == HLB_SCHED_TILED && c->p.flow == HLB_FLOW_SPLIT) continue;
         c->D.sched = k.sched;
         c->D.tz = k.tz;
         hipError_t e = hlb::run_steps(c->D, c->p, 2);  // warm-up

@@ -13,12 +13,16 @@ struct Geom {
     int N;  // nx*ny*nz (< 2^31)
 };
 
+// Fluid coupling (Sec. 2.1, 2.2): off (u == 0), the whole chemical stress as a
+// body force, or the split of Eqs. (17)-(21).
+enum Flow { FLOW_OFF = 0, FLOW_FORCE = 1, FLOW_SPLIT = 2 };
+
 // Parameters of one run in FP64 (converted to the arithmetic type per launch).
 struct PhysParams {
     double tau, rho0;
     double A0, gamma, K, q0;
     double Gamma, xi;
-    int flow;
+    int flow;  // Flow
 };
 
 // Step schedules (see kernels.hip).
@@ -32,7 +36,7 @@ struct Device {
     void *g[2];    // 19 x N each; g[gcur] holds the state
     void *Q[2];    // 5 x N each; Q[qcur] holds the state
     void *u;       // 3 x N
-    void *Pi;      // 9 x N (stress; F in its first 3 x N for the tiled schedule)
+    void *Pi;      // 12 x N: stress (9; F in its first 3 for the tiled schedule) or split terms (12)
     double *part;  // partial_doubles(nx, ny, nz)
     double *res;   // 16 doubles of reduced totals
     int gcur, qcur;

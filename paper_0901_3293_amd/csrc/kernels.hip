@@ -5,7 +5,9 @@
 //   Q[2]   5 x N  order parameter (xx, xy, xz, yy, yz); Q[qcur] is the state,
 //                 the other copy holds the predictor stage or the next Q
 //   u      3 x N  velocity of the last LB step
-//   Pi     9 x N  chemical stress (its first 3 x N hold F in the tiled schedule)
+//   Pi    12 x N  chemical stress, 9 planes (its first 3 hold F in the tiled
+//                 schedule), or the 12 planes of the split coupling (sigma^xi,
+//                 tau, h; see sitekern.h)
 // Scalars of one run are passed by value (Coef<T>).
 //
 // Two schedules of one step (Sec. 2.2), chosen per lattice and precision by
@@ -19,6 +21,8 @@
 //   k_qforce  Q^n -> F^n;  k_lbf  g, F^n -> g', u^n;  k_qupdate  Q^n, u^n -> Q^{n+1}
 //  MIXED (3 sweeps: the per-site stress and LB, then the tiled Q update;
 //  77 values):  k_stress, k_lb, k_qupdate
+// The split coupling (Sec. 2.2) runs the SITES and MIXED schedules with
+// k_stress / k_lb writing and reading the split terms (101 and 83 values).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -433,25 +437,30 @@ __global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGr
 
 __device__ __forceinline__ int site_index() { return logical_block() * BLK + int(threadIdx.x); }
 
-template <typename T>
+// SPLIT: the 12 planes of the split coupling instead of the 9 of Pi.
+template <typename T, bool SPLIT>
 __global__ __launch_bounds__(BLK) void k_stress(Geom G, Coef<T> c, const T *__restrict__ Q,
                                                 T *__restrict__ Pi, double *__restrict__ fpart)
 {
     const int s = site_index();
     double fsum = 0.0;
-    if (s < G.N) fsum = double(stress_at(G, c, Q, Pi, s));
+    if (s < G.N) fsum = double(SPLIT ? split_at(G, c, Q, Pi, s) : stress_at(G, c, Q, Pi, s));
     if (fpart) {
         double v[1] = {fsum};
         block_sum<1, BLK>(v, fpart + logical_block());
     }
 }
 
-template <typename T>
+template <typename T, bool SPLIT>
 __global__ __launch_bounds__(BLK) void k_lb(Geom G, Coef<T> c, const T *__restrict__ gin,
                                             const T *__restrict__ Pi, T *__restrict__ gout, T *__restrict__ u)
 {
     const int s = site_index();
-    if (s < G.N) lb_at(G, c, gin, Pi, gout, u, s);
+    if (s >= G.N) return;
+    if (SPLIT)
+        lb_split_at(G, c, gin, Pi, gout, u, s);
+    else
+        lb_at(G, c, gin, Pi, gout, u, s);
 }
 
 template <typename T>
@@ -513,10 +522,10 @@ __global__ __launch_bounds__(BLK) void k_init(Geom G, Coef<T> c, const double *_
     for (int k = 0; k < 5; ++k) Q[k * N + s] = T(Q_in[k * N + s]);
 }
 
-// Current-level readout: rho, u = (j + F/2)/rho with F = div Pi (u == 0 when
-// Pi is null, i.e. flow off) and Q in FP64; FP64 block partials of
-// (rho - rho0, rho u_x, rho u_y, rho u_z).
-template <typename T>
+// Current-level readout: rho, u = (j + F/2)/rho with F = div Pi, or the split
+// body force b (u == 0 when Pi is null, i.e. flow off) and Q in FP64; FP64
+// block partials of (rho - rho0, rho u_x, rho u_y, rho u_z).
+template <typename T, bool SPLIT>
 __global__ __launch_bounds__(BLK) void k_readout(Geom G, Coef<T> c, const T *__restrict__ g,
                                                  const T *__restrict__ Pi, const T *__restrict__ Q,
                                                  double *__restrict__ rho_out, double *__restrict__ u_out,
@@ -531,7 +540,12 @@ __global__ __launch_bounds__(BLK) void k_readout(Geom G, Coef<T> c, const T *__r
 #pragma unroll
         for (int i = 0; i < 19; ++i) gg[i] = g[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
         lb_moments(gg, drho, j);
-        if (Pi) divergence(Pi, N, S, f);
+        if (Pi) {
+            if (SPLIT)
+                split_force(Pi, N, S, f);
+            else
+                divergence(Pi, N, S, f);
+        }
         const T rho = c.rho0 + drho;
         T uu[3];
 #pragma unroll
@@ -620,9 +634,10 @@ struct Marks {
 
 int tile_tz(const Device &D) { return D.tz > 0 ? D.tz : 16; }
 
-template <typename T>
+template <typename T, bool SPLIT>
 hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer)
 {
+    if (SPLIT && D.sched == SCHED_TILED) return hipErrorNotSupported;  // tiled kernels carry the whole stress only
     const Geom G = D.G;
     const Coef<T> c = make_coef<T>(p);
     const int nb = site_blocks(G.N);
@@ -640,9 +655,9 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             if (p.flow) {
                 T *gin = static_cast<T *>(D.g[D.gcur]);
                 T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
-                e = mark(K_STRESS, [&] { k_stress<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr); });
+                e = mark(K_STRESS, [&] { k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr); });
                 if (e == hipSuccess)
-                    e = mark(K_LB, [&] { k_lb<T><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
+                    e = mark(K_LB, [&] { k_lb<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
                 D.gcur ^= 1;
             }
             if (fused_q) {
@@ -698,7 +713,7 @@ hipError_t init_t(Device &D, const PhysParams &p, const double *stage)
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool SPLIT>
 hipError_t readout_t(Device &D, const PhysParams &p, double *stage, double *totals)
 {
     const Geom G = D.G;
@@ -708,12 +723,12 @@ hipError_t readout_t(Device &D, const PhysParams &p, double *stage, double *tota
     T *Pi = static_cast<T *>(D.Pi);
     const T *Q = static_cast<const T *>(D.Q[D.qcur]);
     if (totals)
-        k_stress<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, D.part + 4 * nb);
+        k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, D.part + 4 * nb);
     else if (p.flow)
-        k_stress<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr);
-    k_readout<T><<<nb, BLK, 0, D.stream>>>(G, c, static_cast<const T *>(D.g[D.gcur]), p.flow ? Pi : nullptr, Q,
-                                           stage, stage ? stage + N : nullptr, stage ? stage + 4 * N : nullptr,
-                                           totals ? D.part : nullptr);
+        k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr);
+    k_readout<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, static_cast<const T *>(D.g[D.gcur]), p.flow ? Pi : nullptr,
+                                                  Q, stage, stage ? stage + N : nullptr,
+                                                  stage ? stage + 4 * N : nullptr, totals ? D.part : nullptr);
     if (totals) {
         k_reduce<<<1, BLK, 0, D.stream>>>(D.part, nb, 4, 4, D.res);
         k_reduce<<<1, BLK, 0, D.stream>>>(D.part + 4 * nb, nb, 1, 1, D.res + 4);
@@ -751,7 +766,9 @@ const char *kernel_name(int k)
 
 hipError_t run_steps(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer)
 {
-    return D.fp32 ? steps_t<float>(D, p, nsteps, timer) : steps_t<double>(D, p, nsteps, timer);
+    if (p.flow == FLOW_SPLIT)
+        return D.fp32 ? steps_t<float, true>(D, p, nsteps, timer) : steps_t<double, true>(D, p, nsteps, timer);
+    return D.fp32 ? steps_t<float, false>(D, p, nsteps, timer) : steps_t<double, false>(D, p, nsteps, timer);
 }
 
 hipError_t run_init(Device &D, const PhysParams &p, const double *stage)
@@ -761,7 +778,9 @@ hipError_t run_init(Device &D, const PhysParams &p, const double *stage)
 
 hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *totals)
 {
-    return D.fp32 ? readout_t<float>(D, p, stage, totals) : readout_t<double>(D, p, stage, totals);
+    if (p.flow == FLOW_SPLIT)
+        return D.fp32 ? readout_t<float, true>(D, p, stage, totals) : readout_t<double, true>(D, p, stage, totals);
+    return D.fp32 ? readout_t<float, false>(D, p, stage, totals) : readout_t<double, false>(D, p, stage, totals);
 }
 
 }  // namespace hlb

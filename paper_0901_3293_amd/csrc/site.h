@@ -165,6 +165,69 @@ __device__ __forceinline__ void site_stress(const Coef<T> &c, const T q[5], cons
     }
 }
 
+// Split coupling (Sec. 2.2, Eqs. (17)-(21)) at one site: the symmetric
+// xi-stress that goes into the second moment of the equilibrium,
+//   sigma^xi = 2 xi (Q + I/3)(Q:H) - xi (HQ + QH + 2H/3)
+// (upper triangle xx, xy, xz, yy, yz, zz), the antisymmetric stress
+// tau = QH - HQ (xy, xz, yz), and h_a = -H:d_a Q, the divergence of the
+// gradient and free-energy part of the stress by the identity of Eq. (21).
+// The body force is b_a = d_b tau_ab + h_a.  Also returns f.
+template <typename T>
+__device__ __forceinline__ void site_split(const Coef<T> &c, const T q[5], const T d[3][5], const T lap[5],
+                                           T sig[6], T tau3[3], T h[3], T &fdens)
+{
+    T Q[3][3], dQ[3][3][3], CQ[3][3], Q2[3][3], trQ2, H5[5];
+    full3(q, Q);
+    full_grad(d, dQ);
+    curl(dQ, CQ);
+    molecular_field(c, Q, CQ, lap, H5, Q2, trQ2);
+    T H[3][3];
+    full3(H5, H);
+
+    T M[3][3], div[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) M[a][b] = CQ[a][b] + c.q0x2 * Q[a][b];
+        div[a] = dQ[0][a][0] + dQ[1][a][1] + dQ[2][a][2];
+    }
+    fdens = free_energy(c, Q, Q2, trQ2, div, M);
+
+    T HQ[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) HQ[a][b] = H[a][0] * Q[0][b] + H[a][1] * Q[1][b] + H[a][2] * Q[2][b];
+    T QdH = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) QdH += Q[a][b] * H[a][b];
+
+    const T third = T(1) / T(3);
+    const int ia[6] = {0, 0, 0, 1, 1, 2};
+    const int ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int a = ia[k], b = ib[k];
+        sig[k] = T(2) * c.xi * (Q[a][b] + (a == b ? third : T(0))) * QdH
+               - c.xi * (HQ[a][b] + HQ[b][a] + T(2) * third * H[a][b]);
+    }
+    // (QH)_ab = (HQ)_ba for symmetric H and Q
+    tau3[0] = HQ[1][0] - HQ[0][1];
+    tau3[1] = HQ[2][0] - HQ[0][2];
+    tau3[2] = HQ[2][1] - HQ[1][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T v = T(0);
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+#pragma unroll
+            for (int n = 0; n < 3; ++n) v += H[g][n] * dQ[a][g][n];
+        h[a] = -v;
+    }
+}
+
 // Right-hand side of the Q equation (Eqs. (2)-(4)) projected on symmetric
 // traceless tensors:
 //   R = P_T[ -u.grad Q + S(W,Q) + Gamma H ],
@@ -274,6 +337,39 @@ __device__ __forceinline__ void lb_collide(const Coef<T> &c, T g[19], const T F[
         const T eu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
         const T eF = T(CX[i]) * F[0] + T(CY[i]) * F[1] + T(CZ[i]) * F[2];
         const T geq = w * drho + w * rho * (T(3) * eu + T(4.5) * eu * eu - uu15);
+        const T src = c.pref * w * (T(3) * (eF - uF) + T(9) * eu * eF);
+        g[i] = keep * g[i] + c.omega * geq + src;
+    }
+}
+
+// The same collision in the split coupling: F is the split body force b and
+// the equilibrium carries the symmetric stress sig (xx, xy, xz, yy, yz, zz)
+// in its second moment (Eq. (17)),
+//   g_i^eq += -(9/2) w_i [sig:e_i e_i - tr(sig)/3],
+// a term with zero mass and momentum.
+template <typename T>
+__device__ __forceinline__ void lb_collide_split(const Coef<T> &c, T g[19], const T F[3], const T sig[6], T u[3],
+                                                 T &rho)
+{
+    T drho, j[3];
+    lb_moments(g, drho, j);
+    rho = c.rho0 + drho;
+    const T irho = T(1) / rho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + T(0.5) * F[a]) * irho;
+    const T uu15 = T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    const T keep = T(1) - c.omega;
+    const T tr3 = (sig[0] + sig[3] + sig[5]) / T(3);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const T w = lb_weight<T>(i);
+        const T ex = T(CX[i]), ey = T(CY[i]), ez = T(CZ[i]);
+        const T eu = ex * u[0] + ey * u[1] + ez * u[2];
+        const T eF = ex * F[0] + ey * F[1] + ez * F[2];
+        const T see = sig[0] * ex * ex + sig[3] * ey * ey + sig[5] * ez * ez
+                    + T(2) * (sig[1] * ex * ey + sig[2] * ex * ez + sig[4] * ey * ez);
+        const T geq = w * drho + w * rho * (T(3) * eu + T(4.5) * eu * eu - uu15) - T(4.5) * w * (see - tr3);
         const T src = c.pref * w * (T(3) * (eF - uF) + T(9) * eu * eF);
         g[i] = keep * g[i] + c.omega * geq + src;
     }

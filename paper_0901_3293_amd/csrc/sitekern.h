@@ -4,7 +4,9 @@
 // from global memory through the L1/L2 of the executing CU.
 //
 // Buffers of one box (structure-of-arrays, component stride N, x fastest):
-//   g 19 x N, Q 5 x N, Qs (predictor stage) 5 x N, u 3 x N, Pi 9 x N.
+//   g 19 x N, Q 5 x N, Qs (predictor stage) 5 x N, u 3 x N, Pi 9 x N
+//   (whole-stress coupling) or 12 x N (split coupling: sigma^xi xx, xy, xz,
+//   yy, yz, zz; tau xy, xz, yz; h x, y, z).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -122,6 +124,58 @@ __device__ __forceinline__ void lb_at(const Geom &G, const Coef<T> &c, const T *
     for (int i = 0; i < 19; ++i) g[i] = gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
     divergence(Pi, N, S, F);
     lb_collide(c, g, F, uu, rho);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) gout[i * N + s] = g[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
+}
+
+// Split-coupling terms at one site (planes of the 12 x N layout above);
+// returns the free-energy density.
+template <typename T>
+__device__ __forceinline__ T split_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q, T *__restrict__ P,
+                                      int s)
+{
+    const size_t N = G.N;
+    const Nbr S = nbr_of(G, s);
+    T q[5], d[3][5], lap[5], sig[6], tau3[3], h[3], fd;
+    gather_q(Q, N, S, q, d, lap);
+    site_split(c, q, d, lap, sig, tau3, h, fd);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) P[k * N + s] = sig[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P[(6 + k) * N + s] = tau3[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P[(9 + k) * N + s] = h[k];
+    return fd;
+}
+
+// Split body force b_a = d_b tau_ab + h_a (centred on the second index;
+// tau antisymmetric, stored as xy, xz, yz).
+template <typename T>
+__device__ __forceinline__ void split_force(const T *__restrict__ P, size_t N, const Nbr &S, T b[3])
+{
+    const T *txy = P + 6 * N, *txz = P + 7 * N, *tyz = P + 8 * N;
+    b[0] = T(0.5) * ((txy[S.nb[2]] - txy[S.nb[3]]) + (txz[S.nb[4]] - txz[S.nb[5]])) + P[9 * N + S.s];
+    b[1] = T(0.5) * ((tyz[S.nb[4]] - tyz[S.nb[5]]) - (txy[S.nb[0]] - txy[S.nb[1]])) + P[10 * N + S.s];
+    b[2] = T(0.5) * (-(txz[S.nb[0]] - txz[S.nb[1]]) - (tyz[S.nb[2]] - tyz[S.nb[3]])) + P[11 * N + S.s];
+}
+
+// LB step of the split coupling at one site: pull, collide with the stress in
+// the equilibrium and the split body force; writes g' and u.
+template <typename T>
+__device__ __forceinline__ void lb_split_at(const Geom &G, const Coef<T> &c, const T *__restrict__ gin,
+                                            const T *__restrict__ P, T *__restrict__ gout, T *__restrict__ u, int s)
+{
+    const size_t N = G.N;
+    const Nbr S = nbr_of(G, s);
+    T g[19], b[3], sig[6], uu[3], rho;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) g[i] = gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
+    split_force(P, N, S, b);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sig[k] = P[k * N + s];
+    lb_collide_split(c, g, b, sig, uu, rho);
 #pragma unroll
     for (int i = 0; i < 19; ++i) gout[i * N + s] = g[i];
 #pragma unroll

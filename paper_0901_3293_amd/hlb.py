@@ -42,6 +42,21 @@ class BeParams(ctypes.Structure):
     _fields_ = [("Gamma", ctypes.c_double), ("xi", ctypes.c_double), ("flow_coupling", ctypes.c_int)]
 
 
+FLOW_CODES = {"force": 1, "split": 2}
+
+
+def flow_code(p):
+    """flow_coupling of the C-ABI: 0 (flow off), 1 (whole stress as a body
+    force) or 2 (split coupling), from p.flow and p.coupling ("force" when
+    absent)."""
+    if not p.flow:
+        return 0
+    c = getattr(p, "coupling", "force")
+    if c not in FLOW_CODES:
+        raise ValueError(f"coupling {c!r}: one of {sorted(FLOW_CODES)}")
+    return FLOW_CODES[c]
+
+
 _lib = None
 
 
@@ -158,7 +173,7 @@ class Solver:
         """p: any object with tau, rho0, A0, gamma, K, q0, Gamma, xi, flow."""
         lb = LbParams(p.tau, p.rho0)
         fe = FeParams(p.A0, p.gamma, p.K, p.q0)
-        be = BeParams(p.Gamma, p.xi, 1 if p.flow else 0)
+        be = BeParams(p.Gamma, p.xi, flow_code(p))
         self._check(lib().hlb_set_params(self.ctx, ctypes.byref(lb), ctypes.byref(fe), ctypes.byref(be)))
 
     def set_fields(self, Q5, u3=None, rho=None):
@@ -280,7 +295,7 @@ class Batch:
     def set_params(self, i, p):
         lb = LbParams(p.tau, p.rho0)
         fe = FeParams(p.A0, p.gamma, p.K, p.q0)
-        be = BeParams(p.Gamma, p.xi, 1 if p.flow else 0)
+        be = BeParams(p.Gamma, p.xi, flow_code(p))
         self._check(lib().hlb_batch_set_params(self.b, i, ctypes.byref(lb), ctypes.byref(fe), ctypes.byref(be)))
 
     def set_fields(self, i, Q5, u3=None, rho=None):

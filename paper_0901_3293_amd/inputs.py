@@ -36,6 +36,7 @@ class PhysParams:
     Gamma: float = 0.3
     xi: float = 0.7
     flow: bool = True
+    coupling: str = "force"  # "force": whole stress as a body force; "split": Sec. 2.2 split
 
     def as_dict(self):
         return asdict(self)

@@ -3,7 +3,8 @@ the same 32^3 helix run drift apart per step when only the rounding order
 differs (the oracle built as usual vs the same source built with FMA
 contraction).  The velocity is a small difference of O(1e-4) stresses, so its
 relative spread sits well above 1e-12; the GPU bound for u is stated relative
-to this spread.  Calls only the oracle."""
+to this spread.  Calls only the oracle.  `--split` writes
+fp64_spread_split.json for the same run with the split coupling of Sec. 2.2."""
 import json
 import os
 import subprocess
@@ -16,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 
-def run(libpath, nsteps):
+def run(libpath, nsteps, coupling):
     code = f"""
 import os, sys, numpy as np
 os.environ['HLB_ORACLE_LIB'] = {libpath!r}
@@ -24,6 +25,7 @@ sys.path.insert(0, {ROOT!r})
 import oracle
 from paper_0901_3293_amd import inputs as I
 p, Q, u, rho = I.helix_case()
+p.coupling = {coupling!r}
 st = oracle.State(oracle.params(**p.as_dict()), Q, u, rho)
 for n in range({nsteps}):
     st.step(1)
@@ -33,7 +35,7 @@ for n in range({nsteps}):
     subprocess.check_call([sys.executable, "-c", code])
 
 
-def main(nsteps=100):
+def main(nsteps=100, coupling="force"):
     import oracle
     tmp = os.path.join(ROOT, "oracle", "_spread")
     os.makedirs(tmp, exist_ok=True)
@@ -43,8 +45,8 @@ def main(nsteps=100):
     base = [f for f in oracle.CFLAGS if f != "-ffp-contract=off"]
     subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", plain, src, "-lm"])
     subprocess.check_call(["gcc", *base, "-ffp-contract=fast", "-mfma", "-o", fma, src, "-lm"])
-    run(plain, nsteps)
-    run(fma, nsteps)
+    run(plain, nsteps, coupling)
+    run(fma, nsteps, coupling)
     N = 32 ** 3
     spread = {"Q": [], "u": [], "rho": []}
     for n in range(nsteps):
@@ -55,14 +57,16 @@ def main(nsteps=100):
     for f in os.listdir(tmp):
         os.remove(os.path.join(tmp, f))
     os.rmdir(tmp)
-    out = {"workload": "32^3 helix, q0 = 2 pi/16, kappa = 1, tau = 0, noise 1e-4 seed 1, FP64",
+    out = {"workload": "32^3 helix, q0 = 2 pi/16, kappa = 1, tau = 0, noise 1e-4 seed 1, FP64, "
+                       f"{coupling} coupling",
            "what": "max|a-b|/max|a| per step between the oracle built -ffp-contract=off and "
                    "built with FMA contraction",
            "spread": spread}
-    with open(os.path.join(HERE, "fp64_spread.json"), "w") as fh:
+    name = "fp64_spread.json" if coupling == "force" else "fp64_spread_split.json"
+    with open(os.path.join(HERE, name), "w") as fh:
         json.dump(out, fh)
     print({k: (v[0], v[9], v[-1]) for k, v in spread.items()})
 
 
 if __name__ == "__main__":
-    main()
+    main(coupling="split" if "--split" in sys.argv else "force")
