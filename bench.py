@@ -175,6 +175,45 @@ def run_batched(steps, graph_steps=50, chunk=0, xcd_local=True):
     return out
 
 
+def run_order(n=128, calls=20, threshold=0.19, relax=6000):
+    """Local order and disclination count (largest eigenvalue of Q per site,
+    FP64 Jacobi) on the n^3 O2 workload in the FP32 form, relaxed first with
+    the flow off (Gamma = 5, `relax` steps) from the analytic seed to a
+    blue-phase texture with disclination lines: device time of a counts-only
+    call (HIP events on the context's stream) and the number of disclination
+    sites."""
+    import numpy as np
+    import torch
+
+    from paper_0901_3293_amd import hlb
+    from paper_0901_3293_amd import inputs as I
+
+    p, Q, u, rho = I.bpii_case(n=n)
+    s = hlb.Solver((n, n, n), "fp32")
+    s.set_params(I.PhysParams(**{**p.as_dict(), "Gamma": 5.0, "flow": False}))
+    s.set_fields(Q, u, rho)
+    s.step(relax)
+    res = s.order(threshold, fields=False)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t = []
+    for _ in range(calls):
+        ev0.record(s.stream)
+        s.order(threshold, fields=False)
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        t.append(ev0.elapsed_time(ev1))
+    ms = float(np.median(t))
+    s.close()
+    torch.cuda.empty_cache()
+    N = n ** 3
+    return {"sites": N, "threshold": threshold, "relax_steps": relax, "n_defect": res["n_defect"],
+            "ms_per_call": ms,
+            "msites_per_s": N / (ms / 1e3) / 1e6,
+            "note": "counts-only call: order kernel (reads 5 FP32 values, writes 1 flag byte per site), "
+                    "per-plane count kernel, one small device-to-host copy"}
+
+
 def run_surrogate(n=96, steps=20000, M=8, iters=1500):
     """The surrogate workload on a 96^3 box: 500 training pairs from five
     O2 runs and two domain-growth runs (kappa 0.7, tau -0.5, noise 1e-3;
@@ -352,7 +391,7 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "network"], default=None,
+    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "network", "order"], default=None,
                     help="run one leg only (profiling runs)")
     ap.add_argument("--coupling", choices=["force", "split"], default="force",
                     help="fluid coupling of the --only fp32/fp64 profiling legs")
@@ -389,8 +428,10 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy probe 512 MiB x3 done")
         del src, dst
-    if a.only in ("batched", "surrogate", "network"):
-        if a.only == "batched":
+    if a.only in ("batched", "surrogate", "network", "order"):
+        if a.only == "order":
+            out = run_order(a.n)
+        elif a.only == "batched":
             out = run_batched(a.batch_steps, a.batch_graph_steps, a.batch_chunk, not a.batch_device_fences)
         elif a.only == "network":
             out = run_network()
@@ -412,6 +453,10 @@ def main():
         split = {k: r[k] for k in ("mlups", "ms_per_step", "schedule", "kernel_ms_per_launch", "roofline",
                                    "step_roofline")}
         log(f"bench: split {split['mlups']:.1f} MLUPS")
+    order = None
+    if not a.only:
+        log(f"bench: order analysis {a.n}^3")
+        order = run_order(a.n)
     batched = None
     if a.batch_steps > 0 and not a.only:
         log(f"bench: batched 96 boxes fp32, {a.batch_steps} steps")
@@ -455,6 +500,7 @@ def main():
                  "roofline": r64["roofline"], "step_roofline": r64["step_roofline"],
                  "kernel_ms_per_launch": r64["kernel_ms_per_launch"]},
         "split_coupling_fp32": split,
+        "order": order,
         "batched": batched,
         "surrogate": sur,
         "checks": {"fp32": r32["checks"], "fp64": r64["checks"]},

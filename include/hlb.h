@@ -147,6 +147,18 @@ int hlb_get_totals(hlb_ctx *ctx, double *mass, double *mom3, double *free_energy
  * fz: host array of nz doubles.  Synchronises the stream. */
 int hlb_get_fz(hlb_ctx *ctx, double *fz);
 
+/* Local order and disclinations of the current Q (Sec. 2.1): q[N] the largest
+ * eigenvalue of Q (the local magnitude of order), dir3[3][N] a unit
+ * eigenvector of it (the director of Sec. 2.3; sign: last non-zero component
+ * positive; (0, 0, 1) where Q = 0), defect[N] = 1 where q < threshold (a
+ * disclination site; the paper's runs use 0.19) else 0, defects_z[nz] the
+ * number of disclination sites per z-plane, *n_defect their total.  Computed
+ * on the device in FP64 from the stored Q (cyclic Jacobi rotations); host
+ * outputs, any of them NULL.  Errors: HLB_ERR_ARG for a non-finite threshold,
+ * HLB_ERR_STATE without fields.  Synchronises the stream. */
+int hlb_get_order(hlb_ctx *ctx, double threshold, double *q, double *dir3, unsigned char *defect,
+                  long long *defects_z, long long *n_defect);
+
 /* Raw checkpoint of the state (populations and Q in the context's precision).
  * hlb_state_bytes gives the size; get/set copy exactly that many bytes. */
 size_t hlb_state_bytes(hlb_ctx *ctx);

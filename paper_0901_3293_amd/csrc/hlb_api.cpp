@@ -330,6 +330,38 @@ int hlb_get_fz(hlb_ctx *c, double *fz)
     return HLB_OK;
 }
 
+int hlb_get_order(hlb_ctx *c, double threshold, double *q, double *dir3, unsigned char *defect, long long *defects_z,
+                  long long *n_defect)
+{
+    HLB_GUARD(c);
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
+    if (!std::isfinite(threshold)) return set_error(c, HLB_ERR_ARG, "threshold not finite");
+    const size_t N = c->D.G.N;
+    const int nz = c->D.G.nz;
+    // device staging in the population buffer that does not hold the state:
+    // q [N] doubles, dir [3N] doubles, per-plane counts [nz] doubles, flags [N] bytes
+    double *st = stage_of(c);
+    double *dq = st, *dd = st + N, *dc = st + 4 * N;
+    unsigned char *df = reinterpret_cast<unsigned char *>(st + 4 * N + nz);
+    const bool want_flags = defect || defects_z || n_defect;
+    HIP_TRY(c, hlb::run_order(c->D, threshold, q ? dq : nullptr, dir3 ? dd : nullptr, want_flags ? df : nullptr,
+                              (defects_z || n_defect) ? dc : nullptr));
+    if (q) HIP_TRY(c, hipMemcpyAsync(q, dq, N * 8, hipMemcpyDeviceToHost, c->D.stream));
+    if (dir3) HIP_TRY(c, hipMemcpyAsync(dir3, dd, 3 * N * 8, hipMemcpyDeviceToHost, c->D.stream));
+    if (defect) HIP_TRY(c, hipMemcpyAsync(defect, df, N, hipMemcpyDeviceToHost, c->D.stream));
+    std::vector<double> cnt(defects_z || n_defect ? nz : 0);
+    if (!cnt.empty()) HIP_TRY(c, hipMemcpyAsync(cnt.data(), dc, nz * 8, hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
+    long long total = 0;
+    for (int z = 0; z < int(cnt.size()); ++z) {
+        const long long v = (long long)cnt[z];
+        if (defects_z) defects_z[z] = v;
+        total += v;
+    }
+    if (n_defect) *n_defect = total;
+    return HLB_OK;
+}
+
 size_t hlb_state_bytes(hlb_ctx *c) { return c ? c->state_bytes : 0; }
 
 int hlb_get_state(hlb_ctx *c, void *buf, size_t nbytes)

@@ -79,4 +79,9 @@ hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *to
 // Plane sums of the free-energy density of the current Q into device fz[nz].
 hipError_t run_fz(Device &D, const PhysParams &p, double *fz);
 
+// Local order of the current Q into device buffers (any may be null; cnt
+// needs defect): q[N] largest eigenvalue, dir[3][N] unit eigenvector,
+// defect[N] = (q < threshold), cnt[nz] defect sites per z-plane (FP64).
+hipError_t run_order(Device &D, double threshold, double *q, double *dir, unsigned char *defect, double *cnt);
+
 }  // namespace hlb

@@ -597,6 +597,110 @@ __global__ __launch_bounds__(BLK) void k_fz(Geom G, Coef<T> c, const T *__restri
     block_sum<1, BLK>(v, fz + z);
 }
 
+// Largest eigenvalue of a symmetric traceless 3x3 tensor and a unit
+// eigenvector of it, in FP64 (local order, Sec. 2.1; director, Sec. 2.3), by
+// the cyclic Jacobi method: plane rotations over the pairs (0,1), (0,2),
+// (1,2), each zeroing its off-diagonal entry (tangent of the smaller rotation
+// angle), repeated until the off-diagonal mass is below 1e-30 of the squared
+// norm (at most 8 sweeps; 4 suffice in practice).  Unlike the closed form of
+// the characteristic cubic, whose double roots lose half the digits, this
+// keeps every eigenvalue within a few ulps of |Q|.  The director is the
+// rotation's column of the largest diagonal entry, signed so that its last
+// non-zero component is positive.  Q = 0 gives 0 and (0, 0, 1).
+__device__ __forceinline__ void order_site(const double q[5], double &lam, double d[3])
+{
+    double A[3][3] = {{q[0], q[1], q[2]}, {q[1], q[3], q[4]}, {q[2], q[4], -q[0] - q[3]}};
+    double V[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+    double nrm = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) nrm += A[a][b] * A[a][b];
+    if (!(nrm > 0.0)) {
+        lam = 0.0;
+        d[0] = 0.0;
+        d[1] = 0.0;
+        d[2] = 1.0;
+        return;
+    }
+    const int P[3] = {0, 0, 1}, R[3] = {1, 2, 2};
+#pragma unroll 1
+    for (int sweep = 0; sweep < 8; ++sweep) {
+        const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        if (!(off > 1e-30 * nrm)) break;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int p = P[k], r = R[k];
+            const double apr = A[p][r];
+            if (apr == 0.0) continue;
+            const double th = (A[r][r] - A[p][p]) / (2.0 * apr);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const double amp = A[m][p], amr = A[m][r];
+                A[m][p] = c * amp - sn * amr;
+                A[m][r] = sn * amp + c * amr;
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const double apm = A[p][m], arm = A[r][m];
+                A[p][m] = c * apm - sn * arm;
+                A[r][m] = sn * apm + c * arm;
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const double vmp = V[m][p], vmr = V[m][r];
+                V[m][p] = c * vmp - sn * vmr;
+                V[m][r] = sn * vmp + c * vmr;
+            }
+        }
+    }
+    int k = 0;
+    if (A[1][1] > A[k][k]) k = 1;
+    if (A[2][2] > A[k][k]) k = 2;
+    lam = A[k][k];
+    const double v0 = V[0][k], v1 = V[1][k], v2 = V[2][k];
+    const double sgn = (v2 != 0.0 ? v2 : (v1 != 0.0 ? v1 : v0)) < 0.0 ? -1.0 : 1.0;
+    d[0] = sgn * v0;
+    d[1] = sgn * v1;
+    d[2] = sgn * v2;
+}
+
+// Local order q, director and disclination flag (q < threshold) per site;
+// any output may be null.
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_order(Geom G, const T *__restrict__ Q, double threshold,
+                                               double *__restrict__ qo, double *__restrict__ dir,
+                                               unsigned char *__restrict__ defect)
+{
+    const int s = site_index();
+    if (s >= G.N) return;
+    const size_t N = G.N;
+    double q[5], lam, d[3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) q[k] = double(Q[k * N + s]);
+    order_site(q, lam, d);
+    if (qo) qo[s] = lam;
+    if (dir)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dir[a * N + s] = d[a];
+    if (defect) defect[s] = lam < threshold ? 1 : 0;
+}
+
+// Disclination sites per z-plane: block z counts plane z (exact integer
+// counts carried in FP64).
+__global__ __launch_bounds__(BLK) void k_plane_count(Geom G, const unsigned char *__restrict__ defect,
+                                                     double *__restrict__ cnt)
+{
+    const int z = blockIdx.x;
+    const int sxy = G.nx * G.ny;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < sxy; k += BLK) acc += double(defect[size_t(z) * sxy + k]);
+    double v[1] = {acc};
+    block_sum<1, BLK>(v, cnt + z);
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_fill(T *__restrict__ p, size_t n, T v)
 {
@@ -744,6 +848,19 @@ hipError_t fz_t(Device &D, const PhysParams &p, double *fz)
 }
 
 }  // namespace
+
+hipError_t run_order(Device &D, double threshold, double *q, double *dir, unsigned char *defect, double *cnt)
+{
+    const int nb = site_blocks(D.G.N);
+    if (D.fp32)
+        k_order<float><<<nb, BLK, 0, D.stream>>>(D.G, static_cast<const float *>(D.Q[D.qcur]), threshold, q, dir,
+                                                 defect);
+    else
+        k_order<double><<<nb, BLK, 0, D.stream>>>(D.G, static_cast<const double *>(D.Q[D.qcur]), threshold, q,
+                                                  dir, defect);
+    if (cnt) k_plane_count<<<D.G.nz, BLK, 0, D.stream>>>(D.G, defect, cnt);
+    return hipGetLastError();
+}
 
 hipError_t run_fz(Device &D, const PhysParams &p, double *fz)
 {

@@ -83,6 +83,7 @@ def lib():
         L.hlb_get_state.argtypes = [vp, vp, sz]
         L.hlb_set_state.argtypes = [vp, vp, sz]
         L.hlb_get_fz.argtypes = [vp, dp]
+        L.hlb_get_order.argtypes = [vp, ctypes.c_double, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.hlb_set_schedule.argtypes = [vp, I, I]
         L.hlb_get_schedule.argtypes = [vp, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.hlb_autotune.argtypes = [vp, I, dp]
@@ -229,6 +230,22 @@ class Solver:
         out = np.zeros(self.shape[2])
         self._check(lib().hlb_get_fz(self.ctx, _dp(out)))
         return out
+
+    def order(self, threshold=0.19, fields=True):
+        """Local order of the current Q: dict with q [z][y][x] (largest
+        eigenvalue), dir [3][z][y][x] (director), defect [z][y][x] (uint8,
+        q < threshold), per_z (disclination sites per plane) and n_defect.
+        fields=False returns the counts only."""
+        nx, ny, nz = self.shape
+        per_z = np.zeros(nz, dtype=np.int64)
+        n = ctypes.c_longlong()
+        q = np.empty((nz, ny, nx)) if fields else None
+        d = np.empty((3, nz, ny, nx)) if fields else None
+        f = np.empty((nz, ny, nx), dtype=np.uint8) if fields else None
+        self._check(lib().hlb_get_order(self.ctx, float(threshold), _dp(q), _dp(d),
+                                        None if f is None else f.ctypes.data_as(ctypes.c_void_p),
+                                        per_z.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+        return {"q": q, "dir": d, "defect": f, "per_z": per_z, "n_defect": int(n.value)}
 
     def totals(self):
         m = np.zeros(1)
