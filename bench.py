@@ -204,10 +204,19 @@ def run_order(n=128, calls=20, threshold=0.19, relax=6000):
         torch.cuda.synchronize()
         t.append(ev0.elapsed_time(ev1))
     ms = float(np.median(t))
+    img = s.optics()
+    to = []
+    for _ in range(max(3, calls // 4)):
+        ev0.record(s.stream)
+        s.optics()
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        to.append(ev0.elapsed_time(ev1))
     s.close()
     torch.cuda.empty_cache()
     N = n ** 3
     return {"sites": N, "threshold": threshold, "relax_steps": relax, "n_defect": res["n_defect"],
+            "optics_ms_per_call": float(np.median(to)), "optics_mean_s0": float(img.mean()),
             "ms_per_call": ms,
             "msites_per_s": N / (ms / 1e3) / 1e6,
             "note": "counts-only call: order kernel (reads 5 FP32 values, writes 1 flag byte per site), "

@@ -159,6 +159,32 @@ int hlb_get_fz(hlb_ctx *ctx, double *fz);
 int hlb_get_order(hlb_ctx *ctx, double threshold, double *q, double *dir3, unsigned char *defect,
                   long long *defects_z, long long *n_defect);
 
+/* Polarised-light texture of the current Q (Sec. 2.3, Mueller-matrix method),
+ * light along +z entering at z = 0, unpolarised before the polariser: every
+ * lattice site is a layer of thickness h acting as a linear retarder whose
+ * axis is the projection of the director d on the (x, y) plane (angle beta
+ * to x) and whose retardance is
+ *   delta = 2 pi q h / lambda (n_o n_e / sqrt(n_o^2 sin^2 alpha + n_e^2 cos^2 alpha) - n_o),
+ * cos alpha = d_z, q the local order (both as in hlb_get_order, FP64).
+ * Polariser and analyser are linear at angles phi_in and phi_out to x
+ * (0 and pi/2: crossed).  image[ny][nx] (host, FP64) receives the weighted
+ * sum over the wavelengths of the first Stokes component behind the
+ * analyser.  The paper's values: n_o = 1.5, n_e = 2.0, h = 1, wavelengths
+ * 16, 18, 20 with weights 0.2, 0.6, 0.2.  Errors: HLB_ERR_ARG for null
+ * pointers, non-positive indices, thickness or wavelengths, non-finite
+ * angles or weights, or a wavelength count outside 1..8; HLB_ERR_STATE
+ * without fields.  Synchronises the stream. */
+#define HLB_OPTICS_MAX_WAVELENGTHS 8
+typedef struct {
+    double n_o, n_e;
+    double h;
+    double phi_in, phi_out;
+    int n_wavelengths;
+    double wavelength[HLB_OPTICS_MAX_WAVELENGTHS];
+    double weight[HLB_OPTICS_MAX_WAVELENGTHS];
+} hlb_optics_params;
+int hlb_get_optics(hlb_ctx *ctx, const hlb_optics_params *params, double *image);
+
 /* Raw checkpoint of the state (populations and Q in the context's precision).
  * hlb_state_bytes gives the size; get/set copy exactly that many bytes. */
 size_t hlb_state_bytes(hlb_ctx *ctx);

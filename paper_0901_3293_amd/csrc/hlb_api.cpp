@@ -16,6 +16,8 @@
 
 namespace {
 
+static_assert(HLB_OPTICS_MAX_WAVELENGTHS == hlb::OPTICS_MAX_WL, "optics wavelength bound");
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
@@ -359,6 +361,49 @@ int hlb_get_order(hlb_ctx *c, double threshold, double *q, double *dir3, unsigne
         total += v;
     }
     if (n_defect) *n_defect = total;
+    return HLB_OK;
+}
+
+int hlb_get_optics(hlb_ctx *c, const hlb_optics_params *op, double *image)
+{
+    HLB_GUARD(c);
+    if (!op || !image) return set_error(c, HLB_ERR_ARG, "null argument");
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
+    if (!(op->n_o > 0.0) || !(op->n_e > 0.0) || !(op->h > 0.0) || !std::isfinite(op->n_o) ||
+        !std::isfinite(op->n_e) || !std::isfinite(op->h) || !std::isfinite(op->phi_in) || !std::isfinite(op->phi_out))
+        return set_error(c, HLB_ERR_ARG, "optics: indices and thickness must be positive, angles finite");
+    if (op->n_wavelengths < 1 || op->n_wavelengths > HLB_OPTICS_MAX_WAVELENGTHS)
+        return set_error(c, HLB_ERR_ARG, "optics: %d wavelengths (1..%d)", op->n_wavelengths,
+                         HLB_OPTICS_MAX_WAVELENGTHS);
+    hlb::OpticsParams p{};
+    p.n_o = op->n_o;
+    p.n_e = op->n_e;
+    p.h = op->h;
+    p.c_in = std::cos(2.0 * op->phi_in);
+    p.s_in = std::sin(2.0 * op->phi_in);
+    p.c_out = std::cos(2.0 * op->phi_out);
+    p.s_out = std::sin(2.0 * op->phi_out);
+    p.nwl = op->n_wavelengths;
+    for (int k = 0; k < p.nwl; ++k) {
+        if (!(op->wavelength[k] > 0.0) || !std::isfinite(op->wavelength[k]) || !std::isfinite(op->weight[k]))
+            return set_error(c, HLB_ERR_ARG, "optics: wavelength %d must be positive, weight finite", k);
+        p.lam[k] = op->wavelength[k];
+        p.w[k] = op->weight[k];
+    }
+    // scratch: the population buffer that does not hold the state; the image
+    // first, the per-segment transfer matrices after it
+    const size_t cols = size_t(c->D.G.nx) * c->D.G.ny;
+    const size_t e = c->D.fp32 ? 4 : 8;
+    const size_t stage_bytes = size_t(19) * c->D.G.N * e;
+    double *st = stage_of(c);
+    const size_t img_bytes = (cols * 8 + 255) & ~size_t(255);
+    double *Tm = st + img_bytes / 8;
+    const size_t tm_bytes = stage_bytes - img_bytes;
+    if (hlb::optics_segments(c->D.G, p.nwl, tm_bytes) < 1)
+        return set_error(c, HLB_ERR_NOMEM, "optics: lattice too small for the transfer-matrix scratch");
+    HIP_TRY(c, hlb::run_optics(c->D, p, Tm, tm_bytes, st));
+    HIP_TRY(c, hipMemcpyAsync(image, st, cols * 8, hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
     return HLB_OK;
 }
 

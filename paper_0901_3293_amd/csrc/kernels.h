@@ -84,4 +84,18 @@ hipError_t run_fz(Device &D, const PhysParams &p, double *fz);
 // defect[N] = (q < threshold), cnt[nz] defect sites per z-plane (FP64).
 hipError_t run_order(Device &D, double threshold, double *q, double *dir, unsigned char *defect, double *cnt);
 
+// Polarised-light texture (Mueller retarder stack along z per column).
+constexpr int OPTICS_MAX_WL = 8;
+struct OpticsParams {
+    double n_o, n_e, h;
+    double c_in, s_in, c_out, s_out;  // cos, sin of twice the polariser / analyser angle
+    int nwl;
+    double lam[OPTICS_MAX_WL], w[OPTICS_MAX_WL];
+};
+// Segments per column for tm_bytes of transfer-matrix scratch (0: too small).
+int optics_segments(const Geom &G, int nwl, size_t tm_bytes);
+// image[ny][nx] (device, FP64): weighted S0 behind the analyser.  Tm: device
+// scratch of tm_bytes (per-segment 3x3 transfer matrices), not aliasing image.
+hipError_t run_optics(Device &D, const OpticsParams &op, double *Tm, size_t tm_bytes, double *image);
+
 }  // namespace hlb

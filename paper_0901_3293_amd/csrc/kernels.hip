@@ -688,6 +688,112 @@ __global__ __launch_bounds__(BLK) void k_order(Geom G, const T *__restrict__ Q, 
     if (defect) defect[s] = lam < threshold ? 1 : 0;
 }
 
+// Polarised-light texture of the current Q (Sec. 2.3), the beam along +z
+// (layer z = 0 first).  Unpolarised light behind the polariser at angle
+// phi_in is S = (1, cos 2phi_in, sin 2phi_in, 0)/2; each site acts as a linear
+// retarder with axis angle beta to x (cos 2beta = (dx^2 - dy^2)/(dx^2 + dy^2),
+// sin 2beta = 2 dx dy/(dx^2 + dy^2)) and retardance
+// delta = 2 pi q h / lambda (n_o n_e / sqrt(n_o^2 sin^2 alpha + n_e^2 cos^2 alpha) - n_o),
+// cos alpha = d_z, from the FP64 local order q and director d (order_site).
+// A retarder leaves S0 unchanged and acts on (S1, S2, S3) by a 3x3 block; the
+// analyser at phi_out passes (S0 + cos 2phi_out S1 + sin 2phi_out S2)/2.
+//
+// Per group of up to OPT_G wavelengths, two kernels: k_optics_seg, one thread
+// per (column, z-segment), multiplies its segment's 3x3 blocks (later layers
+// on the left) into T[seg][g][9][col]; k_optics_compose, one thread per
+// column, applies the segments in order to the polarised input and adds the
+// group's weighted analyser output to the image.  FP64 throughout.
+constexpr int OPT_G = 3;
+
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_optics_seg(Geom G, const T *__restrict__ Q, OpticsParams op, int wl0,
+                                                    int seglen, int nseg, double *__restrict__ Tm)
+{
+    const int cols = G.nx * G.ny;
+    const int id = blockIdx.x * BLK + int(threadIdx.x);
+    if (id >= cols * nseg) return;
+    const int col = id % cols, seg = id / cols;
+    const int z0 = seg * seglen, z1 = min(G.nz, z0 + seglen);
+    const size_t N = G.N;
+    double M[OPT_G][9];
+#pragma unroll
+    for (int g = 0; g < OPT_G; ++g)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) M[g][k] = (k % 4 == 0) ? 1.0 : 0.0;
+    const double two_pi_h = 2.0 * 3.14159265358979323846 * op.h;
+    const double no2 = op.n_o * op.n_o, ne2 = op.n_e * op.n_e, none = op.n_o * op.n_e;
+#pragma unroll 1
+    for (int z = z0; z < z1; ++z) {
+        const size_t s = size_t(z) * cols + col;
+        double q5[5], qo, d[3];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) q5[k] = double(Q[k * N + s]);
+        order_site(q5, qo, d);
+        const double r2 = d[0] * d[0] + d[1] * d[1];
+        double c = 1.0, sn = 0.0;
+        if (r2 > 0.0) {
+            c = (d[0] * d[0] - d[1] * d[1]) / r2;
+            sn = 2.0 * d[0] * d[1] / r2;
+        }
+        const double cz = d[2] > 1.0 ? 1.0 : (d[2] < -1.0 ? -1.0 : d[2]);
+        const double sin2a = 1.0 - cz * cz;
+        const double base = two_pi_h * qo * (none / sqrt(no2 * sin2a + ne2 * cz * cz) - op.n_o);
+        const double cc = c * c, ss = sn * sn, cs = c * sn;
+#pragma unroll
+        for (int g = 0; g < OPT_G; ++g) {
+            if (wl0 + g >= op.nwl) break;
+            double sd, cd;
+            sincos(base / op.lam[wl0 + g], &sd, &cd);
+            const double R[9] = {cc + ss * cd, cs * (1.0 - cd), -sn * sd,
+                                 cs * (1.0 - cd), ss + cc * cd, c * sd,
+                                 sn * sd, -c * sd, cd};
+            double P[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    P[3 * a + b] = R[3 * a] * M[g][b] + R[3 * a + 1] * M[g][3 + b] + R[3 * a + 2] * M[g][6 + b];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) M[g][k] = P[k];
+        }
+    }
+    const int ng = min(OPT_G, op.nwl - wl0);
+#pragma unroll
+    for (int g = 0; g < OPT_G; ++g) {
+        if (g >= ng) break;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Tm[((size_t(seg) * ng + g) * 9 + k) * cols + col] = M[g][k];
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_optics_compose(int cols, int nseg, OpticsParams op, int wl0,
+                                                        const double *__restrict__ Tm, double *__restrict__ image)
+{
+    const int col = blockIdx.x * BLK + int(threadIdx.x);
+    if (col >= cols) return;
+    const int ng = min(OPT_G, op.nwl - wl0);
+    double out = 0.0;
+#pragma unroll 1
+    for (int g = 0; g < ng; ++g) {
+        const int w = wl0 + g;
+        double v[3] = {0.5 * op.c_in, 0.5 * op.s_in, 0.0};
+#pragma unroll 1
+        for (int seg = 0; seg < nseg; ++seg) {
+            const double *t = Tm + (size_t(seg) * ng + g) * 9 * size_t(cols) + col;
+            double u[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                u[a] = t[(3 * a) * size_t(cols)] * v[0] + t[(3 * a + 1) * size_t(cols)] * v[1] +
+                       t[(3 * a + 2) * size_t(cols)] * v[2];
+            v[0] = u[0];
+            v[1] = u[1];
+            v[2] = u[2];
+        }
+        out += op.w[w] * 0.5 * (0.5 + op.c_out * v[0] + op.s_out * v[1]);
+    }
+    image[col] = wl0 == 0 ? out : image[col] + out;
+}
+
 // Disclination sites per z-plane: block z counts plane z (exact integer
 // counts carried in FP64).
 __global__ __launch_bounds__(BLK) void k_plane_count(Geom G, const unsigned char *__restrict__ defect,
@@ -859,6 +965,38 @@ hipError_t run_order(Device &D, double threshold, double *q, double *dir, unsign
         k_order<double><<<nb, BLK, 0, D.stream>>>(D.G, static_cast<const double *>(D.Q[D.qcur]), threshold, q,
                                                   dir, defect);
     if (cnt) k_plane_count<<<D.G.nz, BLK, 0, D.stream>>>(D.G, defect, cnt);
+    return hipGetLastError();
+}
+
+int optics_segments(const Geom &G, int nwl, size_t scratch_bytes)
+{
+    const long long cols = (long long)G.nx * G.ny;
+    const int ng = nwl < OPT_G ? nwl : OPT_G;  // wavelengths per group
+    long long nseg = (262144 + cols - 1) / cols;  // enough threads to fill the device
+    if (nseg > G.nz) nseg = G.nz;
+    const long long cap = (long long)(scratch_bytes / (size_t(cols) * ng * 9 * 8));
+    if (nseg > cap) nseg = cap;
+    return int(nseg);
+}
+
+hipError_t run_optics(Device &D, const OpticsParams &op, double *Tm, size_t tm_bytes, double *image)
+{
+    const Geom G = D.G;
+    const int cols = G.nx * G.ny;
+    const int nseg = optics_segments(G, op.nwl, tm_bytes);
+    if (nseg < 1) return hipErrorInvalidValue;
+    const int seglen = (G.nz + nseg - 1) / nseg;
+    const int nseg_used = (G.nz + seglen - 1) / seglen;
+    const int nb = int((size_t(cols) * nseg_used + BLK - 1) / BLK);
+    for (int wl0 = 0; wl0 < op.nwl; wl0 += OPT_G) {
+        if (D.fp32)
+            k_optics_seg<float><<<nb, BLK, 0, D.stream>>>(G, static_cast<const float *>(D.Q[D.qcur]), op, wl0,
+                                                          seglen, nseg_used, Tm);
+        else
+            k_optics_seg<double><<<nb, BLK, 0, D.stream>>>(G, static_cast<const double *>(D.Q[D.qcur]), op, wl0,
+                                                           seglen, nseg_used, Tm);
+        k_optics_compose<<<(cols + BLK - 1) / BLK, BLK, 0, D.stream>>>(cols, nseg_used, op, wl0, Tm, image);
+    }
     return hipGetLastError();
 }
 

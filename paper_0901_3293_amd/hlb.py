@@ -8,6 +8,7 @@ built (``__graft_entry__.build()``); importing this module without it raises.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -36,6 +37,12 @@ class LbParams(ctypes.Structure):
 class FeParams(ctypes.Structure):
     _fields_ = [("A0", ctypes.c_double), ("gamma", ctypes.c_double), ("K", ctypes.c_double),
                 ("q0", ctypes.c_double)]
+
+
+class OpticsParams(ctypes.Structure):
+    _fields_ = [("n_o", ctypes.c_double), ("n_e", ctypes.c_double), ("h", ctypes.c_double),
+                ("phi_in", ctypes.c_double), ("phi_out", ctypes.c_double), ("n_wavelengths", ctypes.c_int),
+                ("wavelength", ctypes.c_double * 8), ("weight", ctypes.c_double * 8)]
 
 
 class BeParams(ctypes.Structure):
@@ -84,6 +91,7 @@ def lib():
         L.hlb_set_state.argtypes = [vp, vp, sz]
         L.hlb_get_fz.argtypes = [vp, dp]
         L.hlb_get_order.argtypes = [vp, ctypes.c_double, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.hlb_get_optics.argtypes = [vp, ctypes.POINTER(OpticsParams), dp]
         L.hlb_set_schedule.argtypes = [vp, I, I]
         L.hlb_get_schedule.argtypes = [vp, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.hlb_autotune.argtypes = [vp, I, dp]
@@ -246,6 +254,20 @@ class Solver:
                                         None if f is None else f.ctypes.data_as(ctypes.c_void_p),
                                         per_z.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
         return {"q": q, "dir": d, "defect": f, "per_z": per_z, "n_defect": int(n.value)}
+
+    def optics(self, wavelengths=(16.0, 18.0, 20.0), weights=(0.2, 0.6, 0.2), phi_in=0.0,
+               phi_out=math.pi / 2, n_o=1.5, n_e=2.0, h=1.0):
+        """Polarised-light texture: weighted S0 behind the analyser, [y][x]."""
+        if len(wavelengths) != len(weights) or not 1 <= len(wavelengths) <= 8:
+            raise ValueError("1..8 wavelengths with one weight each")
+        op = OpticsParams(n_o, n_e, h, phi_in, phi_out, len(wavelengths))
+        for k, (lam, w) in enumerate(zip(wavelengths, weights)):
+            op.wavelength[k] = lam
+            op.weight[k] = w
+        nx, ny, _ = self.shape
+        img = np.empty((ny, nx))
+        self._check(lib().hlb_get_optics(self.ctx, ctypes.byref(op), _dp(img)))
+        return img
 
     def totals(self):
         m = np.zeros(1)
