@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("Gamma", ctypes.c_double),
         ("xi", ctypes.c_double),
         ("flow", ctypes.c_int),
+        ("lb_model", ctypes.c_int),
     ]
 
 
@@ -58,9 +59,18 @@ def flow_code(flow=True, coupling="force") -> int:
     return 0 if not flow else (2 if coupling == "split" else 1)
 
 
+LB_MODELS = {"d3q19": 0, "d3q15": 1}
+
+
 def params(tau=2.5, rho0=1.0, A0=0.01, gamma=3.0, K=0.0, q0=0.0, Gamma=0.3, xi=0.7,
-           flow=True, coupling="force") -> Params:
-    return Params(tau, rho0, A0, gamma, K, q0, Gamma, xi, flow_code(flow, coupling))
+           flow=True, coupling="force", lb_model="d3q19") -> Params:
+    """lb_model: "d3q19" (BGK with second-order forcing) or "d3q15" (the
+    paper's predictor-corrector scheme)."""
+    return Params(tau, rho0, A0, gamma, K, q0, Gamma, xi, flow_code(flow, coupling), LB_MODELS[lb_model])
+
+
+def n_pop(p: Params) -> int:
+    return 15 if p.lb_model == 1 else 19
 
 
 _lib = None
@@ -85,6 +95,7 @@ def lib():
         L.or_lb.argtypes = [pp, I, I, I, dp, dp, dp, dp, dp]
         L.or_split.argtypes = [pp, I, I, I, dp, dp, dp]
         L.or_lb_split.argtypes = [pp, I, I, I, dp, dp, dp, dp, dp, dp]
+        L.or_lb_pc.argtypes = [pp, I, I, I, dp, dp, dp, dp, dp, dp]
         L.or_init_g.argtypes = [pp, I, I, I, dp, dp, dp]
         L.or_readout.argtypes = [pp, I, I, I, dp, dp, dp, dp]
         L.or_step.argtypes = [pp, I, I, I, dp, dp, I]
@@ -201,11 +212,29 @@ def lb_split(p: Params, g, b3, sig9):
     return gn, rho, u
 
 
+def lb_pc(p: Params, g, b3=None, sig9=None):
+    """One step of the paper's D3Q15 predictor-corrector LB with body force b3
+    and equilibrium stress sig9 (either may be None); returns (g_new, rho, u)
+    with rho, u the moments of the input populations."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    assert g.shape[0] == 15
+    nx, ny, nz = _shape(g)
+    if b3 is not None:
+        b3 = np.ascontiguousarray(b3, dtype=np.float64)
+    if sig9 is not None:
+        sig9 = np.ascontiguousarray(sig9, dtype=np.float64)
+    gn = np.empty_like(g)
+    rho = np.empty(g.shape[1:])
+    u = np.empty((3,) + g.shape[1:])
+    lib().or_lb_pc(ctypes.byref(p), nx, ny, nz, _p(g), _p(b3), _p(sig9), _p(gn), _p(rho), _p(u))
+    return gn, rho, u
+
+
 def init_g(p: Params, rho, u3):
     rho = np.ascontiguousarray(rho, dtype=np.float64)
     u3 = np.ascontiguousarray(u3, dtype=np.float64)
     nx, ny, nz = _shape(u3)
-    g = np.empty((19,) + rho.shape)
+    g = np.empty((n_pop(p),) + rho.shape)
     lib().or_init_g(ctypes.byref(p), nx, ny, nz, _p(rho), _p(u3), _p(g))
     return g
 

@@ -25,6 +25,11 @@
  *   body force b_a = d_b Pi_ab ... Sec. 2.2, Eq. (19): the whole chemical
  *                                  stress enters as a force (centred
  *                                  divergence on the second index)
+ *   D3Q15 predictor-corrector LB . Sec. 2.2, Eqs. (11)-(23): the paper's own
+ *                                  lattice, equilibrium and forcing terms as
+ *                                  the printed polynomial with the printed
+ *                                  coefficients, stepped by the trapezoidal
+ *                                  (predictor-corrector) rule of Eq. (15)
  *   split coupling ............... Sec. 2.2, Eqs. (17)-(21): the symmetric
  *                                  xi-stress enters the second moment of the
  *                                  equilibrium, the body force is the
@@ -58,7 +63,11 @@ typedef struct {
     double xi;     /* flow-aligning parameter, Eqs. (4), (7)              */
     int flow;      /* 0: u == 0 (Sec. 2.1); 1: coupled, whole stress as a
                     * body force; 2: coupled, split coupling (Sec. 2.2)  */
+    int lb_model;  /* 0: D3Q19 BGK with second-order forcing (pull);
+                    * 1: D3Q15 predictor-corrector of Sec. 2.2          */
 } or_params;
+
+static int n_pop(const or_params *p) { return p->lb_model == 1 ? 15 : 19; }
 
 /* ------------------------------------------------------------------------ */
 /* D3Q19 velocity set: rest, 6 faces, 12 edges; weights 1/3, 1/18, 1/36.     */
@@ -580,12 +589,151 @@ void or_lb_split(const or_params *p, int nx, int ny, int nz, const double *g_in,
     lb_step(p, nx, ny, nz, g_in, b3, sig9, g_out, rho_out, u3_out);
 }
 
+/* ------------------------------------------------------------------------ */
+/* The paper's own LB (Sec. 2.2): D3Q15 -- rest, 6 faces, 8 corners -- with
+ * the equilibrium and forcing term written as the printed polynomial
+ *   f_i^eq = A_s + B_s u.e + C_s u^2 + D_s (u.e)^2 + E_s:e e,  p_i = P_s b.e,
+ * s = 0, 1, 2 for |e|^2 = 0, 1, 3, and the printed coefficients (T = 1/3):
+ *   A_2 = rho T/10, A_1 = A_2, A_0 = rho - 14 A_2; B_2 = rho/24, B_1 = 8 B_2;
+ *   C_2 = -rho/24, C_1 = 2 C_2, C_0 = -2 rho/3; D_2 = rho/16, D_1 = 8 D_2;
+ *   E_2 = -(sigma - tr(sigma)/3 I)/16, E_1 = 8 E_2; P_2 = 1/24, P_1 = 8 P_2.
+ * Populations are carried as deviations g_i = f_i - A_s(rho0) and stored
+ * where they are (no pull offset): f_i(x, t) at x. */
+static const int E15[15][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+
+static const double T_LB = 1.0 / 3.0;
+
+/* Equilibrium deviation of velocity i (sig may be NULL: no stress term). */
+static double feq15(int i, double rho0, double rho, const double u[3], const double sig[3][3])
+{
+    const int s = i == 0 ? 0 : (i <= 6 ? 1 : 2);
+    const double ex = E15[i][0], ey = E15[i][1], ez = E15[i][2];
+    const double eu = ex * u[0] + ey * u[1] + ez * u[2];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double dr = rho - rho0;
+    const double A2 = dr * T_LB / 10.0;
+    double A, B, C, D, Es;
+    if (s == 0) {
+        A = dr - 14.0 * A2;
+        B = 0.0;
+        C = -2.0 * rho / 3.0;
+        D = 0.0;
+        Es = 0.0;
+    } else if (s == 1) {
+        A = A2;
+        B = 8.0 * rho / 24.0;
+        C = 2.0 * (-rho / 24.0);
+        D = 8.0 * rho / 16.0;
+        Es = 8.0;
+    } else {
+        A = A2;
+        B = rho / 24.0;
+        C = -rho / 24.0;
+        D = rho / 16.0;
+        Es = 1.0;
+    }
+    double v = A + B * eu + C * uu + D * eu * eu;
+    if (sig && Es != 0.0) {
+        const double e[3] = {ex, ey, ez};
+        const double tr3 = (sig[0][0] + sig[1][1] + sig[2][2]) / 3.0;
+        double see = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int c = 0; c < 3; c++) see += (sig[a][c] - (a == c ? tr3 : 0.0)) * e[a] * e[c];
+        v += Es * (-see / 16.0);
+    }
+    return v;
+}
+
+/* Forcing term p_i = P_s b.e (b may be NULL). */
+static double force15(int i, const double b[3])
+{
+    if (!b || i == 0) return 0.0;
+    const double P = i <= 6 ? 8.0 / 24.0 : 1.0 / 24.0;
+    return P * (E15[i][0] * b[0] + E15[i][1] * b[1] + E15[i][2] * b[2]);
+}
+
+/* Collision operator of Eq. (16) at one site for populations g (local
+ * moments, rho u = sum f e as in Eq. (14)), into C; returns rho and u. */
+static void collide15(const or_params *p, const double g[15], const double sig[3][3], const double b[3],
+                      double C[15], double *rho_out, double u[3])
+{
+    double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 15; i++) {
+        drho += g[i];
+        for (int a = 0; a < 3; a++) j[a] += g[i] * E15[i][a];
+    }
+    const double rho = p->rho0 + drho;
+    for (int a = 0; a < 3; a++) u[a] = j[a] / rho;
+    for (int i = 0; i < 15; i++) C[i] = -(g[i] - feq15(i, p->rho0, rho, u, sig)) / p->tau + force15(i, b);
+    *rho_out = rho;
+}
+
+/* One LB step of the paper's scheme, Eq. (15), with the equilibrium stress
+ * sig9 (9 planes, may be NULL) and the body force b3 (may be NULL) held over
+ * the step:
+ *   f*_i(x + e_i) = f_i(x) + C_i(x, {f}),
+ *   f_i(x + e_i, t + 1) = f_i(x) + [C_i(x, {f}) + C_i(x + e_i, {f*})] / 2.
+ * rho and u (may be NULL) are the moments of f(x, t) (Eq. (14), those of the
+ * first collision): the velocity u^n the Q update takes. */
+void or_lb_pc(const or_params *p, int nx, int ny, int nz, const double *g_in, const double *b3,
+              const double *sig9, double *g_out, double *rho_out, double *u3_out)
+{
+    long N = (long)nx * ny * nz;
+    double *P = (double *)malloc(sizeof(double) * 15 * N);  /* f + C at the departure site */
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; z++)
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++) {
+                long s = site(x, y, z, nx, ny, nz);
+                double g[15], C[15], u[3], rho, sig[3][3], b[3];
+                for (int i = 0; i < 15; i++) g[i] = g_in[i * N + s];
+                if (sig9)
+                    for (int a = 0; a < 9; a++) sig[a / 3][a % 3] = sig9[a * N + s];
+                for (int a = 0; a < 3; a++) b[a] = b3 ? b3[a * N + s] : 0.0;
+                collide15(p, g, sig9 ? sig : NULL, b, C, &rho, u);
+                for (int i = 0; i < 15; i++) P[i * N + s] = g[i] + C[i];
+                if (rho_out) rho_out[s] = rho;
+                if (u3_out)
+                    for (int a = 0; a < 3; a++) u3_out[a * N + s] = u[a];
+            }
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; z++)
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++) {
+                long s = site(x, y, z, nx, ny, nz);
+                double fs[15], fo[15], C[15], u[3], rho, sig[3][3], b[3];
+                for (int i = 0; i < 15; i++) {
+                    long t = site(x - E15[i][0], y - E15[i][1], z - E15[i][2], nx, ny, nz);
+                    fs[i] = P[i * N + t];
+                    fo[i] = 0.5 * (g_in[i * N + t] + P[i * N + t]);
+                }
+                if (sig9)
+                    for (int a = 0; a < 9; a++) sig[a / 3][a % 3] = sig9[a * N + s];
+                for (int a = 0; a < 3; a++) b[a] = b3 ? b3[a * N + s] : 0.0;
+                collide15(p, fs, sig9 ? sig : NULL, b, C, &rho, u);
+                for (int i = 0; i < 15; i++) g_out[i * N + s] = fo[i] + 0.5 * C[i];
+            }
+    free(P);
+}
+
 /* Populations stored so that the first pull returns g^eq(rho(x), u(x)) at
- * every site x:  g_i(y) = g_i^eq(rho(y + e_i), u(y + e_i)). */
+ * every site x:  g_i(y) = g_i^eq(rho(y + e_i), u(y + e_i)).  For the D3Q15
+ * scheme: g_i(x) = f_i^eq(rho(x), u(x)) - A_s(rho0) in place, without the
+ * stress and force terms. */
 void or_init_g(const or_params *p, int nx, int ny, int nz, const double *rho,
                const double *u3, double *g)
 {
     long N = (long)nx * ny * nz;
+    if (p->lb_model == 1) {
+        for (long s = 0; s < N; s++) {
+            double u[3] = {u3[s], u3[N + s], u3[2 * N + s]};
+            for (int i = 0; i < 15; i++) g[i * N + s] = feq15(i, p->rho0, rho[s], u, NULL);
+        }
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; z++)
         for (int y = 0; y < ny; y++)
@@ -605,6 +753,19 @@ void or_readout(const or_params *p, int nx, int ny, int nz, const double *g,
                 const double *Q9, double *rho_out, double *u3_out)
 {
     long N = (long)nx * ny * nz;
+    if (p->lb_model == 1) {  /* D3Q15: moments of the stored f(x), Eq. (14) */
+        for (long s = 0; s < N; s++) {
+            double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < 15; i++) {
+                drho += g[i * N + s];
+                for (int a = 0; a < 3; a++) j[a] += g[i * N + s] * E15[i][a];
+            }
+            double rho = p->rho0 + drho;
+            rho_out[s] = rho;
+            for (int a = 0; a < 3; a++) u3_out[a * N + s] = p->flow ? j[a] / rho : 0.0;
+        }
+        return;
+    }
     double *F3 = (double *)calloc(3 * N, sizeof(double));
     if (p->flow) coupling_force(p, nx, ny, nz, Q9, NULL, F3);
 #pragma omp parallel for schedule(static)
@@ -636,13 +797,16 @@ void or_step(const or_params *p, int nx, int ny, int nz, double *g, double *Q9, 
     double *F3 = (double *)malloc(sizeof(double) * 3 * N);
     double *sig9 = p->flow == 2 ? (double *)malloc(sizeof(double) * 9 * N) : NULL;
     double *u3 = (double *)calloc(3 * N, sizeof(double));
-    double *g2 = (double *)malloc(sizeof(double) * 19 * N);
+    double *g2 = (double *)malloc(sizeof(double) * n_pop(p) * N);
     double *Qn = (double *)malloc(sizeof(double) * 9 * N);
     for (int n = 0; n < nsteps; n++) {
         if (p->flow) {
             coupling_force(p, nx, ny, nz, Q9, sig9, F3);
-            lb_step(p, nx, ny, nz, g, F3, sig9, g2, NULL, u3);
-            memcpy(g, g2, sizeof(double) * 19 * N);
+            if (p->lb_model == 1)
+                or_lb_pc(p, nx, ny, nz, g, F3, sig9, g2, NULL, u3);
+            else
+                lb_step(p, nx, ny, nz, g, F3, sig9, g2, NULL, u3);
+            memcpy(g, g2, sizeof(double) * n_pop(p) * N);
         }
         or_qupdate(p, nx, ny, nz, Q9, u3, Qn);
         memcpy(Q9, Qn, sizeof(double) * 9 * N);

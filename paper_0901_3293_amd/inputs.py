@@ -37,6 +37,7 @@ class PhysParams:
     xi: float = 0.7
     flow: bool = True
     coupling: str = "force"  # "force": whole stress as a body force; "split": Sec. 2.2 split
+    lb_model: str = "d3q19"  # "d3q19": BGK + second-order forcing; "d3q15": the paper's predictor-corrector
 
     def as_dict(self):
         return asdict(self)
