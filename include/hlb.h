@@ -52,12 +52,24 @@ typedef enum { HLB_FP64 = 0, HLB_FP32 = 1 } hlb_precision;
 /* Opaque solver context. */
 typedef struct hlb_ctx hlb_ctx;
 
-/* LB parameters (Sec. 2.2, Eq. (16)): BGK relaxation time tau (> 1/2), giving
- * kinematic viscosity (tau - 1/2)/3, and the reference density rho0 (> 0).
- * Populations are stored as deviations g_i = f_i - w_i rho0. */
+/* LB parameters (Sec. 2.2, Eq. (16)): relaxation time tau, reference density
+ * rho0 (> 0) and the scheme:
+ *   HLB_LB_D3Q19 (0): D3Q19 BGK, collide then pull-stream, second-order
+ *     (Guo) forcing with u = (sum f e + F/2)/rho; tau > 1/2, kinematic
+ *     viscosity (tau - 1/2)/3; populations stored as g_i = f_i - w_i rho0.
+ *   HLB_LB_D3Q15_PC (1): the paper's own scheme -- D3Q15 (rest, 6 faces, 8
+ *     corners), equilibrium and forcing term as the printed polynomial with
+ *     the printed coefficients (T = 1/3; the stress term carries the split
+ *     sigma^xi, the forcing term P_s b.e the body force), stepped by the
+ *     predictor-corrector rule of Eq. (15); u = sum f e / rho (Eq. (14));
+ *     tau > 0, kinematic viscosity tau/3; populations g_i = f_i - A_s(rho0)
+ *     at their own site.  Single-box contexts, sites or mixed schedule.
+ * Other values are rejected with HLB_ERR_PARAM. */
+enum { HLB_LB_D3Q19 = 0, HLB_LB_D3Q15_PC = 1 };
 typedef struct {
     double tau;
     double rho0;
+    int model;
 } hlb_lb_params;
 
 /* Landau-de Gennes free energy (Sec. 2.1, Eq. (1)): bulk scale A0 (> 0),
@@ -113,11 +125,13 @@ int hlb_create(int nx, int ny, int nz, int precision, void *device_workspace,
 int hlb_fe_from_reduced(double kappa, double tau_ldg, double q0, double A0,
                         hlb_fe_params *out);
 
-/* Set all physical parameters.  Rejected with HLB_ERR_PARAM: tau <= 1/2,
- * rho0 <= 0, A0 <= 0, gamma <= 0, K < 0, Gamma <= 0, the explicit diffusion
- * bound 12 Gamma K >= 2 of the forward-Euler predictor, and an unknown
- * flow_coupling; HLB_ERR_STATE for the split coupling while the tiled
- * schedule is selected.  Must be called before hlb_set_fields. */
+/* Set all physical parameters.  Rejected with HLB_ERR_PARAM: tau <= 1/2
+ * (D3Q19) or <= 0 (D3Q15), rho0 <= 0, A0 <= 0, gamma <= 0, K < 0,
+ * Gamma <= 0, the explicit diffusion bound 12 Gamma K >= 2 of the
+ * forward-Euler predictor, an unknown flow_coupling or LB model;
+ * HLB_ERR_STATE for the split coupling or the D3Q15 scheme while the tiled
+ * schedule is selected.  Must be called before hlb_set_fields; changing the
+ * LB model invalidates the fields (call hlb_set_fields again). */
 int hlb_set_params(hlb_ctx *ctx, const hlb_lb_params *lb, const hlb_fe_params *fe,
                    const hlb_be_params *be);
 
@@ -198,13 +212,14 @@ int hlb_set_state(hlb_ctx *ctx, const void *host_buf, size_t nbytes);
  * ring), tz planes per tile column (0: 16).  HLB_SCHED_MIXED: the per-site
  * stress and LB sweeps, then the tiled predictor-corrector.  All give the
  * same step to rounding.  The default is HLB_SCHED_SITES.  With the split
- * coupling, HLB_SCHED_TILED is rejected (HLB_ERR_STATE). */
+ * coupling or the D3Q15 scheme, HLB_SCHED_TILED is rejected (HLB_ERR_STATE). */
 enum { HLB_SCHED_SITES = 0, HLB_SCHED_TILED = 1, HLB_SCHED_MIXED = 2 };
 int hlb_set_schedule(hlb_ctx *ctx, int schedule, int tz);
 int hlb_get_schedule(const hlb_ctx *ctx, int *schedule, int *tz);
 
 /* Autotuner: time trial_steps steps of every candidate schedule (per-site;
- * tiled and mixed with tz = 8, 16, 32; no tiled with the split coupling) on
+ * tiled and mixed with tz = 8, 16, 32; no tiled with the split coupling or
+ * the D3Q15 scheme) on
  * this context's lattice and precision with HIP
  * events on its stream, keep the fastest, and put the state back as it was
  * (through a host copy of hlb_state_bytes bytes).  *best_ms_per_step (may be
@@ -238,7 +253,8 @@ size_t hlb_batch_workspace_bytes(int n, const int *dims, int precision);
 int hlb_batch_create(int n, const int *dims, int precision, void *device_workspace, size_t workspace_bytes,
                      void *hip_stream, hlb_batch **out);
 /* Per box i in [0, n): same validation as hlb_set_params / hlb_set_fields;
- * flow_coupling must be HLB_FLOW_OFF or HLB_FLOW_FORCE (HLB_ERR_PARAM). */
+ * flow_coupling must be HLB_FLOW_OFF or HLB_FLOW_FORCE and the LB model
+ * HLB_LB_D3Q19 (HLB_ERR_PARAM). */
 int hlb_batch_set_params(hlb_batch *b, int i, const hlb_lb_params *lb, const hlb_fe_params *fe,
                          const hlb_be_params *be);
 int hlb_batch_set_fields(hlb_batch *b, int i, const double *Q5, const double *u3, const double *rho);

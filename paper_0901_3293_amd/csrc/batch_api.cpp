@@ -277,6 +277,7 @@ int hlb_batch_set_params(hlb_batch *b, int i, const hlb_lb_params *lb, const hlb
         return bset_error(b, HLB_ERR_PARAM, "box %d: parameters out of range", i);
     if (be->flow_coupling != HLB_FLOW_OFF && be->flow_coupling != HLB_FLOW_FORCE)
         return bset_error(b, HLB_ERR_PARAM, "box %d: the batched kernel takes flow_coupling 0 or 1", i);
+    if (lb->model != HLB_LB_D3Q19) return bset_error(b, HLB_ERR_PARAM, "box %d: the batched kernel runs D3Q19", i);
     b->par[i] = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi, be->flow_coupling};
     b->have_params[i] = 1;
     b->dirty = true;

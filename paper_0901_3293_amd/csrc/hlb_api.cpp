@@ -21,7 +21,7 @@ static_assert(HLB_OPTICS_MAX_WAVELENGTHS == hlb::OPTICS_MAX_WL, "optics waveleng
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, Q, u, Pi, part, res, total;
+    size_t g, Q, u, Pi, aux, part, res, total;
 };
 
 bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
@@ -36,9 +36,10 @@ bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
     L.Q = align256(5 * N * e);
     L.u = align256(3 * N * e);
     L.Pi = align256(12 * N * e);
+    L.aux = align256(15 * N * e);
     L.part = align256(hlb::partial_doubles(nx, ny, nz) * 8);
     L.res = 256;
-    L.total = 2 * L.g + 2 * L.Q + L.u + L.Pi + L.part + L.res;
+    L.total = 2 * L.g + 2 * L.Q + L.u + L.Pi + L.aux + L.part + L.res;
     return true;
 }
 
@@ -105,6 +106,7 @@ int hlb_create(int nx, int ny, int nz, int precision, void *ws, size_t ws_bytes,
     c->D.Q[1] = p; p += L.Q;
     c->D.u = p; p += L.u;
     c->D.Pi = p; p += L.Pi;
+    c->D.aux = p; p += L.aux;
     c->D.part = reinterpret_cast<double *>(p); p += L.part;
     c->D.res = reinterpret_cast<double *>(p);
     c->D.stream = static_cast<hipStream_t>(stream);
@@ -130,7 +132,14 @@ int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe,
 {
     HLB_GUARD(c);
     if (!lb || !fe || !be) return set_error(c, HLB_ERR_ARG, "null parameter struct");
-    if (!(lb->tau > 0.5)) return set_error(c, HLB_ERR_PARAM, "tau = %g must exceed 1/2", lb->tau);
+    if (lb->model != HLB_LB_D3Q19 && lb->model != HLB_LB_D3Q15_PC)
+        return set_error(c, HLB_ERR_PARAM, "LB model %d is not one of 0, 1", lb->model);
+    if (lb->model == HLB_LB_D3Q19 && !(lb->tau > 0.5))
+        return set_error(c, HLB_ERR_PARAM, "tau = %g must exceed 1/2", lb->tau);
+    if (lb->model == HLB_LB_D3Q15_PC && !(lb->tau > 0.0))
+        return set_error(c, HLB_ERR_PARAM, "tau = %g must be positive", lb->tau);
+    if (lb->model == HLB_LB_D3Q15_PC && c->D.sched == HLB_SCHED_TILED)
+        return set_error(c, HLB_ERR_STATE, "the D3Q15 scheme needs the sites or mixed schedule");
     if (!(lb->rho0 > 0.0)) return set_error(c, HLB_ERR_PARAM, "rho0 = %g must be positive", lb->rho0);
     if (!(fe->A0 > 0.0)) return set_error(c, HLB_ERR_PARAM, "A0 = %g must be positive", fe->A0);
     if (!(fe->gamma > 0.0)) return set_error(c, HLB_ERR_PARAM, "gamma = %g must be positive", fe->gamma);
@@ -145,7 +154,8 @@ int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe,
     if (!(12.0 * be->Gamma * fe->K < 2.0))
         return set_error(c, HLB_ERR_PARAM, "12 Gamma K = %g violates the explicit diffusion bound 2",
                          12.0 * be->Gamma * fe->K);
-    c->p = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi, be->flow_coupling};
+    if (c->have_params && c->p.model != lb->model) c->have_fields = false;  // state layout differs
+    c->p = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi, be->flow_coupling, lb->model};
     c->have_params = true;
     ++c->version;
     return HLB_OK;
@@ -222,6 +232,8 @@ int hlb_set_schedule(hlb_ctx *c, int schedule, int tz)
         return set_error(c, HLB_ERR_ARG, "schedule %d / tz %d", schedule, tz);
     if (schedule == HLB_SCHED_TILED && c->have_params && c->p.flow == HLB_FLOW_SPLIT)
         return set_error(c, HLB_ERR_STATE, "the tiled schedule carries the whole-stress force only");
+    if (schedule == HLB_SCHED_TILED && c->have_params && c->p.model == HLB_LB_D3Q15_PC)
+        return set_error(c, HLB_ERR_STATE, "the tiled schedule runs the D3Q19 LB only");
     c->D.sched = schedule;
     c->D.tz = tz;
     return HLB_OK;
@@ -258,7 +270,7 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
     Cand pick = cands[0];
     for (const Cand &k : cands) {
         if (k.sched != HLB_SCHED_SITES && k.tz > c->D.G.nz && k.tz != 8) continue;
-        if (k.sched == HLB_SCHED_TILED && c->p.flow == HLB_FLOW_SPLIT) continue;
+        if (k.sched == HLB_SCHED_TILED && (c->p.flow == HLB_FLOW_SPLIT || c->p.model == HLB_LB_D3Q15_PC)) continue;
         c->D.sched = k.sched;
         c->D.tz = k.tz;
         hipError_t e = hlb::run_steps(c->D, c->p, 2);  // warm-up

@@ -18,11 +18,16 @@ struct Geom {
 enum Flow { FLOW_OFF = 0, FLOW_FORCE = 1, FLOW_SPLIT = 2 };
 
 // Parameters of one run in FP64 (converted to the arithmetic type per launch).
+// Lattice-Boltzmann scheme: D3Q19 BGK with second-order forcing (pull), or
+// the paper's D3Q15 predictor-corrector (Sec. 2.2, Eq. (15)).
+enum LbModel { LB_D3Q19 = 0, LB_D3Q15_PC = 1 };
+
 struct PhysParams {
     double tau, rho0;
     double A0, gamma, K, q0;
     double Gamma, xi;
-    int flow;  // Flow
+    int flow;   // Flow
+    int model;  // LbModel
 };
 
 // Step schedules (see kernels.hip).
@@ -37,6 +42,7 @@ struct Device {
     void *Q[2];    // 5 x N each; Q[qcur] holds the state
     void *u;       // 3 x N
     void *Pi;      // 12 x N: stress (9; F in its first 3 for the tiled schedule) or split terms (12)
+    void *aux;     // 15 x N: predictor populations of the D3Q15 scheme
     double *part;  // partial_doubles(nx, ny, nz)
     double *res;   // 16 doubles of reduced totals
     int gcur, qcur;
@@ -51,7 +57,8 @@ size_t partial_doubles(int nx, int ny, int nz);
 enum KernelKind {
     K_STRESS = 0, K_LB = 1, K_QPRED = 2, K_QCORR = 3,  // per-site schedule
     K_QFORCE = 4, K_LBF = 5, K_QUPDATE = 6,            // tiled schedule
-    K_COUNT = 7
+    K_PC1 = 7, K_PC2 = 8,                              // D3Q15 predictor-corrector LB
+    K_COUNT = 9
 };
 const char *kernel_name(int k);
 

@@ -479,6 +479,79 @@ __global__ __launch_bounds__(BLK) void k_qcorr(Geom G, Coef<T> c, T *__restrict_
     if (s < G.N) corr_at(G, c, Q, Qs, u, s);
 }
 
+// D3Q15 predictor-corrector LB, the two passes (see pc1_at, pc2_at).
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(BLK) void k_pc1(Geom G, Coef<T> c, const T *__restrict__ g, const T *__restrict__ Pi,
+                                             T *__restrict__ P, T *__restrict__ u, T *__restrict__ bsave)
+{
+    const int s = site_index();
+    if (s < G.N) pc1_at<T, SPLIT>(G, c, g, Pi, P, u, bsave, s);
+}
+
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(BLK) void k_pc2(Geom G, Coef<T> c, const T *__restrict__ g, const T *__restrict__ P,
+                                             const T *__restrict__ Pi, const T *__restrict__ bsave,
+                                             T *__restrict__ gout)
+{
+    const int s = site_index();
+    if (s < G.N) pc2_at<T, SPLIT>(G, c, g, P, Pi, bsave, gout, s);
+}
+
+// D3Q15 state from (rho, u): g_i(x) = f_i^eq(rho(x), u(x)) - A_s(rho0) in
+// place, without stress or force terms; Q converted to the storage type.
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_init15(Geom G, Coef<T> c, const double *__restrict__ rho_in,
+                                                const double *__restrict__ u_in, const double *__restrict__ Q_in,
+                                                T *__restrict__ g, T *__restrict__ Q)
+{
+    const int s = site_index();
+    if (s >= G.N) return;
+    const size_t N = G.N;
+    const T uu3[3] = {T(u_in[s]), T(u_in[N + s]), T(u_in[2 * N + s])};
+    const T uu = uu3[0] * uu3[0] + uu3[1] * uu3[1] + uu3[2] * uu3[2];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) g[i * N + s] = lb15_eq(i, c.rho0, T(rho_in[s]), uu3, uu, static_cast<const T *>(nullptr));
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Q[k * N + s] = T(Q_in[k * N + s]);
+}
+
+// D3Q15 readout: rho and u = sum f e / rho of the stored populations
+// (Eq. (14); u == 0 with the flow off), Q in FP64, FP64 block partials.
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_readout15(Geom G, Coef<T> c, const T *__restrict__ g, bool flow,
+                                                   const T *__restrict__ Q, double *__restrict__ rho_out,
+                                                   double *__restrict__ u_out, double *__restrict__ Q_out,
+                                                   double *__restrict__ part)
+{
+    const int s = site_index();
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (s < G.N) {
+        const size_t N = G.N;
+        T drho = T(0), j[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int i = 0; i < 15; ++i) {
+            const T f = g[i * N + s];
+            drho += f;
+            j[0] += T(DX15[i]) * f;
+            j[1] += T(DY15[i]) * f;
+            j[2] += T(DZ15[i]) * f;
+        }
+        const T rho = c.rho0 + drho;
+        if (rho_out) rho_out[s] = double(rho);
+        if (u_out)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) u_out[a * N + s] = flow ? double(j[a] / rho) : 0.0;
+        if (Q_out)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) Q_out[k * N + s] = double(Q[k * N + s]);
+        v[0] = double(drho);
+        if (flow)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[1 + a] = double(j[a]);
+    }
+    if (part) block_sum<4, BLK>(v, part + 4 * logical_block());
+}
+
 // LB with a precomputed body force (tiled schedule).
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_lbf(Geom G, Coef<T> c, const T *__restrict__ gin,
@@ -847,7 +920,9 @@ int tile_tz(const Device &D) { return D.tz > 0 ? D.tz : 16; }
 template <typename T, bool SPLIT>
 hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer)
 {
-    if (SPLIT && D.sched == SCHED_TILED) return hipErrorNotSupported;  // tiled kernels carry the whole stress only
+    // the tiled kernels carry the whole stress and the D3Q19 LB only
+    if ((SPLIT || p.model == LB_D3Q15_PC) && D.sched == SCHED_TILED) return hipErrorNotSupported;
+    const bool pc = p.model == LB_D3Q15_PC;
     const Geom G = D.G;
     const Coef<T> c = make_coef<T>(p);
     const int nb = site_blocks(G.N);
@@ -866,8 +941,20 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
                 T *gin = static_cast<T *>(D.g[D.gcur]);
                 T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
                 e = mark(K_STRESS, [&] { k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr); });
-                if (e == hipSuccess)
+                if (pc) {
+                    T *P = static_cast<T *>(D.aux);
+                    T *bsave = gout + 15 * size_t(G.N);  // planes 15..17 of the target buffer
+                    if (e == hipSuccess)
+                        e = mark(K_PC1, [&] {
+                            k_pc1<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, P, u, bsave);
+                        });
+                    if (e == hipSuccess)
+                        e = mark(K_PC2, [&] {
+                            k_pc2<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, gin, P, Pi, bsave, gout);
+                        });
+                } else if (e == hipSuccess) {
                     e = mark(K_LB, [&] { k_lb<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
+                }
                 D.gcur ^= 1;
             }
             if (fused_q) {
@@ -916,8 +1003,12 @@ hipError_t init_t(Device &D, const PhysParams &p, const double *stage)
     const Coef<T> c = make_coef<T>(p);
     const size_t N = G.N;
     const int nb = site_blocks(G.N);
-    k_init<T><<<nb, BLK, 0, D.stream>>>(G, c, stage, stage + N, stage + 4 * N, static_cast<T *>(D.g[D.gcur]),
-                                        static_cast<T *>(D.Q[D.qcur]));
+    if (p.model == LB_D3Q15_PC)
+        k_init15<T><<<nb, BLK, 0, D.stream>>>(G, c, stage, stage + N, stage + 4 * N,
+                                              static_cast<T *>(D.g[D.gcur]), static_cast<T *>(D.Q[D.qcur]));
+    else
+        k_init<T><<<nb, BLK, 0, D.stream>>>(G, c, stage, stage + N, stage + 4 * N,
+                                            static_cast<T *>(D.g[D.gcur]), static_cast<T *>(D.Q[D.qcur]));
     // u of the last LB step: zero until the first step (and for good with flow off)
     k_fill<T><<<1024, BLK, 0, D.stream>>>(static_cast<T *>(D.u), 3 * N, T(0));
     return hipGetLastError();
@@ -932,6 +1023,18 @@ hipError_t readout_t(Device &D, const PhysParams &p, double *stage, double *tota
     const int nb = site_blocks(G.N);
     T *Pi = static_cast<T *>(D.Pi);
     const T *Q = static_cast<const T *>(D.Q[D.qcur]);
+    if (p.model == LB_D3Q15_PC) {
+        // the stress sweep only for the free-energy partials
+        if (totals) k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, D.part + 4 * nb);
+        k_readout15<T><<<nb, BLK, 0, D.stream>>>(G, c, static_cast<const T *>(D.g[D.gcur]), p.flow != 0, Q, stage,
+                                                 stage ? stage + N : nullptr, stage ? stage + 4 * N : nullptr,
+                                                 totals ? D.part : nullptr);
+        if (totals) {
+            k_reduce<<<1, BLK, 0, D.stream>>>(D.part, nb, 4, 4, D.res);
+            k_reduce<<<1, BLK, 0, D.stream>>>(D.part + 4 * nb, nb, 1, 1, D.res + 4);
+        }
+        return hipGetLastError();
+    }
     if (totals)
         k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, D.part + 4 * nb);
     else if (p.flow)
@@ -1015,7 +1118,7 @@ size_t partial_doubles(int nx, int ny, int nz)
 const char *kernel_name(int k)
 {
     static const char *names[K_COUNT] = {"k_stress", "k_lb", "k_qpred", "k_qcorr", "k_qforce", "k_lbf",
-                                         "k_qupdate"};
+                                         "k_qupdate", "k_pc1", "k_pc2"};
     return (k >= 0 && k < K_COUNT) ? names[k] : nullptr;
 }
 

@@ -375,6 +375,74 @@ __device__ __forceinline__ void lb_collide_split(const Coef<T> &c, T g[19], cons
     }
 }
 
+// ---------------------------------------------------------------- D3Q15
+// The paper's own lattice (Sec. 2.2): rest, 6 faces, 8 corners, in this
+// order; populations stored as deviations g_i = f_i - A_s(rho0) at their own
+// site (no pull offset).
+constexpr int DX15[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+constexpr int DY15[15] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1};
+constexpr int DZ15[15] = {0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1};
+
+// Equilibrium deviation of velocity i, the printed polynomial
+//   A_s + B_s u.e + C_s u^2 + D_s (u.e)^2 + E_s:e e
+// with the printed coefficients at T = 1/3: A_1 = A_2 = rho/30,
+// A_0 = rho - 14 A_2; B = (rho/3, rho/24); C = (-2rho/3, -rho/12, -rho/24);
+// D = (rho/2, rho/16); E_2 = -(sig - tr(sig)/3 I)/16, E_1 = 8 E_2 (faces,
+// corners).  sig: upper triangle xx, xy, xz, yy, yz, zz (null: no stress).
+template <typename T>
+__device__ __forceinline__ T lb15_eq(int i, T rho0, T rho, const T u[3], T uu, const T *sig)
+{
+    const T ex = T(DX15[i]), ey = T(DY15[i]), ez = T(DZ15[i]);
+    const T eu = ex * u[0] + ey * u[1] + ez * u[2];
+    const T dr = rho - rho0;
+    T v;
+    if (i == 0) {
+        v = dr - T(14) * (dr / T(30)) - T(2) * rho / T(3) * uu;
+    } else if (i <= 6) {
+        v = dr / T(30) + rho / T(3) * eu - rho / T(12) * uu + rho / T(2) * eu * eu;
+    } else {
+        v = dr / T(30) + rho / T(24) * eu - rho / T(24) * uu + rho / T(16) * eu * eu;
+    }
+    if (sig && i > 0) {
+        const T tr3 = (sig[0] + sig[3] + sig[5]) / T(3);
+        const T see = (sig[0] - tr3) * ex * ex + (sig[3] - tr3) * ey * ey + (sig[5] - tr3) * ez * ez
+                    + T(2) * (sig[1] * ex * ey + sig[2] * ex * ez + sig[4] * ey * ez);
+        v -= (i <= 6 ? T(8) : T(1)) * see / T(16);
+    }
+    return v;
+}
+
+// Forcing term p_i = P_s b.e with P_1 = 1/3, P_2 = 1/24.
+template <typename T>
+__device__ __forceinline__ T lb15_force(int i, const T b[3])
+{
+    if (i == 0) return T(0);
+    const T eb = T(DX15[i]) * b[0] + T(DY15[i]) * b[1] + T(DZ15[i]) * b[2];
+    return (i <= 6 ? T(1) / T(3) : T(1) / T(24)) * eb;
+}
+
+// Collision operator of Eq. (16) on D3Q15 at one site: local moments
+// (rho u = sum f e, Eq. (14)), C_i = -(g_i - g_i^eq)/tau + p_i.
+template <typename T>
+__device__ __forceinline__ void lb15_collide(const Coef<T> &c, const T g[15], const T *sig, const T b[3], T C[15],
+                                             T u[3], T &rho)
+{
+    T drho = T(0), j[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+        drho += g[i];
+        j[0] += T(DX15[i]) * g[i];
+        j[1] += T(DY15[i]) * g[i];
+        j[2] += T(DZ15[i]) * g[i];
+    }
+    rho = c.rho0 + drho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = j[a] / rho;
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) C[i] = -(g[i] - lb15_eq(i, c.rho0, rho, u, uu, sig)) * c.omega + lb15_force(i, b);
+}
+
 // Equilibrium deviation for initialisation.
 template <typename T>
 __device__ __forceinline__ T lb_geq(const Coef<T> &c, int i, T rho, const T u[3])

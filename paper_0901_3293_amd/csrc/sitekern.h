@@ -182,6 +182,65 @@ __device__ __forceinline__ void lb_split_at(const Geom &G, const Coef<T> &c, con
     for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
 }
 
+// D3Q15 predictor-corrector LB (Eq. (15)), first pass at one site x: the
+// collision C(x, {f}) of the local populations with the stress and body force
+// of this step (split: sigma^xi from the 12-plane layout and b = div tau + h;
+// whole-stress coupling: no stress term and b = div Pi); writes the
+// predictor populations P = f + C at x (to be streamed), the velocity u^n of
+// f(x, t) and b (3 planes, read back by the second pass at the same site).
+template <typename T, bool SPLIT>
+__device__ __forceinline__ void pc1_at(const Geom &G, const Coef<T> &c, const T *__restrict__ g,
+                                       const T *__restrict__ Pi, T *__restrict__ P, T *__restrict__ u,
+                                       T *__restrict__ bsave, int s)
+{
+    const size_t N = G.N;
+    const Nbr S = nbr_of(G, s);
+    T f[15], C[15], b[3], sig[6], uu[3], rho;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) f[i] = g[i * N + s];
+    if (SPLIT) {
+        split_force(Pi, N, S, b);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sig[k] = Pi[k * N + s];
+    } else {
+        divergence(Pi, N, S, b);
+    }
+    lb15_collide(c, f, SPLIT ? sig : static_cast<const T *>(nullptr), b, C, uu, rho);
+#pragma unroll
+    for (int i = 0; i < 15; ++i) P[i * N + s] = f[i] + C[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u[a * N + s] = uu[a];
+        bsave[a * N + s] = b[a];
+    }
+}
+
+// Second pass at one site y: f*_i(y) = P_i(y - e_i), collision C(y, {f*}),
+//   f_i(y, t + 1) = [f_i(y - e_i) + P_i(y - e_i)]/2 + C_i(y, {f*})/2.
+template <typename T, bool SPLIT>
+__device__ __forceinline__ void pc2_at(const Geom &G, const Coef<T> &c, const T *__restrict__ g,
+                                       const T *__restrict__ P, const T *__restrict__ Pi,
+                                       const T *__restrict__ bsave, T *__restrict__ gout, int s)
+{
+    const size_t N = G.N;
+    const Nbr S = nbr_of(G, s);
+    T fs[15], fo[15], C[15], b[3], sig[6], uu[3], rho;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+        const int t = pull_from(G, S, DX15[i], DY15[i], DZ15[i]);
+        fs[i] = P[i * N + t];
+        fo[i] = T(0.5) * (g[i * N + t] + fs[i]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) b[a] = bsave[a * N + s];
+    if (SPLIT)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sig[k] = Pi[k * N + s];
+    lb15_collide(c, fs, SPLIT ? sig : static_cast<const T *>(nullptr), b, C, uu, rho);
+#pragma unroll
+    for (int i = 0; i < 15; ++i) gout[i * N + s] = fo[i] + T(0.5) * C[i];
+}
+
 // Predictor Q* = Q + R(Q, u) at one site (Eqs. (2)-(4)).
 template <typename T>
 __device__ __forceinline__ void pred_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q,

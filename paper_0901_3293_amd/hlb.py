@@ -31,7 +31,18 @@ class HlbError(RuntimeError):
 
 
 class LbParams(ctypes.Structure):
-    _fields_ = [("tau", ctypes.c_double), ("rho0", ctypes.c_double)]
+    _fields_ = [("tau", ctypes.c_double), ("rho0", ctypes.c_double), ("model", ctypes.c_int)]
+
+
+LB_MODELS = {"d3q19": 0, "d3q15": 1}
+
+
+def lb_model_code(p):
+    """model of the C-ABI from p.lb_model ("d3q19" when absent)."""
+    m = getattr(p, "lb_model", "d3q19")
+    if m not in LB_MODELS:
+        raise ValueError(f"lb_model {m!r}: one of {sorted(LB_MODELS)}")
+    return LB_MODELS[m]
 
 
 class FeParams(ctypes.Structure):
@@ -180,7 +191,7 @@ class Solver:
 
     def set_params(self, p):
         """p: any object with tau, rho0, A0, gamma, K, q0, Gamma, xi, flow."""
-        lb = LbParams(p.tau, p.rho0)
+        lb = LbParams(p.tau, p.rho0, lb_model_code(p))
         fe = FeParams(p.A0, p.gamma, p.K, p.q0)
         be = BeParams(p.Gamma, p.xi, flow_code(p))
         self._check(lib().hlb_set_params(self.ctx, ctypes.byref(lb), ctypes.byref(fe), ctypes.byref(be)))
@@ -332,7 +343,7 @@ class Batch:
         return rc
 
     def set_params(self, i, p):
-        lb = LbParams(p.tau, p.rho0)
+        lb = LbParams(p.tau, p.rho0, lb_model_code(p))
         fe = FeParams(p.A0, p.gamma, p.K, p.q0)
         be = BeParams(p.Gamma, p.xi, flow_code(p))
         self._check(lib().hlb_batch_set_params(self.b, i, ctypes.byref(lb), ctypes.byref(fe), ctypes.byref(be)))

@@ -4,7 +4,9 @@ differs (the oracle built as usual vs the same source built with FMA
 contraction).  The velocity is a small difference of O(1e-4) stresses, so its
 relative spread sits well above 1e-12; the GPU bound for u is stated relative
 to this spread.  Calls only the oracle.  `--split` writes
-fp64_spread_split.json for the same run with the split coupling of Sec. 2.2."""
+fp64_spread_split.json for the same run with the split coupling of Sec. 2.2;
+with `--d3q15` as well, fp64_spread_split_d3q15.json for the paper's D3Q15
+predictor-corrector LB."""
 import json
 import os
 import subprocess
@@ -17,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 
-def run(libpath, nsteps, coupling):
+def run(libpath, nsteps, coupling, lb_model="d3q19"):
     code = f"""
 import os, sys, numpy as np
 os.environ['HLB_ORACLE_LIB'] = {libpath!r}
@@ -26,6 +28,7 @@ import oracle
 from paper_0901_3293_amd import inputs as I
 p, Q, u, rho = I.helix_case()
 p.coupling = {coupling!r}
+p.lb_model = {lb_model!r}
 st = oracle.State(oracle.params(**p.as_dict()), Q, u, rho)
 for n in range({nsteps}):
     st.step(1)
@@ -35,7 +38,7 @@ for n in range({nsteps}):
     subprocess.check_call([sys.executable, "-c", code])
 
 
-def main(nsteps=100, coupling="force"):
+def main(nsteps=100, coupling="force", lb_model="d3q19"):
     import oracle
     tmp = os.path.join(ROOT, "oracle", "_spread")
     os.makedirs(tmp, exist_ok=True)
@@ -45,8 +48,8 @@ def main(nsteps=100, coupling="force"):
     base = [f for f in oracle.CFLAGS if f != "-ffp-contract=off"]
     subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", plain, src, "-lm"])
     subprocess.check_call(["gcc", *base, "-ffp-contract=fast", "-mfma", "-o", fma, src, "-lm"])
-    run(plain, nsteps, coupling)
-    run(fma, nsteps, coupling)
+    run(plain, nsteps, coupling, lb_model)
+    run(fma, nsteps, coupling, lb_model)
     N = 32 ** 3
     spread = {"Q": [], "u": [], "rho": []}
     for n in range(nsteps):
@@ -58,15 +61,18 @@ def main(nsteps=100, coupling="force"):
         os.remove(os.path.join(tmp, f))
     os.rmdir(tmp)
     out = {"workload": "32^3 helix, q0 = 2 pi/16, kappa = 1, tau = 0, noise 1e-4 seed 1, FP64, "
-                       f"{coupling} coupling",
+                       f"{coupling} coupling, {lb_model} LB",
            "what": "max|a-b|/max|a| per step between the oracle built -ffp-contract=off and "
                    "built with FMA contraction",
            "spread": spread}
     name = "fp64_spread.json" if coupling == "force" else "fp64_spread_split.json"
+    if lb_model == "d3q15":
+        name = f"fp64_spread_{coupling}_d3q15.json"
     with open(os.path.join(HERE, name), "w") as fh:
         json.dump(out, fh)
     print({k: (v[0], v[9], v[-1]) for k, v in spread.items()})
 
 
 if __name__ == "__main__":
-    main(coupling="split" if "--split" in sys.argv else "force")
+    main(coupling="split" if "--split" in sys.argv else "force",
+         lb_model="d3q15" if "--d3q15" in sys.argv else "d3q19")

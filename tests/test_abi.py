@@ -46,9 +46,10 @@ def test_workspace_bytes(H):
     a = H.workspace_bytes(32, 32, 32, H.HLB_FP64)
     b = H.workspace_bytes(32, 32, 32, H.HLB_FP32)
     N = 32 ** 3
-    # 19+19 populations, 5+5 Q, u, stress: 60 values per site plus partials
-    assert 60 * 8 * N <= a < 60 * 8 * N + 2 ** 20
-    assert 60 * 4 * N <= b < 60 * 4 * N + 2 ** 20
+    # 19+19 populations, 5+5 Q, u 3, stress or split terms 12, D3Q15 predictor
+    # populations 15: 78 values per site plus partials
+    assert 78 * 8 * N <= a < 78 * 8 * N + 2 ** 20
+    assert 78 * 4 * N <= b < 78 * 4 * N + 2 ** 20
 
 
 def test_fe_from_reduced(H):

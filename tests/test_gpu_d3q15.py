@@ -1,0 +1,152 @@
+"""GPU parity of the paper's own LB (Sec. 2.2: D3Q15, printed equilibrium
+coefficients, forcing P_s b.e, predictor-corrector rule of Eq. (15)) against
+the FP64 oracle, through the C-ABI.
+
+Bars as for the D3Q19 form: FP64 GPU vs oracle <= 1e-12 relative per field
+for Q, rho and the total free energy, u within 1e-12 or 8x the spread between
+two valid FP64 roundings of the oracle's own run
+(tests/golden/fp64_spread_split_d3q15.json); FP32 form Q <= 1e-5 after 1000
+steps."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_0901_3293_amd import inputs as I
+from tests.hlbtest import HERE, oracle_params, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_0901_3293_amd import hlb
+
+    return hlb
+
+
+def spread():
+    with open(os.path.join(HERE, "golden", "fp64_spread_split_d3q15.json")) as fh:
+        return json.load(fh)["spread"]["u"]
+
+
+def make(H, p, Q, u, rho, prec="fp64", sched=("sites", 0)):
+    s = H.Solver((Q.shape[3], Q.shape[2], Q.shape[1]), prec)
+    s.set_schedule(*sched)
+    s.set_params(p)
+    s.set_fields(Q, u, rho)
+    return s
+
+
+SCHEDS = [("sites", 0), ("mixed", 8)]
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_d3q15_fp64_helix_every_step(H, orc, sched):
+    say("case: d3q15 split fp64 helix 32^3, 100 steps", sched)
+    p, Q, u, rho = I.helix_case()
+    p.coupling, p.lb_model = "split", "d3q15"
+    gpu = make(H, p, Q, u, rho, sched=sched)
+    ref = orc.State(oracle_params(orc, p), Q, u, rho)
+    sp = spread()
+    worst = {"Q": 0.0, "u": 0.0, "rho": 0.0, "F": 0.0}
+    for n in range(100):
+        gpu.step(1)
+        ref.step(1)
+        Qg, ug, rg = gpu.fields()
+        Qr, ur, rr = ref.fields()
+        mg, _, Fg = gpu.totals()
+        mr, _, Fr = ref.totals()
+        eQ, eu, er, eF = rel(Qg, Qr), rel(ug, ur), rel(rg, rr), abs(Fg - Fr) / abs(Fr)
+        assert eQ <= 1e-12, (n, eQ)
+        assert er <= 1e-12, (n, er)
+        assert eF <= 1e-12, (n, eF)
+        assert eu <= max(1e-12, 8 * sp[n]), (n, eu, sp[n])
+        assert abs(mg - mr) / mr <= 1e-14
+        worst = {k: max(worst[k], v) for k, v in (("Q", eQ), ("u", eu), ("rho", er), ("F", eF))}
+    assert np.abs(ug).max() > 1e-8
+    say("d3q15 fp64 worst:", worst)
+
+
+def test_d3q15_fp32_helix_1000_steps(H, orc):
+    say("case: d3q15 split fp32 helix 32^3, 1000 steps")
+    p, Q, u, rho = I.helix_case()
+    p.coupling, p.lb_model = "split", "d3q15"
+    gpu = make(H, p, Q, u, rho, "fp32")
+    ref = orc.State(oracle_params(orc, p), Q, u, rho)
+    gpu.step(1000)
+    ref.step(1000)
+    eQ = rel(gpu.fields()[0], ref.fields()[0])
+    say(f"d3q15 fp32 after 1000 steps: Q {eQ:.3e}")
+    assert eQ <= 1e-5
+
+
+@pytest.mark.parametrize("coupling", ["force", "split"])
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("shape", [(13, 7, 9), (4, 4, 4), (37, 5, 6)])
+def test_d3q15_fp64_ragged(H, orc, shape, sched, coupling):
+    say("case: d3q15 fp64 ragged", shape, sched, coupling)
+    rng = np.random.default_rng(sum(shape) + 2)
+    nx, ny, nz = shape
+    p = I.PhysParams(tau=5.0, K=0.02, q0=0.35, gamma=3.1, coupling=coupling, lb_model="d3q15")
+    Q = I.smooth_field(shape, amp=0.2, seed=5) + rng.uniform(-0.02, 0.02, size=(5, nz, ny, nx))
+    u = rng.uniform(-1e-3, 1e-3, size=(3, nz, ny, nx))
+    rho = 1 + rng.uniform(-1e-3, 1e-3, size=(nz, ny, nx))
+    gpu = make(H, p, Q, u, rho, sched=sched)
+    ref = orc.State(oracle_params(orc, p), Q, u, rho)
+    for n in (1, 4, 15):
+        gpu.step(n)
+        ref.step(n)
+        Qg, ug, rg = gpu.fields()
+        Qr, ur, rr = ref.fields()
+        assert rel(Qg, Qr) <= 1e-12
+        assert rel(ug, ur) <= 1e-11
+        assert rel(rg, rr) <= 1e-12
+        assert abs(gpu.totals()[2] - ref.totals()[2]) <= 1e-12 * abs(ref.totals()[2])
+
+
+def test_d3q15_flow_off_and_rejections(H, orc):
+    say("case: d3q15 flow off, rejections")
+    p, Q, _, _ = I.helix_case(n=12, q0=2 * math.pi / 12, flow=False)
+    p.lb_model = "d3q15"
+    gpu = make(H, p, Q, None, None)
+    ref = orc.State(oracle_params(orc, p), Q)
+    gpu.step(20)
+    ref.step(20)
+    Qg, ug, rg = gpu.fields()
+    assert rel(Qg, ref.fields()[0]) <= 1e-12
+    assert np.abs(ug).max() == 0.0 and np.abs(rg - 1).max() == 0.0
+    s = H.Solver((8, 8, 8), "fp64")
+    s.set_schedule("tiled", 8)
+    with pytest.raises(H.HlbError):
+        s.set_params(p)
+    s2 = H.Solver((8, 8, 8), "fp64")
+    s2.set_params(p)
+    with pytest.raises(H.HlbError):
+        s2.set_schedule("tiled", 8)
+    b = H.Batch([(8, 8, 8)], "fp32")
+    with pytest.raises(H.HlbError):
+        b.set_params(0, p)
+    b.close()
+
+
+def test_d3q15_split_has_no_spurious_velocity(H):
+    """The paper's scheme at a relaxed O2 unit cell (H = 0 to rounding): the
+    fluid stays at rest."""
+    say("case: d3q15 spurious velocity")
+    p, Q, _, _ = I.bpii_case(n=16, cell=16, kappa=0.7, tau_ldg=-0.5)
+    relax = I.PhysParams(**{**p.as_dict(), "Gamma": 5.0, "flow": False})
+    s = make(H, relax, Q, None, None)
+    s.step(3000)
+    Qr = s.fields()[0]
+    pc = I.PhysParams(**{**p.as_dict(), "tau": 5.0, "coupling": "split", "lb_model": "d3q15"})
+    t = make(H, pc, Qr, None, None)
+    t.step(50)
+    umax = float(np.abs(t.fields()[1]).max())
+    say("max |u| after 50 steps:", umax)
+    assert umax < 1e-12
