@@ -45,6 +45,11 @@ SPLIT_VALUES = {
     "k_stress": 5 + 12,            # Q -> sigma, tau, h
     "k_lb": (19 + 12) + (19 + 3),  # g, sigma, tau, h -> g', u
 }
+# the paper's D3Q15 predictor-corrector LB (split coupling): two passes
+PC_VALUES = {
+    "k_pc1": (15 + 12) + (15 + 3 + 3),  # f, sigma/tau/h -> f + C, u, b
+    "k_pc2": (15 + 15 + 6 + 3) + 15,    # f + C and f pulled, sigma, b -> f'
+}
 STATE_VALUES = 48  # f (19) and Q (5) read and written once
 
 # HBM bytes per launch of the 128^3 kernels, from rocprofv3 FETCH_SIZE and
@@ -61,7 +66,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling="force"):
+def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling="force", lb_model="d3q19"):
     import torch
 
     from paper_0901_3293_amd import hlb
@@ -69,7 +74,12 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
 
     p, Q, u, rho = I.bpii_case(n=n)
     p.coupling = coupling
-    values = {**KERNEL_VALUES, **(SPLIT_VALUES if coupling == "split" else {})}
+    p.lb_model = lb_model
+    if lb_model == "d3q15":
+        p.tau = 5.0  # eta = rho tau / 3 = 5/3, the viscosity of Sec. 2.1
+        if coupling != "split":
+            raise ValueError("the D3Q15 leg measures the paper's scheme: split coupling")
+    values = {**KERNEL_VALUES, **(SPLIT_VALUES if coupling == "split" else {}), **PC_VALUES}
     s = hlb.Solver((n, n, n), prec)
     s.set_params(p)
     s.set_fields(Q, u, rho)
@@ -100,10 +110,12 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
     alg_bytes = values[dom] * esz * N
     achieved = alg_bytes / (per_launch[dom] / 1e3) / 1e9
     step_values = sum(values[k] for k in per_launch)
-    traffic = MEASURED_TRAFFIC.get((prec, dom)) if (n == 128 and coupling == "force") else None
+    traffic = MEASURED_TRAFFIC.get((prec, dom)) if (n == 128 and coupling == "force" and lb_model == "d3q19") \
+        else None
     out = {
         "mlups": mlups,
         "coupling": coupling,
+        "lb_model": lb_model,
         "schedule": {"name": sched, "tz": tz},
         "ms_per_step": ms_step,
         "kernel_ms_per_launch": per_launch,
@@ -404,7 +416,9 @@ def main():
                     help="run one leg only (profiling runs)")
     ap.add_argument("--coupling", choices=["force", "split"], default="force",
                     help="fluid coupling of the --only fp32/fp64 profiling legs")
-    ap.add_argument("--no-split", action="store_true", help="skip the FP32 split-coupling leg")
+    ap.add_argument("--no-split", action="store_true", help="skip the FP32 split-coupling and D3Q15 legs")
+    ap.add_argument("--lb-model", choices=["d3q19", "d3q15"], default="d3q19",
+                    help="LB scheme of the --only fp32/fp64 profiling legs (d3q15 implies --coupling split)")
     ap.add_argument("--schedule", choices=["auto", "sites", "tiled", "mixed"], default="auto",
                     help="step schedule (auto: the library's autotuner picks)")
     ap.add_argument("--tz", type=int, default=0, help="planes per tile column for a fixed tiled/mixed schedule")
@@ -452,16 +466,23 @@ def main():
     forms = (a.only,) if a.only else ("fp32", "fp64")
     for prec in forms:
         log(f"bench: {prec} {a.n}^3, warmup {a.warmup}, steps {a.steps}")
+        if a.only and a.lb_model == "d3q15":
+            a.coupling = "split"
         res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps, a.schedule, a.tz,
-                             a.coupling if a.only else "force")
+                             a.coupling if a.only else "force", a.lb_model if a.only else "d3q19")
         log(f"bench: {prec} {res[prec]['mlups']:.1f} MLUPS, kernels {res[prec]['kernel_ms_per_launch']}")
-    split = None
+    split = d3q15 = None
     if not a.only and not a.no_split:
         log(f"bench: fp32 {a.n}^3 split coupling")
         r = run_form("fp32", a.n, a.steps, a.warmup, a.prof_steps, "auto", 0, "split")
         split = {k: r[k] for k in ("mlups", "ms_per_step", "schedule", "kernel_ms_per_launch", "roofline",
                                    "step_roofline")}
         log(f"bench: split {split['mlups']:.1f} MLUPS")
+        log(f"bench: fp32 {a.n}^3 D3Q15 predictor-corrector LB, split coupling")
+        r = run_form("fp32", a.n, a.steps, a.warmup, a.prof_steps, "auto", 0, "split", "d3q15")
+        d3q15 = {k: r[k] for k in ("mlups", "ms_per_step", "schedule", "kernel_ms_per_launch", "roofline",
+                                   "step_roofline")}
+        log(f"bench: d3q15 {d3q15['mlups']:.1f} MLUPS")
     order = None
     if not a.only:
         log(f"bench: order analysis {a.n}^3")
@@ -509,6 +530,7 @@ def main():
                  "roofline": r64["roofline"], "step_roofline": r64["step_roofline"],
                  "kernel_ms_per_launch": r64["kernel_ms_per_launch"]},
         "split_coupling_fp32": split,
+        "d3q15_predictor_corrector_fp32": d3q15,
         "order": order,
         "batched": batched,
         "surrogate": sur,
