@@ -138,7 +138,7 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
     return out
 
 
-def run_batched(steps, graph_steps=50, chunk=0, xcd_local=True):
+def run_batched(steps, graph_steps=50, chunk=0, xcd_local=True, form=None, group=0):
     """96 uneven periodic boxes (sizes 24/32/48/64, per-box kappa and tau) in
     one persistent launch per graph replay, FP32.  Aggregate MLUPS.  With
     `chunk` > 0 the autotuner is skipped and every box size uses that chunk
@@ -160,7 +160,9 @@ def run_batched(steps, graph_steps=50, chunk=0, xcd_local=True):
             b.set_chunk(L ** 3, chunk)
         chunks = {L ** 3: chunk for L in sorted({r["L"] for r in rs})}
     else:
-        chunks = b.autotune(3)
+        chunks = b.autotune(10)
+    if form:
+        b.set_launch(form, group)  # after the autotuner, which also picks the form
     b.capture(graph_steps)
     b.launch()
     b.sync()
@@ -179,7 +181,9 @@ def run_batched(steps, graph_steps=50, chunk=0, xcd_local=True):
     masses = [b.totals(i)[0] for i in range(len(rs))]
     out = {"mlups": sites * reps * graph_steps / (ms / 1e3) / 1e6, "boxes": len(rs), "sites": sites,
            "steps": reps * graph_steps, "ms_per_step": ms / (reps * graph_steps), "grid": grid,
-           "work_items": items, "xcd_local_barriers": xcd_local, "chunk_by_box_sites": chunks,
+           "work_items": items, "launch_form": b.launch_form(), "cache_group_sites": b.group_sites(),
+           "xcd_local_barriers": xcd_local,
+           "chunk_by_box_sites": chunks,
            "sizes": {str(L): sum(1 for r in rs if r["L"] == L) for L in (24, 32, 48, 64)},
            "finite": bool(all(math.isfinite(m) for m in masses))}
     b.close()
@@ -427,6 +431,10 @@ def main():
     ap.add_argument("--batch-graph-steps", type=int, default=50, help="steps per batched graph replay")
     ap.add_argument("--batch-chunk", type=int, default=0,
                     help="fixed chunk for every box size instead of the autotuner (profiling runs)")
+    ap.add_argument("--batch-launch", choices=["persistent", "phases"], default=None,
+                    help="batched launch form (default: the autotuner's pick; with --batch-chunk: persistent)")
+    ap.add_argument("--batch-group", type=int, default=0,
+                    help="cache-group budget in sites of the phase launch form (0: the autotuner's)")
     ap.add_argument("--batch-device-fences", action="store_true",
                     help="batched run with the fixed work mapping and device-scope barrier fences")
     ap.add_argument("--surrogate-steps", type=int, default=20000,
@@ -455,7 +463,8 @@ def main():
         if a.only == "order":
             out = run_order(a.n)
         elif a.only == "batched":
-            out = run_batched(a.batch_steps, a.batch_graph_steps, a.batch_chunk, not a.batch_device_fences)
+            out = run_batched(a.batch_steps, a.batch_graph_steps, a.batch_chunk, not a.batch_device_fences,
+                              a.batch_launch, a.batch_group)
         elif a.only == "network":
             out = run_network()
         else:

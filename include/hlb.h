@@ -261,10 +261,26 @@ int hlb_batch_set_fields(hlb_batch *b, int i, const double *Q5, const double *u3
 /* Sites per work item for boxes of `sites_of_box` sites (multiple of 256;
  * default 1024). */
 int hlb_batch_set_chunk(hlb_batch *b, int sites_of_box, int chunk);
-/* Autotuner: for each distinct box size, time trial_steps batched steps with
- * chunks of 256, 1024, 4096 and 16384 sites (HIP events on the batch stream)
- * and keep the fastest; the states are put back afterwards (host copies).
- * Writes up to max_out (size, chunk) pairs; returns the number of sizes. */
+/* Launch form of a batched step.  HLB_BATCH_PERSISTENT (default): one
+ * persistent kernel per call, the four phases of a step separated by grid
+ * barriers.  HLB_BATCH_PHASES: four ordinary kernels per step (stress, LB,
+ * predictor, corrector), one block per work item, ordered by the stream
+ * (meant for graph capture); the boxes are packed in index order into cache
+ * groups of at most group_sites sites (a larger box alone) and all steps of a
+ * call run on one group before the next, so that a group's fields stay in
+ * the last-level cache (group_sites = 0 keeps the current budget, default
+ * 2^20).  Results are identical; drops a captured graph. */
+enum { HLB_BATCH_PERSISTENT = 0, HLB_BATCH_PHASES = 1 };
+int hlb_batch_set_launch(hlb_batch *b, int form, long long group_sites);
+int hlb_batch_get_launch(const hlb_batch *b, int *form, long long *group_sites);
+/* Autotuner: coordinate descent over the launch form, the cache-group budget
+ * of the phase form (2^19 .. 2^22 sites, or all boxes in one group) jointly
+ * with one chunk (256 or 1024) for all sizes, the blocks per CU of the
+ * persistent form (1..4) and, for each distinct box size, chunks of 256,
+ * 1024, 4096 and 16384 sites, timing trial_steps batched steps with HIP
+ * events on the batch stream and keeping the fastest; the states are put back
+ * afterwards (host copies).  Writes up to max_out (size, chunk) pairs; returns
+ * the number of sizes. */
 int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunks_out, int max_out);
 /* enable = 1 (default): keep each box on one XCD (boxes packed into 8 groups of
  * about equal site count; the workgroups on XCD x take group x), so the phase
@@ -272,9 +288,9 @@ int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunk
  * follow blockIdx and every barrier uses device-scope fences.  Results are
  * identical; drops a captured graph. */
 int hlb_batch_set_xcd_local(hlb_batch *b, int enable);
-/* Enqueue nsteps steps of every box as one persistent launch. */
+/* Enqueue nsteps steps of every box in the selected launch form. */
 int hlb_batch_step(hlb_batch *b, int nsteps);
-/* Capture one persistent launch of nsteps steps into a HIP graph;
+/* Capture the launch of nsteps steps (either form) into a HIP graph;
  * hlb_batch_launch replays it (nsteps more steps per replay).  Changing any
  * box's parameters or chunk afterwards requires a new capture.  Capture needs
  * a non-null stream (HLB_ERR_ARG otherwise). */
@@ -285,7 +301,8 @@ int hlb_batch_sync(hlb_batch *b);
 /* Readout of box i at the current level (as hlb_get_fields / hlb_get_totals). */
 int hlb_batch_get_fields(hlb_batch *b, int i, double *Q5, double *u3, double *rho);
 int hlb_batch_get_totals(hlb_batch *b, int i, double *mass, double *mom3, double *free_energy);
-/* Grid size of the persistent launch and number of work items. */
+/* Grid size of the launch (persistent: co-resident blocks; phases: one block
+ * per work item) and number of work items. */
 int hlb_batch_info(const hlb_batch *b, int *grid, int *n_items);
 /* After a launch (synchronises): *local = 1 if the last launch kept every box
  * on one XCD (workgroups take the group of the XCD they run on), so its phase

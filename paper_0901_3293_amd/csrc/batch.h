@@ -32,4 +32,15 @@ hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items,
                         int *d_err, int *d_misplaced, int *d_xcnt, bool allow_local, int nsteps, int grid,
                         hipStream_t stream);
 
+// The same steps as four ordinary kernels per step (stress, LB, predictor,
+// corrector), one block per work item, in stream order (no grid barriers;
+// meant to be captured in a graph), plus the reset of the flags (so
+// hlb_batch_sync sees a clean error flag).  The work list is cut into
+// ngroups cache groups, items [clo[c], clo[c + 1]) (host array); all nsteps
+// steps of group c are enqueued before group c + 1 (the boxes are
+// independent), so a group's fields stay in the last-level cache.
+hipError_t batch_launch_phases(bool fp32, void *d_reps, int n_reps, const int *d_items, const int *clo, int ngroups,
+                               unsigned *d_bar, int *d_err, int *d_misplaced, int *d_xcnt, int nsteps,
+                               hipStream_t stream);
+
 }  // namespace hlb

@@ -200,6 +200,31 @@ __global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, int n_
             if (reps[r].flow) reps[r].gcur ^= 1;
 }
 
+// The alternative launch form: one ordinary kernel per phase, one block per
+// work item, stream order in place of the grid barriers (each phase kernel
+// holds only its own registers, so more waves are resident).
+// Blocks reach the XCDs round-robin; block b takes item (b % 8) * (grid / 8)
+// + b / 8, so consecutive items (neighbouring site ranges of a box) run on
+// one XCD and share its L2 for the stencil reads.  The grid is a multiple of
+// 8; blocks past the last item return.
+template <typename T, int PH>
+__global__ __launch_bounds__(BLK) void k_phase(Rep<T> *__restrict__ reps, const int4 *__restrict__ items,
+                                               int first, int n_items, int step)
+{
+    const int it = int(blockIdx.x & 7) * int(gridDim.x >> 3) + int(blockIdx.x >> 3);
+    if (it >= n_items) return;
+    run_phase<T, PH>(reps, items, first + it, first + it + 1, 0, 1, step);
+}
+
+// Advance the device ping-pong index of every box with flow after an odd
+// number of steps of phase kernels.
+template <typename T>
+__global__ void k_flip(Rep<T> *__restrict__ reps, int n_reps)
+{
+    const int r = blockIdx.x * BLK + int(threadIdx.x);
+    if (r < n_reps && reps[r].flow) reps[r].gcur ^= 1;
+}
+
 __global__ void k_batch_reset(unsigned *bar, int *err, int *misplaced, int *xcnt)
 {
     if (threadIdx.x == 0) {
@@ -279,6 +304,37 @@ hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items,
                                                   d_err, d_misplaced, d_xcnt, int(allow_local), nsteps,
                                                  spin_limit);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_phases_t(void *d_reps, int n_reps, const int *d_items, const int *clo, int ngroups, int nsteps,
+                           hipStream_t st)
+{
+    Rep<T> *reps = static_cast<Rep<T> *>(d_reps);
+    const int4 *items = reinterpret_cast<const int4 *>(d_items);
+    for (int c = 0; c < ngroups; ++c) {  // every step of one cache group, then the next
+        const int first = clo[c], n_items = clo[c + 1] - clo[c];
+        if (n_items < 1) continue;
+        const int grid = (n_items + 7) / 8 * 8;
+        for (int n = 0; n < nsteps; ++n) {
+            k_phase<T, PH_STRESS><<<grid, BLK, 0, st>>>(reps, items, first, n_items, n);
+            k_phase<T, PH_LB><<<grid, BLK, 0, st>>>(reps, items, first, n_items, n);
+            k_phase<T, PH_PRED><<<grid, BLK, 0, st>>>(reps, items, first, n_items, n);
+            k_phase<T, PH_CORR><<<grid, BLK, 0, st>>>(reps, items, first, n_items, n);
+        }
+    }
+    if (nsteps & 1) k_flip<T><<<(n_reps + BLK - 1) / BLK, BLK, 0, st>>>(reps, n_reps);
+    return hipGetLastError();
+}
+
+hipError_t batch_launch_phases(bool fp32, void *d_reps, int n_reps, const int *d_items, const int *clo, int ngroups,
+                               unsigned *d_bar, int *d_err, int *d_misplaced, int *d_xcnt, int nsteps,
+                               hipStream_t stream)
+{
+    k_batch_reset<<<1, 64, 0, stream>>>(d_bar, d_err, d_misplaced, d_xcnt);
+    if (ngroups < 1 || nsteps < 1) return hipGetLastError();
+    return fp32 ? launch_phases_t<float>(d_reps, n_reps, d_items, clo, ngroups, nsteps, stream)
+                : launch_phases_t<double>(d_reps, n_reps, d_items, clo, ngroups, nsteps, stream);
 }
 
 }  // namespace hlb

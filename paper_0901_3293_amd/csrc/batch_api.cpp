@@ -38,6 +38,9 @@ struct hlb_batch {
     int grid;
     int bpc;                         // blocks per compute unit of the persistent grid (0: max)
     bool xcd_local = true;           // keep each box on one XCD when the launch allows it
+    int launch_form = HLB_BATCH_PERSISTENT;  // or HLB_BATCH_PHASES
+    long long group_sites = 1 << 20;          // cache-group budget of the phase form (sites)
+    std::vector<int> clo;                     // item offsets of the cache groups (phase form)
     bool dirty;                      // descriptor table / work list must be rebuilt
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -131,17 +134,37 @@ int rebuild(hlb_batch *b)
         load[g] += b->box[i].G.N;
     }
     std::vector<int> items;
-    for (int g = 0; g < 8; ++g) {
-        b->xlo[g] = int(items.size() / 4);
+    auto add_box = [&](int i) {
+        const int N = b->box[i].G.N, ch = chunk_for(b, N);
+        for (int s = 0; s < N; s += ch) {
+            items.push_back(i);
+            items.push_back(s);
+            items.push_back(std::min(ch, N - s));
+            items.push_back(0);
+        }
+    };
+    b->clo.clear();
+    if (b->launch_form == HLB_BATCH_PHASES) {
+        // cache groups: boxes in index order, packed while the group stays
+        // within group_sites sites (a larger box is a group of its own); the
+        // phase form runs all steps of one group before the next
+        long long in_group = 0;
         for (int i = 0; i < b->n; ++i) {
-            if (group[i] != g) continue;
-            const int N = b->box[i].G.N, ch = chunk_for(b, N);
-            for (int s = 0; s < N; s += ch) {
-                items.push_back(i);
-                items.push_back(s);
-                items.push_back(std::min(ch, N - s));
-                items.push_back(0);
+            const long long N = b->box[i].G.N;
+            if (b->clo.empty() || in_group + N > b->group_sites) {
+                b->clo.push_back(int(items.size() / 4));
+                in_group = 0;
             }
+            add_box(i);
+            in_group += N;
+        }
+        b->clo.push_back(int(items.size() / 4));
+        for (int g = 0; g <= 8; ++g) b->xlo[g] = g == 8 ? int(items.size() / 4) : 0;
+    } else {
+        for (int g = 0; g < 8; ++g) {
+            b->xlo[g] = int(items.size() / 4);
+            for (int i = 0; i < b->n; ++i)
+                if (group[i] == g) add_box(i);
         }
     }
     b->n_items = int(items.size() / 4);
@@ -181,6 +204,16 @@ hlb::Device view(hlb_batch *b, int i)
     D.gcur = b->gcur[i];
     D.sched = hlb::SCHED_SITES;
     return D;
+}
+
+// nsteps steps of every box in the selected launch form.
+hipError_t enqueue(hlb_batch *b, int nsteps)
+{
+    if (b->launch_form == HLB_BATCH_PHASES)
+        return hlb::batch_launch_phases(b->fp32, b->d_reps, b->n, b->d_items, b->clo.data(), int(b->clo.size()) - 1,
+                                        b->d_bar, b->d_err, b->d_misplaced, b->d_xcnt, nsteps, b->stream);
+    return hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err, b->d_misplaced,
+                             b->d_xcnt, b->xcd_local, nsteps, b->grid, b->stream);
 }
 
 }  // namespace
@@ -316,6 +349,19 @@ int hlb_batch_set_chunk(hlb_batch *b, int sites_of_box, int chunk)
     return HLB_OK;
 }
 
+int hlb_batch_set_launch(hlb_batch *b, int form, long long group_sites)
+{
+    B_GUARD(b);
+    if (form != HLB_BATCH_PERSISTENT && form != HLB_BATCH_PHASES)
+        return bset_error(b, HLB_ERR_ARG, "launch form %d", form);
+    if (group_sites < 0) return bset_error(b, HLB_ERR_ARG, "group_sites %lld", group_sites);
+    b->launch_form = form;
+    if (group_sites > 0) b->group_sites = group_sites;
+    b->dirty = true;
+    drop_graph(b);
+    return HLB_OK;
+}
+
 int hlb_batch_set_xcd_local(hlb_batch *b, int enable)
 {
     B_GUARD(b);
@@ -333,8 +379,7 @@ int hlb_batch_step(hlb_batch *b, int nsteps)
         if (rc) return rc;
     }
     if (nsteps == 0) return HLB_OK;
-    B_TRY(b, hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err, b->d_misplaced,
-                               b->d_xcnt, b->xcd_local, nsteps, b->grid, b->stream));
+    B_TRY(b, enqueue(b, nsteps));
     advance_host_gcur(b, nsteps);
     return HLB_OK;
 }
@@ -350,8 +395,7 @@ int hlb_batch_capture(hlb_batch *b, int nsteps)
     }
     drop_graph(b);
     B_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err,
-                                     b->d_misplaced, b->d_xcnt, b->xcd_local, nsteps, b->grid, b->stream);
+    hipError_t e = enqueue(b, nsteps);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -408,29 +452,46 @@ int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunk
     B_TRY(b, hipEventCreate(&ea));
     B_TRY(b, hipEventCreate(&eb));
     int rc = HLB_OK;
-    // coordinate descent: blocks per CU first (key 0 below), then the chunk
-    // of each box size in turn
-    std::vector<int> keys(1, 0);
+    // coordinate descent: the launch form (key -1), blocks per CU of the
+    // persistent form (key 0), then the chunk of each box size in turn
+    // (key -2: the cache-group budget of the phase form jointly with one chunk
+    // for every box size -- the two interact through the blocks per group;
+    // option k: budget 2^(19 + k % 5) sites (k % 5 == 4: all boxes in one
+    // group), chunk 256 for k < 5 else 1024)
+    auto set_joint = [&](int k) {
+        b->group_sites = (k % 5 == 4) ? (1ll << 40) : (1ll << (19 + k % 5));
+        for (int N : sizes) b->chunk_of_n[N] = k < 5 ? 256 : 1024;
+    };
+    int joint = -1;
+    std::vector<int> keys{-1, -2, 0};
     keys.insert(keys.end(), sizes.begin(), sizes.end());
     for (int N : keys) {
+        if (N == 0 && b->launch_form != HLB_BATCH_PERSISTENT) continue;
+        if (N == -2 && b->launch_form != HLB_BATCH_PHASES) continue;
         double best = 1e300;
-        int pick = N == 0 ? b->bpc : chunk_for(b, N);
-        const std::vector<int> opts = N == 0 ? std::vector<int>{1, 2, 3, 4}
-                                             : std::vector<int>(std::begin(cands), std::end(cands));
+        int pick = N == -1 ? b->launch_form
+                 : N == -2 ? joint
+                 : N == 0  ? b->bpc
+                           : chunk_for(b, N);
+        const std::vector<int> opts = N == -1 ? std::vector<int>{HLB_BATCH_PERSISTENT, HLB_BATCH_PHASES}
+                                    : N == -2 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6, 7, 8, 9}
+                                    : N == 0  ? std::vector<int>{1, 2, 3, 4}
+                                              : std::vector<int>(std::begin(cands), std::end(cands));
         for (int ch : opts) {
-            if (N != 0 && ch > N && ch != 256) continue;
-            if (N == 0)
+            if (N > 0 && ch > N && ch != 256) continue;
+            if (N == -1)
+                b->launch_form = ch;
+            else if (N == -2)
+                set_joint(ch);
+            else if (N == 0)
                 b->bpc = ch;
             else
                 b->chunk_of_n[N] = ch;
             if ((rc = rebuild(b))) break;
-            hipError_t e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err,
-                                             b->d_misplaced, b->d_xcnt, b->xcd_local, 1, b->grid, b->stream);
+            hipError_t e = enqueue(b, 1);
             advance_host_gcur(b, 1);
             if (e == hipSuccess) e = hipEventRecord(ea, b->stream);
-            if (e == hipSuccess)
-                e = hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err,
-                                      b->d_misplaced, b->d_xcnt, b->xcd_local, trial_steps, b->grid, b->stream);
+            if (e == hipSuccess) e = enqueue(b, trial_steps);
             advance_host_gcur(b, trial_steps);
             if (e == hipSuccess) e = hipEventRecord(eb, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(eb);
@@ -447,7 +508,12 @@ int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunk
             }
         }
         if (rc) break;
-        if (N == 0)
+        if (N == -1)
+            b->launch_form = pick;
+        else if (N == -2) {
+            if (pick >= 0) set_joint(pick);
+            joint = pick;
+        } else if (N == 0)
             b->bpc = pick;
         else
             b->chunk_of_n[N] = pick;
@@ -519,8 +585,16 @@ int hlb_batch_get_totals(hlb_batch *b, int i, double *mass, double *mom3, double
 int hlb_batch_info(const hlb_batch *b, int *grid, int *n_items)
 {
     if (!b) return HLB_ERR_ARG;
-    if (grid) *grid = b->grid;
+    if (grid) *grid = b->launch_form == HLB_BATCH_PHASES ? b->n_items : b->grid;
     if (n_items) *n_items = b->n_items;
+    return HLB_OK;
+}
+
+int hlb_batch_get_launch(const hlb_batch *b, int *form, long long *group_sites)
+{
+    if (!b || !form) return HLB_ERR_ARG;
+    *form = b->launch_form;
+    if (group_sites) *group_sites = b->group_sites;
     return HLB_OK;
 }
 
@@ -531,7 +605,7 @@ int hlb_batch_xcd_local(hlb_batch *b, int *local)
     int mis = 1;
     B_TRY(b, hipMemcpyAsync(&mis, b->d_misplaced, sizeof(int), hipMemcpyDeviceToHost, b->stream));
     B_TRY(b, hipStreamSynchronize(b->stream));
-    *local = mis == 0 ? 1 : 0;
+    *local = (mis == 0 && b->launch_form == HLB_BATCH_PERSISTENT) ? 1 : 0;
     return HLB_OK;
 }
 

@@ -118,6 +118,8 @@ def lib():
         L.hlb_batch_set_fields.argtypes = [vp, I, dp, dp, dp]
         L.hlb_batch_set_chunk.argtypes = [vp, I, I]
         L.hlb_batch_set_xcd_local.argtypes = [vp, I]
+        L.hlb_batch_set_launch.argtypes = [vp, I, ctypes.c_longlong]
+        L.hlb_batch_get_launch.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong)]
         L.hlb_batch_autotune.argtypes = [vp, I, ip, ip, I]
         L.hlb_batch_step.argtypes = [vp, I]
         L.hlb_batch_capture.argtypes = [vp, I]
@@ -358,6 +360,25 @@ class Batch:
 
     def set_chunk(self, sites_of_box, chunk):
         self._check(lib().hlb_batch_set_chunk(self.b, int(sites_of_box), int(chunk)))
+
+    LAUNCH_FORMS = {"persistent": 0, "phases": 1}
+
+    def set_launch(self, form, group_sites=0):
+        """'persistent' (one kernel, grid barriers) or 'phases' (four kernels per
+        step, cache groups of at most group_sites sites; 0 keeps the budget)."""
+        self._check(lib().hlb_batch_set_launch(self.b, self.LAUNCH_FORMS[form], int(group_sites)))
+
+    def launch_form(self):
+        v = ctypes.c_int()
+        g = ctypes.c_longlong()
+        self._check(lib().hlb_batch_get_launch(self.b, ctypes.byref(v), ctypes.byref(g)))
+        return {0: "persistent", 1: "phases"}[v.value]
+
+    def group_sites(self):
+        v = ctypes.c_int()
+        g = ctypes.c_longlong()
+        self._check(lib().hlb_batch_get_launch(self.b, ctypes.byref(v), ctypes.byref(g)))
+        return int(g.value)
 
     def set_xcd_local(self, enable=True):
         self._check(lib().hlb_batch_set_xcd_local(self.b, int(bool(enable))))

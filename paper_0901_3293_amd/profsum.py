@@ -23,6 +23,9 @@ def short(name):
     m = re.search(r"k_wgrad<(\d+)>", name)
     if m:  # weight gradient: 32 input channels, COP output channels
         return f"k_wgrad<32,{m.group(1)}>"
+    m = re.search(r"k_phase<(?:float|double), (\d)>", name)
+    if m:  # batched phase kernels: stress, LB, predictor, corrector
+        return "k_phase_" + ("stress", "lb", "pred", "corr")[int(m.group(1))]
     m = re.search(r"(k_\w+|__amd_rocclr_copyBuffer)", name)
     return m.group(1) if m else name[:40]
 

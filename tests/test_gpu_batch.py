@@ -51,20 +51,26 @@ def make_batch(H, prec, rs):
     return b
 
 
-@pytest.mark.parametrize("local", [True, False])
+@pytest.mark.parametrize("form,local,group", [("persistent", True, 0), ("persistent", False, 0),
+                                              ("phases", False, 0), ("phases", False, 2000)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_matches_single_boxes(H, prec, local):
-    """Both barrier modes: boxes kept on one XCD (XCD-scope release) and the
-    fixed mapping with device-scope fences."""
-    say("case: batch vs single", prec, "xcd-local allowed", local)
+def test_batch_matches_single_boxes(H, prec, form, local, group):
+    """Every launch form: the persistent kernel with boxes kept on one XCD
+    (XCD-scope release) or with the fixed mapping and device-scope fences,
+    and the four phase kernels per step, with all boxes in one cache group
+    or in groups of at most 2000 sites (several groups, boxes larger than
+    the budget alone)."""
+    say("case: batch vs single", prec, form, "xcd-local allowed", local, "group", group)
     rs = small_set()
     b = make_batch(H, prec, rs)
     b.set_chunk(8 ** 3, 256)
+    b.set_launch(form, group)
     b.set_xcd_local(local)
     b.step(7)
     b.step(6)
     went_local = b.xcd_local()
     say("grid, items:", b.info(), "xcd-local barriers:", went_local)
+    assert b.launch_form() == form
     if not local:
         assert not went_local
     for i, r in enumerate(rs):
@@ -74,10 +80,12 @@ def test_batch_matches_single_boxes(H, prec, local):
             assert np.array_equal(x, y), (i, rel(x, y))
 
 
-def test_batch_graph_replay(H):
-    say("case: batch graph capture/replay fp32")
+@pytest.mark.parametrize("form,group", [("persistent", 0), ("phases", 3000)])
+def test_batch_graph_replay(H, form, group):
+    say("case: batch graph capture/replay fp32", form, group)
     rs = small_set()
     b = make_batch(H, "fp32", rs)
+    b.set_launch(form, group)
     b.capture(5)
     for _ in range(3):
         b.launch()
