@@ -212,6 +212,36 @@ def test_full_size_128_fp64_every_site(H, orc):
     assert np.abs(mom1 - mom0).max() < 1e-4
 
 
+@pytest.mark.parametrize("kappa", [0.5, 0.8, 1.0])
+def test_slab_64x64x256_full_size(H, orc, kappa):
+    """The domain-growth slab at its full size (64 x 64 x 256, O2 seed for
+    z < 32 inside an x-helix, tau_LdG = 0), each chirality of the sweep:
+    FP64 GPU against the oracle on every site after 10 steps, and the FP32
+    form's free-energy profile f(z) (the domain-wall tracker) against the
+    oracle's within the FP32 bar."""
+    say("case: slab 64x64x256 kappa", kappa)
+    p, Q, u, rho = I.slab_case(nx=64, ny=64, nz=256, cell=32, seed_depth=32, kappa=kappa)
+    ref = orc.State(oracle_params(orc, p), Q, u, rho)
+    ref.step(10)
+    Qr, ur, rr = ref.fields()
+    _, f, _ = orc.chem(oracle_params(orc, p), ref.Q9)
+    fz_ref = np.array([orc.psum(f[z]) for z in range(f.shape[0])])
+    gpu = make(H, p, Q, u, rho)
+    gpu.step(10)
+    Qg, ug, rg = gpu.fields()
+    eQ, eu, er = rel(Qg, Qr), rel(ug, ur), rel(rg, rr)
+    say(f"slab fp64: Q {eQ:.2e} u {eu:.2e} rho {er:.2e} f(z) {rel(gpu.fz(), fz_ref):.2e}")
+    assert eQ <= 1e-12 and eu <= 1e-10 and er <= 1e-12
+    assert rel(gpu.fz(), fz_ref) <= 1e-12
+    del gpu
+    s32 = make(H, p, Q, u, rho, "fp32")
+    s32.autotune(3)
+    s32.step(10)
+    e32 = rel(s32.fz(), fz_ref)
+    say(f"slab fp32 f(z) {e32:.2e}")
+    assert e32 <= 1e-5
+
+
 def test_autotune_keeps_state(H):
     """The autotuner's trial steps leave the state untouched."""
     say("case: autotune keeps state 24^3")
