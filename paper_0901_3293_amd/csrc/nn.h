@@ -21,7 +21,6 @@ constexpr int NORM_IN_MEAN = 0, NORM_IN_STD = 18, NORM_OUT_MEAN = 36, NORM_OUT_S
 constexpr int NORM_SIZE = 47;
 
 constexpr int WGRAD_BLOCKS = 512;  // persistent blocks of the weight-gradient kernel
-constexpr int CONV_BLOCKS = 512;   // upper bound on convolution blocks (two per CU)
 
 Grid3 make_grid(int nx, int ny, int nz);
 int wgrad_grid(const Grid3 &g);

@@ -62,14 +62,16 @@ __device__ __forceinline__ void tile_origin(const Grid3 &g, int t, int &x0, int 
 // output channels, N = 16 sites of one x-row, K = 32 (the CIN = 32 channels of
 // one tap, or the 16 channels of two taps when CIN = 16).
 //
-// A block owns a tile of 16 x (WY RY) x (WZ RZ) output sites; its input brick
-// (tile plus a one-site periodic halo) is staged in LDS, and the brick of the
-// block's next tile is fetched into registers while the current one is
-// computed.  Each wave owns 16 x RY x RZ output sites with all COUT channels
-// in its accumulators; for each x-offset of the stencil it reads the
-// (RY+2)(RZ+2) brick rows it needs into registers once and runs all nine
-// (y, z) taps of that offset against them.  The weights, pre-arranged in MFMA
-// fragment order (k_wprep), are staged once per block.  Blocks take
+// One block of 8 waves per CU owns a tile of 16 x (WY RY) x (WZ RZ) = 16 x 8
+// x 4 output sites at a time; its input brick (tile plus a one-site periodic
+// halo, 69 KB for 32 channels) is staged in LDS, and the brick of the block's
+// next tile is fetched into registers while the current one is computed.
+// The layer's weights, pre-arranged in MFMA fragment order (k_wprep, 55 KB
+// for 32 -> 32), are staged in LDS once per block, so the per-kstep fragment
+// reads (one kstep ahead) are LDS reads.  Each wave owns 16 x RY x RZ output
+// sites with all COUT channels in its accumulators; for each x-offset of the
+// stencil it reads the (RY+2)(RZ+2) brick rows it needs into registers once
+// and runs all nine (y, z) taps of that offset against them.  Blocks take
 // contiguous runs of tiles, and the block index is remapped so that each XCD
 // (with its own L2) works on one contiguous part of the lattice.
 //
@@ -99,145 +101,6 @@ template <int V>
 __device__ __forceinline__ int brick_chunk(int site, int v)
 {
     return site * V + (v ^ ((site / (16 / V)) % V));
-}
-
-template <int CIN, int COUT, int MODE, int RY, int RZ, int WY, int WZ>
-__global__ __launch_bounds__(BLK, 2) void k_conv(Grid3 g, int ctx, int cty, int ntiles, int per_block,
-                                                 const unsigned short *__restrict__ X, const u32x4 *__restrict__ Wfrag,
-                                                 const float *__restrict__ bias, void *__restrict__ out,
-                                                 const unsigned short *__restrict__ mask, int co_valid)
-{
-    using S = ConvShape<CIN, COUT, RY, RZ, WY, WZ>;
-    constexpr int NS = S::NS, KPD = S::KPD, V = S::V;
-    static_assert(WY * WZ == BLK / 64, "one wave per sub-tile");
-    extern __shared__ __attribute__((aligned(16))) unsigned short smem[];
-    u32x4 *sB = reinterpret_cast<u32x4 *>(smem);
-
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lg = l >> 4;
-    const int wy = w % WY, wz = w / WY;
-    const int cv = CIN == 32 ? lg : (lg & 1);  // chunk of the site this lane feeds to the MFMA
-    const bool upper = lg >= 2;                // CIN == 16: this lane feeds the second tap of a pair
-    float bv[NS][4];
-#pragma unroll
-    for (int ns = 0; ns < NS; ++ns)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = ns * 16 + 4 * lg + r;
-            bv[ns][r] = ((MODE == MODE_RELU || MODE == MODE_LINEAR) && co < co_valid) ? bias[co] : 0.f;
-        }
-    const int b = xcd_logical_block();
-    const int t_begin = b * per_block;
-    const int t_end = min(ntiles, t_begin + per_block);
-    const u32x4 zero = {0u, 0u, 0u, 0u};
-
-    for (int t = t_begin; t < t_end; ++t) {
-        const int x0 = (t % ctx) * 16, rr = t / ctx;
-        const int yb = (rr % cty) * S::TY, zb = (rr / cty) * S::TZ;
-        // stage the brick of this tile (global -> LDS); a second resident
-        // block overlaps its own compute with this
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < S::NCH; ++k) {
-            const int e = threadIdx.x + k * BLK;
-            if (e < S::BN * V) {
-                const int site = e / V, v = e - site * V;
-                const int bx = site % S::BX, r2 = site / S::BX, by = r2 % S::BY, bz = r2 / S::BY;
-                const int x = wrap_near(x0 - 1 + bx, g.nx), y = wrap_near(yb - 1 + by, g.ny),
-                          z = wrap_near(zb - 1 + bz, g.nz);
-                const size_t gs = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
-                sB[brick_chunk<V>(site, v)] = *reinterpret_cast<const u32x4 *>(X + gs * CIN + v * 8);
-            }
-        }
-        __syncthreads();
-        f32x4 acc[RZ * RY][NS];
-#pragma unroll
-        for (int m = 0; m < RZ * RY; ++m)
-#pragma unroll
-            for (int ns = 0; ns < NS; ++ns) acc[m][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // weight fragments straight from global memory (L1/L2-resident), one
-        // kstep ahead
-        u32x4 a[NS], an[NS];
-#pragma unroll
-        for (int ns = 0; ns < NS; ++ns) a[ns] = Wfrag[ns * 64 + l];
-#pragma unroll 1
-        for (int dx = 0; dx < 3; ++dx) {
-            u32x4 f[RZ + 2][RY + 2];
-#pragma unroll
-            for (int zz = 0; zz < RZ + 2; ++zz)
-#pragma unroll
-                for (int yy = 0; yy < RY + 2; ++yy) {
-                    const int site = ((wz * RZ + zz) * S::BY + (wy * RY + yy)) * S::BX + li + dx;
-                    f[zz][yy] = sB[brick_chunk<V>(site, cv)];
-                }
-#pragma unroll
-            for (int k = 0; k < KPD; ++k) {
-                const int ks = dx * KPD + k;
-                if (ks + 1 < S::NKS) {
-#pragma unroll
-                    for (int ns = 0; ns < NS; ++ns) an[ns] = Wfrag[((ks + 1) * NS + ns) * 64 + l];
-                }
-#pragma unroll
-                for (int zz = 0; zz < RZ; ++zz)
-#pragma unroll
-                    for (int yy = 0; yy < RY; ++yy) {
-                        u32x4 bop;
-                        if (CIN == 32) {
-                            bop = f[zz + k / 3][yy + k % 3];
-                        } else {
-                            const int qa = 2 * k, qb = 2 * k + 1 < 9 ? 2 * k + 1 : 0;
-                            const u32x4 lo = f[zz + qa / 3][yy + qa % 3];
-                            const u32x4 hi = 2 * k + 1 < 9 ? f[zz + qb / 3][yy + qb % 3] : zero;
-                            bop = upper ? hi : lo;
-                        }
-#pragma unroll
-                        for (int ns = 0; ns < NS; ++ns)
-                            acc[zz * RY + yy][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                __builtin_bit_cast(bf16x8, a[ns]), __builtin_bit_cast(bf16x8, bop),
-                                acc[zz * RY + yy][ns], 0, 0, 0);
-                    }
-#pragma unroll
-                for (int ns = 0; ns < NS; ++ns) a[ns] = an[ns];
-            }
-        }
-        // D[r] of lane (li, lg): output channel 16 ns + 4 lg + r of site x0 + li
-        const int xo = x0 + li, y0 = yb + wy * RY, z0 = zb + wz * RZ;
-#pragma unroll
-        for (int zz = 0; zz < RZ; ++zz)
-#pragma unroll
-            for (int yy = 0; yy < RY; ++yy) {
-                const int yo = y0 + yy, zo = z0 + zz;
-                if (xo >= g.nx || yo >= g.ny || zo >= g.nz) continue;
-                const size_t s = size_t(xo) + size_t(g.nx) * (size_t(yo) + size_t(g.ny) * zo);
-#pragma unroll
-                for (int ns = 0; ns < NS; ++ns) {
-                    const f32x4 v = acc[zz * RY + yy][ns];
-                    const int co = ns * 16 + 4 * lg;
-                    if (MODE == MODE_RELU) {
-                        unsigned short h[4];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) h[r] = co + r < co_valid ? f2bf(fmaxf(v[r] + bv[ns][r], 0.f)) : 0;
-                        *reinterpret_cast<uint2 *>(static_cast<unsigned short *>(out) + s * COUT + co) =
-                            make_uint2(unsigned(h[0]) | (unsigned(h[1]) << 16), unsigned(h[2]) | (unsigned(h[3]) << 16));
-                    } else if (MODE == MODE_LINEAR) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (co + r < co_valid) static_cast<float *>(out)[s * co_valid + co + r] = v[r] + bv[ns][r];
-                    } else if (MODE == MODE_MASK) {
-                        const uint2 mk = *reinterpret_cast<const uint2 *>(mask + s * COUT + co);
-                        const unsigned short mh[4] = {(unsigned short)(mk.x & 0xffffu), (unsigned short)(mk.x >> 16),
-                                                      (unsigned short)(mk.y & 0xffffu), (unsigned short)(mk.y >> 16)};
-                        unsigned short h[4];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) h[r] = bf2f(mh[r]) > 0.f ? f2bf(v[r]) : (unsigned short)0;
-                        *reinterpret_cast<uint2 *>(static_cast<unsigned short *>(out) + s * COUT + co) =
-                            make_uint2(unsigned(h[0]) | (unsigned(h[1]) << 16), unsigned(h[2]) | (unsigned(h[3]) << 16));
-                    } else {
-                        *reinterpret_cast<float4 *>(static_cast<float *>(out) + s * COUT + co) =
-                            make_float4(v[0], v[1], v[2], v[3]);
-                    }
-                }
-            }
-    }
 }
 
 // Weight gradient dW[tap][ci][co] = sum_s dZ[s][co] X[s + off(tap)][ci] and
@@ -769,31 +632,202 @@ int device_cus()
     return cus;
 }
 
-template <int CIN, int COUT, int MODE>
-hipError_t conv_launch(const Grid3 &g, const unsigned short *X, const unsigned short *W, const float *bias, void *out,
-                       const unsigned short *mask, int co_valid, hipStream_t st)
-{
-    constexpr int RY = 4, RZ = 2, WY = 2, WZ = 2;
+// One block of WBLK threads (8 waves) per CU.
+constexpr int WBLK = 512;
+
+template <int CIN, int COUT, int RY, int RZ, int WY, int WZ>
+struct ConvLds {
     using S = ConvShape<CIN, COUT, RY, RZ, WY, WZ>;
+    static constexpr int NCH = (S::BN * S::V + WBLK - 1) / WBLK;   // brick chunks per thread
+    static constexpr int NW = S::NKS * S::NS * 64;                  // weight fragments (16 B)
+    static constexpr size_t brick_bytes = size_t(S::BN) * CIN * 2;
+    static constexpr size_t lds_bytes = brick_bytes + size_t(NW) * 16;
+};
+
+template <int CIN, int COUT, int MODE, int RY, int RZ, int WY, int WZ>
+__global__ __launch_bounds__(WBLK, 1) void k_conv(Grid3 g, int ctx, int cty, int ntiles, int per_block,
+                                                       const unsigned short *__restrict__ X,
+                                                       const u32x4 *__restrict__ Wfrag,
+                                                       const float *__restrict__ bias, void *__restrict__ out,
+                                                       const unsigned short *__restrict__ mask, int co_valid)
+{
+    using S = ConvShape<CIN, COUT, RY, RZ, WY, WZ>;
+    using WS = ConvLds<CIN, COUT, RY, RZ, WY, WZ>;
+    constexpr int NS = S::NS, KPD = S::KPD, V = S::V, NCH = WS::NCH;
+    static_assert(WY * WZ == WBLK / 64, "one wave per sub-tile");
+    extern __shared__ __attribute__((aligned(16))) unsigned short smem[];
+    u32x4 *sB = reinterpret_cast<u32x4 *>(smem);
+    u32x4 *sW = reinterpret_cast<u32x4 *>(smem + WS::brick_bytes / 2);
+
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lg = l >> 4;
+    const int wy = w % WY, wz = w / WY;
+    const int cv = CIN == 32 ? lg : (lg & 1);
+    const bool upper = lg >= 2;
+    float bv[NS][4];
+#pragma unroll
+    for (int ns = 0; ns < NS; ++ns)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = ns * 16 + 4 * lg + r;
+            bv[ns][r] = ((MODE == MODE_RELU || MODE == MODE_LINEAR) && co < co_valid) ? bias[co] : 0.f;
+        }
+    const int b = xcd_logical_block();
+    const int t_begin = b * per_block;
+    const int t_end = min(ntiles, t_begin + per_block);
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    if (t_begin >= t_end) return;
+
+    for (int e = threadIdx.x; e < WS::NW; e += WBLK) sW[e] = Wfrag[e];
+
+    // brick of tile t into registers: chunk e = threadIdx.x + k WBLK
+    u32x4 pre[NCH];
+    auto fetch = [&](int t) __attribute__((always_inline)) {
+        const int x0 = (t % ctx) * 16, rr = t / ctx;
+        const int yb = (rr % cty) * S::TY, zb = (rr / cty) * S::TZ;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int e = threadIdx.x + k * WBLK;
+            if (e < S::BN * V) {
+                const int site = e / V, v = e - site * V;
+                const int bx = site % S::BX, r2 = site / S::BX, by = r2 % S::BY, bz = r2 / S::BY;
+                const int x = wrap_near(x0 - 1 + bx, g.nx), y = wrap_near(yb - 1 + by, g.ny),
+                          z = wrap_near(zb - 1 + bz, g.nz);
+                const size_t gs = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
+                pre[k] = *reinterpret_cast<const u32x4 *>(X + gs * CIN + v * 8);
+            }
+        }
+    };
+    fetch(t_begin);
+
+    for (int t = t_begin; t < t_end; ++t) {
+        const int x0 = (t % ctx) * 16, rr = t / ctx;
+        const int yb = (rr % cty) * S::TY, zb = (rr / cty) * S::TZ;
+        __syncthreads();  // the previous tile's reads of the brick are done
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int e = threadIdx.x + k * WBLK;
+            if (e < S::BN * V) {
+                const int site = e / V, v = e - site * V;
+                sB[brick_chunk<V>(site, v)] = pre[k];
+            }
+        }
+        __syncthreads();
+        if (t + 1 < t_end) fetch(t + 1);  // in flight during this tile's MFMAs
+        f32x4 acc[RZ * RY][NS];
+#pragma unroll
+        for (int m = 0; m < RZ * RY; ++m)
+#pragma unroll
+            for (int ns = 0; ns < NS; ++ns) acc[m][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+        u32x4 a[NS], an[NS];
+#pragma unroll
+        for (int ns = 0; ns < NS; ++ns) a[ns] = sW[ns * 64 + l];
+#pragma unroll 1
+        for (int dx = 0; dx < 3; ++dx) {
+            u32x4 f[RZ + 2][RY + 2];
+#pragma unroll
+            for (int zz = 0; zz < RZ + 2; ++zz)
+#pragma unroll
+                for (int yy = 0; yy < RY + 2; ++yy) {
+                    const int site = ((wz * RZ + zz) * S::BY + (wy * RY + yy)) * S::BX + li + dx;
+                    f[zz][yy] = sB[brick_chunk<V>(site, cv)];
+                }
+#pragma unroll
+            for (int k = 0; k < KPD; ++k) {
+                const int ks = dx * KPD + k;
+                if (ks + 1 < S::NKS) {
+#pragma unroll
+                    for (int ns = 0; ns < NS; ++ns) an[ns] = sW[((ks + 1) * NS + ns) * 64 + l];
+                }
+#pragma unroll
+                for (int zz = 0; zz < RZ; ++zz)
+#pragma unroll
+                    for (int yy = 0; yy < RY; ++yy) {
+                        u32x4 bop;
+                        if (CIN == 32) {
+                            bop = f[zz + k / 3][yy + k % 3];
+                        } else {
+                            const int qa = 2 * k, qb = 2 * k + 1 < 9 ? 2 * k + 1 : 0;
+                            const u32x4 lo = f[zz + qa / 3][yy + qa % 3];
+                            const u32x4 hi = 2 * k + 1 < 9 ? f[zz + qb / 3][yy + qb % 3] : zero;
+                            bop = upper ? hi : lo;
+                        }
+#pragma unroll
+                        for (int ns = 0; ns < NS; ++ns)
+                            acc[zz * RY + yy][ns] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf16x8, a[ns]), __builtin_bit_cast(bf16x8, bop),
+                                acc[zz * RY + yy][ns], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int ns = 0; ns < NS; ++ns) a[ns] = an[ns];
+            }
+        }
+        const int xo = x0 + li, y0 = yb + wy * RY, z0 = zb + wz * RZ;
+#pragma unroll
+        for (int zz = 0; zz < RZ; ++zz)
+#pragma unroll
+            for (int yy = 0; yy < RY; ++yy) {
+                const int yo = y0 + yy, zo = z0 + zz;
+                if (xo >= g.nx || yo >= g.ny || zo >= g.nz) continue;
+                const size_t s = size_t(xo) + size_t(g.nx) * (size_t(yo) + size_t(g.ny) * zo);
+#pragma unroll
+                for (int ns = 0; ns < NS; ++ns) {
+                    const f32x4 v = acc[zz * RY + yy][ns];
+                    const int co = ns * 16 + 4 * lg;
+                    if (MODE == MODE_RELU) {
+                        unsigned short h[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h[r] = co + r < co_valid ? f2bf(fmaxf(v[r] + bv[ns][r], 0.f)) : 0;
+                        *reinterpret_cast<uint2 *>(static_cast<unsigned short *>(out) + s * COUT + co) =
+                            make_uint2(unsigned(h[0]) | (unsigned(h[1]) << 16), unsigned(h[2]) | (unsigned(h[3]) << 16));
+                    } else if (MODE == MODE_LINEAR) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (co + r < co_valid) static_cast<float *>(out)[s * co_valid + co + r] = v[r] + bv[ns][r];
+                    } else if (MODE == MODE_MASK) {
+                        const uint2 mk = *reinterpret_cast<const uint2 *>(mask + s * COUT + co);
+                        const unsigned short mh[4] = {(unsigned short)(mk.x & 0xffffu), (unsigned short)(mk.x >> 16),
+                                                      (unsigned short)(mk.y & 0xffffu), (unsigned short)(mk.y >> 16)};
+                        unsigned short h[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h[r] = bf2f(mh[r]) > 0.f ? f2bf(v[r]) : (unsigned short)0;
+                        *reinterpret_cast<uint2 *>(static_cast<unsigned short *>(out) + s * COUT + co) =
+                            make_uint2(unsigned(h[0]) | (unsigned(h[1]) << 16), unsigned(h[2]) | (unsigned(h[3]) << 16));
+                    } else {
+                        *reinterpret_cast<float4 *>(static_cast<float *>(out) + s * COUT + co) =
+                            make_float4(v[0], v[1], v[2], v[3]);
+                    }
+                }
+            }
+    }
+}
+
+template <int CIN, int COUT, int MODE>
+hipError_t conv_launch(const Grid3 &g, const unsigned short *X, const unsigned short *W, const float *bias,
+                            void *out, const unsigned short *mask, int co_valid, hipStream_t st)
+{
+    constexpr int RY = 2, RZ = 2, WY = 4, WZ = 2;
+    using S = ConvShape<CIN, COUT, RY, RZ, WY, WZ>;
+    using WS = ConvLds<CIN, COUT, RY, RZ, WY, WZ>;
     auto kern = k_conv<CIN, COUT, MODE, RY, RZ, WY, WZ>;
     static bool attr = false;
     if (!attr) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(S::lds_bytes));
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(WS::lds_bytes));
         if (e != hipSuccess) return e;
         attr = true;
     }
     const int ctx = (g.nx + 15) / 16, cty = (g.ny + S::TY - 1) / S::TY, ctz = (g.nz + S::TZ - 1) / S::TZ;
     const int ntiles = ctx * cty * ctz;
-    // two resident blocks per CU (the LDS bound), a multiple of the 8 XCDs
-    int grid = 2 * device_cus();
+    // one resident block per CU (the LDS bound), a multiple of the 8 XCDs
+    int grid = device_cus();
     grid = ntiles < grid ? ntiles : grid;
     grid = (grid + 7) & ~7;
     const int per_block = (ntiles + grid - 1) / grid;
-    kern<<<grid, BLK, S::lds_bytes, st>>>(g, ctx, cty, ntiles, per_block, X, reinterpret_cast<const u32x4 *>(W), bias,
-                                          out, mask, co_valid);
+    kern<<<grid, WBLK, WS::lds_bytes, st>>>(g, ctx, cty, ntiles, per_block, X, reinterpret_cast<const u32x4 *>(W),
+                                            bias, out, mask, co_valid);
     return hipGetLastError();
 }
+
 
 }  // namespace
 
