@@ -309,6 +309,11 @@ def run_surrogate(n=96, steps=20000, M=8, iters=1500):
         sweep[str(m)] = {"seconds": sm.seconds, "speedup": t_plain / sm.seconds,
                          "q_error_vs_plain": S.q_error(sv, plain), "fallbacks": sm.fallbacks, "cycles": sm.cycles}
         del sv
+    sv = S.new_solver(case)
+    sn = S.run(sv, net, steps, M=M, refresh=None)
+    no_refresh = {"seconds": sn.seconds, "speedup": t_plain / sn.seconds, "q_error_vs_plain": S.q_error(sv, plain),
+                  "fallbacks": sn.fallbacks, "cycles": sn.cycles, "plain_cycles": sn.plain_cycles}
+    del sv
     ex_net = hlb.Net((n, n, n))
     S.extrapolation_only(ex_net, 0.0)
     ext = S.new_solver(case)
@@ -317,18 +322,19 @@ def run_surrogate(n=96, steps=20000, M=8, iters=1500):
     flop = 2.0 * N * S.MACS_PER_SITE
     out = {
         "workload": f"{n}^3 domain-growth box (O2 slab z<32 in an x-helix, kappa 0.7, tau -0.5), FP32, "
-                    f"{steps} steps; k = 8, M = {M}, threshold {S.THRESHOLD:g}",
+                    f"{steps} steps; k = 8, M = {M}, threshold {S.THRESHOLD:g}, refresh {S.REFRESH:g}",
         "plain_fp32_s": t_plain,
         "surrogate_s": st.seconds,
         "speedup": t_plain / st.seconds,
         "q_error_vs_plain": S.q_error(sur, plain),
         "fz_max_dev_over_spread": float(np.abs(fz_sur - fz_plain).max() / spread) if spread > 0 else None,
         "domain_planes": {"plain": S.domain_size(fz_plain), "surrogate": S.domain_size(fz_sur)},
-        "cycles": st.cycles, "fallbacks": st.fallbacks, "plain_cooldown_cycles": st.plain_cycles,
+        "cycles": st.cycles, "fallbacks": st.fallbacks, "plain_cycles": st.plain_cycles,
         "fallback_steps": st.fallback_steps,
         "residual_median": float(np.median(st.residuals)) if st.residuals else None,
         "residual_max": float(np.max(st.residuals)) if st.residuals else None,
         "m_sweep": sweep,
+        "without_refresh": no_refresh,
         "extrapolation_only": {"seconds": sx.seconds, "q_error_vs_plain": S.q_error(ext, plain),
                                "fallbacks": sx.fallbacks, "cycles": sx.cycles},
         "increment_error_heldout": evals,

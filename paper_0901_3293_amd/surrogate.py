@@ -28,6 +28,7 @@ from . import hlb, inputs
 
 K_JUMP = 8            # solver steps replaced by one network application
 THRESHOLD = 1e-3      # relative residual from which a cycle falls back
+REFRESH = 0.1         # fraction of THRESHOLD from which an accepted cycle is followed by a plain one
 N_IN = 18             # network inputs: Q (5), u (3), d1 (5), s2 (5)
 
 
@@ -193,7 +194,7 @@ class RunStats:
     fallback_steps: list = field(default_factory=list)  # solver step at which each fallback cycle began
 
 
-def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64):
+def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64, refresh=REFRESH):
     """Advance `solver` by `steps` solver steps: a 2k-step history warm-up,
     then cycles of M*k steps while a whole cycle fits, plain steps for the
     rest.  A cycle is a surrogate cycle (M network jumps, the last one checked
@@ -201,7 +202,10 @@ def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64)
     reaches `threshold`) unless the runner is cooling down: after a fallback
     the next c cycles are plain (c = 1, 2, 4, ... up to cooldown_max on
     consecutive fallbacks, reset by an accepted cycle), so a fast transient is
-    not paid for twice."""
+    not paid for twice.  An accepted cycle whose residual reaches
+    refresh * threshold is followed by one plain cycle (refresh=None turns this
+    off): the errors of the unchecked jumps accumulate in the state, and a plain
+    cycle taken before the check fails costs less than a rolled-back one."""
     cyc = k * M
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -230,6 +234,8 @@ def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64)
             penalty = min(2 * penalty, cooldown_max)
         else:
             penalty = 1
+            if refresh is not None and r >= refresh * threshold:
+                wait = 1
     rest = steps - 2 * k - n_cyc * cyc
     if rest:
         solver.step(rest)
