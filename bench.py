@@ -239,13 +239,13 @@ def run_order(n=128, calls=20, threshold=0.19, relax=6000):
                     "per-plane count kernel, one small device-to-host copy"}
 
 
-def run_surrogate(n=96, steps=20000, M=8, iters=1500):
+def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500):
     """The surrogate workload on a 96^3 box: 500 training pairs from five
     O2 runs and two domain-growth runs (kappa 0.7, tau -0.5, noise 1e-3;
     the last run of each kind held out), training on the GPU, then 20000 steps
     of the domain-growth box (O2 slab z < 32 inside an x-helix) with the
-    surrogate (k = 8, M jumps per checked cycle, threshold 1e-3) against the
-    plain FP32 form from the same state."""
+    surrogate (one network jump for k solver steps, M jumps per checked
+    cycle, threshold 1e-3) against the plain FP32 form from the same state."""
     import numpy as np
     import torch
 
@@ -266,7 +266,7 @@ def run_surrogate(n=96, steps=20000, M=8, iters=1500):
     for kind, seed, count in runs:
         case = S.o2_run(n, seed=seed) if kind == "o2" else S.growth_run(n, noise_amp=1e-3, seed=seed)
         sv = S.new_solver(case)
-        S.record_pairs(net, sv, pairs, slot, count, spacing, burn_in=burn, tag=f"{kind}-{seed}")
+        S.record_pairs(net, sv, pairs, slot, count, spacing, k=k, burn_in=burn, tag=f"{kind}-{seed}")
         spans[f"{kind}-{seed}"] = list(range(slot, slot + count))
         slot += count
         del sv
@@ -300,29 +300,29 @@ def run_surrogate(n=96, steps=20000, M=8, iters=1500):
     t_plain = S.plain_run(plain, steps)
     fz_plain = S.domain_profile(plain)
     sur = S.new_solver(case)
-    st = S.run(sur, net, steps, M=M)
+    st = S.run(sur, net, steps, k=k, M=M)
     fz_sur = S.domain_profile(sur)
     sweep = {}
-    for m in (16, 32):  # jumps per checked cycle
+    for m in (2 * M, 4 * M):  # jumps per checked cycle
         sv = S.new_solver(case)
-        sm = S.run(sv, net, steps, M=m)
+        sm = S.run(sv, net, steps, k=k, M=m)
         sweep[str(m)] = {"seconds": sm.seconds, "speedup": t_plain / sm.seconds,
                          "q_error_vs_plain": S.q_error(sv, plain), "fallbacks": sm.fallbacks, "cycles": sm.cycles}
         del sv
     sv = S.new_solver(case)
-    sn = S.run(sv, net, steps, M=M, refresh=None)
+    sn = S.run(sv, net, steps, k=k, M=M, refresh=None)
     no_refresh = {"seconds": sn.seconds, "speedup": t_plain / sn.seconds, "q_error_vs_plain": S.q_error(sv, plain),
                   "fallbacks": sn.fallbacks, "cycles": sn.cycles, "plain_cycles": sn.plain_cycles}
     del sv
     ex_net = hlb.Net((n, n, n))
     S.extrapolation_only(ex_net, 0.0)
     ext = S.new_solver(case)
-    sx = S.run(ext, ex_net, steps, M=M)
+    sx = S.run(ext, ex_net, steps, k=k, M=M)
     spread = float(fz_plain.max() - fz_plain.min())
     flop = 2.0 * N * S.MACS_PER_SITE
     out = {
         "workload": f"{n}^3 domain-growth box (O2 slab z<32 in an x-helix, kappa 0.7, tau -0.5), FP32, "
-                    f"{steps} steps; k = 8, M = {M}, threshold {S.THRESHOLD:g}, refresh {S.REFRESH:g}",
+                    f"{steps} steps; k = {k}, M = {M}, threshold {S.THRESHOLD:g}, refresh {S.REFRESH:g}",
         "plain_fp32_s": t_plain,
         "surrogate_s": st.seconds,
         "speedup": t_plain / st.seconds,
@@ -445,7 +445,8 @@ def main():
                     help="batched run with the fixed work mapping and device-scope barrier fences")
     ap.add_argument("--surrogate-steps", type=int, default=20000,
                     help="steps of the 96^3 surrogate-vs-plain run (0: skip the surrogate leg)")
-    ap.add_argument("--surrogate-m", type=int, default=8, help="jumps per checked surrogate cycle")
+    ap.add_argument("--surrogate-k", type=int, default=32, help="solver steps replaced by one network jump")
+    ap.add_argument("--surrogate-m", type=int, default=4, help="jumps per checked surrogate cycle")
     ap.add_argument("--surrogate-iters", type=int, default=1500, help="training iterations of the surrogate")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
@@ -474,7 +475,7 @@ def main():
         elif a.only == "network":
             out = run_network()
         else:
-            out = run_surrogate(steps=a.surrogate_steps, M=a.surrogate_m, iters=a.surrogate_iters)
+            out = run_surrogate(steps=a.surrogate_steps, k=a.surrogate_k, M=a.surrogate_m, iters=a.surrogate_iters)
         print(json.dumps({"profiling_run": a.only, **out}), flush=True)
         return
     res = {}
@@ -509,8 +510,8 @@ def main():
         log(f"bench: batched {batched['mlups']:.1f} MLUPS aggregate")
     sur = None
     if a.surrogate_steps > 0 and not a.only:
-        log(f"bench: surrogate 96^3, {a.surrogate_steps} steps, M {a.surrogate_m}")
-        sur = run_surrogate(steps=a.surrogate_steps, M=a.surrogate_m, iters=a.surrogate_iters)
+        log(f"bench: surrogate 96^3, {a.surrogate_steps} steps, k {a.surrogate_k}, M {a.surrogate_m}")
+        sur = run_surrogate(steps=a.surrogate_steps, k=a.surrogate_k, M=a.surrogate_m, iters=a.surrogate_iters)
         log(f"bench: surrogate speedup {sur['speedup']:.2f}, Q error {sur['q_error_vs_plain']:.2e}")
     cpu = None
     if not a.no_cpu:
