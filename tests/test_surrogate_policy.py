@@ -1,0 +1,100 @@
+"""Host logic of the surrogate run (`surrogate.run`): step accounting, the
+cool-down after a fallback and the refresh after an accepted cycle with a
+large residual.  The solver, the network and the checked cycle are stand-ins
+that count steps and return scripted residuals; nothing touches a GPU."""
+import pytest
+
+from paper_0901_3293_amd import surrogate as S
+
+
+class Clock:
+    """Solver steps taken, and the kind of each cycle in order."""
+
+    def __init__(self):
+        self.steps = 0
+        self.log = []
+
+
+class FakeSolver:
+    def __init__(self, clock):
+        self.c = clock
+
+    def step(self, n):
+        self.c.steps += n
+
+
+class FakeNet:
+    def __init__(self, clock):
+        self.c = clock
+
+    def warmup(self, solver, k):
+        self.c.steps += 2 * k  # two k-step increments of history
+
+
+def run(monkeypatch, script, steps, k=4, M=3, **kw):
+    """Run the policy with surrogate cycles returning (fell_back, residual)
+    from `script` in order; returns the stats and the clock."""
+    clock = Clock()
+    it = iter(script)
+
+    def advance(solver, net, k, M, threshold):
+        f, r = next(it)
+        clock.steps += M * k
+        clock.log.append("F" if f else "S")
+        return f, r
+
+    monkeypatch.setattr(S.hlb, "surrogate_advance", advance)
+    monkeypatch.setattr(S.torch.cuda, "synchronize", lambda: None)
+    solver, net = FakeSolver(clock), FakeNet(clock)
+    orig_step = solver.step
+
+    def step(n):
+        if n == M * k - 2 * k:
+            clock.log.append("P")
+        orig_step(n)
+
+    solver.step = step
+    st = S.run(solver, net, steps, k=k, M=M, **kw)
+    return st, clock
+
+
+@pytest.mark.parametrize("steps", [8, 20, 8 + 12 * 5, 8 + 12 * 5 + 7])
+def test_steps_add_up(monkeypatch, steps):
+    st, clock = run(monkeypatch, [(False, 1e-5)] * 100, steps)
+    assert clock.steps == steps
+    assert st.cycles == (steps - 8) // 12 and st.fallbacks == 0 and st.plain_cycles == 0
+
+
+def test_cooldown_doubles_and_resets(monkeypatch):
+    """Fallback, fallback, accept, fallback: plain cycles 1, then 2, then none,
+    then 1 again (the penalty was reset by the accepted cycle)."""
+    script = [(True, 2e-3), (True, 2e-3), (False, 1e-5), (True, 2e-3), (False, 1e-5), (False, 1e-5)]
+    st, clock = run(monkeypatch, script, 8 + 12 * 10, refresh=None)
+    assert "".join(clock.log) == "FPFPPSFPSS"
+    assert st.fallbacks == 3 and st.plain_cycles == 4 and st.cycles == 6
+    assert clock.steps == 8 + 12 * 10
+    assert st.fallback_steps == [8, 8 + 2 * 12, 8 + 6 * 12]
+
+
+def test_cooldown_is_capped(monkeypatch):
+    st, clock = run(monkeypatch, [(True, 1.0)] * 10, 8 + 12 * (1 + 1 + 2 + 2 + 1 + 2 + 1), cooldown_max=2,
+                    refresh=None)
+    assert "".join(clock.log) == "FPFPPFPPFP"
+
+
+def test_refresh_after_large_accepted_residual(monkeypatch):
+    """An accepted cycle at or above refresh * threshold is followed by one
+    plain cycle; below it, by another surrogate cycle."""
+    thr = 1e-3
+    script = [(False, 1e-5), (False, 1e-4), (False, 0.99e-4), (False, 5e-4), (False, 1e-6)]
+    st, clock = run(monkeypatch, script, 8 + 12 * 7, threshold=thr, refresh=0.1)
+    assert "".join(clock.log) == "SSPSSPS"
+    assert st.plain_cycles == 2 and st.fallbacks == 0 and st.cycles == 5
+    # the same residuals without the rule: no plain cycles
+    st2, clock2 = run(monkeypatch, script, 8 + 12 * 5, threshold=thr, refresh=None)
+    assert "".join(clock2.log) == "SSSSS" and st2.plain_cycles == 0
+
+
+def test_refresh_is_the_default(monkeypatch):
+    st, clock = run(monkeypatch, [(False, S.REFRESH * S.THRESHOLD), (False, 0.0)], 8 + 12 * 3)
+    assert "".join(clock.log) == "SPS"
