@@ -123,8 +123,10 @@ __device__ __forceinline__ Coef<T> uni(const Coef<T> &c)
 }
 
 // The items [lo, hi) of this block's group, taken by its `per` blocks in
-// turn starting at `rank`.
-template <typename T, int PH>
+// turn starting at `rank`.  STREAM: nontemporal population loads and stores
+// in the LB phase (see pop_load in sitekern.h); measured faster for the phase
+// kernels in cache groups, slower for the persistent kernel.
+template <typename T, int PH, bool STREAM = false>
 __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 *__restrict__ items, int lo, int hi,
                                           int rank, int per, int step)
 {
@@ -148,7 +150,7 @@ __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 
             if (PH == PH_STRESS)
                 stress_at(G, c, Q, Pi, s);
             else if (PH == PH_LB)
-                lb_at(G, c, gin, Pi, gout, u, s);
+                lb_at<T, STREAM>(G, c, gin, Pi, gout, u, s);
             else if (PH == PH_PRED)
                 pred_at(G, c, Q, u, Qs, s);
             else
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(BLK) void k_phase(Rep<T> *__restrict__ reps, const 
 {
     const int it = int(blockIdx.x & 7) * int(gridDim.x >> 3) + int(blockIdx.x >> 3);
     if (it >= n_items) return;
-    run_phase<T, PH>(reps, items, first + it, first + it + 1, 0, 1, step);
+    run_phase<T, PH, true>(reps, items, first + it, first + it + 1, 0, 1, step);
 }
 
 // Advance the device ping-pong index of every box with flow after an odd

@@ -23,6 +23,8 @@
 //  77 values):  k_stress, k_lb, k_qupdate
 // The split coupling (Sec. 2.2) runs the SITES and MIXED schedules with
 // k_stress / k_lb writing and reading the split terms (101 and 83 values).
+// The population sweeps (k_lb, k_lbf, the second D3Q15 pass k_pc2) load and
+// store the populations nontemporally (pop_load / pop_store in sitekern.h).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -458,9 +460,9 @@ __global__ __launch_bounds__(BLK) void k_lb(Geom G, Coef<T> c, const T *__restri
     const int s = site_index();
     if (s >= G.N) return;
     if (SPLIT)
-        lb_split_at(G, c, gin, Pi, gout, u, s);
+        lb_split_at<T, true>(G, c, gin, Pi, gout, u, s);
     else
-        lb_at(G, c, gin, Pi, gout, u, s);
+        lb_at<T, true>(G, c, gin, Pi, gout, u, s);
 }
 
 template <typename T>
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(BLK) void k_pc2(Geom G, Coef<T> c, const T *__restr
                                              T *__restrict__ gout)
 {
     const int s = site_index();
-    if (s < G.N) pc2_at<T, SPLIT>(G, c, g, P, Pi, bsave, gout, s);
+    if (s < G.N) pc2_at<T, SPLIT, true>(G, c, g, P, Pi, bsave, gout, s);
 }
 
 // D3Q15 state from (rho, u): g_i(x) = f_i^eq(rho(x), u(x)) - A_s(rho0) in
@@ -563,12 +565,12 @@ __global__ __launch_bounds__(BLK) void k_lbf(Geom G, Coef<T> c, const T *__restr
     const Nbr S = nbr_of(G, s);
     T g[19], f[3], uu[3], rho;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
+    for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(&gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) f[a] = F[a * N + s];
     lb_collide(c, g, f, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) gout[i * N + s] = g[i];
+    for (int i = 0; i < 19; ++i) pop_store<true>(&gout[i * N + s], g[i]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
 }

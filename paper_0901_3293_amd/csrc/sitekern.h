@@ -39,6 +39,27 @@ __device__ __forceinline__ Nbr nbr_of(const Geom &G, int s)
     return S;
 }
 
+// Population access.  In a sweep over one whole box every population value
+// is read once and written once per step, and the next reader of the written
+// value is the next step's sweep, after the Q-side kernels have moved their
+// own fields; with STREAM the loads and stores are nontemporal so that the
+// populations do not push Q, u and the stress out of the L2 and the
+// last-level cache between the kernels of a step.  The batched kernels keep
+// a cache group's populations resident on purpose and use plain accesses.
+template <bool STREAM, typename T>
+__device__ __forceinline__ T pop_load(const T *p)
+{
+    if constexpr (STREAM) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool STREAM, typename T>
+__device__ __forceinline__ void pop_store(T *p, T v)
+{
+    if constexpr (STREAM) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Pulled source of population i arriving at (x,y,z): site (x,y,z) - e_i.
 __device__ __forceinline__ int pull_from(const Geom &G, const Nbr &S, int cx, int cy, int cz)
 {
@@ -113,7 +134,7 @@ __device__ __forceinline__ T stress_at(const Geom &G, const Coef<T> &c, const T 
 
 // Pull-stream, BGK collision with the body force div Pi (Eqs. (14), (16),
 // (19)) at one site; writes g' and u.
-template <typename T>
+template <typename T, bool STREAM = false>
 __device__ __forceinline__ void lb_at(const Geom &G, const Coef<T> &c, const T *__restrict__ gin,
                                       const T *__restrict__ Pi, T *__restrict__ gout, T *__restrict__ u, int s)
 {
@@ -121,11 +142,11 @@ __device__ __forceinline__ void lb_at(const Geom &G, const Coef<T> &c, const T *
     const Nbr S = nbr_of(G, s);
     T g[19], F[3], uu[3], rho;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
+    for (int i = 0; i < 19; ++i) g[i] = pop_load<STREAM>(&gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])]);
     divergence(Pi, N, S, F);
     lb_collide(c, g, F, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) gout[i * N + s] = g[i];
+    for (int i = 0; i < 19; ++i) pop_store<STREAM>(&gout[i * N + s], g[i]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
 }
@@ -163,7 +184,7 @@ __device__ __forceinline__ void split_force(const T *__restrict__ P, size_t N, c
 
 // LB step of the split coupling at one site: pull, collide with the stress in
 // the equilibrium and the split body force; writes g' and u.
-template <typename T>
+template <typename T, bool STREAM = false>
 __device__ __forceinline__ void lb_split_at(const Geom &G, const Coef<T> &c, const T *__restrict__ gin,
                                             const T *__restrict__ P, T *__restrict__ gout, T *__restrict__ u, int s)
 {
@@ -171,13 +192,13 @@ __device__ __forceinline__ void lb_split_at(const Geom &G, const Coef<T> &c, con
     const Nbr S = nbr_of(G, s);
     T g[19], b[3], sig[6], uu[3], rho;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
+    for (int i = 0; i < 19; ++i) g[i] = pop_load<STREAM>(&gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])]);
     split_force(P, N, S, b);
 #pragma unroll
     for (int k = 0; k < 6; ++k) sig[k] = P[k * N + s];
     lb_collide_split(c, g, b, sig, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) gout[i * N + s] = g[i];
+    for (int i = 0; i < 19; ++i) pop_store<STREAM>(&gout[i * N + s], g[i]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
 }
@@ -217,7 +238,7 @@ __device__ __forceinline__ void pc1_at(const Geom &G, const Coef<T> &c, const T 
 
 // Second pass at one site y: f*_i(y) = P_i(y - e_i), collision C(y, {f*}),
 //   f_i(y, t + 1) = [f_i(y - e_i) + P_i(y - e_i)]/2 + C_i(y, {f*})/2.
-template <typename T, bool SPLIT>
+template <typename T, bool SPLIT, bool STREAM = false>
 __device__ __forceinline__ void pc2_at(const Geom &G, const Coef<T> &c, const T *__restrict__ g,
                                        const T *__restrict__ P, const T *__restrict__ Pi,
                                        const T *__restrict__ bsave, T *__restrict__ gout, int s)
@@ -228,8 +249,8 @@ __device__ __forceinline__ void pc2_at(const Geom &G, const Coef<T> &c, const T 
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
         const int t = pull_from(G, S, DX15[i], DY15[i], DZ15[i]);
-        fs[i] = P[i * N + t];
-        fo[i] = T(0.5) * (g[i * N + t] + fs[i]);
+        fs[i] = pop_load<STREAM>(&P[i * N + t]);
+        fo[i] = T(0.5) * (pop_load<STREAM>(&g[i * N + t]) + fs[i]);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) b[a] = bsave[a * N + s];
@@ -238,7 +259,7 @@ __device__ __forceinline__ void pc2_at(const Geom &G, const Coef<T> &c, const T 
         for (int k = 0; k < 6; ++k) sig[k] = Pi[k * N + s];
     lb15_collide(c, fs, SPLIT ? sig : static_cast<const T *>(nullptr), b, C, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 15; ++i) gout[i * N + s] = fo[i] + T(0.5) * C[i];
+    for (int i = 0; i < 15; ++i) pop_store<STREAM>(&gout[i * N + s], fo[i] + T(0.5) * C[i]);
 }
 
 // Predictor Q* = Q + R(Q, u) at one site (Eqs. (2)-(4)).

@@ -3,10 +3,12 @@ passes) into a short text table: per kernel, average duration, HBM bytes per
 dispatch (counter KiB scaled by the reading of a plain copy of known size),
 and the algorithmic bytes the kernel has to move.
 
-usage: python -m paper_0901_3293_amd.profsum TRACE_DB FETCH_DB WRITE_DB
+usage: python -m paper_0901_3293_amd.profsum TRACE_DB [FETCH_DB WRITE_DB]
        --copy-bytes 536870912 --alg k_lb=VALUES ... --esz 4 --sites N
        [--mfma]   (convolution kernels: padded MFMA flops per dispatch from the
                    channel counts in the kernel name, TFLOP/s against 2.5 PFLOP/s)
+With the trace alone: calls, average and total duration per kernel, and the
+algorithmic rate where --alg gives the kernel's values per site.
 """
 from __future__ import annotations
 
@@ -64,8 +66,8 @@ def counter(db, cname):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("trace_db")
-    ap.add_argument("fetch_db")
-    ap.add_argument("write_db")
+    ap.add_argument("fetch_db", nargs="?")
+    ap.add_argument("write_db", nargs="?")
     ap.add_argument("--copy-bytes", type=float, default=512 * 2 ** 20)
     ap.add_argument("--sites", type=int, required=True)
     ap.add_argument("--esz", type=int, required=True)
@@ -76,6 +78,13 @@ def main():
     a = ap.parse_args()
     alg = {k: float(v) for k, v in (x.split("=") for x in a.alg)}
     t = trace(a.trace_db)
+    if a.fetch_db is None or a.write_db is None:
+        print(f"# {a.title}")
+        print(f"{'kernel':16s} {'calls':>6s} {'avg_us':>9s} {'total_ms':>9s} {'alg_MB':>8s} {'alg_GB/s':>9s}")
+        for k, (n, us) in sorted(t.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+            al = alg.get(k, float("nan")) * a.esz * a.sites / 1e6
+            print(f"{k:16s} {n:6d} {us:9.2f} {n * us / 1e3:9.3f} {al:8.1f} {al / us * 1e3:9.0f}")
+        return
     fe = counter(a.fetch_db, "FETCH_SIZE")
     wr = counter(a.write_db, "WRITE_SIZE")
     cname = COPY
