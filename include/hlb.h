@@ -219,9 +219,10 @@ int hlb_get_schedule(const hlb_ctx *ctx, int *schedule, int *tz);
 
 /* Autotuner: time trial_steps steps of every candidate schedule (per-site;
  * tiled and mixed with tz = 8, 16, 32; no tiled with the split coupling or
- * the D3Q15 scheme) on
- * this context's lattice and precision with HIP
- * events on its stream, keep the fastest, and put the state back as it was
+ * the D3Q15 scheme) on this context's lattice and precision with HIP events
+ * on its stream, in two passes over the candidates (each scored by its faster
+ * pass, 2 untimed steps before every trial), keep the fastest, and put the
+ * state back as it was
  * (through a host copy of hlb_state_bytes bytes).  *best_ms_per_step (may be
  * NULL) receives the winner's time per step.  Synchronises the stream. */
 int hlb_autotune(hlb_ctx *ctx, int trial_steps, double *best_ms_per_step);

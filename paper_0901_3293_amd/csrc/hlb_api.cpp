@@ -1,6 +1,7 @@
 // hlb_api.cpp -- the C-ABI of include/hlb.h: validation, workspace layout,
 // sticky error handling and the host side of every entry point.  All
 // arithmetic on the state runs in the kernels of kernels.hip.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -266,30 +267,42 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
     hipEvent_t a, b;
     HIP_TRY(c, hipEventCreate(&a));
     HIP_TRY(c, hipEventCreate(&b));
-    double best = 1e300;
-    Cand pick = cands[0];
-    for (const Cand &k : cands) {
-        if (k.sched != HLB_SCHED_SITES && k.tz > c->D.G.nz && k.tz != 8) continue;
-        if (k.sched == HLB_SCHED_TILED && (c->p.flow == HLB_FLOW_SPLIT || c->p.model == HLB_LB_D3Q15_PC)) continue;
-        c->D.sched = k.sched;
-        c->D.tz = k.tz;
-        hipError_t e = hlb::run_steps(c->D, c->p, 2);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(a, c->D.stream);
-        if (e == hipSuccess) e = hlb::run_steps(c->D, c->p, trial_steps);
-        if (e == hipSuccess) e = hipEventRecord(b, c->D.stream);
-        if (e == hipSuccess) e = hipEventSynchronize(b);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-        if (e != hipSuccess) {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-            return hip_fail(c, e, "hlb_autotune trial");
-        }
-        if (ms / trial_steps < best) {
-            best = ms / trial_steps;
-            pick = k;
+    // Two passes over the candidates, each candidate scored by its faster
+    // pass: the first trials of a call can run before the clocks and caches
+    // have settled, which would penalise whichever candidate comes first.
+    constexpr int NC = sizeof(cands) / sizeof(cands[0]);
+    double t[NC];
+    for (int i = 0; i < NC; ++i) t[i] = 1e300;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i < NC; ++i) {
+            const Cand &k = cands[i];
+            if (k.sched != HLB_SCHED_SITES && k.tz > c->D.G.nz && k.tz != 8) continue;
+            if (k.sched == HLB_SCHED_TILED && (c->p.flow == HLB_FLOW_SPLIT || c->p.model == HLB_LB_D3Q15_PC))
+                continue;
+            c->D.sched = k.sched;
+            c->D.tz = k.tz;
+            hipError_t e = hlb::run_steps(c->D, c->p, 2);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(a, c->D.stream);
+            if (e == hipSuccess) e = hlb::run_steps(c->D, c->p, trial_steps);
+            if (e == hipSuccess) e = hipEventRecord(b, c->D.stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                return hip_fail(c, e, "hlb_autotune trial");
+            }
+            t[i] = std::min(t[i], double(ms) / trial_steps);
         }
     }
+    double best = 1e300;
+    Cand pick = cands[0];
+    for (int i = 0; i < NC; ++i)
+        if (t[i] < best) {
+            best = t[i];
+            pick = cands[i];
+        }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     c->D.sched = pick.sched;
