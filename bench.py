@@ -84,7 +84,7 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
     s.set_params(p)
     s.set_fields(Q, u, rho)
     if schedule == "auto":
-        sched, tz, _ = s.autotune(10)
+        sched, tz, _ = s.autotune(40)
     else:
         s.set_schedule(schedule, tz)
         sched, tz = s.schedule()

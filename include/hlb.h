@@ -107,7 +107,9 @@ typedef struct {
 
 /* Bytes of device workspace a context of this size and precision needs.
  * Returns 0 if the arguments are invalid (any n < 4, unknown precision, or a
- * lattice too large to index). */
+ * lattice too large to index: nx*ny*nz >= 2^30 sites, or one field plane of
+ * nx*ny*nz values of 4 GiB or more, i.e. FP64 lattices of 2^29 sites and
+ * above). */
 size_t hlb_workspace_bytes(int nx, int ny, int nz, int precision);
 
 /* Create a context on the current HIP device for an nx*ny*nz periodic lattice
@@ -249,7 +251,8 @@ const char *hlb_kernel_name(int k);
  * ------------------------------------------------------------------------ */
 typedef struct hlb_batch hlb_batch;
 
-/* dims: n triples (nx, ny, nz), each >= 4.  Returns 0 for invalid input. */
+/* dims: n triples (nx, ny, nz), each >= 4, each box within the size limits
+ * of hlb_workspace_bytes.  Returns 0 for invalid input. */
 size_t hlb_batch_workspace_bytes(int n, const int *dims, int precision);
 int hlb_batch_create(int n, const int *dims, int precision, void *device_workspace, size_t workspace_bytes,
                      void *hip_stream, hlb_batch **out);

@@ -104,6 +104,11 @@ __device__ __forceinline__ P *uni(P *p)
     return reinterpret_cast<P *>(((unsigned long long)hi << 32) | lo);
 }
 
+__device__ __forceinline__ FastDiv uni(const FastDiv &f)
+{
+    return FastDiv{unsigned(__builtin_amdgcn_readfirstlane(int(f.m))), uni(f.l)};
+}
+
 template <typename T>
 __device__ __forceinline__ Coef<T> uni(const Coef<T> &c)
 {
@@ -137,7 +142,7 @@ __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 
         const Rep<T> &R = reps[box];
         if ((PH == PH_STRESS || PH == PH_LB) && !uni(R.flow)) continue;
         const int gc = uni(R.gcur) ^ (step & 1);
-        const Geom G = {uni(R.G.nx), uni(R.G.ny), uni(R.G.nz), uni(R.G.N)};
+        const Geom G = {uni(R.G.nx), uni(R.G.ny), uni(R.G.nz), uni(R.G.N), uni(R.G.dx), uni(R.G.dy)};
         const Coef<T> c = uni(R.c);
         T *__restrict__ Q = uni(R.Q);
         T *__restrict__ Qs = uni(R.Qs);

@@ -59,6 +59,7 @@ bool box_bytes(int nx, int ny, int nz, bool fp32, size_t &bytes, size_t &part)
     const double n = double(nx) * ny * nz;
     if (n >= 2147483647.0 / 2) return false;
     const size_t N = size_t(nx) * ny * nz, e = fp32 ? 4 : 8;
+    if (N * e >= (size_t(1) << 32)) return false;  // kernels address a plane with 32-bit byte offsets
     bytes = 2 * align256(19 * N * e) + 2 * align256(5 * N * e) + align256(3 * N * e) + align256(9 * N * e);
     part = align256(hlb::partial_doubles(nx, ny, nz) * 8);
     return true;
@@ -283,7 +284,7 @@ int hlb_batch_create(int n, const int *dims, int precision, void *ws, size_t ws_
         const size_t N = size_t(nx) * ny * nz, e = b->fp32 ? 4 : 8;
         hlb::Device &D = b->box[i];
         std::memset(&D, 0, sizeof(D));
-        D.G = {nx, ny, nz, int(N)};
+        D.G = hlb::make_geom(nx, ny, nz);
         D.fp32 = b->fp32;
         D.g[0] = p; p += align256(19 * N * e);
         D.g[1] = p; p += align256(19 * N * e);

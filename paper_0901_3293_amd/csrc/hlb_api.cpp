@@ -33,6 +33,7 @@ bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
     if (n >= 2147483647.0 / 2) return false;
     const size_t N = size_t(nx) * ny * nz;
     const size_t e = precision == HLB_FP64 ? 8 : 4;
+    if (N * e >= (size_t(1) << 32)) return false;  // kernels address a plane with 32-bit byte offsets
     L.g = align256(19 * N * e);
     L.Q = align256(5 * N * e);
     L.u = align256(3 * N * e);
@@ -99,7 +100,7 @@ int hlb_create(int nx, int ny, int nz, int precision, void *ws, size_t ws_bytes,
     if (!c) return HLB_ERR_NOMEM;
     std::memset(c, 0, sizeof(*c));
     char *p = static_cast<char *>(ws);
-    c->D.G = {nx, ny, nz, nx * ny * nz};
+    c->D.G = hlb::make_geom(nx, ny, nz);
     c->D.fp32 = precision == HLB_FP32;
     c->D.g[0] = p; p += L.g;
     c->D.g[1] = p; p += L.g;

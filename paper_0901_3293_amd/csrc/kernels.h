@@ -8,10 +8,36 @@
 
 namespace hlb {
 
+// Division of a site index by a run-time divisor d as a multiply-high and a
+// shift (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, floor(n / d) = (umulhi(n, m) + n) >> l
+// for every n < 2^31 (the sum then stays below 2^32).
+struct FastDiv {
+    unsigned m;
+    int l;
+};
+
+inline FastDiv make_fastdiv(int d)
+{
+    int l = 0;
+    while ((1ll << l) < d) ++l;
+    const unsigned long long m = ((1ull << 32) * ((1ull << l) - (unsigned long long)d)) / (unsigned long long)d + 1;
+    return FastDiv{unsigned(m), l};
+}
+
+__device__ __forceinline__ unsigned fastdiv(unsigned n, FastDiv f) { return (__umulhi(n, f.m) + n) >> f.l; }
+
 struct Geom {
     int nx, ny, nz;
-    int N;  // nx*ny*nz (< 2^31)
+    int N;  // nx*ny*nz (< 2^30; one plane of N values < 4 GiB)
+    FastDiv dx, dy;  // division by nx and ny
 };
+
+inline Geom make_geom(int nx, int ny, int nz)
+{
+    return Geom{nx, ny, nz, nx * ny * nz, make_fastdiv(nx), make_fastdiv(ny)};
+}
 
 // Fluid coupling (Sec. 2.1, 2.2): off (u == 0), the whole chemical stress as a
 // body force, or the split of Eqs. (17)-(21).

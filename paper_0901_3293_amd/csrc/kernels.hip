@@ -561,18 +561,18 @@ __global__ __launch_bounds__(BLK) void k_lbf(Geom G, Coef<T> c, const T *__restr
 {
     const int s = site_index();
     if (s >= G.N) return;
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
+    const int N = G.N;
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T g[19], f[3], uu[3], rho;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(&gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])]);
+    for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
 #pragma unroll
-    for (int a = 0; a < 3; ++a) f[a] = F[a * N + s];
+    for (int a = 0; a < 3; ++a) f[a] = *at(plane(F, a, N), O.s);
     lb_collide(c, g, f, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) pop_store<true>(&gout[i * N + s], g[i]);
+    for (int i = 0; i < 19; ++i) pop_store<true>(plane(gout, i, N), O.s, g[i]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
+    for (int a = 0; a < 3; ++a) *at(plane(u, a, N), O.s) = uu[a];
 }
 
 // Populations such that the first pull returns g^eq(rho(x), u(x)):
@@ -616,10 +616,11 @@ __global__ __launch_bounds__(BLK) void k_readout(Geom G, Coef<T> c, const T *__r
         for (int i = 0; i < 19; ++i) gg[i] = g[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])];
         lb_moments(gg, drho, j);
         if (Pi) {
+            const Off<T> O = offsets<T>(S);
             if (SPLIT)
-                split_force(Pi, N, S, f);
+                split_force(Pi, G.N, O, f);
             else
-                divergence(Pi, N, S, f);
+                divergence(Pi, G.N, O, f);
         }
         const T rho = c.rho0 + drho;
         T uu[3];

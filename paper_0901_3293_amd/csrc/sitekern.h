@@ -25,10 +25,10 @@ __device__ __forceinline__ Nbr nbr_of(const Geom &G, int s)
 {
     Nbr S;
     S.s = s;
-    S.x = s % G.nx;
-    const int yz = s / G.nx;
-    S.y = yz % G.ny;
-    S.z = yz / G.ny;
+    const int yz = int(fastdiv(unsigned(s), G.dx));
+    S.x = s - yz * G.nx;
+    S.z = int(fastdiv(unsigned(yz), G.dy));
+    S.y = yz - S.z * G.ny;
     const int sxy = G.nx * G.ny;
     S.nb[0] = (S.x == G.nx - 1) ? s - (G.nx - 1) : s + 1;
     S.nb[1] = (S.x == 0) ? s + (G.nx - 1) : s - 1;
@@ -39,6 +39,62 @@ __device__ __forceinline__ Nbr nbr_of(const Geom &G, int s)
     return S;
 }
 
+// Byte offsets of a site and of its six neighbours within one field plane of
+// elements of type T.  A plane of N values is under 4 GiB (checked when a
+// context is created), so 32-bit offsets from the plane's base address it;
+// the base (field + c N) is the same for the whole wave, and one site's
+// offsets serve every component of every field.
+template <typename T>
+struct Off {
+    unsigned s;
+    unsigned nb[6];  // x+1, x-1, y+1, y-1, z+1, z-1
+};
+
+template <typename T>
+__device__ __forceinline__ Off<T> offsets(const Nbr &S)
+{
+    Off<T> O;
+    O.s = unsigned(S.s) * unsigned(sizeof(T));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) O.nb[k] = unsigned(S.nb[k]) * unsigned(sizeof(T));
+    return O;
+}
+
+// Plane c of a component-major field of N values per component.
+template <typename T>
+__device__ __forceinline__ T *plane(T *f, int c, int N)
+{
+    return f + size_t(c) * size_t(N);
+}
+
+template <typename T>
+__device__ __forceinline__ T *at(T *P, unsigned b)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(P) + b);
+}
+
+template <typename T>
+__device__ __forceinline__ const T *at(const T *P, unsigned b)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(P) + b);
+}
+
+// Byte offset of the site x - e of a population with velocity e = (cx, cy,
+// cz): each nonzero component adds the byte distance to the neighbour on the
+// opposite side (periodic), so a pull costs one or two additions.
+template <typename T>
+__device__ __forceinline__ unsigned pull_off(const Off<T> &O, int cx, int cy, int cz)
+{
+    unsigned b = O.s;
+    if (cx > 0) b += O.nb[1] - O.s;
+    else if (cx < 0) b += O.nb[0] - O.s;
+    if (cy > 0) b += O.nb[3] - O.s;
+    else if (cy < 0) b += O.nb[2] - O.s;
+    if (cz > 0) b += O.nb[5] - O.s;
+    else if (cz < 0) b += O.nb[4] - O.s;
+    return b;
+}
+
 // Population access.  In a sweep over one whole box every population value
 // is read once and written once per step, and the next reader of the written
 // value is the next step's sweep, after the Q-side kernels have moved their
@@ -47,17 +103,17 @@ __device__ __forceinline__ Nbr nbr_of(const Geom &G, int s)
 // last-level cache between the kernels of a step.  The batched kernels keep
 // a cache group's populations resident on purpose and use plain accesses.
 template <bool STREAM, typename T>
-__device__ __forceinline__ T pop_load(const T *p)
+__device__ __forceinline__ T pop_load(const T *P, unsigned b)
 {
-    if constexpr (STREAM) return __builtin_nontemporal_load(p);
-    else return *p;
+    if constexpr (STREAM) return __builtin_nontemporal_load(at(P, b));
+    else return *at(P, b);
 }
 
 template <bool STREAM, typename T>
-__device__ __forceinline__ void pop_store(T *p, T v)
+__device__ __forceinline__ void pop_store(T *P, unsigned b, T v)
 {
-    if constexpr (STREAM) __builtin_nontemporal_store(v, p);
-    else *p = v;
+    if constexpr (STREAM) __builtin_nontemporal_store(v, at(P, b));
+    else *at(P, b) = v;
 }
 
 // Pulled source of population i arriving at (x,y,z): site (x,y,z) - e_i.
@@ -71,16 +127,16 @@ __device__ __forceinline__ int pull_from(const Geom &G, const Nbr &S, int cx, in
 }
 
 template <typename T>
-__device__ __forceinline__ void gather_q(const T *__restrict__ Q, size_t N, const Nbr &S, T q[5], T d[3][5],
+__device__ __forceinline__ void gather_q(const T *__restrict__ Q, int N, const Off<T> &O, T q[5], T d[3][5],
                                          T lap[5])
 {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        const T *P = Q + c * N;
-        const T v = P[S.s];
-        const T xp = P[S.nb[0]], xm = P[S.nb[1]];
-        const T yp = P[S.nb[2]], ym = P[S.nb[3]];
-        const T zp = P[S.nb[4]], zm = P[S.nb[5]];
+        const T *P = plane(Q, c, N);
+        const T v = *at(P, O.s);
+        const T xp = *at(P, O.nb[0]), xm = *at(P, O.nb[1]);
+        const T yp = *at(P, O.nb[2]), ym = *at(P, O.nb[3]);
+        const T zp = *at(P, O.nb[4]), zm = *at(P, O.nb[5]);
         q[c] = v;
         d[0][c] = T(0.5) * (xp - xm);
         d[1][c] = T(0.5) * (yp - ym);
@@ -90,28 +146,29 @@ __device__ __forceinline__ void gather_q(const T *__restrict__ Q, size_t N, cons
 }
 
 template <typename T>
-__device__ __forceinline__ void gather_u(const T *__restrict__ u, size_t N, const Nbr &S, T uc[3], T W[3][3])
+__device__ __forceinline__ void gather_u(const T *__restrict__ u, int N, const Off<T> &O, T uc[3], T W[3][3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const T *P = u + a * N;
-        uc[a] = P[S.s];
-        W[a][0] = T(0.5) * (P[S.nb[0]] - P[S.nb[1]]);
-        W[a][1] = T(0.5) * (P[S.nb[2]] - P[S.nb[3]]);
-        W[a][2] = T(0.5) * (P[S.nb[4]] - P[S.nb[5]]);
+        const T *P = plane(u, a, N);
+        uc[a] = *at(P, O.s);
+        W[a][0] = T(0.5) * (*at(P, O.nb[0]) - *at(P, O.nb[1]));
+        W[a][1] = T(0.5) * (*at(P, O.nb[2]) - *at(P, O.nb[3]));
+        W[a][2] = T(0.5) * (*at(P, O.nb[4]) - *at(P, O.nb[5]));
     }
 }
 
 // Body force F_a = sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2 (Eq. (19)).
 template <typename T>
-__device__ __forceinline__ void divergence(const T *__restrict__ Pi, size_t N, const Nbr &S, T F[3])
+__device__ __forceinline__ void divergence(const T *__restrict__ Pi, int N, const Off<T> &O, T F[3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const T *Px = Pi + (3 * a + 0) * N;
-        const T *Py = Pi + (3 * a + 1) * N;
-        const T *Pz = Pi + (3 * a + 2) * N;
-        F[a] = T(0.5) * ((Px[S.nb[0]] - Px[S.nb[1]]) + (Py[S.nb[2]] - Py[S.nb[3]]) + (Pz[S.nb[4]] - Pz[S.nb[5]]));
+        const T *Px = plane(Pi, 3 * a + 0, N);
+        const T *Py = plane(Pi, 3 * a + 1, N);
+        const T *Pz = plane(Pi, 3 * a + 2, N);
+        F[a] = T(0.5) * ((*at(Px, O.nb[0]) - *at(Px, O.nb[1])) + (*at(Py, O.nb[2]) - *at(Py, O.nb[3])) +
+                         (*at(Pz, O.nb[4]) - *at(Pz, O.nb[5])));
     }
 }
 
@@ -120,15 +177,14 @@ template <typename T>
 __device__ __forceinline__ T stress_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q,
                                        T *__restrict__ Pi, int s)
 {
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
-    gather_q(Q, N, S, q, d, lap);
+    gather_q(Q, G.N, O, q, d, lap);
     site_stress(c, q, d, lap, P, fd, H);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) Pi[(3 * a + b) * N + s] = P[a][b];
+        for (int b = 0; b < 3; ++b) *at(plane(Pi, 3 * a + b, G.N), O.s) = P[a][b];
     return fd;
 }
 
@@ -138,17 +194,17 @@ template <typename T, bool STREAM = false>
 __device__ __forceinline__ void lb_at(const Geom &G, const Coef<T> &c, const T *__restrict__ gin,
                                       const T *__restrict__ Pi, T *__restrict__ gout, T *__restrict__ u, int s)
 {
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
+    const int N = G.N;
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T g[19], F[3], uu[3], rho;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = pop_load<STREAM>(&gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])]);
-    divergence(Pi, N, S, F);
+    for (int i = 0; i < 19; ++i) g[i] = pop_load<STREAM>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
+    divergence(Pi, N, O, F);
     lb_collide(c, g, F, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) pop_store<STREAM>(&gout[i * N + s], g[i]);
+    for (int i = 0; i < 19; ++i) pop_store<STREAM>(plane(gout, i, N), O.s, g[i]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
+    for (int a = 0; a < 3; ++a) *at(plane(u, a, N), O.s) = uu[a];
 }
 
 // Split-coupling terms at one site (planes of the 12 x N layout above);
@@ -157,29 +213,32 @@ template <typename T>
 __device__ __forceinline__ T split_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q, T *__restrict__ P,
                                       int s)
 {
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
+    const int N = G.N;
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T q[5], d[3][5], lap[5], sig[6], tau3[3], h[3], fd;
-    gather_q(Q, N, S, q, d, lap);
+    gather_q(Q, N, O, q, d, lap);
     site_split(c, q, d, lap, sig, tau3, h, fd);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) P[k * N + s] = sig[k];
+    for (int k = 0; k < 6; ++k) *at(plane(P, k, N), O.s) = sig[k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) P[(6 + k) * N + s] = tau3[k];
+    for (int k = 0; k < 3; ++k) *at(plane(P, 6 + k, N), O.s) = tau3[k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) P[(9 + k) * N + s] = h[k];
+    for (int k = 0; k < 3; ++k) *at(plane(P, 9 + k, N), O.s) = h[k];
     return fd;
 }
 
 // Split body force b_a = d_b tau_ab + h_a (centred on the second index;
 // tau antisymmetric, stored as xy, xz, yz).
 template <typename T>
-__device__ __forceinline__ void split_force(const T *__restrict__ P, size_t N, const Nbr &S, T b[3])
+__device__ __forceinline__ void split_force(const T *__restrict__ P, int N, const Off<T> &O, T b[3])
 {
-    const T *txy = P + 6 * N, *txz = P + 7 * N, *tyz = P + 8 * N;
-    b[0] = T(0.5) * ((txy[S.nb[2]] - txy[S.nb[3]]) + (txz[S.nb[4]] - txz[S.nb[5]])) + P[9 * N + S.s];
-    b[1] = T(0.5) * ((tyz[S.nb[4]] - tyz[S.nb[5]]) - (txy[S.nb[0]] - txy[S.nb[1]])) + P[10 * N + S.s];
-    b[2] = T(0.5) * (-(txz[S.nb[0]] - txz[S.nb[1]]) - (tyz[S.nb[2]] - tyz[S.nb[3]])) + P[11 * N + S.s];
+    const T *txy = plane(P, 6, N), *txz = plane(P, 7, N), *tyz = plane(P, 8, N);
+    b[0] = T(0.5) * ((*at(txy, O.nb[2]) - *at(txy, O.nb[3])) + (*at(txz, O.nb[4]) - *at(txz, O.nb[5]))) +
+           *at(plane(P, 9, N), O.s);
+    b[1] = T(0.5) * ((*at(tyz, O.nb[4]) - *at(tyz, O.nb[5])) - (*at(txy, O.nb[0]) - *at(txy, O.nb[1]))) +
+           *at(plane(P, 10, N), O.s);
+    b[2] = T(0.5) * (-(*at(txz, O.nb[0]) - *at(txz, O.nb[1])) - (*at(tyz, O.nb[2]) - *at(tyz, O.nb[3]))) +
+           *at(plane(P, 11, N), O.s);
 }
 
 // LB step of the split coupling at one site: pull, collide with the stress in
@@ -188,19 +247,19 @@ template <typename T, bool STREAM = false>
 __device__ __forceinline__ void lb_split_at(const Geom &G, const Coef<T> &c, const T *__restrict__ gin,
                                             const T *__restrict__ P, T *__restrict__ gout, T *__restrict__ u, int s)
 {
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
+    const int N = G.N;
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T g[19], b[3], sig[6], uu[3], rho;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = pop_load<STREAM>(&gin[i * N + pull_from(G, S, CX[i], CY[i], CZ[i])]);
-    split_force(P, N, S, b);
+    for (int i = 0; i < 19; ++i) g[i] = pop_load<STREAM>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
+    split_force(P, N, O, b);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) sig[k] = P[k * N + s];
+    for (int k = 0; k < 6; ++k) sig[k] = *at(plane(P, k, N), O.s);
     lb_collide_split(c, g, b, sig, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) pop_store<STREAM>(&gout[i * N + s], g[i]);
+    for (int i = 0; i < 19; ++i) pop_store<STREAM>(plane(gout, i, N), O.s, g[i]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a * N + s] = uu[a];
+    for (int a = 0; a < 3; ++a) *at(plane(u, a, N), O.s) = uu[a];
 }
 
 // D3Q15 predictor-corrector LB (Eq. (15)), first pass at one site x: the
@@ -214,25 +273,25 @@ __device__ __forceinline__ void pc1_at(const Geom &G, const Coef<T> &c, const T 
                                        const T *__restrict__ Pi, T *__restrict__ P, T *__restrict__ u,
                                        T *__restrict__ bsave, int s)
 {
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
+    const int N = G.N;
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T f[15], C[15], b[3], sig[6], uu[3], rho;
 #pragma unroll
-    for (int i = 0; i < 15; ++i) f[i] = g[i * N + s];
+    for (int i = 0; i < 15; ++i) f[i] = *at(plane(g, i, N), O.s);
     if (SPLIT) {
-        split_force(Pi, N, S, b);
+        split_force(Pi, N, O, b);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) sig[k] = Pi[k * N + s];
+        for (int k = 0; k < 6; ++k) sig[k] = *at(plane(Pi, k, N), O.s);
     } else {
-        divergence(Pi, N, S, b);
+        divergence(Pi, N, O, b);
     }
     lb15_collide(c, f, SPLIT ? sig : static_cast<const T *>(nullptr), b, C, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 15; ++i) P[i * N + s] = f[i] + C[i];
+    for (int i = 0; i < 15; ++i) *at(plane(P, i, N), O.s) = f[i] + C[i];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        u[a * N + s] = uu[a];
-        bsave[a * N + s] = b[a];
+        *at(plane(u, a, N), O.s) = uu[a];
+        *at(plane(bsave, a, N), O.s) = b[a];
     }
 }
 
@@ -243,23 +302,23 @@ __device__ __forceinline__ void pc2_at(const Geom &G, const Coef<T> &c, const T 
                                        const T *__restrict__ P, const T *__restrict__ Pi,
                                        const T *__restrict__ bsave, T *__restrict__ gout, int s)
 {
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
+    const int N = G.N;
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T fs[15], fo[15], C[15], b[3], sig[6], uu[3], rho;
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
-        const int t = pull_from(G, S, DX15[i], DY15[i], DZ15[i]);
-        fs[i] = pop_load<STREAM>(&P[i * N + t]);
-        fo[i] = T(0.5) * (pop_load<STREAM>(&g[i * N + t]) + fs[i]);
+        const unsigned t = pull_off(O, DX15[i], DY15[i], DZ15[i]);
+        fs[i] = pop_load<STREAM>(plane(P, i, N), t);
+        fo[i] = T(0.5) * (pop_load<STREAM>(plane(g, i, N), t) + fs[i]);
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) b[a] = bsave[a * N + s];
+    for (int a = 0; a < 3; ++a) b[a] = *at(plane(bsave, a, N), O.s);
     if (SPLIT)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) sig[k] = Pi[k * N + s];
+        for (int k = 0; k < 6; ++k) sig[k] = *at(plane(Pi, k, N), O.s);
     lb15_collide(c, fs, SPLIT ? sig : static_cast<const T *>(nullptr), b, C, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 15; ++i) pop_store<STREAM>(&gout[i * N + s], fo[i] + T(0.5) * C[i]);
+    for (int i = 0; i < 15; ++i) pop_store<STREAM>(plane(gout, i, N), O.s, fo[i] + T(0.5) * C[i]);
 }
 
 // Predictor Q* = Q + R(Q, u) at one site (Eqs. (2)-(4)).
@@ -267,14 +326,14 @@ template <typename T>
 __device__ __forceinline__ void pred_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q,
                                         const T *__restrict__ u, T *__restrict__ Qs, int s)
 {
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
+    const int N = G.N;
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
-    gather_q(Q, N, S, q, d, lap);
-    gather_u(u, N, S, uc, W);
+    gather_q(Q, N, O, q, d, lap);
+    gather_u(u, N, O, uc, W);
     site_rhs(c, q, d, lap, uc, W, R);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Qs[k * N + s] = q[k] + R[k];
+    for (int k = 0; k < 5; ++k) *at(plane(Qs, k, N), O.s) = q[k] + R[k];
 }
 
 // Corrector Q^{n+1} = Q^n + [R(Q^n) + R(Q*)]/2 = [Q^n + Q* + R(Q*)]/2, in
@@ -283,23 +342,25 @@ template <typename T>
 __device__ __forceinline__ void corr_at(const Geom &G, const Coef<T> &c, T *__restrict__ Q,
                                         const T *__restrict__ Qs, const T *__restrict__ u, int s)
 {
-    const size_t N = G.N;
-    const Nbr S = nbr_of(G, s);
-    T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
-    gather_q(Qs, N, S, q, d, lap);
-    gather_u(u, N, S, uc, W);
+    const int N = G.N;
+    const Off<T> O = offsets<T>(nbr_of(G, s));
+    T qn[5], q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) qn[k] = *at(plane(Q, k, N), O.s);  // issued with the stencil loads
+    gather_q(Qs, N, O, q, d, lap);
+    gather_u(u, N, O, uc, W);
     site_rhs(c, q, d, lap, uc, W, R);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Q[k * N + s] = T(0.5) * (Q[k * N + s] + q[k] + R[k]);
+    for (int k = 0; k < 5; ++k) *at(plane(Q, k, N), O.s) = T(0.5) * (qn[k] + q[k] + R[k]);
 }
 
 // Free-energy density at one site (Eq. (1) with the divergence term).
 template <typename T>
 __device__ __forceinline__ T fdens_at(const Geom &G, const Coef<T> &c, const T *__restrict__ Q, int s)
 {
-    const Nbr S = nbr_of(G, s);
+    const Off<T> O = offsets<T>(nbr_of(G, s));
     T q[5], d[3][5], lap[5], Qf[3][3], dQ[3][3][3], CQ[3][3], Q2[3][3], M[3][3], div[3];
-    gather_q(Q, size_t(G.N), S, q, d, lap);
+    gather_q(Q, G.N, O, q, d, lap);
     full3(q, Qf);
     full_grad(d, dQ);
     curl(dQ, CQ);

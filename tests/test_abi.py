@@ -52,6 +52,21 @@ def test_workspace_bytes(H):
     assert 78 * 4 * N <= b < 78 * 4 * N + 2 ** 20
 
 
+def test_workspace_size_limits(H):
+    """Kernels address one field plane with 32-bit byte offsets and index
+    sites in 31 bits: FP64 lattices stop below 2^29 sites (a plane of 4 GiB),
+    FP32 ones below 2^30."""
+    assert H.workspace_bytes(1024, 1024, 511, H.HLB_FP64) > 0
+    assert H.workspace_bytes(1024, 1024, 512, H.HLB_FP64) == 0
+    assert H.workspace_bytes(1024, 1024, 512, H.HLB_FP32) > 0
+    assert H.workspace_bytes(1024, 1024, 1023, H.HLB_FP32) > 0
+    assert H.workspace_bytes(1024, 1024, 1024, H.HLB_FP32) == 0
+    L = H.lib()
+    dims = (ctypes.c_int * 3)(1024, 1024, 512)
+    assert L.hlb_batch_workspace_bytes(1, dims, H.HLB_FP64) == 0
+    assert L.hlb_batch_workspace_bytes(1, dims, H.HLB_FP32) > 0
+
+
 def test_fe_from_reduced(H):
     q0 = 2 * math.pi / 16
     fe = H.fe_from_reduced(1.0, 0.0, q0, 0.01)
