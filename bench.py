@@ -392,25 +392,47 @@ def run_network(n=96, predicts=20, train_steps=10):
     return {"lattice": n, "predict_ms": ms_pred, "train_step_ms": ms_train}
 
 
-def cpu_baseline(n, budget_s=15.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(n, budget_s=15.0, budget_one_s=10.0):
     """The FP64 oracle (test infrastructure) on the host: steps of the same
-    128^3 workload until the time budget is spent (at least one step)."""
+    128^3 workload until the time budget is spent (at least one step), with
+    the oracle's default OpenMP thread count, then with one thread."""
     import oracle
     from paper_0901_3293_amd import inputs as I
 
     p, Q, u, rho = I.bpii_case(n=n)
     st = oracle.State(oracle.params(**p.as_dict()), Q, u, rho)
-    st.step(1)  # warm caches and OpenMP pool
-    done, t0 = 0, time.perf_counter()
-    while True:
-        st.step(1)
-        done += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def timed(budget):
+        st.step(1)  # warm caches and the OpenMP pool
+        done, t0 = 0, time.perf_counter()
+        while True:
+            st.step(1)
+            done += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return done, el
+
+    cores = oracle.max_threads()
+    done, el = timed(budget_s)
+    oracle.set_threads(1)
+    done1, el1 = timed(budget_one_s)
+    oracle.set_threads(cores)
     return {"value": n ** 3 * done / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{done} FP64 oracle steps of the {n}^3 workload ({el:.1f} s)"}
+            "sample": f"{done} FP64 oracle steps of the {n}^3 workload ({el:.1f} s)",
+            "one_thread": {"value": n ** 3 * done1 / el1 / 1e6, "unit": "MLUPS",
+                           "sample": f"{done1} steps ({el1:.1f} s)"},
+            "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count()}}
 
 
 def main():

@@ -102,8 +102,19 @@ def lib():
         L.or_sum.argtypes = [dp, ctypes.c_long]
         L.or_sum.restype = ctypes.c_double
         L.or_totals.argtypes = [pp, I, I, I, dp, dp, dp, dp, dp]
+        L.or_set_threads.argtypes = [I]
+        L.or_max_threads.restype = I
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Thread count of the oracle's OpenMP loops (for timing runs)."""
+    lib().or_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().or_max_threads())
 
 
 def _p(a):

@@ -49,6 +49,7 @@
  * part, not to w_i rho0.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -855,3 +856,9 @@ void or_totals(const or_params *p, int nx, int ny, int nz, const double *g,
     free(fd);
     free(tmp);
 }
+
+/* Thread count of the OpenMP loops (timing runs only; results do not depend
+ * on it: every loop writes disjoint sites and the sums are serial). */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+int or_max_threads(void) { return omp_get_max_threads(); }
