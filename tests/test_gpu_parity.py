@@ -212,6 +212,31 @@ def test_full_size_128_fp64_every_site(H, orc):
     assert np.abs(mom1 - mom0).max() < 1e-4
 
 
+def test_full_size_128_fp32_vs_fp64_1000_steps(H):
+    """The 128^3 benchmark workload, both forms in the benchmark's launch
+    configuration (the autotuner's schedules), 1000 steps: the FP32 form
+    against the FP64 GPU run (the reference at this size, itself held to the
+    oracle on every site by the test above) per field -- Q within the FP32
+    bar 1e-5, rho and u reported, and the free energy within 1e-5."""
+    say("case: 128^3 O2 fp32 vs fp64, 1000 steps")
+    p, Q, u, rho = I.bpii_case(n=128)
+    a = make(H, p, Q, u, rho, "fp64")
+    say("fp64 autotuned:", a.autotune(5))
+    b = make(H, p, Q, u, rho, "fp32")
+    say("fp32 autotuned:", b.autotune(5))
+    a.step(1000)
+    b.step(1000)
+    Qa, ua, ra = a.fields()
+    Qb, ub, rb = b.fields()
+    eQ, eu, er = rel(Qb, Qa), rel(ub, ua), rel(rb - 1.0, ra - 1.0)
+    Fa, Fb = a.totals()[2], b.totals()[2]
+    eF = abs(Fb - Fa) / abs(Fa)
+    say(f"128^3 fp32 vs fp64 after 1000 steps: Q {eQ:.2e} u {eu:.2e} rho-1 {er:.2e} F {eF:.2e}")
+    assert eQ <= 1e-5
+    assert eF <= 1e-5
+    assert np.isfinite(ub).all() and np.isfinite(rb).all()
+
+
 @pytest.mark.parametrize("kappa", [0.5, 0.8, 1.0])
 def test_slab_64x64x256_full_size(H, orc, kappa):
     """The domain-growth slab at its full size (64 x 64 x 256, O2 seed for
