@@ -108,7 +108,9 @@ __device__ __forceinline__ int brick_chunk(int site, int v)
 // tile of 16x4x4 sites, M = 16 output channels, N = 16 input channels,
 // K = 32 sites (two x-rows).  The tile's dZ and its input brick (18x6x6
 // sites, periodic wrap) are staged channel-major in LDS (brick rows padded to
-// 24 sites).  An operand of 8 consecutive sites shifted by the tap's
+// 24 sites; each channel plane padded so that its stride is 4 dwords modulo
+// the 32 LDS banks, which keeps the 16 channels a 16-byte operand read
+// touches on distinct banks).  An operand of 8 consecutive sites shifted by the tap's
 // x-offset comes from one aligned 16-byte read and one 4-byte read of the
 // brick row, shared by the three x-offsets of a (y, z) offset pair (odd
 // offsets take a 16-bit funnel shift).  With 32 output channels wave w owns
@@ -123,10 +125,15 @@ __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__
     constexpr int CIP = 32;
     constexpr int XR = 24, BYs = TYs + 2, BZs = TZs + 2, ROWS = BYs * BZs;
     constexpr int TS = TXs * TYs * TZs;  // 256 sites, 8 K-chunks of 32
+    constexpr int CSX = ROWS * XR + 40;  // brick channel stride (halfwords): 452 dwords, 4 mod 32
+    constexpr int CSD = TS + 8;          // dZ channel stride (halfwords): 132 dwords, 4 mod 32
+    static_assert((CSX / 2) % 32 == 4 && (CSD / 2) % 32 == 4, "bank-spread channel strides");
+    static_assert(CSX % 8 == 0 && CSD % 8 == 0, "16-byte aligned operand rows");
+    static_assert((TXs + 2) % 2 == 0 && XR % 2 == 0 && TXs % 2 == 0, "sites staged in x-pairs");
     constexpr int PS = 27 * CIP * COP + COP;
     constexpr int NBX = (TXs + 2) * ROWS;  // brick sites
-    __shared__ __attribute__((aligned(16))) unsigned short sX[CIP * ROWS * XR];
-    __shared__ __attribute__((aligned(16))) unsigned short sD[COP * TS];
+    __shared__ __attribute__((aligned(16))) unsigned short sX[CIP * CSX];
+    __shared__ __attribute__((aligned(16))) unsigned short sD[COP * CSD];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lg = l >> 4;
     const int mt = COP == 32 ? (w >> 1) : 0, nt = w & 1;
     const int half = COP == 32 ? 0 : (w >> 1);  // COP == 16: which K-chunks this wave takes
@@ -139,44 +146,58 @@ __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__
         int x0, y0, z0;
         tile_origin(g, t, x0, y0, z0);
         __syncthreads();
-        // input brick, channel-major: sX[ci][bz][by][bx]
-        for (int e = threadIdx.x; e < NBX * 4; e += BLK) {
-            const int site = e >> 2, v = e & 3;
-            const int bx = site % (TXs + 2), r = site / (TXs + 2), by = r % BYs, bz = r / BYs;
-            const int x = wrap(x0 - 1 + bx, g.nx), y = wrap(y0 - 1 + by, g.ny), z = wrap(z0 - 1 + bz, g.nz);
-            const size_t gs = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
-            const u32x4 val = *reinterpret_cast<const u32x4 *>(X + gs * CIP + v * 8);
-            unsigned short *d = sX + ((8 * v) * ROWS + bz * BYs + by) * XR + bx;
+        // input brick, channel-major: sX[ci][bz][by][bx].  A thread takes two
+        // x-neighbouring sites (bx, bx + 1) with all their channels and writes
+        // one 32-bit word (the two sites' values) per channel.
+        unsigned *sXw = reinterpret_cast<unsigned *>(sX);
+        for (int e = threadIdx.x; e < NBX / 2; e += BLK) {
+            const int px = e % ((TXs + 2) / 2), r = e / ((TXs + 2) / 2), by = r % BYs, bz = r / BYs;
+            const int y = wrap(y0 - 1 + by, g.ny), z = wrap(z0 - 1 + bz, g.nz);
+            const size_t row = size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
+            const size_t ga = row + size_t(wrap(x0 - 1 + 2 * px, g.nx));
+            const size_t gb = row + size_t(wrap(x0 + 2 * px, g.nx));
+            unsigned *d = sXw + r * (XR / 2) + px;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                d[(2 * c) * ROWS * XR] = (unsigned short)(val[c] & 0xffffu);
-                d[(2 * c + 1) * ROWS * XR] = (unsigned short)(val[c] >> 16);
+            for (int v = 0; v < CIP / 8; ++v) {
+                const u32x4 a = *reinterpret_cast<const u32x4 *>(X + ga * CIP + v * 8);
+                const u32x4 b = *reinterpret_cast<const u32x4 *>(X + gb * CIP + v * 8);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    d[(8 * v + 2 * c) * (CSX / 2)] = (a[c] & 0xffffu) | (b[c] << 16);
+                    d[(8 * v + 2 * c + 1) * (CSX / 2)] = (a[c] >> 16) | (b[c] & 0xffff0000u);
+                }
             }
         }
-        // output gradient of the tile, channel-major: sD[co][site]
-        for (int e = threadIdx.x; e < TS * (COP / 8); e += BLK) {
-            const int si = e / (COP / 8), v = e - si * (COP / 8);
-            const int tx = si % TXs, r = si / TXs, ty = r % TYs, tz = r / TYs;
+        // output gradient of the tile, channel-major: sD[co][site], two x-neighbouring
+        // sites per thread as above (sites outside the lattice contribute zero)
+        unsigned *sDw = reinterpret_cast<unsigned *>(sD);
+        for (int e = threadIdx.x; e < TS / 2; e += BLK) {
+            const int si = 2 * e, tx = si % TXs, r = si / TXs, ty = r % TYs, tz = r / TYs;
             const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
-            u32x4 val = {0u, 0u, 0u, 0u};
-            if (x < g.nx && y < g.ny && z < g.nz) {
-                const size_t gs = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
-                val = *reinterpret_cast<const u32x4 *>(dZ + gs * COP + v * 8);
-            }
+            const bool inyz = y < g.ny && z < g.nz;
+            const bool oka = inyz && x < g.nx, okb = inyz && x + 1 < g.nx;
+            const size_t ga = size_t(x) + size_t(g.nx) * (size_t(y) + size_t(g.ny) * z);
+            unsigned *d = sDw + e;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                sD[(8 * v + 2 * c) * TS + si] = (unsigned short)(val[c] & 0xffffu);
-                sD[(8 * v + 2 * c + 1) * TS + si] = (unsigned short)(val[c] >> 16);
+            for (int v = 0; v < COP / 8; ++v) {
+                const u32x4 zero4 = {0u, 0u, 0u, 0u};
+                const u32x4 a = oka ? *reinterpret_cast<const u32x4 *>(dZ + ga * COP + v * 8) : zero4;
+                const u32x4 b = okb ? *reinterpret_cast<const u32x4 *>(dZ + (ga + 1) * COP + v * 8) : zero4;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    d[(8 * v + 2 * c) * (CSD / 2)] = (a[c] & 0xffffu) | (b[c] << 16);
+                    d[(8 * v + 2 * c + 1) * (CSD / 2)] = (a[c] >> 16) | (b[c] & 0xffff0000u);
+                }
             }
         }
         __syncthreads();
         if (int(threadIdx.x) < COP)
-            for (int si = 0; si < TS; ++si) dbacc += bf2f(sD[threadIdx.x * TS + si]);
+            for (int si = 0; si < TS; ++si) dbacc += bf2f(sD[threadIdx.x * CSD + si]);
 #pragma unroll 1
         for (int c = half; c < TS / 32; c += cstep) {
             const int rowk = 2 * c + (lg >> 1), yy = rowk % TYs, zz = rowk / TYs, xo = 8 * (lg & 1);
-            const u32x4 A = *reinterpret_cast<const u32x4 *>(sD + (16 * mt + li) * TS + c * 32 + 8 * lg);
-            const unsigned short *xrow = sX + ((16 * nt + li) * ROWS) * XR + xo;
+            const u32x4 A = *reinterpret_cast<const u32x4 *>(sD + (16 * mt + li) * CSD + c * 32 + 8 * lg);
+            const unsigned short *xrow = sX + (16 * nt + li) * CSX + xo;
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int dz = q / 3, dy = q % 3;
@@ -200,7 +221,8 @@ __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__
     float *P = part + size_t(blockIdx.x) * PS;
     if (COP == 16) {
         // waves 2 and 3 hand their half-sums to waves 0 and 1 through LDS
-        float *sA = reinterpret_cast<float *>(sX);  // 2 x 27 x 64 x 4 floats == sizeof(sX)
+        float *sA = reinterpret_cast<float *>(sX);  // 2 x 27 x 64 x 4 floats <= sizeof(sX)
+        static_assert(2 * 27 * 64 * 4 * sizeof(float) <= sizeof(sX), "exchange fits the brick buffer");
         __syncthreads();
         if (half == 1)
 #pragma unroll
