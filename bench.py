@@ -56,8 +56,8 @@ STATE_VALUES = 48  # f (19) and Q (5) read and written once
 # WRITE_SIZE passes scaled by a 512 MiB device copy (profiles/*.md); valid
 # while the kernels are unchanged since those counters were taken.
 MEASURED_TRAFFIC = {
-    ("fp32", "k_lb"): (259.7 + 184.5) * 1e6,       # profiles/step_sites_128cubed.md
-    ("fp64", "k_lb"): (524.2 + 369.1) * 1e6,       # profiles/step_fp64_mixed_128cubed.md
+    ("fp32", "k_lb"): (252.0 + 184.5) * 1e6,       # profiles/step_sites_128cubed.md
+    ("fp64", "k_lb"): (527.4 + 369.1) * 1e6,       # profiles/step_sites_128cubed.md
     ("fp64", "k_qupdate"): (160.9 + 83.9) * 1e6,   # profiles/step_fp64_mixed_128cubed.md
 }
 
