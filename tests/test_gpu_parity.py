@@ -111,6 +111,36 @@ def test_fp64_ragged_shapes(H, orc, shape, sched):
         assert abs(gpu.totals()[2] - ref.totals()[2]) <= 1e-12 * abs(ref.totals()[2])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_large_ragged_lattice(H, orc, prec):
+    """A 2.2M-site lattice with no power-of-two side (255 x 129 x 67): the
+    kernels split site indices up to 2.2M by multiply-high division by 255
+    and 129 and address planes by 32-bit byte offsets; every site against
+    the oracle after 3 coupled steps (FP64 bar 1e-12; FP32 form within 1e-5
+    on Q)."""
+    shape = (255, 129, 67)
+    say("case: large ragged lattice", shape, prec)
+    rng = np.random.default_rng(7)
+    nx, ny, nz = shape
+    p = I.PhysParams(K=0.02, q0=0.35, gamma=3.1)
+    Q = I.smooth_field(shape, amp=0.2, seed=6) + rng.uniform(-0.02, 0.02, size=(5, nz, ny, nx))
+    u = rng.uniform(-1e-3, 1e-3, size=(3, nz, ny, nx))
+    rho = 1 + rng.uniform(-1e-3, 1e-3, size=(nz, ny, nx))
+    gpu = make(H, p, Q, u, rho, prec)
+    say("autotuned:", gpu.autotune(3))
+    ref = orc.State(oracle_params(orc, p), Q, u, rho)
+    gpu.step(3)
+    ref.step(3)
+    Qg, ug, rg = gpu.fields()
+    Qr, ur, rr = ref.fields()
+    eQ, eu, er = rel(Qg, Qr), rel(ug, ur), rel(rg, rr)
+    say(f"{prec} 255x129x67: Q {eQ:.2e} u {eu:.2e} rho {er:.2e}")
+    if prec == "fp64":
+        assert eQ <= 1e-12 and eu <= 1e-11 and er <= 1e-12
+    else:
+        assert eQ <= 1e-5
+
+
 @pytest.mark.parametrize("sched", SCHEDS[:2])
 def test_fp64_flow_off(H, orc, sched):
     """Pure relaxation (u == 0, populations untouched)."""
