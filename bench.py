@@ -239,10 +239,12 @@ def run_order(n=128, calls=20, threshold=0.19, relax=6000):
                     "per-plane count kernel, one small device-to-host copy"}
 
 
-def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500):
-    """The surrogate workload on a 96^3 box: 500 training pairs from five
-    O2 runs and two domain-growth runs (kappa 0.7, tau -0.5, noise 1e-3;
-    the last run of each kind held out), training on the GPU, then 20000 steps
+def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500, train_set="mixed"):
+    """The surrogate workload on a 96^3 box: training pairs ("mixed": 500
+    from five O2 runs and two domain-growth runs, kappa 0.7, tau -0.5, noise
+    1e-3, the last run of each kind held out; "growth": 60 from each of five
+    domain-growth runs after 1000 steps, one held out, and 60 from an O2 run
+    for evaluation only), training on the GPU, then 20000 steps
     of the domain-growth box (O2 slab z < 32 inside an x-helix) with the
     surrogate (one network jump for k solver steps, M jumps per checked
     cycle, threshold 1e-3) against the plain FP32 form from the same state."""
@@ -255,9 +257,15 @@ def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500):
 
     N = n ** 3
     net = hlb.Net((n, n, n))
-    o2_pairs, gr_pairs, spacing, burn = 80, 50, 240, 300
-    runs = ([("o2", s, o2_pairs) for s in range(4)] + [("growth", 1, gr_pairs)] +
-            [("o2", 4, o2_pairs)] + [("growth", 2, gr_pairs)])
+    if train_set == "mixed":
+        o2_pairs, gr_pairs, spacing, burn = 80, 50, 240, 300
+        runs = ([("o2", s, o2_pairs) for s in range(4)] + [("growth", 1, gr_pairs)] +
+                [("o2", 4, o2_pairs)] + [("growth", 2, gr_pairs)])
+        n_train = 4 * o2_pairs + gr_pairs
+    else:  # domain-growth runs only, past the early transient
+        gr_pairs, spacing, burn = 60, 240, 1000
+        runs = [("growth", s, gr_pairs) for s in (1, 3, 4, 5)] + [("growth", 2, gr_pairs)] + [("o2", 4, gr_pairs)]
+        n_train = 4 * gr_pairs
     total = sum(r[2] for r in runs)
     pairs = S.allocate_pairs(total, N)
     torch.cuda.synchronize()
@@ -272,10 +280,11 @@ def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500):
         del sv
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    train_idx = list(range(0, 4 * o2_pairs + gr_pairs))
+    train_idx = list(range(0, n_train))
     S.fit_norm(net, pairs, 0.0, index=train_idx)
     net.set_params(I.cnn_params(seed=0))
-    tl = S.train(net, pairs, iters, lr=2e-3, index=train_idx, log_every=max(1, iters // 5))
+    lr = 2e-3 if train_set == "mixed" else 1e-3
+    tl = S.train(net, pairs, iters, lr=lr, index=train_idx, log_every=max(1, iters // 5))
     evals = {}
     for tag in ("o2-4", "growth-2"):
         e = S.evaluate(net, pairs, spans[tag])
@@ -318,6 +327,10 @@ def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500):
     S.extrapolation_only(ex_net, 0.0)
     ext = S.new_solver(case)
     sx = S.run(ext, ex_net, steps, k=k, M=M)
+    qx_net = hlb.Net((n, n, n))
+    S.extrapolation_only(qx_net, 1.0)
+    qxt = S.new_solver(case)
+    sq = S.run(qxt, qx_net, steps, k=k, M=M)
     spread = float(fz_plain.max() - fz_plain.min())
     flop = 2.0 * N * S.MACS_PER_SITE
     out = {
@@ -335,19 +348,24 @@ def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500):
         "residual_max": float(np.max(st.residuals)) if st.residuals else None,
         "m_sweep": sweep,
         "without_refresh": no_refresh,
-        "extrapolation_only": {"seconds": sx.seconds, "q_error_vs_plain": S.q_error(ext, plain),
-                               "fallbacks": sx.fallbacks, "cycles": sx.cycles},
+        "extrapolation_only": {"seconds": sx.seconds, "speedup": t_plain / sx.seconds,
+                               "q_error_vs_plain": S.q_error(ext, plain), "fallbacks": sx.fallbacks,
+                               "cycles": sx.cycles},
+        "quadratic_extrapolation_only": {"seconds": sq.seconds, "speedup": t_plain / sq.seconds,
+                                         "q_error_vs_plain": S.q_error(qxt, plain), "fallbacks": sq.fallbacks,
+                                         "cycles": sq.cycles},
         "increment_error_heldout": evals,
-        "training": {"pairs": total, "train_pairs": len(train_idx), "iters": iters, "seconds": tl.seconds,
+        "training": {"set": train_set, "pairs": total, "train_pairs": len(train_idx), "iters": iters, "lr": lr,
+                     "seconds": tl.seconds,
                      "data_seconds": t_data, "final_loss": tl.losses[-1][1] if tl.losses else None},
         "network_ms": ms_net,
         "conv_roofline": {"bound": "mfma", "achieved": flop / (ms_net * 1e-3) / 1e12, "peak": 2500.0,
                           "unit": "TFLOP/s", "frac": flop / (ms_net * 1e-3) / 1e12 / 2500.0,
                           "flop_per_site": 2 * S.MACS_PER_SITE, "kernel": "k_conv (4 layers)"},
     }
-    for o in (net, ex_net):
+    for o in (net, ex_net, qx_net):
         o.close()
-    del plain, sur, ext
+    del plain, sur, ext, qxt
     torch.cuda.empty_cache()
     return out
 
@@ -470,6 +488,8 @@ def main():
     ap.add_argument("--surrogate-k", type=int, default=32, help="solver steps replaced by one network jump")
     ap.add_argument("--surrogate-m", type=int, default=4, help="jumps per checked surrogate cycle")
     ap.add_argument("--surrogate-iters", type=int, default=1500, help="training iterations of the surrogate")
+    ap.add_argument("--surrogate-train", choices=["mixed", "growth"], default="mixed",
+                    help="training pairs: O2 and domain-growth runs, or domain-growth runs only")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -497,7 +517,8 @@ def main():
         elif a.only == "network":
             out = run_network()
         else:
-            out = run_surrogate(steps=a.surrogate_steps, k=a.surrogate_k, M=a.surrogate_m, iters=a.surrogate_iters)
+            out = run_surrogate(steps=a.surrogate_steps, k=a.surrogate_k, M=a.surrogate_m, iters=a.surrogate_iters,
+                                train_set=a.surrogate_train)
         print(json.dumps({"profiling_run": a.only, **out}), flush=True)
         return
     res = {}
@@ -533,7 +554,8 @@ def main():
     sur = None
     if a.surrogate_steps > 0 and not a.only:
         log(f"bench: surrogate 96^3, {a.surrogate_steps} steps, k {a.surrogate_k}, M {a.surrogate_m}")
-        sur = run_surrogate(steps=a.surrogate_steps, k=a.surrogate_k, M=a.surrogate_m, iters=a.surrogate_iters)
+        sur = run_surrogate(steps=a.surrogate_steps, k=a.surrogate_k, M=a.surrogate_m, iters=a.surrogate_iters,
+                                train_set=a.surrogate_train)
         log(f"bench: surrogate speedup {sur['speedup']:.2f}, Q error {sur['q_error_vs_plain']:.2e}")
     cpu = None
     if not a.no_cpu:
