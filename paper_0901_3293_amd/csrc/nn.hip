@@ -116,6 +116,9 @@ __device__ __forceinline__ int brick_chunk(int site, int v)
 // offsets take a 16-bit funnel shift).  With 32 output channels wave w owns
 // the (co block, ci block) pair (w >> 1, w & 1) for all 27 taps; with 16, ci
 // block w & 1 over half the K-chunks, the two halves summed in LDS at the end.
+// The bias gradient is summed while dZ is staged (each thread keeps the
+// running sums of the channels of the sites it stages; the block adds the
+// threads' sums per channel in thread order at the end).
 // Per-block FP32 partials; the final sum is FP64 in a fixed order
 // (k_wgrad_reduce), so the result is deterministic.
 template <int COP>
@@ -141,7 +144,10 @@ __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__
     f32x4 acc[27];
 #pragma unroll
     for (int j = 0; j < 27; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float dbacc = 0.f;
+    static_assert(TS / 2 <= BLK, "one site pair of dZ per thread and tile");
+    float dsum[COP];
+#pragma unroll
+    for (int co = 0; co < COP; ++co) dsum[co] = 0.f;
     for (int t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
         int x0, y0, z0;
         tile_origin(g, t, x0, y0, z0);
@@ -187,12 +193,12 @@ __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__
                 for (int c = 0; c < 4; ++c) {
                     d[(8 * v + 2 * c) * (CSD / 2)] = (a[c] & 0xffffu) | (b[c] << 16);
                     d[(8 * v + 2 * c + 1) * (CSD / 2)] = (a[c] >> 16) | (b[c] & 0xffff0000u);
+                    dsum[8 * v + 2 * c] += bf2f((unsigned short)(a[c] & 0xffffu)) + bf2f((unsigned short)(b[c] & 0xffffu));
+                    dsum[8 * v + 2 * c + 1] += bf2f((unsigned short)(a[c] >> 16)) + bf2f((unsigned short)(b[c] >> 16));
                 }
             }
         }
         __syncthreads();
-        if (int(threadIdx.x) < COP)
-            for (int si = 0; si < TS; ++si) dbacc += bf2f(sD[threadIdx.x * CSD + si]);
 #pragma unroll 1
         for (int c = half; c < TS / 32; c += cstep) {
             const int rowk = 2 * c + (lg >> 1), yy = rowk % TYs, zz = rowk / TYs, xo = 8 * (lg & 1);
@@ -219,6 +225,21 @@ __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__
         }
     }
     float *P = part + size_t(blockIdx.x) * PS;
+    {
+        // bias: channel co summed over the TS / 2 threads that stage dZ, in order
+        float *sS = reinterpret_cast<float *>(sX);
+        static_assert(size_t(TS / 2) * COP * sizeof(float) <= sizeof(sX), "bias sums fit the brick buffer");
+        __syncthreads();
+        if (int(threadIdx.x) < TS / 2)
+#pragma unroll
+            for (int co = 0; co < COP; ++co) sS[threadIdx.x * COP + co] = dsum[co];
+        __syncthreads();
+        if (int(threadIdx.x) < COP) {
+            float db = 0.f;
+            for (int t = 0; t < TS / 2; ++t) db += sS[t * COP + threadIdx.x];
+            P[27 * CIP * COP + threadIdx.x] = db;
+        }
+    }
     if (COP == 16) {
         // waves 2 and 3 hand their half-sums to waves 0 and 1 through LDS
         float *sA = reinterpret_cast<float *>(sX);  // 2 x 27 x 64 x 4 floats <= sizeof(sX)
@@ -241,7 +262,6 @@ __global__ __launch_bounds__(BLK) void k_wgrad(Grid3 g, const unsigned short *__
     for (int j = 0; j < 27; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) P[(j * CIP + 16 * nt + li) * COP + 16 * mt + 4 * lg + r] = acc[j][r];
-    if (int(threadIdx.x) < COP) P[27 * CIP * COP + threadIdx.x] = dbacc;
 }
 
 // Sum the per-block partials (FP64, block order) into the flat gradient of
