@@ -370,6 +370,50 @@ def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500, train_set="mixed"):
     return out
 
 
+def run_slab(steps=20000, every=100, kappas=(0.5, 0.8, 1.0), prec="fp32"):
+    """The domain-growth slab (64 x 64 x 256, O2 seed for z < 32 inside an
+    x-helix, tau_LdG = 0) for each chirality: `steps` steps with the
+    plane-averaged free energy f(z) and the disclination sites per plane
+    (order analysis, q < 0.19) read every `every` steps; the blue-phase
+    domain is the set of planes that carry disclination sites, its walls the
+    boundaries of that set."""
+    import numpy as np
+
+    from paper_0901_3293_amd import hlb
+    from paper_0901_3293_amd import inputs as I
+    from paper_0901_3293_amd import surrogate as S
+
+    out = {}
+    for kappa in kappas:
+        p, Q, u, rho = I.slab_case(nx=64, ny=64, nz=256, cell=32, seed_depth=32, kappa=kappa)
+        s = hlb.Solver((64, 64, 256), prec)
+        s.set_params(p)
+        s.set_fields(Q, u, rho)
+        s.autotune(10)
+        track = []
+        t0 = time.perf_counter()
+        for t in range(0, steps + 1, every):
+            if t:
+                s.step(every)
+            fz = S.domain_profile(s)
+            per_z = s.order(threshold=0.19, fields=False)["per_z"]
+            mask, walls = S.defect_walls(per_z)
+            f_bp = float(np.median(fz[mask])) if mask.any() else None
+            f_ch = float(np.median(fz[~mask])) if (~mask).any() else None
+            track.append({"step": t, "bp_planes": int(mask.sum()), "walls": walls,
+                          "defect_sites": int(np.sum(per_z)), "f_bp": f_bp, "f_cholesteric": f_ch})
+        el = time.perf_counter() - t0
+        keep = (0, 100, 500, 1000, 2000, 5000, 10000, 15000, 20000)
+        out[str(kappa)] = {"seconds": el, "mlups_with_readouts": 64 * 64 * 256 * steps / el / 1e6,
+                           "track": [r for r in track if r["step"] in keep],
+                           "bp_planes_every_1000": [r["bp_planes"] for r in track if r["step"] % 1000 == 0]}
+        log(f"bench: slab kappa {kappa}: blue-phase planes {track[0]['bp_planes']} -> {track[-1]['bp_planes']}, "
+            f"walls {track[-1]['walls']}")
+        s.close()
+    return {"workload": f"64x64x256 domain-growth slab (O2 seed z < 32 in an x-helix, tau_LdG = 0), {prec}, "
+                        f"{steps} steps, f(z) and disclinations per plane every {every}", "kappa": out}
+
+
 def run_network(n=96, predicts=20, train_steps=10):
     """The surrogate network alone on an n^3 lattice with seeded random
     inputs: `predicts` forward applications, then `train_steps` training
@@ -462,7 +506,7 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "network", "order"], default=None,
+    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "network", "order", "slab"], default=None,
                     help="run one leg only (profiling runs)")
     ap.add_argument("--coupling", choices=["force", "split"], default="force",
                     help="fluid coupling of the --only fp32/fp64 profiling legs")
@@ -508,9 +552,11 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy probe 512 MiB x3 done")
         del src, dst
-    if a.only in ("batched", "surrogate", "network", "order"):
+    if a.only in ("batched", "surrogate", "network", "order", "slab"):
         if a.only == "order":
             out = run_order(a.n)
+        elif a.only == "slab":
+            out = run_slab()
         elif a.only == "batched":
             out = run_batched(a.batch_steps, a.batch_graph_steps, a.batch_chunk, not a.batch_device_fences,
                               a.batch_launch, a.batch_group)

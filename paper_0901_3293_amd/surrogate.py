@@ -282,5 +282,17 @@ def domain_size(fz):
     return int((fz > 0.5 * (fz.max() + fz.min())).sum())
 
 
+def defect_walls(per_z):
+    """Blue-phase planes and domain walls of a periodic box from the
+    disclination sites per z-plane (order analysis): a plane carrying
+    disclination sites belongs to the blue-phase domain (the cholesteric
+    carries none); a wall sits between two neighbouring planes of different
+    kind, at z + 1/2.  Returns (mask of blue-phase planes, wall positions)."""
+    mask = np.asarray(per_z) > 0
+    nz = len(mask)
+    walls = [z + 0.5 for z in range(nz) if mask[z] != mask[(z + 1) % nz]]
+    return mask, walls
+
+
 # Multiply-adds per site of one network application (3x3x3 taps, real channels).
 MACS_PER_SITE = 27 * (N_IN * 32 + 32 * 32 + 32 * 32 + 32 * 5)

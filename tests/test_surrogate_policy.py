@@ -1,6 +1,6 @@
 """Host logic of the surrogate run (`surrogate.run`): step accounting, the
 cool-down after a fallback and the refresh after an accepted cycle with a
-large residual.  The solver, the network and the checked cycle are stand-ins
+large residual; and the domain-wall finder of the growth runs.  The solver, the network and the checked cycle are stand-ins
 that count steps and return scripted residuals; nothing touches a GPU."""
 import pytest
 
@@ -98,3 +98,16 @@ def test_refresh_after_large_accepted_residual(monkeypatch):
 def test_refresh_is_the_default(monkeypatch):
     st, clock = run(monkeypatch, [(False, S.REFRESH * S.THRESHOLD), (False, 0.0)], 8 + 12 * 3)
     assert "".join(clock.log) == "SPS"
+
+
+def test_defect_walls_periodic():
+    """A blue-phase slab on planes 0..31 of 256 (disclination sites there,
+    none elsewhere): walls between planes 31|32 and 255|0, 32 blue-phase
+    planes; a box without disclinations has no walls."""
+    import numpy as np
+
+    per_z = np.zeros(256, dtype=np.int64)
+    per_z[0:32] = np.arange(1, 33)
+    mask, walls = S.defect_walls(per_z)
+    assert mask.sum() == 32 and walls == [31.5, 255.5]
+    assert S.defect_walls(np.zeros(8))[1] == []
