@@ -97,6 +97,45 @@ def test_layer_backward(H, shape, layer):
     assert e_w <= 1e-5 and e_b <= 1e-5 and e_x <= 1e-5
 
 
+@pytest.mark.parametrize("layer", [1, 3])
+def test_weight_gradient_full_size_sampled(H, layer):
+    """Weight and bias gradient of one layer on the 96^3 lattice of the
+    surrogate workload, where each block of the weight-gradient kernel
+    accumulates several tiles: the whole bias gradient against the FP64 sum of
+    the bfloat16 output gradient, and 64 sampled weight-gradient entries
+    against direct FP64 sums over all sites (same bfloat16 operands; FP32
+    accumulation, bar 1e-5 of the largest entry)."""
+    shape = (96, 96, 96)
+    say("case: weight gradient 96^3, layer", layer)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(30 + layer)
+    net = H.Net(shape)
+    net.set_params(inputs.cnn_params(seed=5))
+    x = rng.normal(size=(CI[layer],) + shape[::-1]).astype(np.float32)
+    dz = (rng.normal(size=(CO[layer],) + shape[::-1]) * 1e-3).astype(np.float32)
+    xb = to_bf16_bits(channels_last(x, CIP[layer]))
+    dzb = to_bf16_bits(channels_last(dz, COP[layer]))
+    _, g = net.layer_backward(layer, xb, dzb)
+    xf = cnn.bf16(torch.tensor(x)).double().numpy()    # [ci][z][y][x]
+    dzf = cnn.bf16(torch.tensor(dz)).double().numpy()  # [co][z][y][x]
+    ci_n, co_n = CI[layer], CO[layer]
+    db = dzf.reshape(co_n, -1).sum(1)
+    gb = g[-co_n:]
+    eb = np.abs(gb - db).max() / np.abs(db).max()
+    gw = g[:-co_n].reshape(co_n, ci_n, 27)  # W[co][ci][tap], tap = kz*9 + ky*3 + kx
+    ref, got = [], []
+    for _ in range(64):
+        co, ci, tap = int(rng.integers(co_n)), int(rng.integers(ci_n)), int(rng.integers(27))
+        kz, ky, kx = tap // 9, (tap // 3) % 3, tap % 3
+        shifted = np.roll(xf[ci], shift=(-(kz - 1), -(ky - 1), -(kx - 1)), axis=(0, 1, 2))  # X(s + off)
+        ref.append(float((dzf[co] * shifted).sum()))
+        got.append(float(gw[co, ci, tap]))
+    ref, got = np.array(ref), np.array(got)
+    ew = np.abs(got - ref).max() / np.abs(ref).max()
+    say("rel err db, sampled dW", eb, ew)
+    assert eb <= 1e-5 and ew <= 1e-5
+
+
 def norm_block(x, dq, beta):
     """Standardisation block (47 floats) from one raw input x [18, ...] and
     target dq [5, ...]."""
