@@ -239,7 +239,7 @@ def run_order(n=128, calls=20, threshold=0.19, relax=6000):
                     "per-plane count kernel, one small device-to-host copy"}
 
 
-def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500, train_set="mixed"):
+def run_surrogate(n=96, steps=20000, k=32, M=4, iters=3000, train_set="mixed"):
     """The surrogate workload on a 96^3 box: training pairs ("mixed": 500
     from five O2 runs and two domain-growth runs, kappa 0.7, tau -0.5, noise
     1e-3, the last run of each kind held out; "growth": 60 from each of five
@@ -283,7 +283,7 @@ def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500, train_set="mixed"):
     train_idx = list(range(0, n_train))
     S.fit_norm(net, pairs, 0.0, index=train_idx)
     net.set_params(I.cnn_params(seed=0))
-    lr = 2e-3 if train_set == "mixed" else 1e-3
+    lr = 5e-4 if train_set == "mixed" else 1e-3
     tl = S.train(net, pairs, iters, lr=lr, index=train_idx, log_every=max(1, iters // 5))
     evals = {}
     for tag in ("o2-4", "growth-2"):
@@ -342,6 +342,8 @@ def run_surrogate(n=96, steps=20000, k=32, M=4, iters=1500, train_set="mixed"):
         "q_error_vs_plain": S.q_error(sur, plain),
         "fz_max_dev_over_spread": float(np.abs(fz_sur - fz_plain).max() / spread) if spread > 0 else None,
         "domain_planes": {"plain": S.domain_size(fz_plain), "surrogate": S.domain_size(fz_sur)},
+        "blue_phase_planes": {"plain": int(S.defect_walls(plain.order(fields=False)["per_z"])[0].sum()),
+                              "surrogate": int(S.defect_walls(sur.order(fields=False)["per_z"])[0].sum())},
         "cycles": st.cycles, "fallbacks": st.fallbacks, "plain_cycles": st.plain_cycles,
         "fallback_steps": st.fallback_steps,
         "residual_median": float(np.median(st.residuals)) if st.residuals else None,
@@ -527,11 +529,13 @@ def main():
                     help="cache-group budget in sites of the phase launch form (0: the autotuner's)")
     ap.add_argument("--batch-device-fences", action="store_true",
                     help="batched run with the fixed work mapping and device-scope barrier fences")
+    ap.add_argument("--slab-steps", type=int, default=20000,
+                    help="steps of the 64x64x256 domain-growth slab per chirality (0: skip)")
     ap.add_argument("--surrogate-steps", type=int, default=20000,
                     help="steps of the 96^3 surrogate-vs-plain run (0: skip the surrogate leg)")
     ap.add_argument("--surrogate-k", type=int, default=32, help="solver steps replaced by one network jump")
     ap.add_argument("--surrogate-m", type=int, default=4, help="jumps per checked surrogate cycle")
-    ap.add_argument("--surrogate-iters", type=int, default=1500, help="training iterations of the surrogate")
+    ap.add_argument("--surrogate-iters", type=int, default=3000, help="training iterations of the surrogate")
     ap.add_argument("--surrogate-train", choices=["mixed", "growth"], default="mixed",
                     help="training pairs: O2 and domain-growth runs, or domain-growth runs only")
     ap.add_argument("--copy-probe", action="store_true",
@@ -597,6 +601,14 @@ def main():
         log(f"bench: batched 96 boxes fp32, {a.batch_steps} steps")
         batched = run_batched(a.batch_steps)
         log(f"bench: batched {batched['mlups']:.1f} MLUPS aggregate")
+    growth = None
+    if a.slab_steps > 0 and not a.only:
+        log(f"bench: domain-growth slab 64x64x256, {a.slab_steps} steps, three chiralities")
+        sl = run_slab(steps=a.slab_steps)
+        growth = {"workload": sl["workload"],
+                  "blue_phase_planes_every_1000": {k: v["bp_planes_every_1000"] for k, v in sl["kappa"].items()},
+                  "final": {k: v["track"][-1] for k, v in sl["kappa"].items()},
+                  "mlups_with_readouts": {k: v["mlups_with_readouts"] for k, v in sl["kappa"].items()}}
     sur = None
     if a.surrogate_steps > 0 and not a.only:
         log(f"bench: surrogate 96^3, {a.surrogate_steps} steps, k {a.surrogate_k}, M {a.surrogate_m}")
@@ -639,6 +651,7 @@ def main():
         "d3q15_predictor_corrector_fp32": d3q15,
         "order": order,
         "batched": batched,
+        "domain_growth": growth,
         "surrogate": sur,
         "checks": {"fp32": r32["checks"], "fp64": r64["checks"]},
         "cpu_baseline": cpu,
