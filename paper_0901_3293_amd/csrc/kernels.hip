@@ -487,7 +487,7 @@ __global__ __launch_bounds__(BLK) void k_pc1(Geom G, Coef<T> c, const T *__restr
                                              T *__restrict__ P, T *__restrict__ u, T *__restrict__ bsave)
 {
     const int s = site_index();
-    if (s < G.N) pc1_at<T, SPLIT>(G, c, g, Pi, P, u, bsave, s);
+    if (s < G.N) pc1_at<T, SPLIT, true>(G, c, g, Pi, P, u, bsave, s);
 }
 
 template <typename T, bool SPLIT>

@@ -268,7 +268,7 @@ __device__ __forceinline__ void lb_split_at(const Geom &G, const Coef<T> &c, con
 // whole-stress coupling: no stress term and b = div Pi); writes the
 // predictor populations P = f + C at x (to be streamed), the velocity u^n of
 // f(x, t) and b (3 planes, read back by the second pass at the same site).
-template <typename T, bool SPLIT>
+template <typename T, bool SPLIT, bool STREAM = false>
 __device__ __forceinline__ void pc1_at(const Geom &G, const Coef<T> &c, const T *__restrict__ g,
                                        const T *__restrict__ Pi, T *__restrict__ P, T *__restrict__ u,
                                        T *__restrict__ bsave, int s)
@@ -287,7 +287,7 @@ __device__ __forceinline__ void pc1_at(const Geom &G, const Coef<T> &c, const T 
     }
     lb15_collide(c, f, SPLIT ? sig : static_cast<const T *>(nullptr), b, C, uu, rho);
 #pragma unroll
-    for (int i = 0; i < 15; ++i) *at(plane(P, i, N), O.s) = f[i] + C[i];
+    for (int i = 0; i < 15; ++i) pop_store<STREAM>(plane(P, i, N), O.s, f[i] + C[i]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         *at(plane(u, a, N), O.s) = uu[a];
