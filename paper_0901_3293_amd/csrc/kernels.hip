@@ -24,7 +24,8 @@
 // The split coupling (Sec. 2.2) runs the SITES and MIXED schedules with
 // k_stress / k_lb writing and reading the split terms (101 and 83 values).
 // The population sweeps (k_lb, k_lbf, the second D3Q15 pass k_pc2) load and
-// store the populations nontemporally (pop_load / pop_store in sitekern.h).
+// store the populations nontemporally, and the first D3Q15 pass k_pc1 stores
+// its predicted populations so (pop_load / pop_store in sitekern.h).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
