@@ -100,8 +100,11 @@ __device__ __forceinline__ unsigned pull_off(const Off<T> &O, int cx, int cy, in
 // value is the next step's sweep, after the Q-side kernels have moved their
 // own fields; with STREAM the loads and stores are nontemporal so that the
 // populations do not push Q, u and the stress out of the L2 and the
-// last-level cache between the kernels of a step.  The batched kernels keep
-// a cache group's populations resident on purpose and use plain accesses.
+// last-level cache between the kernels of a step.  (The predicted
+// populations of the first D3Q15 pass are read once, by the second pass right
+// after it, but at 15 values per site they are too many to stay cached beside
+// the rest: they are streamed too.)  The batched kernels keep a cache group's
+// populations resident on purpose and use plain accesses.
 template <bool STREAM, typename T>
 __device__ __forceinline__ T pop_load(const T *P, unsigned b)
 {
