@@ -1,7 +1,10 @@
 // sitekern.h -- one-site-per-thread work of the step, as device functions
 // over a linear site index of one periodic box.  The plain kernels and the
-// batched persistent kernel both call these; neighbour values come straight
-// from global memory through the L1/L2 of the executing CU.
+// batched kernels all call these; neighbour values come straight from global
+// memory through the L1/L2 of the executing CU.  A site index is split into
+// (x, y, z) by multiply-high division (FastDiv in kernels.h), and every field
+// plane is read through its wave-uniform base address plus 32-bit byte
+// offsets (Off below).
 //
 // Buffers of one box (structure-of-arrays, component stride N, x fastest):
 //   g 19 x N, Q 5 x N, Qs (predictor stage) 5 x N, u 3 x N, Pi 9 x N
