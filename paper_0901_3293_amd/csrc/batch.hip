@@ -95,13 +95,19 @@ __device__ __forceinline__ double uni(double v)
     const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(b >> 32)));
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
+// A device-memory pointer made wave-uniform.  It is rebuilt through a
+// global-address-space pointer: rebuilt as a plain (generic) pointer, the
+// compiler could no longer tell that it points to global memory and would
+// address every access through flat instructions with 64-bit per-lane
+// addresses instead of a scalar base and a 32-bit offset.
 template <typename P>
 __device__ __forceinline__ P *uni(P *p)
 {
     const unsigned long long b = reinterpret_cast<unsigned long long>(p);
     const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b & 0xffffffffull)));
     const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(b >> 32)));
-    return reinterpret_cast<P *>(((unsigned long long)hi << 32) | lo);
+    using GP = __attribute__((address_space(1))) P *;
+    return (P *)(GP)(((unsigned long long)hi << 32) | lo);
 }
 
 __device__ __forceinline__ FastDiv uni(const FastDiv &f)
