@@ -80,7 +80,7 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
         if coupling != "split":
             raise ValueError("the D3Q15 leg measures the paper's scheme: split coupling")
     values = {**KERNEL_VALUES, **(SPLIT_VALUES if coupling == "split" else {}), **PC_VALUES}
-    s = hlb.Solver((n, n, n), prec)
+    s = hlb.Solver((n, n, n), prec, lb_model=lb_model, coupling=coupling)
     s.set_params(p)
     s.set_fields(Q, u, rho)
     if schedule == "auto":

@@ -105,16 +105,26 @@ typedef struct {
     int flow_coupling;
 } hlb_be_params;
 
-/* Bytes of device workspace a context of this size and precision needs.
- * Returns 0 if the arguments are invalid (any n < 4, unknown precision, or a
- * lattice too large to index: nx*ny*nz >= 2^30 sites, or one field plane of
- * nx*ny*nz values of 4 GiB or more, i.e. FP64 lattices of 2^29 sites and
- * above). */
+/* Bytes of device workspace a context of this size and precision needs for
+ * the default model: the D3Q19 LB with the fluid off or coupled through the
+ * whole chemical stress -- populations 2 x 19, Q 2 x 5, u 3 and the stress 9
+ * values per site (60), plus reduction partials.  hlb_workspace_bytes_for
+ * gives the size for another LB model and coupling: the split coupling
+ * (HLB_FLOW_SPLIT) needs 3 more values per site (63), the D3Q15 scheme
+ * (HLB_LB_D3Q15_PC) 15 more for its predicted populations (75 with the whole
+ * stress, 78 split) (Sec. 2.2: the hybrid scheme's small per-site state).
+ * Returns 0 if the arguments are invalid (any n < 4, unknown precision, LB
+ * model or coupling, or a lattice too large to index: nx*ny*nz >= 2^30
+ * sites, or one field plane of nx*ny*nz values of 4 GiB or more, i.e. FP64
+ * lattices of 2^29 sites and above). */
 size_t hlb_workspace_bytes(int nx, int ny, int nz, int precision);
+size_t hlb_workspace_bytes_for(int nx, int ny, int nz, int precision, int lb_model, int flow_coupling);
 
 /* Create a context on the current HIP device for an nx*ny*nz periodic lattice
- * (each n >= 4).  device_workspace: caller-owned device memory of at least
- * workspace_bytes bytes, 256-byte aligned.  hip_stream: a hipStream_t (may be
+ * (each n >= 4).  device_workspace: caller-owned device memory of
+ * workspace_bytes bytes, 256-byte aligned, at least hlb_workspace_bytes()
+ * (HLB_ERR_NOMEM otherwise); the LB model and coupling later set with
+ * hlb_set_params must fit in it (hlb_workspace_bytes_for).  hip_stream: a hipStream_t (may be
  * NULL for the null stream).  On success *out receives the context. */
 int hlb_create(int nx, int ny, int nz, int precision, void *device_workspace,
                size_t workspace_bytes, void *hip_stream, hlb_ctx **out);
@@ -132,8 +142,10 @@ int hlb_fe_from_reduced(double kappa, double tau_ldg, double q0, double A0,
  * Gamma <= 0, the explicit diffusion bound 12 Gamma K >= 2 of the
  * forward-Euler predictor, an unknown flow_coupling or LB model;
  * HLB_ERR_STATE for the split coupling or the D3Q15 scheme while the tiled
- * schedule is selected.  Must be called before hlb_set_fields; changing the
- * LB model invalidates the fields (call hlb_set_fields again). */
+ * schedule is selected; HLB_ERR_NOMEM if the context's workspace is smaller
+ * than hlb_workspace_bytes_for this model and coupling.  Must be called
+ * before hlb_set_fields; changing the LB model invalidates the fields (call
+ * hlb_set_fields again). */
 int hlb_set_params(hlb_ctx *ctx, const hlb_lb_params *lb, const hlb_fe_params *fe,
                    const hlb_be_params *be);
 

@@ -58,7 +58,9 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, int *err, unsigned &tar
         atomicAdd(bar, 1u);
         int ok = 1;
         unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        // the counter and the target wrap together after 2^32 arrivals: compare
+        // their difference (the grid never lags by 2^31 arrivals)
+        while (int(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > spin_limit) {
                 atomicMax(err, 1);
                 ok = 0;
@@ -305,7 +307,9 @@ hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items,
                         int *d_err, int *d_misplaced, int *d_xcnt, bool allow_local, int nsteps, int grid,
                         hipStream_t stream)
 {
-    const unsigned spin_limit = 1u << 24;  // ~1 s of polling per barrier
+    // polls per barrier before giving up: each sleeps ~50 ns and waits for one
+    // device-scope load, so a stalled barrier is abandoned after about 1-10 s
+    const unsigned spin_limit = 1u << 24;
     k_batch_reset<<<1, 64, 0, stream>>>(d_bar, d_err, d_misplaced, d_xcnt);
     const int4 *items = reinterpret_cast<const int4 *>(d_items);
     if (fp32)

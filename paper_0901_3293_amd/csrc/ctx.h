@@ -12,6 +12,8 @@ struct hlb_ctx {
     int status;
     char msg[512];
     size_t state_bytes;
+    void *ws;         // the caller's workspace and its size
+    size_t ws_bytes;
     // bumped by every call that changes the state or the parameters from
     // outside the surrogate driver (which keeps a Q history per context)
     unsigned long long version;

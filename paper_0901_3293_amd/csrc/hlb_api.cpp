@@ -22,13 +22,22 @@ static_assert(HLB_OPTICS_MAX_WAVELENGTHS == hlb::OPTICS_MAX_WL, "optics waveleng
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, Q, u, Pi, aux, part, res, total;
+    size_t g, Q, u, part, res, fixed;  // the part every model uses
+    size_t Pi, aux, total;             // the model's planes after it
 };
 
-bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
+// Stress planes of a coupling (the whole stress: 9; the split terms: 12) and
+// the predictor populations of the D3Q15 scheme (15 planes) sit after the
+// fixed part, so one context can switch models within its workspace.
+int stress_planes(int flow_coupling) { return flow_coupling == HLB_FLOW_SPLIT ? 12 : 9; }
+int aux_planes(int lb_model) { return lb_model == HLB_LB_D3Q15_PC ? 15 : 0; }
+
+bool make_layout(int nx, int ny, int nz, int precision, int lb_model, int flow_coupling, Layout &L)
 {
     if (nx < 4 || ny < 4 || nz < 4) return false;
     if (precision != HLB_FP64 && precision != HLB_FP32) return false;
+    if (lb_model != HLB_LB_D3Q19 && lb_model != HLB_LB_D3Q15_PC) return false;
+    if (flow_coupling < HLB_FLOW_OFF || flow_coupling > HLB_FLOW_SPLIT) return false;
     const double n = double(nx) * double(ny) * double(nz);
     if (n >= 2147483647.0 / 2) return false;
     const size_t N = size_t(nx) * ny * nz;
@@ -37,11 +46,12 @@ bool make_layout(int nx, int ny, int nz, int precision, Layout &L)
     L.g = align256(19 * N * e);
     L.Q = align256(5 * N * e);
     L.u = align256(3 * N * e);
-    L.Pi = align256(12 * N * e);
-    L.aux = align256(15 * N * e);
     L.part = align256(hlb::partial_doubles(nx, ny, nz) * 8);
     L.res = 256;
-    L.total = 2 * L.g + 2 * L.Q + L.u + L.Pi + L.aux + L.part + L.res;
+    L.fixed = 2 * L.g + 2 * L.Q + L.u + L.part + L.res;
+    L.Pi = align256(stress_planes(flow_coupling) * N * e);
+    L.aux = align256(aux_planes(lb_model) * N * e);
+    L.total = L.fixed + L.Pi + L.aux;
     return true;
 }
 
@@ -83,8 +93,13 @@ extern "C" {
 
 size_t hlb_workspace_bytes(int nx, int ny, int nz, int precision)
 {
+    return hlb_workspace_bytes_for(nx, ny, nz, precision, HLB_LB_D3Q19, HLB_FLOW_FORCE);
+}
+
+size_t hlb_workspace_bytes_for(int nx, int ny, int nz, int precision, int lb_model, int flow_coupling)
+{
     Layout L;
-    return make_layout(nx, ny, nz, precision, L) ? L.total : 0;
+    return make_layout(nx, ny, nz, precision, lb_model, flow_coupling, L) ? L.total : 0;
 }
 
 int hlb_create(int nx, int ny, int nz, int precision, void *ws, size_t ws_bytes, void *stream,
@@ -93,7 +108,7 @@ int hlb_create(int nx, int ny, int nz, int precision, void *ws, size_t ws_bytes,
     if (!out) return HLB_ERR_ARG;
     *out = nullptr;
     Layout L;
-    if (!make_layout(nx, ny, nz, precision, L)) return HLB_ERR_ARG;
+    if (!make_layout(nx, ny, nz, precision, HLB_LB_D3Q19, HLB_FLOW_FORCE, L)) return HLB_ERR_ARG;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return HLB_ERR_ARG;
     if (ws_bytes < L.total) return HLB_ERR_NOMEM;
     hlb_ctx *c = new (std::nothrow) hlb_ctx;
@@ -107,11 +122,13 @@ int hlb_create(int nx, int ny, int nz, int precision, void *ws, size_t ws_bytes,
     c->D.Q[0] = p; p += L.Q;
     c->D.Q[1] = p; p += L.Q;
     c->D.u = p; p += L.u;
-    c->D.Pi = p; p += L.Pi;
-    c->D.aux = p; p += L.aux;
     c->D.part = reinterpret_cast<double *>(p); p += L.part;
-    c->D.res = reinterpret_cast<double *>(p);
+    c->D.res = reinterpret_cast<double *>(p); p += L.res;
+    c->D.Pi = p; p += L.Pi;
+    c->D.aux = nullptr;  // placed by hlb_set_params for the D3Q15 scheme
     c->D.stream = static_cast<hipStream_t>(stream);
+    c->ws = ws;
+    c->ws_bytes = ws_bytes;
     const size_t e = c->D.fp32 ? 4 : 8;
     c->state_bytes = size_t(24) * c->D.G.N * e;
     *out = c;
@@ -156,6 +173,14 @@ int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe,
     if (!(12.0 * be->Gamma * fe->K < 2.0))
         return set_error(c, HLB_ERR_PARAM, "12 Gamma K = %g violates the explicit diffusion bound 2",
                          12.0 * be->Gamma * fe->K);
+    Layout L;
+    const hlb::Geom &G = c->D.G;
+    make_layout(G.nx, G.ny, G.nz, c->D.fp32 ? HLB_FP32 : HLB_FP64, lb->model, be->flow_coupling, L);
+    if (c->ws_bytes < L.total)
+        return set_error(c, HLB_ERR_NOMEM,
+                         "workspace of %zu bytes is smaller than the %zu this LB model and coupling need "
+                         "(hlb_workspace_bytes_for)", c->ws_bytes, L.total);
+    c->D.aux = L.aux ? static_cast<char *>(c->ws) + L.fixed + L.Pi : nullptr;
     if (c->have_params && c->p.model != lb->model) c->have_fields = false;  // state layout differs
     c->p = {lb->tau, lb->rho0, fe->A0, fe->gamma, fe->K, fe->q0, be->Gamma, be->xi, be->flow_coupling, lb->model};
     c->have_params = true;

@@ -68,7 +68,7 @@ struct Device {
     void *Q[2];    // 5 x N each; Q[qcur] holds the state
     void *u;       // 3 x N
     void *Pi;      // 12 x N: stress (9; F in its first 3 for the tiled schedule) or split terms (12)
-    void *aux;     // 15 x N: predictor populations of the D3Q15 scheme
+    void *aux;     // 15 x N: predictor populations of the D3Q15 scheme (null otherwise)
     double *part;  // partial_doubles(nx, ny, nz)
     double *res;   // 16 doubles of reduced totals
     int gcur, qcur;

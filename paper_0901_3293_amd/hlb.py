@@ -61,6 +61,7 @@ class BeParams(ctypes.Structure):
 
 
 FLOW_CODES = {"force": 1, "split": 2}
+COUPLINGS = {"off": 0, **FLOW_CODES}
 
 
 def flow_code(p):
@@ -88,6 +89,8 @@ def lib():
         vp, dp, I, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_size_t
         L.hlb_workspace_bytes.argtypes = [I, I, I, I]
         L.hlb_workspace_bytes.restype = sz
+        L.hlb_workspace_bytes_for.argtypes = [I, I, I, I, I, I]
+        L.hlb_workspace_bytes_for.restype = sz
         L.hlb_create.argtypes = [I, I, I, I, vp, sz, vp, ctypes.POINTER(vp)]
         L.hlb_fe_from_reduced.argtypes = [ctypes.c_double] * 4 + [ctypes.POINTER(FeParams)]
         L.hlb_set_params.argtypes = [vp, ctypes.POINTER(LbParams), ctypes.POINTER(FeParams),
@@ -155,8 +158,11 @@ def fe_from_reduced(kappa, tau_ldg, q0, A0=0.01):
     return out
 
 
-def workspace_bytes(nx, ny, nz, precision=HLB_FP64):
-    return lib().hlb_workspace_bytes(nx, ny, nz, precision)
+def workspace_bytes(nx, ny, nz, precision=HLB_FP64, lb_model=None, coupling=None):
+    if lb_model is None and coupling is None:
+        return lib().hlb_workspace_bytes(nx, ny, nz, precision)
+    return lib().hlb_workspace_bytes_for(nx, ny, nz, precision, LB_MODELS[lb_model or "d3q19"],
+                                         COUPLINGS[coupling or "force"])
 
 
 class Solver:
@@ -165,11 +171,15 @@ class Solver:
     ``shape`` is (nx, ny, nz); host arrays are float64 ``[c][z][y][x]``.
     """
 
-    def __init__(self, shape, precision="fp64", device="cuda", stream=None):
+    def __init__(self, shape, precision="fp64", device="cuda", stream=None, lb_model="d3q19",
+                 coupling="force"):
+        """lb_model ("d3q19" or "d3q15") and coupling ("off", "force" or
+        "split") size the workspace; parameters of another model or coupling
+        that need more raise HLB_ERR_NOMEM in set_params."""
         self.shape = tuple(int(n) for n in shape)
         self.prec = {"fp64": HLB_FP64, "fp32": HLB_FP32}[precision]
         L = lib()
-        nbytes = L.hlb_workspace_bytes(*self.shape, self.prec)
+        nbytes = L.hlb_workspace_bytes_for(*self.shape, self.prec, LB_MODELS[lb_model], COUPLINGS[coupling])
         if nbytes == 0:
             raise HlbError(-1, f"invalid lattice {self.shape}")
         self.device = torch.device(device)

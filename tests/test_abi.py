@@ -43,13 +43,20 @@ def test_exports_every_declared_symbol(H):
 def test_workspace_bytes(H):
     assert H.workspace_bytes(3, 8, 8) == 0
     assert H.workspace_bytes(8, 8, 8, 7) == 0
-    a = H.workspace_bytes(32, 32, 32, H.HLB_FP64)
-    b = H.workspace_bytes(32, 32, 32, H.HLB_FP32)
     N = 32 ** 3
-    # 19+19 populations, 5+5 Q, u 3, stress or split terms 12, D3Q15 predictor
-    # populations 15: 78 values per site plus partials
-    assert 78 * 8 * N <= a < 78 * 8 * N + 2 ** 20
-    assert 78 * 4 * N <= b < 78 * 4 * N + 2 ** 20
+    # per site: populations 19+19, Q 5+5, u 3, then the model's own planes --
+    # the whole stress 9 (default, 60 values), the split terms 12 (63), and
+    # for the D3Q15 scheme its 15 predicted populations (75 / 78); plus the
+    # reduction partials
+    for prec, e in ((H.HLB_FP64, 8), (H.HLB_FP32, 4)):
+        want = {(None, None): 60, ("d3q19", "off"): 60, ("d3q19", "force"): 60, ("d3q19", "split"): 63,
+                ("d3q15", "force"): 75, ("d3q15", "split"): 78}
+        for (model, coupling), v in want.items():
+            got = H.workspace_bytes(32, 32, 32, prec, model, coupling)
+            assert v * e * N <= got < v * e * N + 2 ** 20, (model, coupling, got / (e * N))
+    L = H.lib()
+    assert L.hlb_workspace_bytes_for(32, 32, 32, H.HLB_FP32, 2, 1) == 0
+    assert L.hlb_workspace_bytes_for(32, 32, 32, H.HLB_FP32, 0, 3) == 0
 
 
 def test_workspace_size_limits(H):
@@ -142,3 +149,24 @@ def test_call_order_errors(H):
     assert L.hlb_get_totals(c.ctx, None, None, None) == -5
     assert L.hlb_state_bytes(c.ctx) == 24 * 8 ** 3 * 8
     c.close()
+
+
+def test_set_params_checks_workspace_for_model(H):
+    """A context sized for the default model rejects parameters of a model or
+    coupling that needs more planes (HLB_ERR_NOMEM, sticky); one sized with
+    hlb_workspace_bytes_for accepts them."""
+    L = H.lib()
+    p = I.PhysParams(K=0.01, q0=0.3)
+    fe = H.FeParams(p.A0, p.gamma, p.K, p.q0)
+    for model, coupling, tau in ((0, 2, 2.5), (1, 1, 5.0), (1, 2, 5.0)):
+        for sized in (False, True):
+            n = L.hlb_workspace_bytes_for(8, 8, 8, 0, model, coupling) if sized else L.hlb_workspace_bytes(8, 8, 8, 0)
+            ctx = ctypes.c_void_p()
+            assert L.hlb_create(8, 8, 8, 0, ctypes.c_void_p(1 << 40), n, None, ctypes.byref(ctx)) == 0
+            lb = H.LbParams(tau, p.rho0, model)
+            be = H.BeParams(p.Gamma, p.xi, coupling)
+            rc = L.hlb_set_params(ctx, ctypes.byref(lb), ctypes.byref(fe), ctypes.byref(be))
+            assert rc == (0 if sized else -6), (model, coupling, sized, rc)
+            if not sized:
+                assert "hlb_workspace_bytes_for" in L.hlb_last_error(ctx).decode()
+            L.hlb_destroy(ctx)

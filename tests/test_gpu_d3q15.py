@@ -36,7 +36,8 @@ def spread():
 
 
 def make(H, p, Q, u, rho, prec="fp64", sched=("sites", 0)):
-    s = H.Solver((Q.shape[3], Q.shape[2], Q.shape[1]), prec)
+    s = H.Solver((Q.shape[3], Q.shape[2], Q.shape[1]), prec, lb_model=getattr(p, "lb_model", "d3q19"),
+                 coupling=getattr(p, "coupling", "force"))
     s.set_schedule(*sched)
     s.set_params(p)
     s.set_fields(Q, u, rho)
@@ -125,7 +126,7 @@ def test_d3q15_flow_off_and_rejections(H, orc):
     s.set_schedule("tiled", 8)
     with pytest.raises(H.HlbError):
         s.set_params(p)
-    s2 = H.Solver((8, 8, 8), "fp64")
+    s2 = H.Solver((8, 8, 8), "fp64", lb_model=getattr(p, "lb_model", "d3q19"), coupling=p.coupling)
     s2.set_params(p)
     with pytest.raises(H.HlbError):
         s2.set_schedule("tiled", 8)
