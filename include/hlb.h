@@ -411,6 +411,19 @@ int hlbnn_jump(hlbnn *nn, hlb_ctx *solver);
  * 1e-8) with learning rate lr.  *loss (may be NULL; reading it
  * synchronises) receives the loss before the update. */
 int hlbnn_train_step(hlbnn *nn, const float *x_dev, const float *dq_dev, float lr, double *loss);
+/* The gradient of one training step (as hlbnn_train_step: same kernels in
+ * the same order, but no Adam update and no change to the parameters), with
+ * what the kernels passed between layers copied to host arrays, so each
+ * layer can be checked on exactly the operands it received:
+ * acts_host [4][N][32] bfloat16 bits, the input of each layer (layer 0: the
+ * standardised inputs, channels 18..31 zero); y_host [N][5] FP32, the
+ * standardised output of the last layer; dz_host [4][N][32] bfloat16 bits,
+ * the loss gradient with respect to each layer's pre-activation output
+ * (layer l uses the first N x cout_padded(l) values of its slot: 32, and 16
+ * for the last layer); grad_host the flat gradient (hlbnn_param_count()
+ * floats).  Synchronises the network's stream. */
+int hlbnn_grad_trace(hlbnn *nn, const float *x_dev, const float *dq_dev, unsigned short *acts_host, float *y_host,
+                     unsigned short *dz_host, float *grad_host);
 /* Single-layer entry points (host arrays) used to check the kernels layer by
  * layer: x_bf16 [N][32] bfloat16 bits (channels beyond the layer's inputs
  * zero); z [N][c_out] FP32 = conv + bias; dz_bf16 [N][cout_padded] (32, or 16

@@ -142,12 +142,17 @@ int forward(hlbnn *n, hipStream_t st)
     return HLB_OK;
 }
 
-// Backward from dZ of the last layer (in dZ[0], 16 channels); gradients into n->grads.
-int backward(hlbnn *n)
+// Backward from dZ of the last layer (in dZ[0], 16 channels); gradients into
+// n->grads.  With dz_host, each layer's output gradient dZ_l is copied to
+// dz_host + l N 32 (N x COP[l] values) before it is used.
+int backward(hlbnn *n, unsigned short *dz_host = nullptr)
 {
     using namespace hlb::nn;
     int cur = 0;
     for (int l = NL - 1; l >= 0; --l) {
+        if (dz_host)
+            N_TRY(n, hipMemcpyAsync(dz_host + size_t(l) * n->g.N * 32, n->dZ[cur], size_t(n->g.N) * COP[l] * 2,
+                                    hipMemcpyDeviceToHost, n->stream));
         N_TRY(n, wgrad(n->g, CIP[l], COP[l], n->A[l], n->dZ[cur], n->part, CI[l], CO[l], n->grads + layer_offset(l),
                        n->stream));
         if (l > 0) {
@@ -413,6 +418,28 @@ int hlbnn_train_step(hlbnn *n, const float *x_dev, const float *dq_dev, float lr
         *loss = s / (5.0 * n->g.N);
         if (!std::isfinite(*loss)) return nerr(n, HLB_ERR_NONFINITE, "non-finite training loss");
     }
+    return HLB_OK;
+}
+
+int hlbnn_grad_trace(hlbnn *n, const float *x_dev, const float *dq_dev, unsigned short *acts_host, float *y_host,
+                     unsigned short *dz_host, float *grad_host)
+{
+    N_GUARD(n);
+    if (!n->have_params || !n->have_norm) return nerr(n, HLB_ERR_STATE, "parameters and normalisation first");
+    if (!x_dev || !dq_dev || !acts_host || !y_host || !dz_host || !grad_host)
+        return nerr(n, HLB_ERR_ARG, "hlbnn_grad_trace arguments");
+    const size_t N = n->g.N;
+    N_TRY(n, hlb::nn::pack(n->g.N, x_dev, n->norm, n->A[0], n->stream));
+    int rc = forward(n, n->stream);
+    if (rc) return rc;
+    N_TRY(n, hlb::nn::lossgrad(n->g.N, n->Y, dq_dev, x_dev, n->norm, n->dZ[0], n->red, n->red + 4096, n->stream));
+    for (int l = 0; l < NL; ++l)
+        N_TRY(n, hipMemcpyAsync(acts_host + size_t(l) * N * 32, n->A[l], N * 32 * 2, hipMemcpyDeviceToHost,
+                                n->stream));
+    N_TRY(n, hipMemcpyAsync(y_host, n->Y, N * 5 * 4, hipMemcpyDeviceToHost, n->stream));
+    if ((rc = backward(n, dz_host))) return rc;
+    N_TRY(n, hipMemcpyAsync(grad_host, n->grads, size_t(param_total()) * 4, hipMemcpyDeviceToHost, n->stream));
+    N_TRY(n, hipStreamSynchronize(n->stream));
     return HLB_OK;
 }
 

@@ -477,6 +477,7 @@ def _nn_lib():
         L.hlbnn_train_step.argtypes = [vp, vp, vp, ctypes.c_float, dp]
         L.hlbnn_layer_forward.argtypes = [vp, I, up, fp]
         L.hlbnn_layer_backward.argtypes = [vp, I, up, up, fp, fp]
+        L.hlbnn_grad_trace.argtypes = [vp, vp, vp, up, fp, up, fp]
         L.hlbnn_last_error.argtypes = [vp]
         L.hlbnn_last_error.restype = ctypes.c_char_p
         L.hlbnn_destroy.argtypes = [vp]
@@ -610,6 +611,20 @@ class Net:
         self._check(_nn_lib().hlbnn_train_step(self.h, self._ptr(x), self._ptr(dq), float(lr),
                                                 _dp(loss) if want_loss else None))
         return float(loss[0]) if want_loss else None
+
+    def grad_trace(self, x, dq):
+        """Gradient of one training step without the update, with the layer
+        inputs, the last output and each layer's output gradient: returns
+        (acts [4][N][32] uint16 bf16 bits, y [N][5], dz list of [N][cout_padded]
+        uint16, grad)."""
+        acts = np.empty((4, self.N, 32), dtype=np.uint16)
+        y = np.empty((self.N, 5), dtype=np.float32)
+        dz = np.zeros((4, self.N, 32), dtype=np.uint16)
+        g = np.empty(_nn_lib().hlbnn_param_count(), dtype=np.float32)
+        self._check(_nn_lib().hlbnn_grad_trace(self.h, self._ptr(x), self._ptr(dq), _up(acts), _fp(y), _up(dz),
+                                               _fp(g)))
+        dzl = [dz[l].reshape(-1)[:self.N * (16 if l == 3 else 32)].reshape(self.N, -1) for l in range(4)]
+        return acts, y, dzl, g
 
     def layer_forward(self, layer, x_bf16):
         co = (32, 32, 32, 5)[layer]

@@ -3,9 +3,14 @@
 Per layer, on the same bfloat16 operands: forward pre-activation, weight and
 bias gradients and the backward-data convolution within 1e-5 relative of the
 FP64 oracle (FP32 accumulation of at most 864 exact bf16 products).  Whole
-network: the bfloat16 rounding of intermediate activations can flip at ties
-between the two sides, so the end-to-end output and gradient are held to
-looser bars derived from that rounding (stated per test)."""
+network, teacher-forced: each layer of a full training step is checked on
+the very operands the GPU passed it (hlbnn_grad_trace), so the output and
+the gradient of every layer are held to the same 1e-5, and each bfloat16
+activation or gradient the GPU hands on is within half an ulp of the
+oracle's exact value.  Free-running (the oracle's own activations), the two
+sides may round a few activations to different neighbours at ties; the
+whole-network output and gradient are held to 1e-3 there, with the number of
+such flips reported."""
 import numpy as np
 import pytest
 import torch
@@ -158,10 +163,13 @@ def random_inputs(rng, shape):
 
 def test_network_forward_and_training_step(H):
     """Whole network and one Adam step on a 24x12x16 lattice, extrapolation
-    weight beta = 1.  Bars: predicted increment within 2e-2 (max) and 1e-3
-    (mean) relative to the network's share of it; gradient within 5e-2 (max
-    norm) relative; loss within 1e-4; Adam update exactly the textbook step
-    on the GPU's own gradient (1e-6)."""
+    weight beta = 1, free-running (the oracle rounds its own activations).
+    Bars: predicted increment within 5e-3 (max) of the network's share of it
+    (the two sides round a few activations to different bfloat16 neighbours
+    at ties, which moves the output by up to about 2e-3 of its scale; the
+    teacher-forced test below holds every layer to 1e-5 instead); gradient
+    within 1e-3 relative; loss within 1e-4; Adam update exactly the textbook
+    step on the GPU's own gradient (1e-6)."""
     say("case: nn network forward + train step")
     shape = (24, 12, 16)
     rng = np.random.default_rng(3)
@@ -180,7 +188,7 @@ def test_network_forward_and_training_step(H):
     share = ref - x32[8:13].astype(np.float64) - x32[13:18].astype(np.float64)
     d = np.abs(out - ref)
     say("forward rel max, mean:", d.max() / np.abs(share).max(), d.mean() / np.abs(share).mean())
-    assert d.max() / np.abs(share).max() <= 2e-2 and d.mean() / np.abs(share).mean() <= 1e-3
+    assert d.max() / np.abs(share).max() <= 5e-3
     loss = net.train_step(xd, dqd, lr=1e-3)
     acts, z = cnn.forward(p0, cnn.standardise(x32, norm))
     c = dq.astype(np.float32) - x32[8:13] - np.float32(1.0) * x32[13:18]
@@ -192,7 +200,7 @@ def test_network_forward_and_training_step(H):
     gref = cnn.backward(p0, acts, z, t).numpy()
     eg = rel(g, gref)
     say("grad rel err", eg)
-    assert eg <= 5e-2
+    assert eg <= 1e-3
     p1 = net.params()
     p_ref, _, _ = cnn.adam(p0, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
     assert np.abs(p1 - p_ref).max() <= 1e-6 * max(1.0, np.abs(p_ref).max())
@@ -215,3 +223,93 @@ def test_training_is_deterministic(H):
             net.train_step(x, dq, 1e-3, want_loss=False)
         res.append(net.params())
     assert np.array_equal(res[0], res[1])
+
+
+def bits_to_f64(bits):
+    return torch.from_numpy(np.ascontiguousarray(bits).view(np.int16)).view(torch.bfloat16).to(torch.float64).numpy()
+
+
+def handed_on(got, exact, zscale, name):
+    """A bfloat16 value the GPU hands to the next layer against the oracle's
+    exact FP64 value of the same quantity: within half an ulp of bfloat16
+    (at most 2^-8 of the value: 8 significant bits) plus the FP32
+    accumulation bar (2e-5 of the layer's scale).  Returns the number of entries that round to a different
+    bfloat16 neighbour than the exact value does (ties split by rounding
+    error)."""
+    bound = 2.0 ** -8 * np.abs(exact) + 2e-5 * zscale
+    bad = np.abs(got - exact) > bound
+    assert not bad.any(), (name, int(bad.sum()), float(np.abs(got - exact).max()))
+    return int((got != cnn.bf16(torch.tensor(exact)).numpy()).sum())
+
+
+def test_network_teacher_forced(H):
+    """One training step on a 24x12x16 lattice (beta = 1), every layer
+    checked on the operands the GPU itself passed it: each layer's
+    pre-activation from the GPU's bfloat16 input against the oracle's FP64
+    convolution of that input (last layer: the FP32 output within 1e-5;
+    hidden layers: the bfloat16 activation handed on within half an ulp);
+    the loss gradient; each layer's weight and bias gradient from the GPU's
+    input and output gradient within 1e-5 relative (so a 1% scale error in
+    the weight-gradient kernel fails); each backward-data output handed on
+    within half an ulp.  Then the whole network free-running against the
+    oracle's own forward and backward within 1e-3, with the tie flips per
+    layer reported."""
+    say("case: nn teacher-forced network")
+    shape = (24, 12, 16)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(8)
+    net = H.Net(shape)
+    p0 = (inputs.cnn_params(seed=9) + rng.normal(0, 0.01, size=cnn.param_count())).astype(np.float32)
+    net.set_params(p0)
+    x = random_inputs(rng, shape)
+    dq = x[8:13] + x[13:18] + rng.normal(size=(5,) + shape[::-1]) * 1e-6
+    norm = norm_block(x, dq, 1.0)
+    net.set_norm(norm)
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    dqd = torch.tensor(dq, dtype=torch.float32, device="cuda")
+    acts_b, y, dz_b, g = net.grad_trace(xd, dqd)
+    assert np.array_equal(net.params(), p0)  # no update
+    layers = cnn.unflatten(p0)
+    A = [from_channels_last(bits_to_f64(acts_b[l]), CI[l], shape) for l in range(4)]
+    # layer 0 input: the standardised inputs (FP32) rounded to bfloat16
+    x32 = x.astype(np.float32)
+    xs = cnn.standardise(x32, norm).astype(np.float64)
+    flips = {"in": handed_on(A[0], xs, np.abs(xs).max(), "inputs")}
+    assert not bits_to_f64(acts_b[0])[:, 18:].any()
+    for l in range(4):
+        W, b = layers[l]
+        z = cnn.conv(A[l], cnn.bf16(W), b).numpy()
+        if l < 3:
+            flips[f"a{l + 1}"] = handed_on(A[l + 1], np.maximum(z, 0.0), np.abs(z).max(), f"act {l + 1}")
+        else:
+            ey = rel(from_channels_last(y, 5, shape), z)
+            say("last layer output rel err (teacher-forced):", ey)
+            assert ey <= 1e-5
+    # loss gradient: 2 (y - t) / (5 N) with the standardised target in FP32
+    c = dq.astype(np.float32) - x32[8:13] - np.float32(1.0) * x32[13:18]
+    t = (c - norm[cnn.OUT_MEAN:cnn.OUT_MEAN + 5, None, None, None]) / norm[cnn.OUT_STD:cnn.OUT_STD + 5, None, None, None]
+    yg = from_channels_last(y, 5, shape).astype(np.float64)
+    dz3 = 2.0 * (yg - t.astype(np.float64)) / yg.size
+    DZ = [from_channels_last(bits_to_f64(dz_b[l]), CO[l], shape) for l in range(4)]
+    flips["dz3"] = handed_on(DZ[3], dz3, np.abs(dz3).max(), "loss gradient")
+    assert not bits_to_f64(dz_b[3])[:, 5:].any()
+    starts = np.cumsum([0] + [co * ci * 27 + co for co, ci, *_ in cnn.layer_shapes()])
+    for l in range(3, -1, -1):
+        W, _ = layers[l]
+        dW, db, dx = cnn.layer_backward(A[l], DZ[l], cnn.bf16(W))
+        gl = g[starts[l]:starts[l + 1]]
+        ew = rel(gl[:-CO[l]], dW.reshape(-1).numpy())
+        eb = rel(gl[-CO[l]:], db.numpy())
+        say(f"layer {l} teacher-forced grad rel err: dW {ew:.2e} db {eb:.2e}")
+        assert ew <= 1e-5 and eb <= 1e-5
+        if l > 0:
+            dzp = dx.numpy() * (A[l] > 0)
+            flips[f"dz{l - 1}"] = handed_on(DZ[l - 1], dzp, np.abs(dzp).max(), f"dz {l - 1}")
+    say("entries rounded to the other bfloat16 neighbour (of", A[0].size, "per 18-32 channels):", flips)
+    # free-running: the oracle's own activations and gradient
+    acts_o, z_o = cnn.forward(p0, xs)
+    ef = rel(yg, z_o.numpy())
+    gref = cnn.backward(p0, acts_o, z_o, t).numpy()
+    eg = rel(g, gref)
+    say(f"free-running: output rel err {ef:.2e}, gradient rel err {eg:.2e}")
+    assert ef <= 1e-3 and eg <= 1e-3
