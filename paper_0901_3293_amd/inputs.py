@@ -215,6 +215,17 @@ def replica_set(n_replicas=96, sizes=(24, 32, 48, 64), seed=4, noise_amp=1e-4):
     return out
 
 
+def batch_parity_set():
+    """A small uneven set for checking batched runs box by box: seven cubes
+    of side 8 to 20 from replica_set (seed 9), the third with the flow off,
+    and a non-cubic 10 x 6 x 14 box with a z-helix plus noise 1e-3."""
+    rs = replica_set(n_replicas=7, sizes=(8, 12, 16, 20), seed=9)
+    rs[2]["params"].flow = False
+    Qn = helix_q5((10, 6, 14), 2 * math.pi / 14, 0.4, "z") + noise((10, 6, 14), 1e-3, 5)
+    rs.append(dict(L=None, params=reduced(0.8, -0.2, 2 * math.pi / 14), Q=Qn, u=None, rho=None))
+    return rs
+
+
 def smooth_field(shape, amp=0.1, seed=7, modes=2):
     """Smooth periodic symmetric-traceless field: a few random low Fourier modes
     per stored component (for continuum-limit checks)."""

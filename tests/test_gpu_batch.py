@@ -1,14 +1,18 @@
-"""Batched form: uneven periodic boxes with their own (kappa, tau) in one
-persistent launch (and its graph replay) give, box by box, exactly the result
-of a single context on that box (same per-site device code), and the full
-96-box replica set runs with conservation intact."""
+"""Batched form: uneven periodic boxes with their own (kappa, tau) (Sec. 2.1,
+the reduced chirality and temperature) in one persistent launch (and its
+graph replay) match the FP64 oracle box by box, give exactly the result of a
+single context on that box (same per-site device code), and the full 96-box
+replica set runs with conservation intact and matches the oracle on sampled
+boxes in FP32."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
 from paper_0901_3293_amd import inputs as I
-from tests.hlbtest import rel, say
+from tests.hlbtest import oracle_params, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -24,12 +28,7 @@ def H():
 
 
 def small_set():
-    rs = I.replica_set(n_replicas=7, sizes=(8, 12, 16, 20), seed=9)
-    # one box with flow switched off and one non-cubic box
-    rs[2]["params"].flow = False
-    Qn = I.helix_q5((10, 6, 14), 2 * math.pi / 14, 0.4, "z") + I.noise((10, 6, 14), 1e-3, 5)
-    rs.append(dict(L=None, params=I.reduced(0.8, -0.2, 2 * math.pi / 14), Q=Qn, u=None, rho=None))
-    return rs
+    return I.batch_parity_set()
 
 
 def single(H, prec, r, nsteps):
@@ -134,3 +133,68 @@ def test_replica_set_96_full_size(H):
     for i in (0, 17, 95):
         for x, y in zip(b.fields(i), single(H, "fp32", rs[i], 50)):
             assert np.array_equal(x, y), i
+
+
+@pytest.mark.parametrize("form,local,group", [("persistent", True, 0), ("phases", False, 2000)])
+def test_batch_fp64_matches_oracle(H, orc, form, local, group):
+    """Every box of the uneven set -- cubes of 8 to 20 with their own (kappa,
+    tau), the flow-off box and the 10 x 6 x 14 box -- against the FP64 oracle
+    after 13 steps (7 + 6 in two calls): Q, rho and the total free energy
+    within 1e-12 relative, mass to 1e-14; u within 8 times the spread of two
+    valid FP64 roundings of the oracle itself on that box after 13 steps
+    (tests/golden/fp64_spread_batch.json; the velocity is a small difference
+    of much larger stresses), and exactly zero with the flow off."""
+    say("case: batch fp64 vs oracle", form, "xcd-local allowed", local, "group", group)
+    rs = small_set()
+    b = make_batch(H, "fp64", rs)
+    b.set_chunk(8 ** 3, 256)
+    b.set_launch(form, group)
+    b.set_xcd_local(local)
+    b.step(7)
+    b.step(6)
+    worst = {"Q": 0.0, "u": 0.0, "rho": 0.0, "F": 0.0}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fp64_spread_batch.json")) as fh:
+        spread_u = json.load(fh)["spread_u"]
+    assert len(spread_u) == len(rs)
+    for i, r in enumerate(rs):
+        ref = orc.State(oracle_params(orc, r["params"]), r["Q"], r["u"], r["rho"])
+        ref.step(13)
+        Qg, ug, rg = b.fields(i)
+        Qr, ur, rr = ref.fields()
+        mg, _, Fg = b.totals(i)
+        mr, _, Fr = ref.totals()
+        eQ, er, eF = rel(Qg, Qr), rel(rg, rr), abs(Fg - Fr) / abs(Fr)
+        eu = rel(ug, ur) if r["params"].flow else float(np.abs(ug).max())
+        say(f"box {i} {Qg.shape[1:]} flow {r['params'].flow}: Q {eQ:.1e} u {eu:.1e} rho {er:.1e} F {eF:.1e}")
+        assert eQ <= 1e-12 and er <= 1e-12 and eF <= 1e-12, i
+        assert eu <= (max(1e-12, 8 * spread_u[i]) if r["params"].flow else 0.0), (i, eu, spread_u[i])
+        assert abs(mg - mr) / mr <= 1e-14, i
+        worst = {k: max(worst[k], v) for k, v in zip(worst, (eQ, eu, er, eF))}
+    say("worst:", worst)
+
+
+@pytest.mark.parametrize("form", ["phases", "persistent"])
+def test_replica_set_96_fp32_matches_oracle(H, orc, form):
+    """The full 96-box FP32 scan for 1000 steps in 20 graph replays of 50
+    steps; two boxes of it (a 24^3 and a 32^3 box with their own kappa and
+    tau) against the FP64 oracle: Q within 1e-5 relative, the FP32 bar of
+    the single-box form."""
+    say("case: 96 replicas fp32, 1000 steps vs oracle on two boxes", form)
+    rs = I.replica_set()
+    picks = [next(i for i, r in enumerate(rs) if r["L"] == L) for L in (24, 32)]
+    b = make_batch(H, "fp32", rs)
+    b.set_launch(form, 1 << 21 if form == "phases" else 0)
+    b.capture(50)
+    for _ in range(20):
+        b.launch()
+    b.sync()
+    for i in picks:
+        r = rs[i]
+        ref = orc.State(oracle_params(orc, r["params"]), r["Q"], r["u"], r["rho"])
+        ref.step(1000)
+        Qg, ug, rg = b.fields(i)
+        Qr, ur, rr = ref.fields()
+        eQ = rel(Qg, Qr)
+        say(f"box {i} L {r['L']} kappa {r['kappa']:.3f} tau {r['tau_ldg']:.3f}: Q {eQ:.2e} "
+            f"u {rel(ug, ur):.2e} rho-1 {rel(rg - 1, rr - 1):.2e}")
+        assert eQ <= 1e-5, i
