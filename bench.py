@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# Algorithmic values moved per site per launch (each array read or written
-# once): reads + writes.
+# Values moved per site per launch by each kernel as scheduled (each array
+# read or written once): reads + writes.  The per-site schedule's stress sweep
+# writes Pi and its LB kernel reads Pi (9) instead of F (3).
 KERNEL_VALUES = {
     # per-site schedule (95 values per site per step)
     "k_stress": 5 + 9,            # Q -> Pi
@@ -40,6 +41,18 @@ KERNEL_VALUES = {
     "k_lbf": (19 + 3) + (19 + 3),  # g, F -> g', u
     "k_qupdate": (5 + 3) + 5,     # Q, u -> Q'
 }
+# Algorithmic values of the step of the method each kernel carries out: the
+# Q-side stencil Q -> F (5 + 3), the LB step g, F -> g', u (22 + 22), the
+# predictor Q, u -> Q* (8 + 5), the corrector Q, Q*, u -> Q (13 + 5), the fused
+# predictor-corrector Q, u -> Q (8 + 5).  The stress sweep of the per-site
+# schedule is half of the Q-side stencil; it is counted with its own bytes.
+METHOD_VALUES = {"k_lb": 44, "k_lbf": 44, "k_qforce": 8, "k_qupdate": 13, "k_qpred": 13, "k_qcorr": 18,
+                 "k_stress": 14}
+# Values per site per step of the whole step by design: four launches
+# (stencil | LB | predictor | corrector), three (fused predictor-corrector),
+# two (stencil fused into the LB step), and the state itself (populations and
+# Q read and written once).
+STEP_DESIGNS = {"4-kernel": 83, "3-kernel": 65, "2-kernel": 59, "state-minimum": 48}
 # split coupling: the stress sweep writes sigma^xi (6), tau (3) and h (3)
 SPLIT_VALUES = {
     "k_stress": 5 + 12,            # Q -> sigma, tau, h
@@ -50,16 +63,40 @@ PC_VALUES = {
     "k_pc1": (15 + 12) + (15 + 3 + 3),  # f, sigma/tau/h -> f + C, u, b
     "k_pc2": (15 + 15 + 6 + 3) + 15,    # f + C and f pulled, sigma, b -> f'
 }
-STATE_VALUES = 48  # f (19) and Q (5) read and written once
 
-# HBM bytes per launch of the 128^3 kernels, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes scaled by a 512 MiB device copy (profiles/*.md); valid
-# while the kernels are unchanged since those counters were taken.
-MEASURED_TRAFFIC = {
-    ("fp32", "k_lb"): (252.0 + 184.5) * 1e6,       # profiles/step_sites_128cubed.md
-    ("fp64", "k_lb"): (527.4 + 369.1) * 1e6,       # profiles/step_sites_128cubed.md
-    ("fp64", "k_qupdate"): (160.9 + 83.9) * 1e6,   # profiles/step_fp64_mixed_128cubed.md
-}
+KERNEL_SOURCES = ["kernels.hip", "site.h", "sitekern.h", "tiles.h", "kernels.h"]
+
+
+def kernel_source_sha():
+    """sha256 (first 16 hex digits) of the step kernels' sources."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0901_3293_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec, kernel):
+    """HBM bytes per launch of `kernel` at 128^3 from the FETCH_SIZE and
+    WRITE_SIZE counter passes recorded in profiles/ (a line
+    'bench-traffic: {json}' in a profile summary), if they were taken on the
+    current kernel sources; None otherwise."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    sha = kernel_source_sha()
+    for name in sorted(os.listdir(d)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(d, name)) as fh:
+            for line in fh:
+                if line.startswith("bench-traffic:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("kernel_source_sha") == sha and kernel in rec.get(prec, {}):
+                        return float(rec[prec][kernel]), name
+    return None
 
 
 def log(*a):
@@ -107,11 +144,13 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
     mlups = N * steps / (ms / 1e3) / 1e6
     per_launch = {k: v / prof_steps for k, v in kern.items() if v > 0}
     dom = max(per_launch, key=per_launch.get)
-    alg_bytes = values[dom] * esz * N
+    alg_values = METHOD_VALUES.get(dom, values[dom]) if coupling == "force" and lb_model == "d3q19" \
+        else values[dom]
+    alg_bytes = alg_values * esz * N
     achieved = alg_bytes / (per_launch[dom] / 1e3) / 1e9
     step_values = sum(values[k] for k in per_launch)
-    traffic = MEASURED_TRAFFIC.get((prec, dom)) if (n == 128 and coupling == "force" and lb_model == "d3q19") \
-        else None
+    tr = measured_traffic(prec, dom) if (n == 128 and coupling == "force" and lb_model == "d3q19") else None
+    gbs_of = lambda v: mlups * 1e6 * v * esz / 1e9  # noqa: E731
     out = {
         "mlups": mlups,
         "coupling": coupling,
@@ -122,12 +161,14 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
         "dominant_kernel": dom,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": dom,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "traffic": tr[0] if tr else None, "traffic_source": tr[1] if tr else None,
+                     "kernel": dom, "alg_values_per_site": alg_values,
+                     "alg_bytes_per_launch": alg_bytes,
+                     "kernel_source_sha": kernel_source_sha()},
         "step_roofline": {
-            "bytes_per_site": step_values * esz,
-            "frac": mlups * 1e6 * step_values * esz / (HBM_PEAK_GBS * 1e9),
-            "frac_vs_state_minimum": mlups * 1e6 * STATE_VALUES * esz / (HBM_PEAK_GBS * 1e9),
+            "schedule_values_per_site": step_values,
+            "frac_at_schedule_values": gbs_of(step_values) / HBM_PEAK_GBS,
+            **{f"frac_at_{k}_{v}": gbs_of(v) / HBM_PEAK_GBS for k, v in STEP_DESIGNS.items()},
         },
         "checks": {"mass": m, "momentum": [float(x) for x in mom], "free_energy": ftot,
                    "finite": bool(math.isfinite(m) and math.isfinite(ftot))},
@@ -372,6 +413,102 @@ def run_surrogate(n=96, steps=20000, k=32, M=4, iters=3000, train_set="mixed"):
     return out
 
 
+def run_surrogate_growth(n=96, kappa=1.0, tau_ldg=0.0, target=44, every=512, max_steps=30720, k=32, M=4,
+                         iters=3000, lr=1e-3, train_seeds=(1, 3, 4, 5), heldout_seed=2, pairs_per_run=60,
+                         spacing=240, burn=1000):
+    """Time to a stated domain size on a growing box: an n^3 box with a
+    double-twist (O2) slab z < 32 inside a cholesteric x-helix at kappa, tau
+    (FP32), whose blue-phase domain (planes carrying disclination sites)
+    grows.  Training pairs come from growth runs of the same box with seeded
+    noise 1e-3 on Q (`pairs_per_run` per run, one every `spacing` steps after
+    `burn`), one run held out; the timed runs start from the noise-free seed.
+    Each predictor -- the trained network on the linear base, linear
+    extrapolation alone, quadratic extrapolation alone (the driver without a
+    network) -- runs in the same checked driver (k steps per jump, M jumps
+    per checked cycle) and the plain FP32 step without a driver; all are read
+    every `every` steps and timed (stepping only) to the first read-out at
+    `target` blue-phase planes or more.  The Q error of each predictor is
+    taken against the plain run at the plain run's crossing step."""
+    import numpy as np
+    import torch
+
+    from paper_0901_3293_amd import hlb
+    from paper_0901_3293_amd import inputs as I
+    from paper_0901_3293_amd import surrogate as S
+
+    N = n ** 3
+    grow = dict(kappa=kappa, tau_ldg=tau_ldg)
+    net = hlb.Net((n, n, n))
+    seeds = list(train_seeds) + [heldout_seed]
+    pairs = S.allocate_pairs(len(seeds) * pairs_per_run, N)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j, seed in enumerate(seeds):
+        sv = S.new_solver(S.growth_run(n, noise_amp=1e-3, seed=seed, **grow))
+        S.record_pairs(net, sv, pairs, j * pairs_per_run, pairs_per_run, spacing, k=k, burn_in=burn,
+                       tag=f"growth-{seed}")
+        del sv
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    n_train = len(train_seeds) * pairs_per_run
+    train_idx = list(range(n_train))
+    held = list(range(n_train, n_train + pairs_per_run))
+    S.fit_norm(net, pairs, 0.0, index=train_idx)
+    net.set_params(I.cnn_params(seed=0))
+    tl = S.train(net, pairs, iters, lr=lr, index=train_idx, log_every=max(1, iters // 5))
+    ev = S.evaluate(net, pairs, held)
+    heldout = {key: float(np.median(v)) for key, v in ev.items()}
+    del pairs
+    torch.cuda.empty_cache()
+
+    case = S.growth_run(n, **grow)
+    plain = S.new_solver(case)
+    T, t_plain, track_plain, _ = S.time_to_domain(plain, plain.step, target, every, max_steps)
+    q_plain = plain.fields()[0] if T is not None else None
+    start = track_plain[0][1] if track_plain else None
+    res = {"plain": {"steps_to_target": T, "seconds": t_plain, "planes_every_read": [b for _, b in track_plain]}}
+    preds = {"network": net}
+    for name, beta in (("linear_extrapolation", 0.0), ("quadratic_extrapolation", 1.0)):
+        e = hlb.Net((n, n, n))
+        S.extrapolation_only(e, beta)
+        preds[name] = e
+    for name, nn_ in preds.items():
+        sv = S.new_solver(case)
+        R = S.Runner(sv, nn_, k=k, M=M)
+        cross, secs, track, snap = S.time_to_domain(sv, R.advance, target, every, max_steps, snap_at=T)
+        qe = float(np.linalg.norm(snap - q_plain) / np.linalg.norm(q_plain)) if snap is not None else None
+        res[name] = {"steps_to_target": cross, "seconds": secs,
+                     "speedup": (t_plain / secs) if (cross is not None and T is not None) else None,
+                     "q_error_at_plain_crossing": qe, "cycles": R.attempted, "fallbacks": R.fallbacks,
+                     "plain_cycles": R.plain,
+                     "residual_median": float(np.median(R.residuals)) if R.residuals else None,
+                     "planes_every_read": [b for _, b in track]}
+        log(f"bench: growth {name}: crossing {cross} steps, {secs:.3f} s, Q error {qe}")
+        del sv
+    for o in preds.values():
+        o.close()
+    ok = {k_: v for k_, v in res.items() if k_ != "plain" and v["speedup"] is not None
+          and v["q_error_at_plain_crossing"] is not None and v["q_error_at_plain_crossing"] <= S.THRESHOLD}
+    best = max(ok, key=lambda k_: ok[k_]["speedup"]) if ok else None
+    net_r = res["network"]
+    return {
+        "workload": f"{n}^3 growing box (O2 slab z < 32 in an x-helix), kappa {kappa}, tau {tau_ldg}, FP32; "
+                    f"time until the blue-phase domain reaches {target} planes (from {start} at the first "
+                    f"read-out), read every {every} steps; k = {k}, M = {M}, threshold {S.THRESHOLD:g}, "
+                    f"refresh {S.REFRESH:g}",
+        "target_planes": target,
+        **res,
+        "best_predictor": best,
+        "learned_gain": (best == "network"),
+        "increment_error_heldout": heldout,
+        "training": {"pairs": n_train, "heldout_pairs": pairs_per_run, "iters": iters, "lr": lr,
+                     "data_seconds": t_data, "train_seconds": tl.seconds,
+                     "final_loss": tl.losses[-1][1] if tl.losses else None},
+        "network_speedup_with_training": (t_plain / (net_r["seconds"] + t_data + tl.seconds))
+        if net_r["speedup"] else None,
+    }
+
+
 def run_slab(steps=20000, every=100, kappas=(0.5, 0.8, 1.0), prec="fp32"):
     """The domain-growth slab (64 x 64 x 256, O2 seed for z < 32 inside an
     x-helix, tau_LdG = 0) for each chirality: `steps` steps with the
@@ -508,7 +645,8 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "network", "order", "slab"], default=None,
+    ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "surrogate-mixed", "network", "order",
+                                       "slab"], default=None,
                     help="run one leg only (profiling runs)")
     ap.add_argument("--coupling", choices=["force", "split"], default="force",
                     help="fluid coupling of the --only fp32/fp64 profiling legs")
@@ -532,7 +670,13 @@ def main():
     ap.add_argument("--slab-steps", type=int, default=20000,
                     help="steps of the 64x64x256 domain-growth slab per chirality (0: skip)")
     ap.add_argument("--surrogate-steps", type=int, default=20000,
-                    help="steps of the 96^3 surrogate-vs-plain run (0: skip the surrogate leg)")
+                    help="steps of the 96^3 surrogate-vs-plain run of --only surrogate-mixed")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate time-to-domain-size leg")
+    ap.add_argument("--growth-target", type=int, default=44,
+                    help="blue-phase planes the growing 96^3 box must reach (surrogate leg)")
+    ap.add_argument("--growth-every", type=int, default=512, help="steps between domain read-outs")
+    ap.add_argument("--growth-max-steps", type=int, default=30720, help="steps before a run gives up")
+    ap.add_argument("--growth-kappa", type=float, default=1.0, help="chirality of the growing box")
     ap.add_argument("--surrogate-k", type=int, default=32, help="solver steps replaced by one network jump")
     ap.add_argument("--surrogate-m", type=int, default=4, help="jumps per checked surrogate cycle")
     ap.add_argument("--surrogate-iters", type=int, default=3000, help="training iterations of the surrogate")
@@ -556,7 +700,7 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy probe 512 MiB x3 done")
         del src, dst
-    if a.only in ("batched", "surrogate", "network", "order", "slab"):
+    if a.only in ("batched", "surrogate", "surrogate-mixed", "network", "order", "slab"):
         if a.only == "order":
             out = run_order(a.n)
         elif a.only == "slab":
@@ -566,6 +710,10 @@ def main():
                               a.batch_launch, a.batch_group)
         elif a.only == "network":
             out = run_network()
+        elif a.only == "surrogate":
+            out = run_surrogate_growth(kappa=a.growth_kappa, target=a.growth_target, every=a.growth_every,
+                                       max_steps=a.growth_max_steps, k=a.surrogate_k, M=a.surrogate_m,
+                                       iters=a.surrogate_iters)
         else:
             out = run_surrogate(steps=a.surrogate_steps, k=a.surrogate_k, M=a.surrogate_m, iters=a.surrogate_iters,
                                 train_set=a.surrogate_train)
@@ -610,11 +758,13 @@ def main():
                   "final": {k: v["track"][-1] for k, v in sl["kappa"].items()},
                   "mlups_with_readouts": {k: v["mlups_with_readouts"] for k, v in sl["kappa"].items()}}
     sur = None
-    if a.surrogate_steps > 0 and not a.only:
-        log(f"bench: surrogate 96^3, {a.surrogate_steps} steps, k {a.surrogate_k}, M {a.surrogate_m}")
-        sur = run_surrogate(steps=a.surrogate_steps, k=a.surrogate_k, M=a.surrogate_m, iters=a.surrogate_iters,
-                                train_set=a.surrogate_train)
-        log(f"bench: surrogate speedup {sur['speedup']:.2f}, Q error {sur['q_error_vs_plain']:.2e}")
+    if not a.no_surrogate and not a.only:
+        log(f"bench: surrogate, time to {a.growth_target} blue-phase planes on the growing 96^3 box, "
+            f"k {a.surrogate_k}, M {a.surrogate_m}")
+        sur = run_surrogate_growth(kappa=a.growth_kappa, target=a.growth_target, every=a.growth_every,
+                                   max_steps=a.growth_max_steps, k=a.surrogate_k, M=a.surrogate_m,
+                                   iters=a.surrogate_iters)
+        log(f"bench: surrogate best predictor {sur['best_predictor']}")
     cpu = None
     if not a.no_cpu:
         log("bench: cpu baseline (oracle)")

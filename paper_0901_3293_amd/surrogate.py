@@ -194,53 +194,123 @@ class RunStats:
     fallback_steps: list = field(default_factory=list)  # solver step at which each fallback cycle began
 
 
-def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64, refresh=REFRESH):
-    """Advance `solver` by `steps` solver steps: a 2k-step history warm-up,
-    then cycles of M*k steps while a whole cycle fits, plain steps for the
-    rest.  A cycle is a surrogate cycle (M network jumps, the last one checked
+class Runner:
+    """Cycles of M*k solver steps on one solver with the surrogate policy.
+
+    A cycle is a surrogate cycle (M network jumps, the last one checked
     against k plain steps, rolled back to plain steps when its residual
     reaches `threshold`) unless the runner is cooling down: after a fallback
     the next c cycles are plain (c = 1, 2, 4, ... up to cooldown_max on
     consecutive fallbacks, reset by an accepted cycle), so a fast transient is
     not paid for twice.  An accepted cycle whose residual reaches
-    refresh * threshold is followed by one plain cycle (refresh=None turns this
-    off): the errors of the unchecked jumps accumulate in the state, and a plain
-    cycle taken before the check fails costs less than a rolled-back one."""
-    cyc = k * M
+    refresh * threshold is followed by one plain cycle (refresh=None turns
+    this off): the errors of the unchecked jumps accumulate in the state, and
+    a plain cycle taken before the check fails costs less than a rolled-back
+    one.  A plain cycle leaves a valid history behind (its last 2k steps are
+    the network's warm-up)."""
+
+    def __init__(self, solver, net, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64, refresh=REFRESH):
+        self.solver, self.net, self.k, self.M = solver, net, k, M
+        self.threshold, self.cooldown_max, self.refresh = threshold, cooldown_max, refresh
+        self.cyc = k * M
+        self.wait = 0
+        self.penalty = 1
+        self.steps = 0
+        self.attempted = self.fallbacks = self.plain = 0
+        self.residuals = []
+        self.fallback_steps = []
+
+    def plain_cycle(self):
+        self.solver.step(self.cyc - 2 * self.k)
+        self.net.warmup(self.solver, self.k)
+        self.steps += self.cyc
+
+    def cycle(self):
+        if self.wait > 0:
+            self.plain_cycle()
+            self.wait -= 1
+            self.plain += 1
+            return
+        f, r = hlb.surrogate_advance(self.solver, self.net, k=self.k, M=self.M, threshold=self.threshold)
+        self.attempted += 1
+        self.residuals.append(r)
+        if f:
+            self.fallbacks += 1
+            self.fallback_steps.append(self.steps)
+            self.wait = self.penalty
+            self.penalty = min(2 * self.penalty, self.cooldown_max)
+        else:
+            self.penalty = 1
+            if self.refresh is not None and r >= self.refresh * self.threshold:
+                self.wait = 1
+        self.steps += self.cyc
+
+    def advance(self, nsteps):
+        """nsteps (a multiple of the cycle length) more steps; the first cycle
+        of a run is a plain one, which records the network's history."""
+        if nsteps % self.cyc:
+            raise ValueError(f"advance({nsteps}) is not a whole number of {self.cyc}-step cycles")
+        for _ in range(nsteps // self.cyc):
+            if self.steps == 0:
+                self.plain_cycle()
+            else:
+                self.cycle()
+
+    def stats(self, seconds):
+        return RunStats(self.steps, self.attempted, self.fallbacks, self.plain, self.residuals, seconds,
+                        self.fallback_steps)
+
+
+def run(solver, net, steps, k=K_JUMP, M=8, threshold=THRESHOLD, cooldown_max=64, refresh=REFRESH):
+    """Advance `solver` by `steps` solver steps: a 2k-step history warm-up,
+    then cycles of M*k steps (Runner) while a whole cycle fits, plain steps
+    for the rest."""
+    R = Runner(solver, net, k, M, threshold, cooldown_max, refresh)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net.warmup(solver, k)
-    n_cyc = (steps - 2 * k) // cyc
-    fb = plain = attempted = 0
-    res = []
-    fb_at = []
-    wait = 0
-    penalty = 1
-    for c in range(n_cyc):
-        if wait > 0:
-            # a plain cycle that leaves a valid history behind
-            solver.step(cyc - 2 * k)
-            net.warmup(solver, k)
-            wait -= 1
-            plain += 1
-            continue
-        f, r = hlb.surrogate_advance(solver, net, k=k, M=M, threshold=threshold)
-        attempted += 1
-        res.append(r)
-        if f:
-            fb += 1
-            fb_at.append(2 * k + c * cyc)
-            wait = penalty
-            penalty = min(2 * penalty, cooldown_max)
-        else:
-            penalty = 1
-            if refresh is not None and r >= refresh * threshold:
-                wait = 1
-    rest = steps - 2 * k - n_cyc * cyc
+    R.steps = 2 * k
+    n_cyc = (steps - 2 * k) // R.cyc
+    for _ in range(n_cyc):
+        R.cycle()
+    rest = steps - R.steps
     if rest:
         solver.step(rest)
+        R.steps += rest
     torch.cuda.synchronize()
-    return RunStats(steps, attempted, fb, plain, res, time.perf_counter() - t0, fb_at)
+    st = R.stats(time.perf_counter() - t0)
+    st.fallback_steps = list(R.fallback_steps)
+    return st
+
+
+def blue_phase_planes(solver, threshold=0.19):
+    """Planes of the blue-phase domain: z-planes carrying disclination sites
+    (local order below the threshold; the cholesteric carries none)."""
+    return int((solver.order(threshold=threshold, fields=False)["per_z"] > 0).sum())
+
+
+def time_to_domain(solver, advance, target, every, max_steps, snap_at=None):
+    """Advance `solver` with `advance(n)` in chunks of `every` steps, reading
+    the blue-phase planes after each chunk, until they reach `target` or
+    `max_steps` steps have run (and at least `snap_at` steps, where Q is
+    copied to the host).  Only the stepping is timed (device synchronised
+    around each chunk).  Returns (steps at the crossing or None, seconds
+    to the crossing, track [(step, planes)], Q at snap_at or None)."""
+    t, secs, track, snap, cross, cross_s = 0, 0.0, [], None, None, None
+    while t < max_steps and (cross is None or (snap_at is not None and t < snap_at)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        advance(every)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        t += every
+        bp = blue_phase_planes(solver)
+        track.append((t, bp))
+        if cross is None and bp >= target:
+            cross, cross_s = t, secs
+        if snap_at is not None and t == snap_at:
+            snap = solver.fields()[0]
+    return cross, cross_s, track, snap
 
 
 def plain_run(solver, steps):

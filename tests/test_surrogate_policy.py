@@ -111,3 +111,67 @@ def test_defect_walls_periodic():
     mask, walls = S.defect_walls(per_z)
     assert mask.sum() == 32 and walls == [31.5, 255.5]
     assert S.defect_walls(np.zeros(8))[1] == []
+
+
+def test_runner_advance_starts_plain_and_counts_steps(monkeypatch):
+    """Runner.advance in chunks: the first cycle of a run is plain (it records
+    the history), every later one follows the policy; steps add up per chunk,
+    and a chunk that is not a whole number of cycles is refused."""
+    clock = Clock()
+    script = iter([(False, 1e-5), (True, 2e-3), (False, 1e-5), (False, 1e-5)])
+
+    def advance(solver, net, k, M, threshold):
+        f, r = next(script)
+        clock.steps += M * k
+        clock.log.append("F" if f else "S")
+        return f, r
+
+    monkeypatch.setattr(S.hlb, "surrogate_advance", advance)
+    solver, net = FakeSolver(clock), FakeNet(clock)
+    orig = solver.step
+
+    def step(n):
+        clock.log.append("P")
+        orig(n)
+
+    solver.step = step
+    R = S.Runner(solver, net, k=4, M=3, refresh=None)
+    R.advance(24)
+    assert clock.steps == 24 and R.steps == 24 and "".join(clock.log) == "PS"
+    R.advance(36)
+    assert clock.steps == 60 and R.steps == 60 and "".join(clock.log) == "PSFPS"
+    assert R.fallbacks == 1 and R.plain == 1 and R.attempted == 3
+    with pytest.raises(ValueError):
+        R.advance(13)
+
+
+def test_time_to_domain_stops_at_target_and_snapshots(monkeypatch):
+    """time_to_domain reads the blue-phase planes after each chunk, reports
+    the first chunk at or above the target, and keeps going to the snapshot
+    step when that comes later."""
+    import numpy as np
+
+    monkeypatch.setattr(S.torch.cuda, "synchronize", lambda: None)
+
+    class GrowingSolver:
+        def __init__(self):
+            self.t = 0
+
+        def step(self, n):
+            self.t += n
+
+        def order(self, threshold=0.19, fields=False):
+            planes = 10 + self.t // 100  # one plane per 100 steps
+            per_z = np.zeros(64, dtype=np.int64)
+            per_z[:planes] = 1
+            return {"per_z": per_z}
+
+        def fields(self):
+            return np.full((5, 1, 1, 1), float(self.t)), None, None
+
+    s = GrowingSolver()
+    cross, secs, track, snap = S.time_to_domain(s, s.step, target=14, every=50, max_steps=1000, snap_at=600)
+    assert cross == 400 and track[7] == (400, 14) and s.t == 600 and snap[0, 0, 0, 0] == 600.0
+    s2 = GrowingSolver()
+    cross2, _, track2, snap2 = S.time_to_domain(s2, s2.step, target=99, every=100, max_steps=500)
+    assert cross2 is None and len(track2) == 5 and snap2 is None
