@@ -231,6 +231,16 @@ enum { HLB_SCHED_SITES = 0, HLB_SCHED_TILED = 1, HLB_SCHED_MIXED = 2 };
 int hlb_set_schedule(hlb_ctx *ctx, int schedule, int tz);
 int hlb_get_schedule(const hlb_ctx *ctx, int *schedule, int *tz);
 
+/* Debug flags.  HLB_DEBUG_NAN_LDS: the tiled kernels (HLB_SCHED_TILED, and
+ * the Q update of HLB_SCHED_MIXED) overwrite every LDS plane with NaN before
+ * staging a lattice plane into it or evaluating the stress or the predictor
+ * stage into it, so a halo point the kernels fail to write surfaces as NaN
+ * in Q, u and the totals (HLB_ERR_NONFINITE) instead of a stale value; the
+ * results are otherwise unchanged.  For testing the tile halos only: the
+ * fills cost time.  flags = 0 turns it off; HLB_ERR_ARG for unknown bits. */
+enum { HLB_DEBUG_NAN_LDS = 1 };
+int hlb_set_debug(hlb_ctx *ctx, int flags);
+
 /* Autotuner: time trial_steps steps of every candidate schedule (per-site;
  * tiled and mixed with tz = 8, 16, 32; no tiled with the split coupling or
  * the D3Q15 scheme) on this context's lattice and precision with HIP events

@@ -18,6 +18,7 @@
 namespace {
 
 static_assert(HLB_OPTICS_MAX_WAVELENGTHS == hlb::OPTICS_MAX_WL, "optics wavelength bound");
+static_assert(HLB_DEBUG_NAN_LDS == hlb::DEBUG_NAN_LDS, "debug flag");
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -263,6 +264,14 @@ int hlb_set_schedule(hlb_ctx *c, int schedule, int tz)
         return set_error(c, HLB_ERR_STATE, "the tiled schedule runs the D3Q19 LB only");
     c->D.sched = schedule;
     c->D.tz = tz;
+    return HLB_OK;
+}
+
+int hlb_set_debug(hlb_ctx *c, int flags)
+{
+    HLB_GUARD(c);
+    if (flags & ~HLB_DEBUG_NAN_LDS) return set_error(c, HLB_ERR_ARG, "unknown debug flags 0x%x", flags);
+    c->D.debug = flags;
     return HLB_OK;
 }
 

@@ -56,6 +56,11 @@ struct PhysParams {
     int model;  // LbModel
 };
 
+// Debug flags: fill the LDS planes of the tiled kernels with NaN before
+// each plane is staged or evaluated into them, so a halo point that is never
+// written surfaces as NaN in the results.
+enum DebugFlags { DEBUG_NAN_LDS = 1 };
+
 // Step schedules (see kernels.hip).
 enum Schedule { SCHED_SITES = 0, SCHED_TILED = 1, SCHED_MIXED = 2 };
 
@@ -74,6 +79,7 @@ struct Device {
     int gcur, qcur;
     int sched;     // Schedule
     int tz;        // z-chunk of the tiled kernels (0: default)
+    int debug;     // debug flags (DEBUG_NAN_LDS)
     hipStream_t stream;
 };
 

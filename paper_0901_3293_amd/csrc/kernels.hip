@@ -38,8 +38,8 @@ namespace hlb {
 namespace {
 
 constexpr int BLK = 256;  // per-site kernels
-constexpr int TX = 32, TY = 8;
-using Shape = TileShape<TX, TY>;
+using Shape = KernelTile;
+constexpr int TX = Shape::TX, TY = Shape::TY;
 
 // ---------------------------------------------------------------- helpers
 
@@ -64,6 +64,17 @@ __device__ __forceinline__ void block_sum(double v[NV], double *out)
         for (int k = 0; k < NV; ++k) out[k] = buf[k][0];
 }
 
+// Debug mode of the tiled kernels: every LDS plane is overwritten with NaN
+// (by all threads, independently of the loaders' element mapping) before the
+// plane is staged or evaluated into it; the caller puts a workgroup barrier
+// between the fill and the writes that follow.
+template <typename T>
+__device__ __forceinline__ void nan_fill(T *slot, int n)
+{
+    const T q = __builtin_nan("");
+    for (int i = int(threadIdx.x); i < n; i += int(blockDim.x)) slot[i] = q;
+}
+
 // Staging of one z-plane of an NC-component field into an LDS ring slot with
 // a two-site halo in x and y (periodic wrap of the global coordinates).  The
 // element -> (component, in-plane offset) assignment is computed once per
@@ -81,10 +92,7 @@ struct PlaneLoader {
         for (int k = 0; k < NL; ++k) {
             const int e = int(threadIdx.x) + k * Shape::NT;
             if (e < NE) {
-                const int cc = e / Shape::RN, r = e - cc * Shape::RN;
-                const int ri = r % Shape::RX, rj = r / Shape::RX;
-                comp[k] = cc;
-                off[k] = wrapi(x0 - 2 + ri, G.nx) + G.nx * wrapi(y0 - 2 + rj, G.ny);
+                TileMap<Shape>::staged(e, x0, y0, G.nx, G.ny, comp[k], off[k]);
             } else {
                 comp[k] = -1;
                 off[k] = 0;
@@ -206,12 +214,17 @@ __device__ __forceinline__ Block block_of(const Geom &G, const TileGrid &tg)
 template <typename T, bool WITH_F>
 __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGrid tg,
                                                       const T *__restrict__ Q, T *__restrict__ F,
-                                                      double *__restrict__ fpart)
+                                                      double *__restrict__ fpart, bool dbg_nan)
 {
     __shared__ T sQ[3][5 * Shape::RN];
     __shared__ T sP[6 * Shape::PN];
     const Block B = block_of(G, tg);
     if (!B.ok) return;
+    if (dbg_nan) {
+        nan_fill(&sQ[0][0], 3 * 5 * Shape::RN);
+        nan_fill(sP, 6 * Shape::PN);
+        __syncthreads();
+    }
     const size_t N = G.N;
     const int sxy = G.nx * G.ny;
     const int tx = int(threadIdx.x) % Shape::TX, ty = int(threadIdx.x) / Shape::TX;
@@ -227,15 +240,9 @@ __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGri
     __syncthreads();
 
     // own site in halo-1 coordinates and in staged coordinates
-    const int pc = (ty + 1) * Shape::PX + (tx + 1);
-    const int rc = (ty + 2) * Shape::RX + (tx + 2);
-    int hp = -1, hr = -1;
-    if (int(threadIdx.x) < Shape::NH) {
-        int i, j;
-        Shape::halo_point(threadIdx.x, i, j);
-        hp = j * Shape::PX + i;
-        hr = (j + 1) * Shape::RX + (i + 1);
-    }
+    int pc, rc, hp, hr;
+    TileMap<Shape>::own(int(threadIdx.x), pc, rc);
+    TileMap<Shape>::halo(int(threadIdx.x), hp, hr);
 
     T Fin[3] = {T(0), T(0), T(0)}, Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
     double facc = 0.0;
@@ -283,6 +290,12 @@ __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGri
             Pz2[a] = Pz1[a];
             Pz1[a] = Pz[a];
         }
+        if (dbg_nan) {  // plane p-1 and the stress of plane p are no longer read
+            __syncthreads();
+            nan_fill(sQ[sb], 5 * Shape::RN);
+            nan_fill(sP, 6 * Shape::PN);
+            __syncthreads();
+        }
         if (p + 2 <= B.z1 + 1) L.store(cur, sQ[sb]);  // plane p-1 is no longer read: it becomes p+2
         __syncthreads();
         const int o = sb;
@@ -310,13 +323,19 @@ __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGri
 template <typename T>
 __global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGrid tg,
                                                        const T *__restrict__ Qin, const T *__restrict__ u,
-                                                       T *__restrict__ Qout)
+                                                       T *__restrict__ Qout, bool dbg_nan)
 {
     __shared__ T sQ[3][5 * Shape::RN];
     __shared__ T sU[3][3 * Shape::RN];
     __shared__ T sS[3][5 * Shape::PN];
     const Block B = block_of(G, tg);
     if (!B.ok) return;
+    if (dbg_nan) {
+        nan_fill(&sQ[0][0], 3 * 5 * Shape::RN);
+        nan_fill(&sU[0][0], 3 * 3 * Shape::RN);
+        nan_fill(&sS[0][0], 3 * 5 * Shape::PN);
+        __syncthreads();
+    }
     const size_t N = G.N;
     const int sxy = G.nx * G.ny;
     const int tx = int(threadIdx.x) % Shape::TX, ty = int(threadIdx.x) / Shape::TX;
@@ -337,15 +356,9 @@ __global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGr
     LU.load(u, N, wrapi(B.z0, G.nz) * sxy, sU[st]);
     __syncthreads();
 
-    const int pc = (ty + 1) * Shape::PX + (tx + 1);
-    const int rc = (ty + 2) * Shape::RX + (tx + 2);
-    int hp = -1, hr = -1;
-    if (int(threadIdx.x) < Shape::NH) {
-        int i, j;
-        Shape::halo_point(threadIdx.x, i, j);
-        hp = j * Shape::PX + i;
-        hr = (j + 1) * Shape::RX + (i + 1);
-    }
+    int pc, rc, hp, hr;
+    TileMap<Shape>::own(int(threadIdx.x), pc, rc);
+    TileMap<Shape>::halo(int(threadIdx.x), hp, hr);
 
     T qprev[5] = {T(0), T(0), T(0), T(0), T(0)};  // Q^n at the own site of plane p-1
     T up1[3] = {T(0), T(0), T(0)};                 // u at the own site, plane p-1
@@ -414,6 +427,12 @@ __global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGr
             up1[a] = ucur[a];
         }
         __syncthreads();  // slot sb (plane p-1) and the Q* slot q2 are free now
+        if (dbg_nan) {
+            nan_fill(sQ[sb], 5 * Shape::RN);
+            nan_fill(sU[sb], 3 * Shape::RN);
+            nan_fill(sS[q2], 5 * Shape::PN);
+            __syncthreads();
+        }
         if (p + 2 <= B.z1 + 1) {
             LQ.store(curQ, sQ[sb]);
             LU.store(curU, sU[sb]);
@@ -927,6 +946,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
     // the tiled kernels carry the whole stress and the D3Q19 LB only
     if ((SPLIT || p.model == LB_D3Q15_PC) && D.sched == SCHED_TILED) return hipErrorNotSupported;
     const bool pc = p.model == LB_D3Q15_PC;
+    const bool dbg_nan = (D.debug & DEBUG_NAN_LDS) != 0;
     const Geom G = D.G;
     const Coef<T> c = make_coef<T>(p);
     const int nb = site_blocks(G.N);
@@ -964,7 +984,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             if (fused_q) {
                 if (e == hipSuccess)
                     e = mark(K_QUPDATE, [&] {
-                        k_qupdate<T><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Q, u, Qs);
+                        k_qupdate<T><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Q, u, Qs, dbg_nan);
                     });
                 D.qcur ^= 1;
             } else {
@@ -983,7 +1003,8 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
                 T *gin = static_cast<T *>(D.g[D.gcur]);
                 T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
                 e = mark(K_QFORCE, [&] {
-                    k_qforce<T, false><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Qn, Pi, nullptr);
+                    k_qforce<T, false><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Qn, Pi, nullptr,
+                                                                              dbg_nan);
                 });
                 if (e == hipSuccess)
                     e = mark(K_LBF, [&] { k_lbf<T><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
@@ -991,7 +1012,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             }
             if (e == hipSuccess)
                 e = mark(K_QUPDATE, [&] {
-                    k_qupdate<T><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Qn, u, Qn1);
+                    k_qupdate<T><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Qn, u, Qn1, dbg_nan);
                 });
             D.qcur ^= 1;
         }

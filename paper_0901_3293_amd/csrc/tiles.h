@@ -23,7 +23,7 @@ struct TileShape {
 
     // Halo-ring point h in [0, NH) -> (i, j) in halo-1 plane coordinates:
     // bottom row, top row, then left/right columns.
-    __device__ static __forceinline__ void halo_point(int h, int &i, int &j)
+    __host__ __device__ static __forceinline__ void halo_point(int h, int &i, int &j)
     {
         if (h < PX) {
             i = h;
@@ -39,11 +39,51 @@ struct TileShape {
     }
 };
 
-__device__ __forceinline__ int wrapi(int v, int n)
+// The tile of the fused Q-side kernels: 32 x 8 sites per block.
+using KernelTile = TileShape<32, 8>;
+
+__host__ __device__ __forceinline__ int wrapi(int v, int n)
 {
     v %= n;
     return v < 0 ? v + n : v;
 }
+
+// Index maps of the tile kernels, shared by the kernels and the host-side
+// check of their halo coverage.
+template <class S>
+struct TileMap {
+    // Own site of thread t: its place on the halo-1 plane (pc) and on the
+    // staged plane (rc).
+    __host__ __device__ static __forceinline__ void own(int t, int &pc, int &rc)
+    {
+        const int tx = t % S::TX, ty = t / S::TX;
+        pc = (ty + 1) * S::PX + (tx + 1);
+        rc = (ty + 2) * S::RX + (tx + 2);
+    }
+    // Halo-ring point of thread t < NH on the halo-1 plane (hp) and on the
+    // staged plane (hr); -1 for the other threads.
+    __host__ __device__ static __forceinline__ void halo(int t, int &hp, int &hr)
+    {
+        hp = hr = -1;
+        if (t < S::NH) {
+            int i, j;
+            S::halo_point(t, i, j);
+            hp = j * S::PX + i;
+            hr = (j + 1) * S::RX + (i + 1);
+        }
+    }
+    // Element e of an NC-component staged plane (component-major, RN points
+    // per component): its component and its in-plane offset in the lattice
+    // for a tile at (x0, y0), periodic wrap.  The block stages element
+    // e = t + k NT from thread t, k = 0, 1, ...
+    __host__ __device__ static __forceinline__ void staged(int e, int x0, int y0, int nx, int ny, int &comp, int &off)
+    {
+        comp = e / S::RN;
+        const int r = e - comp * S::RN;
+        const int ri = r % S::RX, rj = r / S::RX;
+        off = wrapi(x0 - 2 + ri, nx) + nx * wrapi(y0 - 2 + rj, ny);
+    }
+};
 
 // Block decomposition shared by the fused kernels: tiles over x and y, chunks
 // of `tz` planes over z.  Consecutive logical blocks share planes, so the

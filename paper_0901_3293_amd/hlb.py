@@ -107,6 +107,7 @@ def lib():
         L.hlb_get_order.argtypes = [vp, ctypes.c_double, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.hlb_get_optics.argtypes = [vp, ctypes.POINTER(OpticsParams), dp]
         L.hlb_set_schedule.argtypes = [vp, I, I]
+        L.hlb_set_debug.argtypes = [vp, I]
         L.hlb_get_schedule.argtypes = [vp, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.hlb_autotune.argtypes = [vp, I, dp]
         L.hlb_step_timed.argtypes = [vp, I, dp, I]
@@ -225,6 +226,11 @@ class Solver:
 
     def set_schedule(self, schedule="sites", tz=0):
         self._check(lib().hlb_set_schedule(self.ctx, SCHEDULES[schedule], int(tz)))
+
+    def set_debug(self, nan_lds=False):
+        """nan_lds: fill the tiled kernels' LDS planes with NaN before each
+        plane is staged or evaluated into them (halo-coverage testing)."""
+        self._check(lib().hlb_set_debug(self.ctx, 1 if nan_lds else 0))
 
     def schedule(self):
         sc, tz = ctypes.c_int(), ctypes.c_int()

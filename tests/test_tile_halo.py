@@ -1,0 +1,43 @@
+"""Halo coverage of the LDS tiles of the fused Q-side kernels, checked on the
+host: tests/hostcheck/tile_halo.cpp stages a plane with the kernels' own
+index maps (tiles.h) into an array prefilled with NaN, as the kernels'
+HLB_DEBUG_NAN_LDS mode does to their LDS, and reads every value the stencils
+read.  With the maps as built nothing reads NaN or a wrong site and every
+site of the halo-1 plane is evaluated exactly once; a staging that misses a
+halo column or row (planted in the checker, not in the library) surfaces as
+NaN reads."""
+import os
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("tile") / "tile_halo")
+    subprocess.check_call([HIPCC, "-O1", "-std=c++17", "-I" + os.path.join(ROOT, "include"),
+                           os.path.join(HERE, "hostcheck", "tile_halo.cpp"), "-o", exe],
+                          stderr=subprocess.DEVNULL)
+    return exe
+
+
+def run(exe, drop):
+    out = subprocess.run([exe, str(drop)], capture_output=True, text=True, check=True).stdout.split()
+    return tuple(int(v) for v in out)
+
+
+def test_tile_maps_cover_every_halo_read(checker):
+    nan, bad, cover = run(checker, 0)
+    assert (nan, bad, cover) == (0, 0, 0)
+
+
+@pytest.mark.parametrize("drop", [1, 2])
+def test_missed_halo_surfaces_as_nan(checker, drop):
+    nan, bad, cover = run(checker, drop)
+    assert nan > 0 and bad == 0
