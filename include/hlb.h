@@ -169,6 +169,21 @@ int hlb_get_fields(hlb_ctx *ctx, double *Q5, double *u3, double *rho);
  * HLB_ERR_NONFINITE if any total is NaN or Inf.  Synchronises the stream. */
 int hlb_get_totals(hlb_ctx *ctx, double *mass, double *mom3, double *free_energy);
 
+/* hlb_get_totals for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same totals, reduced by the same kernels in the same order (so bitwise
+ * equal to hlb_get_totals), with the block partials and totals kept in a
+ * static device array of 4 MiB that the library holds per device until the
+ * process ends, instead of the context's workspace.  It allocates nothing
+ * (no hipMalloc, hipFree or allocating library call); the stress planes of
+ * the context's own workspace still carry the force term of the momentum.
+ * Lattices of at most 26,843,136 sites; larger ones fail with HLB_ERR_NOMEM
+ * (sticky, like every error) before any GPU work.  The context's device must
+ * be current.  All calls on one device share its array: calls that overlap
+ * on one device (other threads, other streams) race and must be serialised
+ * by the caller.  Synchronises the stream. */
+int hlb_get_totals_noalloc(hlb_ctx *ctx, double *mass, double *mom3, double *free_energy);
+
 /* Free-energy profile along z: fz[z] = sum over the plane z of the
  * free-energy density (Eq. (1)) of the current Q, FP64, fixed-order per-plane
  * reduction; the domain-wall position of a slab run is read off this profile.

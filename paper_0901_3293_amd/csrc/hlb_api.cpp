@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -87,6 +88,37 @@ int hip_fail(hlb_ctx *c, hipError_t e, const char *what)
 // FP64 staging area for host transfers: the population buffer that does not
 // hold the state (19 x N x 4 bytes >= 9 x N doubles in both precisions).
 double *stage_of(hlb_ctx *c) { return static_cast<double *>(c->D.g[c->D.gcur ^ 1]); }
+
+// Reduction scratch of hlb_get_totals_noalloc: the reduced totals in its
+// first 8 doubles, the block partials after them.  One copy per device,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in: its device address is looked up once per device and only that
+// address is passed to kernels and copies.
+constexpr size_t NOALLOC_DOUBLES = size_t(1) << 19;  // 4 MiB
+constexpr size_t NOALLOC_TOTALS = 8;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+std::mutex scratch_mu;
+double *scratch_dev[NOALLOC_MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with it current).
+hipError_t scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *out = scratch_dev[dev];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -247,6 +279,31 @@ int hlb_get_totals(hlb_ctx *c, double *mass, double *mom3, double *free_energy)
     for (int k = 0; k < 5; ++k)
         if (!std::isfinite(r[k])) return set_error(c, HLB_ERR_NONFINITE, "non-finite total (component %d)", k);
     if (mass) *mass = m;
+    if (mom3)
+        for (int a = 0; a < 3; ++a) mom3[a] = r[1 + a];
+    if (free_energy) *free_energy = r[4];
+    return HLB_OK;
+}
+
+int hlb_get_totals_noalloc(hlb_ctx *c, double *mass, double *mom3, double *free_energy)
+{
+    HLB_GUARD(c);
+    const size_t need = NOALLOC_TOTALS + hlb::readout_partials(c->D.G);
+    if (need > NOALLOC_DOUBLES)
+        return set_error(c, HLB_ERR_NOMEM,
+                         "hlb_get_totals_noalloc: %d sites need %zu doubles of reduction scratch, more than the "
+                         "%zu it holds (at most %zu sites)", c->D.G.N, need, NOALLOC_DOUBLES,
+                         (NOALLOC_DOUBLES - NOALLOC_TOTALS) / 5 / 8 * 8 * 256);
+    if (!c->have_fields) return set_error(c, HLB_ERR_STATE, "no fields set");
+    double *sp = nullptr;
+    HIP_TRY(c, scratch_on_current_device(&sp));
+    double r[5];
+    HIP_TRY(c, hlb::run_readout(c->D, c->p, nullptr, sp, sp + NOALLOC_TOTALS));
+    HIP_TRY(c, hipMemcpyAsync(r, sp, sizeof(r), hipMemcpyDeviceToHost, c->D.stream));
+    HIP_TRY(c, hipStreamSynchronize(c->D.stream));
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(r[k])) return set_error(c, HLB_ERR_NONFINITE, "non-finite total (component %d)", k);
+    if (mass) *mass = double(c->D.G.N) * c->p.rho0 + r[0];
     if (mom3)
         for (int a = 0; a < 3; ++a) mom3[a] = r[1 + a];
     if (free_energy) *free_energy = r[4];

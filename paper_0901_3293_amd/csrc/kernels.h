@@ -111,9 +111,12 @@ hipError_t run_steps(Device &D, const PhysParams &p, int nsteps, KernelTimer *ti
 hipError_t run_init(Device &D, const PhysParams &p, const double *stage);
 
 // Current-level readout into device FP64 stage [rho N][u 3N][Q 5N] (may be
-// null) and, if totals is non-null, the reductions into D.res:
-// res[0] = sum (rho - rho0), res[1..3] = sum rho u, res[4] = sum f.
-hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *totals);
+// null) and, if totals is non-null, the reductions into totals[0..4]:
+// totals[0] = sum (rho - rho0), totals[1..3] = sum rho u, totals[4] = sum f.
+// The block partials of the reductions go to part (null: D.part), which
+// needs readout_partials(G) doubles.
+hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *totals, double *part = nullptr);
+size_t readout_partials(const Geom &G);
 
 // Plane sums of the free-energy density of the current Q into device fz[nz].
 hipError_t run_fz(Device &D, const PhysParams &p, double *fz);

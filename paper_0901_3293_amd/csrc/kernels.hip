@@ -1040,7 +1040,7 @@ hipError_t init_t(Device &D, const PhysParams &p, const double *stage)
 }
 
 template <typename T, bool SPLIT>
-hipError_t readout_t(Device &D, const PhysParams &p, double *stage, double *totals)
+hipError_t readout_t(Device &D, const PhysParams &p, double *stage, double *totals, double *part)
 {
     const Geom G = D.G;
     const Coef<T> c = make_coef<T>(p);
@@ -1050,26 +1050,26 @@ hipError_t readout_t(Device &D, const PhysParams &p, double *stage, double *tota
     const T *Q = static_cast<const T *>(D.Q[D.qcur]);
     if (p.model == LB_D3Q15_PC) {
         // the stress sweep only for the free-energy partials
-        if (totals) k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, D.part + 4 * nb);
+        if (totals) k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, part + 4 * nb);
         k_readout15<T><<<nb, BLK, 0, D.stream>>>(G, c, static_cast<const T *>(D.g[D.gcur]), p.flow != 0, Q, stage,
                                                  stage ? stage + N : nullptr, stage ? stage + 4 * N : nullptr,
-                                                 totals ? D.part : nullptr);
+                                                 totals ? part : nullptr);
         if (totals) {
-            k_reduce<<<1, BLK, 0, D.stream>>>(D.part, nb, 4, 4, D.res);
-            k_reduce<<<1, BLK, 0, D.stream>>>(D.part + 4 * nb, nb, 1, 1, D.res + 4);
+            k_reduce<<<1, BLK, 0, D.stream>>>(part, nb, 4, 4, totals);
+            k_reduce<<<1, BLK, 0, D.stream>>>(part + 4 * nb, nb, 1, 1, totals + 4);
         }
         return hipGetLastError();
     }
     if (totals)
-        k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, D.part + 4 * nb);
+        k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, part + 4 * nb);
     else if (p.flow)
         k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr);
     k_readout<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, static_cast<const T *>(D.g[D.gcur]), p.flow ? Pi : nullptr,
                                                   Q, stage, stage ? stage + N : nullptr,
-                                                  stage ? stage + 4 * N : nullptr, totals ? D.part : nullptr);
+                                                  stage ? stage + 4 * N : nullptr, totals ? part : nullptr);
     if (totals) {
-        k_reduce<<<1, BLK, 0, D.stream>>>(D.part, nb, 4, 4, D.res);
-        k_reduce<<<1, BLK, 0, D.stream>>>(D.part + 4 * nb, nb, 1, 1, D.res + 4);
+        k_reduce<<<1, BLK, 0, D.stream>>>(part, nb, 4, 4, totals);
+        k_reduce<<<1, BLK, 0, D.stream>>>(part + 4 * nb, nb, 1, 1, totals + 4);
     }
     return hipGetLastError();
 }
@@ -1159,11 +1159,16 @@ hipError_t run_init(Device &D, const PhysParams &p, const double *stage)
     return D.fp32 ? init_t<float>(D, p, stage) : init_t<double>(D, p, stage);
 }
 
-hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *totals)
+hipError_t run_readout(Device &D, const PhysParams &p, double *stage, double *totals, double *part)
 {
+    if (!part) part = D.part;
     if (p.flow == FLOW_SPLIT)
-        return D.fp32 ? readout_t<float, true>(D, p, stage, totals) : readout_t<double, true>(D, p, stage, totals);
-    return D.fp32 ? readout_t<float, false>(D, p, stage, totals) : readout_t<double, false>(D, p, stage, totals);
+        return D.fp32 ? readout_t<float, true>(D, p, stage, totals, part)
+                      : readout_t<double, true>(D, p, stage, totals, part);
+    return D.fp32 ? readout_t<float, false>(D, p, stage, totals, part)
+                  : readout_t<double, false>(D, p, stage, totals, part);
 }
+
+size_t readout_partials(const Geom &G) { return size_t(5) * site_blocks(G.N); }
 
 }  // namespace hlb

@@ -99,6 +99,7 @@ def lib():
         L.hlb_step.argtypes = [vp, I]
         L.hlb_get_fields.argtypes = [vp, dp, dp, dp]
         L.hlb_get_totals.argtypes = [vp, dp, dp, dp]
+        L.hlb_get_totals_noalloc.argtypes = [vp, dp, dp, dp]
         L.hlb_state_bytes.argtypes = [vp]
         L.hlb_state_bytes.restype = sz
         L.hlb_get_state.argtypes = [vp, vp, sz]
@@ -298,11 +299,15 @@ class Solver:
         self._check(lib().hlb_get_optics(self.ctx, ctypes.byref(op), _dp(img)))
         return img
 
-    def totals(self):
+    def totals(self, noalloc=False):
+        """(mass, momentum[3], total free energy) at the current level;
+        noalloc=True reduces in the library's static device scratch instead
+        of the workspace (hlb_get_totals_noalloc)."""
         m = np.zeros(1)
         mom = np.zeros(3)
         f = np.zeros(1)
-        self._check(lib().hlb_get_totals(self.ctx, _dp(m), _dp(mom), _dp(f)))
+        fn = lib().hlb_get_totals_noalloc if noalloc else lib().hlb_get_totals
+        self._check(fn(self.ctx, _dp(m), _dp(mom), _dp(f)))
         return float(m[0]), mom, float(f[0])
 
     def get_state(self):

@@ -170,3 +170,17 @@ def test_set_params_checks_workspace_for_model(H):
             if not sized:
                 assert "hlb_workspace_bytes_for" in L.hlb_last_error(ctx).decode()
             L.hlb_destroy(ctx)
+
+
+def test_noalloc_totals_reject_large_lattice_before_gpu_work(H):
+    """hlb_get_totals_noalloc refuses a lattice whose reduction partials do
+    not fit its static scratch (26,843,136 sites at most) before touching
+    the device; the error is sticky."""
+    L = H.lib()
+    c = FakeCtx(H, shape=(300, 300, 300))
+    assert c.rc == 0
+    m = ctypes.c_double()
+    assert L.hlb_get_totals_noalloc(c.ctx, ctypes.byref(m), None, None) == -6
+    assert "26843136" in L.hlb_last_error(c.ctx).decode()
+    assert L.hlb_get_totals_noalloc(c.ctx, ctypes.byref(m), None, None) == -6
+    c.close()
