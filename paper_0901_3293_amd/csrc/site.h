@@ -29,7 +29,7 @@ struct Coef {
 };
 
 template <typename T>
-__device__ __forceinline__ void full3(const T q[5], T Q[3][3])
+__host__ __device__ __forceinline__ void full3(const T q[5], T Q[3][3])
 {
     Q[0][0] = q[0]; Q[0][1] = q[1]; Q[0][2] = q[2];
     Q[1][0] = q[1]; Q[1][1] = q[3]; Q[1][2] = q[4];
@@ -38,7 +38,7 @@ __device__ __forceinline__ void full3(const T q[5], T Q[3][3])
 
 // d_g Q_ab as a full tensor from the stored components.
 template <typename T>
-__device__ __forceinline__ void full_grad(const T d[3][5], T dQ[3][3][3])
+__host__ __device__ __forceinline__ void full_grad(const T d[3][5], T dQ[3][3][3])
 {
 #pragma unroll
     for (int g = 0; g < 3; ++g) full3(d[g], dQ[g]);
@@ -47,7 +47,7 @@ __device__ __forceinline__ void full_grad(const T d[3][5], T dQ[3][3][3])
 // (CQ)_ab = eps_agd d_g Q_db (the curl in Eq. (1)), written out:
 //   row x: d_y Q_zb - d_z Q_yb;  row y: d_z Q_xb - d_x Q_zb;  row z: d_x Q_yb - d_y Q_xb.
 template <typename T>
-__device__ __forceinline__ void curl(const T dQ[3][3][3], T CQ[3][3])
+__host__ __device__ __forceinline__ void curl(const T dQ[3][3][3], T CQ[3][3])
 {
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -63,7 +63,7 @@ __device__ __forceinline__ void curl(const T dQ[3][3][3], T CQ[3][3])
 //       - 2 K q0 (CQ + CQ^T) - 4 K q0^2 Q.
 // Returns the five stored components; also hands back Q^2 and tr(Q^2).
 template <typename T>
-__device__ __forceinline__ void molecular_field(const Coef<T> &c, const T Q[3][3], const T CQ[3][3],
+__host__ __device__ __forceinline__ void molecular_field(const Coef<T> &c, const T Q[3][3], const T CQ[3][3],
                                                 const T lap[5], T H[5], T Q2[3][3], T &trQ2)
 {
 #pragma unroll
@@ -89,7 +89,7 @@ __device__ __forceinline__ void molecular_field(const Coef<T> &c, const T Q[3][3
 //   f = a/2 tr Q^2 - bg/3 tr Q^3 + bg/4 (tr Q^2)^2 + K/2 |div Q|^2 + K/2 M:M,
 //   M = CQ + 2 q0 Q,  (div Q)_a = d_b Q_ab.
 template <typename T>
-__device__ __forceinline__ T free_energy(const Coef<T> &c, const T Q[3][3], const T Q2[3][3], T trQ2,
+__host__ __device__ __forceinline__ T free_energy(const Coef<T> &c, const T Q[3][3], const T Q2[3][3], T trQ2,
                                          const T div[3], const T M[3][3])
 {
     T trQ3 = T(0);
@@ -106,61 +106,131 @@ __device__ __forceinline__ T free_energy(const Coef<T> &c, const T Q[3][3], cons
     return T(0.5) * c.a * trQ2 - c.bg * trQ3 / T(3) + T(0.25) * c.bg * trQ2 * trQ2 + T(0.5) * c.K * (dd + mm);
 }
 
+// Upper triangle (xx, xy, xz, yy, yz, zz) of Q^2 for symmetric Q, and its
+// trace.
+template <typename T>
+__host__ __device__ __forceinline__ void square_sym(const T q[5], T qzz, T s[6], T &tr)
+{
+    s[0] = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+    s[1] = q[0] * q[1] + q[1] * q[3] + q[2] * q[4];
+    s[2] = q[0] * q[2] + q[1] * q[4] + q[2] * qzz;
+    s[3] = q[1] * q[1] + q[3] * q[3] + q[4] * q[4];
+    s[4] = q[1] * q[2] + q[3] * q[4] + q[4] * qzz;
+    s[5] = q[2] * q[2] + q[4] * q[4] + qzz * qzz;
+    tr = s[0] + s[3] + s[5];
+}
+
+// Symmetric part (stored components) of CQ + (CQ)^T, the curl term of H, from
+// the derivatives of the stored components (d_g Q_zz = -(d_g Q_xx + d_g Q_yy)).
+template <typename T>
+__host__ __device__ __forceinline__ void curl_sym(const T d[3][5], T C[5])
+{
+    const T dzz0 = -(d[0][0] + d[0][3]), dzz1 = -(d[1][0] + d[1][3]);
+    C[0] = T(2) * (d[1][2] - d[2][1]);                    // 2 (dy Q_zx - dz Q_yx)
+    C[1] = (d[1][4] - d[2][3]) + (d[2][0] - d[0][2]);     // CQ_xy + CQ_yx
+    C[2] = (dzz1 - d[2][4]) + (d[0][1] - d[1][0]);        // CQ_xz + CQ_zx
+    C[3] = T(2) * (d[2][1] - d[0][4]);                    // 2 (dz Q_xy - dx Q_zy)
+    C[4] = (d[2][2] - dzz0) + (d[0][3] - d[1][1]);        // CQ_yz + CQ_zy
+}
+
+// Curl (CQ)_ab = eps_agd d_g Q_db from the derivatives of the stored
+// components (the full, non-symmetric tensor).
+template <typename T>
+__host__ __device__ __forceinline__ void curl5(const T d[3][5], const T dzz[3], T CQ[3][3])
+{
+    CQ[0][0] = d[1][2] - d[2][1];  // dy Q_zx - dz Q_yx
+    CQ[0][1] = d[1][4] - d[2][3];  // dy Q_zy - dz Q_yy
+    CQ[0][2] = dzz[1] - d[2][4];   // dy Q_zz - dz Q_yz
+    CQ[1][0] = d[2][0] - d[0][2];  // dz Q_xx - dx Q_zx
+    CQ[1][1] = d[2][1] - d[0][4];  // dz Q_xy - dx Q_zy
+    CQ[1][2] = d[2][2] - dzz[0];   // dz Q_xz - dx Q_zz
+    CQ[2][0] = d[0][1] - d[1][0];  // dx Q_yx - dy Q_xx
+    CQ[2][1] = d[0][3] - d[1][1];  // dx Q_yy - dy Q_xy
+    CQ[2][2] = d[0][4] - d[1][2];  // dx Q_yz - dy Q_xz
+}
+
 // Chemical stress (Eqs. (6)-(8), the rho T part of the pressure left to the
 // lattice): Pi_ab = f d_ab + sigma^xi_ab - G_ab + tau_ab with
 //   sigma^xi = 2 xi (Q + I/3)(Q:H) - xi (HQ + QH + 2H/3),
 //   tau      = QH - HQ,
 //   G_ab     = d_a Q_gn Phi_gnb,  Phi_gnb = K [d_nb (div Q)_g + eps_lbg M_ln],
-// i.e. G_ab = K [ d_a Q_gb (div Q)_g + eps_bgl d_a Q_gn M_ln ].
-// Also returns f and H (five components).
+// i.e. G_ab = K [ d_a Q_gb (div Q)_g + eps_bgl d_a Q_gn M_ln ], M = CQ + 2 q0 Q.
+// Also returns f (Eq. (1) plus K/2 (d_b Q_ab)^2) and H (five components).
+// sigma^xi is symmetric and tau antisymmetric (QH = (HQ)^T for symmetric H
+// and Q), so each is formed once per pair of entries.
 template <typename T>
-__device__ __forceinline__ void site_stress(const Coef<T> &c, const T q[5], const T d[3][5],
-                                            const T lap[5], T Pi[3][3], T &fdens, T H5[5])
+__host__ __device__ __forceinline__ void site_stress(const Coef<T> &c, const T q[5], const T d[3][5],
+                                                     const T lap[5], T Pi[3][3], T &fdens, T H5[5])
 {
-    T Q[3][3], dQ[3][3][3], CQ[3][3], Q2[3][3], trQ2;
-    full3(q, Q);
-    full_grad(d, dQ);
-    curl(dQ, CQ);
-    molecular_field(c, Q, CQ, lap, H5, Q2, trQ2);
-    T H[3][3];
-    full3(H5, H);
-
-    T M[3][3], div[3];
+    const T third = T(1) / T(3);
+    const T qzz = -q[0] - q[3];
+    const T dzz[3] = {-(d[0][0] + d[0][3]), -(d[1][0] + d[1][3]), -(d[2][0] + d[2][3])};
+    T s[6], trQ2, CQ[3][3];
+    square_sym(q, qzz, s, trQ2);
+    curl5(d, dzz, CQ);
+    {
+        const T lin = -(c.a + c.bg * trQ2 + c.Kq0sq4);
+        const T diag = c.bg * trQ2 * third;
+        const T C[5] = {T(2) * CQ[0][0], CQ[0][1] + CQ[1][0], CQ[0][2] + CQ[2][0], T(2) * CQ[1][1],
+                        CQ[1][2] + CQ[2][1]};
+        const int k2s[5] = {0, 1, 2, 3, 4};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+        for (int k = 0; k < 5; ++k) {
+            T v = lin * q[k] + c.bg * s[k2s[k]] + c.K * lap[k] - c.Kq0x2 * C[k];
+            if (k == 0 || k == 3) v -= diag;
+            H5[k] = v;
+        }
+    }
+    const T Q[3][3] = {{q[0], q[1], q[2]}, {q[1], q[3], q[4]}, {q[2], q[4], qzz}};
+    const T hzz = -H5[0] - H5[3];
+    const T H[3][3] = {{H5[0], H5[1], H5[2]}, {H5[1], H5[3], H5[4]}, {H5[2], H5[4], hzz}};
+    T M[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) M[a][b] = CQ[a][b] + c.q0x2 * Q[a][b];
-        div[a] = dQ[0][a][0] + dQ[1][a][1] + dQ[2][a][2];
+    const T div[3] = {d[0][0] + d[1][1] + d[2][2], d[0][1] + d[1][3] + d[2][4], d[0][2] + d[1][4] + dzz[2]};
+    {
+        const T trQ3 = s[0] * q[0] + s[3] * q[3] + s[5] * qzz + T(2) * (s[1] * q[1] + s[2] * q[2] + s[4] * q[4]);
+        T mm = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) mm += M[a][b] * M[a][b];
+        const T dd = div[0] * div[0] + div[1] * div[1] + div[2] * div[2];
+        fdens = T(0.5) * c.a * trQ2 - c.bg * trQ3 * third + T(0.25) * c.bg * trQ2 * trQ2 + T(0.5) * c.K * (dd + mm);
     }
-    fdens = free_energy(c, Q, Q2, trQ2, div, M);
-
     T HQ[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) HQ[a][b] = H[a][0] * Q[0][b] + H[a][1] * Q[1][b] + H[a][2] * Q[2][b];
-    T QdH = T(0);
+    const T QdH = q[0] * H5[0] + q[3] * H5[3] + qzz * hzz + T(2) * (q[1] * H5[1] + q[2] * H5[2] + q[4] * H5[4]);
+    const T xq = T(2) * c.xi * QdH;
+    T sig[3][3], tau[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) QdH += Q[a][b] * H[a][b];
-
-    const T third = T(1) / T(3);
+        for (int b = a; b < 3; ++b) {
+            const T v = xq * (Q[a][b] + (a == b ? third : T(0))) -
+                        c.xi * (HQ[a][b] + HQ[b][a] + T(2) * third * H[a][b]);
+            sig[a][b] = v;
+            sig[b][a] = v;
+            const T w = HQ[b][a] - HQ[a][b];
+            tau[a][b] = w;
+            tau[b][a] = -w;
+        }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+        const T P[3][3] = {{d[a][0], d[a][1], d[a][2]}, {d[a][1], d[a][3], d[a][4]}, {d[a][2], d[a][4], dzz[a]}};
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             // G_ab; the eps_bgl M-contraction written out per column b
-            T g = dQ[a][0][b] * div[0] + dQ[a][1][b] * div[1] + dQ[a][2][b] * div[2];
+            T g = P[0][b] * div[0] + P[1][b] * div[1] + P[2][b] * div[2];
             const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
 #pragma unroll
-            for (int n = 0; n < 3; ++n) g += dQ[a][b1][n] * M[b2][n] - dQ[a][b2][n] * M[b1][n];
-            g *= c.K;
-            // HQ^T = QH for symmetric H and Q
-            T sxi = T(2) * c.xi * (Q[a][b] + (a == b ? third : T(0))) * QdH
-                  - c.xi * (HQ[a][b] + HQ[b][a] + T(2) * third * H[a][b]);
-            T tau = HQ[b][a] - HQ[a][b];
-            Pi[a][b] = (a == b ? fdens : T(0)) + sxi - g + tau;
+            for (int n = 0; n < 3; ++n) g += P[b1][n] * M[b2][n] - P[b2][n] * M[b1][n];
+            Pi[a][b] = (a == b ? fdens : T(0)) + sig[a][b] - c.K * g + tau[a][b];
         }
     }
 }
@@ -173,7 +243,7 @@ __device__ __forceinline__ void site_stress(const Coef<T> &c, const T q[5], cons
 // gradient and free-energy part of the stress by the identity of Eq. (21).
 // The body force is b_a = d_b tau_ab + h_a.  Also returns f.
 template <typename T>
-__device__ __forceinline__ void site_split(const Coef<T> &c, const T q[5], const T d[3][5], const T lap[5],
+__host__ __device__ __forceinline__ void site_split(const Coef<T> &c, const T q[5], const T d[3][5], const T lap[5],
                                            T sig[6], T tau3[3], T h[3], T &fdens)
 {
     T Q[3][3], dQ[3][3][3], CQ[3][3], Q2[3][3], trQ2, H5[5];
@@ -228,61 +298,70 @@ __device__ __forceinline__ void site_split(const Coef<T> &c, const T q[5], const
     }
 }
 
+// Molecular field from the stored components (the same H as molecular_field,
+// written for the five components).
+template <typename T>
+__host__ __device__ __forceinline__ void molecular_field5(const Coef<T> &c, const T q[5], const T d[3][5],
+                                                          const T lap[5], T H[5])
+{
+    const T qzz = -q[0] - q[3];
+    T s[6], trQ2, C[5];
+    square_sym(q, qzz, s, trQ2);
+    curl_sym(d, C);
+    const T third = T(1) / T(3);
+    const T lin = -(c.a + c.bg * trQ2 + c.Kq0sq4);
+    const T diag = c.bg * trQ2 * third;
+    const int k2s[5] = {0, 1, 2, 3, 4};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        T v = lin * q[k] + c.bg * s[k2s[k]] + c.K * lap[k] - c.Kq0x2 * C[k];
+        if (k == 0 || k == 3) v -= diag;
+        H[k] = v;
+    }
+}
+
 // Right-hand side of the Q equation (Eqs. (2)-(4)) projected on symmetric
 // traceless tensors:
 //   R = P_T[ -u.grad Q + S(W,Q) + Gamma H ],
-//   S = xi (D A + A D) + (w A - A w) - 2 xi A tr(Q W),  A = Q + I/3,
+//   S = (xi D + w)(Q + I/3) + (Q + I/3)(xi D - w) - 2 xi (Q + I/3) tr(QW),
 //   D = (W + W^T)/2, w = (W - W^T)/2, W_ab = d_b u_a.
+// Written with M = xi D + w: the first two terms are M Q + (M Q)^T + (2 xi/3) D
+// (Q symmetric, so Q M^T = (M Q)^T), tr(QW) = Q:W, and tr S = (2 xi/3) div u
+// is the only trace in the bracket (u.grad Q and H are traceless), so the
+// projection removes (2 xi/9) div u from the diagonal.
 template <typename T>
-__device__ __forceinline__ void site_rhs(const Coef<T> &c, const T q[5], const T d[3][5], const T lap[5],
-                                         const T u[3], const T W[3][3], T R[5])
+__host__ __device__ __forceinline__ void site_rhs(const Coef<T> &c, const T q[5], const T d[3][5], const T lap[5],
+                                                  const T u[3], const T W[3][3], T R[5])
 {
-    T Q[3][3], dQ[3][3][3], CQ[3][3], Q2[3][3], trQ2, H5[5];
-    full3(q, Q);
-    full_grad(d, dQ);
-    curl(dQ, CQ);
-    molecular_field(c, Q, CQ, lap, H5, Q2, trQ2);
-
-    T D[3][3], w[3][3], A[3][3];
+    T H[5];
+    molecular_field5(c, q, d, lap, H);
+    const T qzz = -q[0] - q[3];
+    const T Q[3][3] = {{q[0], q[1], q[2]}, {q[1], q[3], q[4]}, {q[2], q[4], qzz}};
+    const T hp = T(0.5) * (c.xi + T(1)), hm = T(0.5) * (c.xi - T(1));
+    T M[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) M[a][b] = a == b ? c.xi * W[a][a] : hp * W[a][b] + hm * W[b][a];
+    // M Q, the entries the five stored components of S need
+    T P[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) P[a][b] = M[a][0] * Q[0][b] + M[a][1] * Q[1][b] + M[a][2] * Q[2][b];
+    const T s01 = W[0][1] + W[1][0], s02 = W[0][2] + W[2][0], s12 = W[1][2] + W[2][1];
+    const T QW = q[0] * W[0][0] + q[3] * W[1][1] + qzz * W[2][2] + q[1] * s01 + q[2] * s02 + q[4] * s12;
     const T third = T(1) / T(3);
+    const T t = T(-2) * c.xi * QW;
+    const T x3 = c.xi * third;
+    const T dtr = T(2) * x3 * (W[0][0] + W[1][1] + W[2][2]) * third;  // (2 xi/9) div u
+    const T S[5] = {T(2) * P[0][0] + T(2) * x3 * W[0][0] + t * (q[0] + third) - dtr,
+                    (P[0][1] + P[1][0]) + x3 * s01 + t * q[1],
+                    (P[0][2] + P[2][0]) + x3 * s02 + t * q[2],
+                    T(2) * P[1][1] + T(2) * x3 * W[1][1] + t * (q[3] + third) - dtr,
+                    (P[1][2] + P[2][1]) + x3 * s12 + t * q[4]};
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            D[a][b] = T(0.5) * (W[a][b] + W[b][a]);
-            w[a][b] = T(0.5) * (W[a][b] - W[b][a]);
-            A[a][b] = Q[a][b] + (a == b ? third : T(0));
-        }
-    T trQW = T(0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) trQW += Q[a][b] * D[a][b];
-
-    // upper triangle of X = -u.grad Q + S + Gamma H (X is symmetric)
-    const int ia[6] = {0, 0, 0, 1, 1, 2};
-    const int ib[6] = {0, 1, 2, 1, 2, 2};
-    T X[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int a = ia[k], b = ib[k];
-        T da = T(0), wa = T(0);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            da += D[a][m] * A[m][b] + A[a][m] * D[m][b];
-            wa += w[a][m] * A[m][b] - A[a][m] * w[m][b];
-        }
-        T S = c.xi * da + wa - T(2) * c.xi * A[a][b] * trQW;
-        T adv = u[0] * dQ[0][a][b] + u[1] * dQ[1][a][b] + u[2] * dQ[2][a][b];
-        T h = (k < 5) ? H5[k] : -H5[0] - H5[3];
-        X[k] = -adv + S + c.Gamma * h;
-    }
-    const T tr3 = (X[0] + X[3] + X[5]) * third;
-    R[0] = X[0] - tr3;
-    R[1] = X[1];
-    R[2] = X[2];
-    R[3] = X[3] - tr3;
-    R[4] = X[4];
+    for (int k = 0; k < 5; ++k) R[k] = -(u[0] * d[0][k] + u[1] * d[1][k] + u[2] * d[2][k]) + S[k] + c.Gamma * H[k];
 }
 
 // ---------------------------------------------------------------- D3Q19
@@ -294,7 +373,7 @@ constexpr int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1
 constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
 template <typename T>
-__device__ __forceinline__ T lb_weight(int i)
+__host__ __device__ __forceinline__ T lb_weight(int i)
 {
     return i == 0 ? T(1) / T(3) : (i <= 6 ? T(1) / T(18) : T(1) / T(36));
 }
@@ -303,7 +382,7 @@ __device__ __forceinline__ T lb_weight(int i)
 // opposite velocities are differenced first so the momentum keeps the
 // precision of the small dynamical part.
 template <typename T>
-__device__ __forceinline__ void lb_moments(const T g[19], T &drho, T j[3])
+__host__ __device__ __forceinline__ void lb_moments(const T g[19], T &drho, T j[3])
 {
     T s = T(0);
 #pragma unroll
@@ -320,7 +399,7 @@ __device__ __forceinline__ void lb_moments(const T g[19], T &drho, T j[3])
 //   g_i^eq = w_i drho + w_i rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2).
 // g is updated in place; u and rho are returned.
 template <typename T>
-__device__ __forceinline__ void lb_collide(const Coef<T> &c, T g[19], const T F[3], T u[3], T &rho)
+__host__ __device__ __forceinline__ void lb_collide(const Coef<T> &c, T g[19], const T F[3], T u[3], T &rho)
 {
     T drho, j[3];
     lb_moments(g, drho, j);
@@ -348,7 +427,7 @@ __device__ __forceinline__ void lb_collide(const Coef<T> &c, T g[19], const T F[
 //   g_i^eq += -(9/2) w_i [sig:e_i e_i - tr(sig)/3],
 // a term with zero mass and momentum.
 template <typename T>
-__device__ __forceinline__ void lb_collide_split(const Coef<T> &c, T g[19], const T F[3], const T sig[6], T u[3],
+__host__ __device__ __forceinline__ void lb_collide_split(const Coef<T> &c, T g[19], const T F[3], const T sig[6], T u[3],
                                                  T &rho)
 {
     T drho, j[3];
@@ -390,7 +469,7 @@ constexpr int DZ15[15] = {0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1};
 // D = (rho/2, rho/16); E_2 = -(sig - tr(sig)/3 I)/16, E_1 = 8 E_2 (faces,
 // corners).  sig: upper triangle xx, xy, xz, yy, yz, zz (null: no stress).
 template <typename T>
-__device__ __forceinline__ T lb15_eq(int i, T rho0, T rho, const T u[3], T uu, const T *sig)
+__host__ __device__ __forceinline__ T lb15_eq(int i, T rho0, T rho, const T u[3], T uu, const T *sig)
 {
     const T ex = T(DX15[i]), ey = T(DY15[i]), ez = T(DZ15[i]);
     const T eu = ex * u[0] + ey * u[1] + ez * u[2];
@@ -414,7 +493,7 @@ __device__ __forceinline__ T lb15_eq(int i, T rho0, T rho, const T u[3], T uu, c
 
 // Forcing term p_i = P_s b.e with P_1 = 1/3, P_2 = 1/24.
 template <typename T>
-__device__ __forceinline__ T lb15_force(int i, const T b[3])
+__host__ __device__ __forceinline__ T lb15_force(int i, const T b[3])
 {
     if (i == 0) return T(0);
     const T eb = T(DX15[i]) * b[0] + T(DY15[i]) * b[1] + T(DZ15[i]) * b[2];
@@ -424,7 +503,7 @@ __device__ __forceinline__ T lb15_force(int i, const T b[3])
 // Collision operator of Eq. (16) on D3Q15 at one site: local moments
 // (rho u = sum f e, Eq. (14)), C_i = -(g_i - g_i^eq)/tau + p_i.
 template <typename T>
-__device__ __forceinline__ void lb15_collide(const Coef<T> &c, const T g[15], const T *sig, const T b[3], T C[15],
+__host__ __device__ __forceinline__ void lb15_collide(const Coef<T> &c, const T g[15], const T *sig, const T b[3], T C[15],
                                              T u[3], T &rho)
 {
     T drho = T(0), j[3] = {T(0), T(0), T(0)};
@@ -445,7 +524,7 @@ __device__ __forceinline__ void lb15_collide(const Coef<T> &c, const T g[15], co
 
 // Equilibrium deviation for initialisation.
 template <typename T>
-__device__ __forceinline__ T lb_geq(const Coef<T> &c, int i, T rho, const T u[3])
+__host__ __device__ __forceinline__ T lb_geq(const Coef<T> &c, int i, T rho, const T u[3])
 {
     const T w = lb_weight<T>(i);
     const T eu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];

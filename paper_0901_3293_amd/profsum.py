@@ -7,6 +7,10 @@ usage: python -m paper_0901_3293_amd.profsum TRACE_DB [FETCH_DB WRITE_DB]
        --copy-bytes 536870912 --alg k_lb=VALUES ... --esz 4 --sites N
        [--mfma]   (convolution kernels: padded MFMA flops per dispatch from the
                    channel counts in the kernel name, TFLOP/s against 2.5 PFLOP/s)
+       [--valu DB] (a pass of SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_WAVES,
+                   GRBM_GUI_ACTIVE: VALU instructions per site and the time
+                   their issue takes at the chip's vector rate against the
+                   kernel's duration)
 With the trace alone: calls, average and total duration per kernel, and the
 algorithmic rate where --alg gives the kernel's values per site.
 """
@@ -51,16 +55,49 @@ COPY = "__amd_rocclr_copyBuffer"
 
 
 def counter(db, cname):
-    """KiB per dispatch, averaged per kernel.  For the runtime's copy kernel
+    """Value per dispatch, averaged per kernel (KiB for FETCH_SIZE and
+    WRITE_SIZE).  A counter read from several hardware instances (one row
+    per shader engine or XCD) is reduced per dispatch first: summed, or the
+    maximum for GRBM_ (clock-type) counters.  For the runtime's copy kernel
     only the dispatches of the calibration copy (the largest ones) count."""
     con = sqlite3.connect(db)
+    per = defaultdict(list)
+    for name, disp, v in con.execute(
+            "select name, dispatch_id, counter_value from pmc_events where counter_name = ?", (cname,)):
+        per[(short(name), disp)].append(v)
+    red = max if cname.startswith("GRBM_") else sum
     d = defaultdict(list)
-    for name, v in con.execute("select name, counter_value from pmc_events where counter_name = ?", (cname,)):
-        d[short(name)].append(v)
+    for (k, _), vals in per.items():
+        d[k].append(red(vals))
     if COPY in d:
         top = max(d[COPY])
         d[COPY] = [v for v in d[COPY] if v > 0.5 * top]
     return {k: sum(v) / len(v) for k, v in d.items()}
+
+
+# Vector issue rate of the chip: 256 CUs x 4 SIMDs, one 64-lane VALU
+# instruction per SIMD every 4 cycles (16 lanes per cycle), at 2.4 GHz.
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+
+
+def valu_table(t, db, sites):
+    """Per kernel: VALU instructions per site (wave instructions x 64 lanes /
+    sites), the issue time of those instructions at the chip's full vector
+    rate (the ALU bound of the kernel), its fraction of the measured
+    duration, and the waves and VALU-active cycles the counters saw."""
+    cs = {c: counter(db, c) for c in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES", "GRBM_GUI_ACTIVE")}
+    print(f"{'kernel':12s} {'avg_us':>8s} {'waves':>9s} {'valu/site':>9s} {'alu_us':>7s} {'alu/dur':>7s} "
+          f"{'gui_MHz':>8s}")
+    for k, (n, us) in sorted(t.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+        if k == COPY or k not in cs["SQ_INSTS_VALU"]:
+            continue
+        wi = cs["SQ_INSTS_VALU"][k]
+        per_site = wi * 64 / sites
+        alu_us = wi * 4 / SIMDS / CLOCK_HZ * 1e6
+        gui = cs["GRBM_GUI_ACTIVE"].get(k, float("nan"))
+        print(f"{k:12s} {us:8.2f} {cs['SQ_WAVES'].get(k, float('nan')):9.0f} {per_site:9.1f} {alu_us:7.2f} "
+              f"{alu_us / us:7.2f} {gui / us:8.0f}")
 
 
 def main():
@@ -75,9 +112,16 @@ def main():
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default="")
     ap.add_argument("--mfma", action="store_true")
+    ap.add_argument("--valu", default=None, help="database of a VALU counter pass")
     a = ap.parse_args()
     alg = {k: float(v) for k, v in (x.split("=") for x in a.alg)}
     t = trace(a.trace_db)
+    if a.valu:
+        print(f"# {a.title}")
+        if a.command:
+            print(f"command: {a.command}")
+        valu_table(t, a.valu, a.sites)
+        return
     if a.fetch_db is None or a.write_db is None:
         print(f"# {a.title}")
         print(f"{'kernel':16s} {'calls':>6s} {'avg_us':>9s} {'total_ms':>9s} {'alg_MB':>8s} {'alg_GB/s':>9s}")

@@ -306,10 +306,41 @@ def test_network_teacher_forced(H):
             dzp = dx.numpy() * (A[l] > 0)
             flips[f"dz{l - 1}"] = handed_on(DZ[l - 1], dzp, np.abs(dzp).max(), f"dz {l - 1}")
     say("entries rounded to the other bfloat16 neighbour (of", A[0].size, "per 18-32 channels):", flips)
-    # free-running: the oracle's own activations and gradient
+    # free-running: the oracle's own activations and gradient.  The two sides
+    # round the counted entries to different neighbours; the bar for the
+    # output is three times what the same number of one-ulp changes at random
+    # entries of the oracle's activations does to its output (at least 1e-3).
     acts_o, z_o = cnn.forward(p0, xs)
     ef = rel(yg, z_o.numpy())
     gref = cnn.backward(p0, acts_o, z_o, t).numpy()
     eg = rel(g, gref)
-    say(f"free-running: output rel err {ef:.2e}, gradient rel err {eg:.2e}")
-    assert ef <= 1e-3 and eg <= 1e-3
+    effect = flip_effect(p0, acts_o, z_o.numpy(), [flips[f"a{l}"] for l in (1, 2, 3)], rng)
+    bar = max(1e-3, 3 * effect)
+    say(f"free-running: output rel err {ef:.2e} (bar {bar:.2e}: one-ulp changes at as many entries move it "
+        f"by {effect:.2e}), gradient rel err {eg:.2e}")
+    assert ef <= bar and eg <= 1e-3
+
+
+def flip_effect(params, acts, z, counts, rng, trials=4):
+    """Largest relative change of the network output, over a few trials,
+    when counts[l - 1] random non-zero entries of the oracle's bfloat16
+    activation l (l = 1, 2, 3) move to the next bfloat16 value and the layers
+    after it are evaluated again with the oracle's rounding."""
+    layers = cnn.unflatten(params)
+    worst = 0.0
+    for _ in range(trials):
+        h = None
+        for l in range(4):
+            a = (acts[l] if h is None else h).clone()
+            if l >= 1 and counts[l - 1]:
+                flat = a.reshape(-1)
+                nz = torch.nonzero(flat).reshape(-1).numpy()
+                idx = rng.choice(nz, size=min(counts[l - 1], nz.size), replace=False)
+                v = flat[idx]
+                up = torch.nextafter(v.to(torch.bfloat16), torch.full_like(v.to(torch.bfloat16), float("inf")))
+                flat[idx] = up.to(torch.float64)
+            W, b = layers[l]
+            zz = cnn.conv(a, cnn.bf16(W), b)
+            h = cnn.bf16(torch.relu(zz)) if l < 3 else zz
+        worst = max(worst, rel(h.numpy(), z))
+    return worst

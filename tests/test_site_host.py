@@ -1,0 +1,65 @@
+"""The per-site physics of the HIP path (site.h: molecular field, free
+energy, chemical stress, right-hand side of the Q equation), built for the
+host and evaluated at every site of small periodic lattices with the
+kernels' own stencils (tests/hostcheck/site_host.cpp), against the FP64
+oracle's lattice routines: H, f, Pi and R within 1e-13 relative per field.
+This checks the GPU arithmetic on the CPU, before any kernel runs."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_0901_3293_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+Q5_TO_9 = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2)]
+
+
+@pytest.fixture(scope="module")
+def site_host(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("site") / "site_host")
+    subprocess.check_call([HIPCC, "-O2", "-std=c++17", "-I" + os.path.join(ROOT, "include"),
+                           os.path.join(HERE, "hostcheck", "site_host.cpp"), "-o", exe],
+                          stderr=subprocess.DEVNULL)
+    return exe
+
+
+def evaluate(exe, tmp, p, Q5, u3):
+    nz, ny, nx = Q5.shape[1:]
+    N = nx * ny * nz
+    hdr = np.array([nx, ny, nz, p.A0, p.gamma, p.K, p.q0, p.Gamma, p.xi, p.tau, p.rho0], dtype=np.float64)
+    fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
+    np.concatenate([hdr, Q5.ravel(), u3.ravel()]).tofile(fin)
+    subprocess.check_call([exe, fin, fout])
+    out = np.fromfile(fout, dtype=np.float64).reshape(20, nz, ny, nx)
+    assert out.size == 20 * N
+    return out[0:5], out[5], out[6:15], out[15:20]
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("shape,seed", [((9, 7, 6), 1), ((5, 11, 8), 2), ((16, 4, 5), 3)])
+@pytest.mark.parametrize("q0,K,xi", [(0.35, 0.02, 0.7), (0.0, 0.01, 0.5), (-0.6, 0.03, 1.1)])
+def test_site_physics_matches_oracle(orc, site_host, tmp_path, shape, seed, q0, K, xi):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    p = I.PhysParams(K=K, q0=q0, gamma=3.1, xi=xi, Gamma=0.4)
+    Q5 = I.smooth_field(shape, amp=0.25, seed=seed) + rng.uniform(-0.05, 0.05, size=(5, nz, ny, nx))
+    u3 = rng.uniform(-1e-2, 1e-2, size=(3, nz, ny, nx))
+    H5, f, Pi9, R5 = evaluate(site_host, str(tmp_path), p, Q5, u3)
+    op = orc.params(**p.as_dict())
+    Q9 = orc.q5_to_q9(Q5)
+    Hr, fr, Pir = orc.chem(op, Q9)
+    Rr = orc.rhs(op, Q9, u3)
+    Hr5 = np.stack([Hr[3 * a + b] for a, b in Q5_TO_9])
+    Rr5 = np.stack([Rr[3 * a + b] for a, b in Q5_TO_9])
+    errs = {"H": rel(H5, Hr5), "f": rel(f, fr), "Pi": rel(Pi9, Pir), "R": rel(R5, Rr5)}
+    assert max(errs.values()) <= 1e-13, errs
