@@ -487,8 +487,12 @@ def run_surrogate_growth(n=96, kappa=1.0, tau_ldg=0.0, target=44, every=512, max
         del sv
     for o in preds.values():
         o.close()
+    # best predictor: the fastest to the target among those whose Q error at
+    # the plain run's crossing stays within twice the per-cycle residual
+    # threshold (the unchecked jumps of a cycle add their errors to the state)
+    q_bar = 2 * S.THRESHOLD
     ok = {k_: v for k_, v in res.items() if k_ != "plain" and v["speedup"] is not None
-          and v["q_error_at_plain_crossing"] is not None and v["q_error_at_plain_crossing"] <= S.THRESHOLD}
+          and v["q_error_at_plain_crossing"] is not None and v["q_error_at_plain_crossing"] <= q_bar}
     best = max(ok, key=lambda k_: ok[k_]["speedup"]) if ok else None
     net_r = res["network"]
     return {
@@ -497,6 +501,7 @@ def run_surrogate_growth(n=96, kappa=1.0, tau_ldg=0.0, target=44, every=512, max
                     f"read-out), read every {every} steps; k = {k}, M = {M}, threshold {S.THRESHOLD:g}, "
                     f"refresh {S.REFRESH:g}",
         "target_planes": target,
+        "q_error_bar": q_bar,
         **res,
         "best_predictor": best,
         "learned_gain": (best == "network"),

@@ -6,8 +6,8 @@
 - The fallback contract: threshold 0 reproduces the plain run bit for bit;
   an infinite threshold never falls back.
 - A full-size (96^3) convolution layer at sampled sites against direct sums.
-- What the trained network gains over the method without it (the zero
-  increment) on a held-out trajectory."""
+- What the trained network gains over the method without it (the driver
+  with the extrapolation alone) on held-out pairs of a growing domain."""
 import math
 
 import numpy as np
@@ -201,26 +201,29 @@ def test_full_size_layer_at_sampled_sites(H):
     assert e <= 1e-5
 
 
-def test_trained_network_gains_over_zero_increment(H, S):
-    """Train on two 32^3 O2 runs (the surrogate's own kernels), evaluate the
-    predicted 8-step increment on a held-out run.  The method without the
-    network leaves Q unchanged over a jump (relative increment error 1); the
-    trained network must cut that at least tenfold, and stay within 1.5x of
-    the linear extrapolation it corrects."""
-    say("case: trained surrogate vs zero increment")
+def test_trained_network_gains_over_extrapolation(H, S):
+    """What the trained network gains over the method without it, on held-out
+    pairs of a growing domain: train (the surrogate's own kernels) on pairs
+    from three growth runs of a 32^3 box (an O2 slab of 16 planes in a
+    cholesteric x-helix, kappa 1, tau 0, noise 1e-3 with seeds 1, 3, 4),
+    evaluate the predicted 8-step increment on a fourth run (seed 2).  The
+    driver without the network jumps by the linear extrapolation d1 (the
+    network's base, beta = 0); the network must cut its median increment
+    error by at least a quarter.  Quadratic extrapolation is reported beside
+    it."""
+    say("case: trained surrogate vs extrapolation on held-out growth pairs")
     n, P = 32, 24
     shape = (n, n, n)
     net = H.Net(shape)
-    pairs = S.allocate_pairs(3 * P, n ** 3)
-    for r, seed in enumerate((0, 1, 2)):
-        s = S.new_solver(S.o2_run(n, seed=seed))
-        S.record_pairs(net, s, pairs, r * P, P, spacing=120, burn_in=300, tag=f"o2-{seed}")
-    train_idx, test_idx = list(range(2 * P)), list(range(2 * P, 3 * P))
+    pairs = S.allocate_pairs(4 * P, n ** 3)
+    for r, seed in enumerate((1, 3, 4, 2)):
+        s = S.new_solver(S.growth_run(n, cell=16, seed_depth=16, kappa=1.0, tau_ldg=0.0, noise_amp=1e-3, seed=seed))
+        S.record_pairs(net, s, pairs, r * P, P, spacing=96, burn_in=500, tag=f"growth-{seed}")
+    train_idx, test_idx = list(range(3 * P)), list(range(3 * P, 4 * P))
     S.fit_norm(net, pairs, 0.0, index=train_idx)
     net.set_params(inputs.cnn_params(seed=0))
-    log = S.train(net, pairs, 400, lr=2e-3, index=train_idx, log_every=100)
+    log = S.train(net, pairs, 600, lr=1e-3, index=train_idx, log_every=150)
     ev = S.evaluate(net, pairs, test_idx)
-    say("train s", log.seconds, "net median", np.median(ev["net"]), "linear", np.median(ev["linear"]),
-        "quadratic", np.median(ev["quadratic"]))
-    assert np.median(ev["net"]) <= 0.1
-    assert np.median(ev["net"]) <= 1.5 * np.median(ev["linear"])
+    med = {k: float(np.median(v)) for k, v in ev.items()}
+    say("train s", log.seconds, "held-out median increment error:", med)
+    assert med["net"] <= 0.75 * med["linear"], med
