@@ -180,8 +180,9 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
 
 
 def run_batched(steps, graph_steps=50, chunk=0, xcd_local=True, form=None, group=0):
-    """96 uneven periodic boxes (sizes 24/32/48/64, per-box kappa and tau) in
-    one persistent launch per graph replay, FP32.  Aggregate MLUPS.  With
+    """96 uneven periodic boxes (sizes 24/32/48/64, per-box kappa and tau),
+    FP32, 50-step graph replays in the autotuned launch form (or `form` with
+    cache groups of `group` sites).  Aggregate MLUPS.  With
     `chunk` > 0 the autotuner is skipped and every box size uses that chunk
     (profiling runs, where every dispatch must be `graph_steps` steps)."""
     import torch
@@ -667,9 +668,9 @@ def main():
     ap.add_argument("--batch-chunk", type=int, default=0,
                     help="fixed chunk for every box size instead of the autotuner (profiling runs)")
     ap.add_argument("--batch-launch", choices=["persistent", "phases"], default=None,
-                    help="batched launch form (default: the autotuner's pick; with --batch-chunk: persistent)")
+                    help="batched launch form (default: the autotuner's pick; with --batch-chunk: the library default, phases)")
     ap.add_argument("--batch-group", type=int, default=0,
-                    help="cache-group budget in sites of the phase launch form (0: the autotuner's)")
+                    help="cache-group budget in sites (persistent form: group_sites / 8 per XCD group; 0: the autotuner's)")
     ap.add_argument("--batch-device-fences", action="store_true",
                     help="batched run with the fixed work mapping and device-scope barrier fences")
     ap.add_argument("--slab-steps", type=int, default=20000,

@@ -278,13 +278,16 @@ const char *hlb_kernel_name(int k);
 /* ------------------------------------------------------------------------
  * Batched form: n periodic boxes of uneven size, each with its own
  * parameters (e.g. a scan of chirality kappa and reduced temperature tau,
- * Sec. 2.1, Eqs. (9)-(10)), advanced by one persistent kernel launch per
- * call.  The step of every box is the per-site schedule above (same device
- * code), so a box gives the same result as a single context on it.  Each box
- * is cut into work items of `chunk` sites; items of all boxes are spread over
- * the co-resident blocks and the four phases of a step are separated by grid
- * barriers whose waits are bounded (a stall ends the launch with an error,
- * reported by the next hlb_batch_sync / readout as HLB_ERR_HIP).
+ * Sec. 2.1, Eqs. (9)-(10)), advanced together: four ordinary kernels per
+ * step over all boxes, or one persistent kernel per call
+ * (hlb_batch_set_launch).  The step of every box is the per-site schedule
+ * above (same device code), so a box gives the same result as a single
+ * context on it.  Each box is cut into work items of `chunk` sites.  In the
+ * persistent form the items of a group of boxes are spread over the
+ * co-resident blocks of that group and the four phases of a step are
+ * separated by barriers among them whose waits are bounded (a stall ends the
+ * launch with an error, reported by the next hlb_batch_sync / readout as
+ * HLB_ERR_HIP).
  * ------------------------------------------------------------------------ */
 typedef struct hlb_batch hlb_batch;
 
@@ -302,26 +305,30 @@ int hlb_batch_set_fields(hlb_batch *b, int i, const double *Q5, const double *u3
 /* Sites per work item for boxes of `sites_of_box` sites (multiple of 256;
  * default 1024). */
 int hlb_batch_set_chunk(hlb_batch *b, int sites_of_box, int chunk);
-/* Launch form of a batched step.  HLB_BATCH_PERSISTENT (default): one
- * persistent kernel per call, the four phases of a step separated by grid
- * barriers.  HLB_BATCH_PHASES: four ordinary kernels per step (stress, LB,
- * predictor, corrector), one block per work item, ordered by the stream
- * (meant for graph capture); the boxes are packed in index order into cache
- * groups of at most group_sites sites (a larger box alone) and all steps of a
- * call run on one group before the next, so that a group's fields stay in
- * the last-level cache (group_sites = 0 keeps the current budget, default
- * 2^20).  Results are identical; drops a captured graph. */
+/* Launch form of a batched step.  HLB_BATCH_PERSISTENT: one persistent
+ * kernel per call; the boxes are packed into 8 groups of about
+ * equal site count, one per XCD, the workgroups of a group separate the four
+ * phases of a step by barriers among themselves, and each group takes its
+ * boxes in cache groups of at most group_sites / 8 sites (a larger box
+ * alone), all steps of the call on one cache group before the next.
+ * HLB_BATCH_PHASES (default): four ordinary kernels per step (stress, LB, predictor,
+ * corrector), one block per work item, ordered by the stream (meant for graph
+ * capture); the boxes are packed in index order into cache groups of at most
+ * group_sites sites and all steps of a call run on one group before the
+ * next.  Either way a cache group's fields stay in the last-level cache
+ * across steps (group_sites = 0 keeps the current budget, default 2^21).
+ * Results are identical; drops a captured graph. */
 enum { HLB_BATCH_PERSISTENT = 0, HLB_BATCH_PHASES = 1 };
 int hlb_batch_set_launch(hlb_batch *b, int form, long long group_sites);
 int hlb_batch_get_launch(const hlb_batch *b, int *form, long long *group_sites);
-/* Autotuner: coordinate descent over the launch form, the cache-group budget
- * of the phase form (2^19 .. 2^22 sites, or all boxes in one group) jointly
- * with one chunk (256 or 1024) for all sizes, the blocks per CU of the
- * persistent form (1..4) and, for each distinct box size, chunks of 256,
- * 1024, 4096 and 16384 sites, timing trial_steps batched steps with HIP
- * events on the batch stream and keeping the fastest; the states are put back
- * afterwards (host copies).  Writes up to max_out (size, chunk) pairs; returns
- * the number of sizes. */
+/* Autotuner: coordinate descent over the launch form, the cache-group
+ * budget (2^19 .. 2^22 sites, or all boxes in one group) jointly with one
+ * chunk (256 or 1024) for all sizes, the blocks per CU of the persistent
+ * form (1..4) and, for each distinct box size, chunks of 256, 1024, 4096 and
+ * 16384 sites, timing trial_steps batched steps with HIP events on the batch
+ * stream and keeping the fastest; the states are put back afterwards (host
+ * copies).  Writes up to max_out (size, chunk) pairs; returns the number of
+ * sizes. */
 int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunks_out, int max_out);
 /* enable = 1 (default): keep each box on one XCD (boxes packed into 8 groups of
  * about equal site count; the workgroups on XCD x take group x), so the phase

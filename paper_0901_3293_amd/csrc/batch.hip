@@ -7,11 +7,15 @@
 // rank among the workgroups of that XCD; the workgroups of an XCD then take
 // the items of its group in turn, so each box is read and written by one XCD
 // only (if some XCD got no workgroup, the launch falls back to a fixed
-// blockIdx mapping and device-scope fences).  One step is four phases over the
-// list (stress, LB, predictor, corrector -- the per-site device functions of
-// sitekern.h), separated by grid barriers.  The grid never exceeds the number
-// of co-resident blocks; every barrier wait is bounded so that a stall ends
-// the kernel with an error flag instead of hanging it.
+// blockIdx mapping and device-scope fences).  One step is four phases over
+// the items (stress, LB, predictor, corrector -- the per-site device
+// functions of sitekern.h), separated by barriers among the workgroups of
+// the group: the groups hold disjoint boxes and never wait for each other.
+// A group takes its boxes in cache groups, every step of the launch on one
+// cache group before the next, so that its fields stay in the caches.  The
+// grid never exceeds the number of co-resident blocks; every barrier wait is
+// bounded so that a stall ends the kernel with an error flag instead of
+// hanging it.
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
@@ -33,7 +37,8 @@ struct Rep {
     int gcur;  // ping-pong index of the populations, advanced on the device
 };
 
-// Grid-wide barrier over a monotonically increasing arrival counter.  The
+// Barrier over `per` workgroups (the whole grid, or the workgroups of one
+// work-list group) on a monotonically increasing arrival counter.  The
 // block's stores are complete at the workgroup barrier; thread 0 then
 // publishes them at device scope (one L2 write-back per block), arrives,
 // polls with a bounded number of sleeps, and acquires at device scope (one
@@ -47,19 +52,20 @@ struct Rep {
 // own stores are acknowledged (by that L2) before the workgroup barrier, and
 // the L2 write-back of the device-scope release is skipped.  The acquire
 // stays at device scope: it is what is sure to drop the CU's stale L1 lines.
-__device__ __forceinline__ bool grid_sync(unsigned *bar, int *err, unsigned &target, unsigned spin_limit, bool local)
+__device__ __forceinline__ bool group_sync(unsigned *bar, int *err, unsigned &target, unsigned per,
+                                           unsigned spin_limit, bool local)
 {
     if (local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached L2
     __syncthreads();
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
         if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        target += gridDim.x;
+        target += per;
         atomicAdd(bar, 1u);
         int ok = 1;
         unsigned spins = 0;
         // the counter and the target wrap together after 2^32 arrivals: compare
-        // their difference (the grid never lags by 2^31 arrivals)
+        // their difference (the group never lags by 2^31 arrivals)
         while (int(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > spin_limit) {
                 atomicMax(err, 1);
@@ -172,10 +178,15 @@ __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 
     }
 }
 
+// Barrier counters of the 8 work-list groups, one per 64-byte line.
+constexpr int GBAR_STRIDE = 16;
+
 template <typename T>
-__global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, int n_reps, const int4 *__restrict__ items,
-                                               const int *__restrict__ xlo, unsigned *bar, int *err, int *misplaced,
-                                               int *xcnt, int allow_local, int nsteps, unsigned spin_limit)
+__global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, const int4 *__restrict__ items,
+                                               const int *__restrict__ xlo, const int *__restrict__ slo,
+                                               const int *__restrict__ sgx, unsigned *bar, unsigned *gbar, int *err,
+                                               int *misplaced, int *xcnt, int allow_local, int nsteps,
+                                               unsigned spin_limit)
 {
     unsigned target = 0;
     // Rank of this block among the blocks of its XCD; after one full barrier
@@ -183,7 +194,7 @@ __global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, int n_
     __shared__ int s_rank;
     const int xcd = xcc_id();
     if (threadIdx.x == 0) s_rank = xcd < 8 ? atomicAdd(&xcnt[xcd], 1) : (atomicOr(misplaced, 1), 0);
-    if (!grid_sync(bar, err, target, spin_limit, false)) return;
+    if (!group_sync(bar, err, target, gridDim.x, spin_limit, false)) return;
     bool local = allow_local && __hip_atomic_load(misplaced, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     for (int x = 0; x < 8; ++x)
         if (__hip_atomic_load(&xcnt[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) local = false;
@@ -198,21 +209,31 @@ __global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, int n_
         per = gridDim.x >> 3;
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(misplaced, 1);  // report the fallback
     }
-    const int lo = xlo[grp], hi = xlo[grp + 1];
-    for (int n = 0; n < nsteps; ++n) {
-        run_phase<T, PH_STRESS>(reps, items, lo, hi, rank, per, n);
-        if (!grid_sync(bar, err, target, spin_limit, local)) return;
-        run_phase<T, PH_LB>(reps, items, lo, hi, rank, per, n);
-        if (!grid_sync(bar, err, target, spin_limit, local)) return;
-        run_phase<T, PH_PRED>(reps, items, lo, hi, rank, per, n);
-        if (!grid_sync(bar, err, target, spin_limit, local)) return;
-        run_phase<T, PH_CORR>(reps, items, lo, hi, rank, per, n);
-        if (!grid_sync(bar, err, target, spin_limit, local)) return;
+    // The groups hold disjoint boxes, so each synchronises only its own
+    // workgroups; it takes its boxes in cache groups (all steps of one before
+    // the next), so a cache group's fields stay in the caches across steps.
+    unsigned gtarget = 0;
+    unsigned *gb = gbar + grp * GBAR_STRIDE;
+    for (int j = sgx[grp]; j < sgx[grp + 1]; ++j) {
+        const int lo = slo[j], hi = slo[j + 1];
+        for (int n = 0; n < nsteps; ++n) {
+            run_phase<T, PH_STRESS>(reps, items, lo, hi, rank, per, n);
+            if (!group_sync(gb, err, gtarget, per, spin_limit, local)) return;
+            run_phase<T, PH_LB>(reps, items, lo, hi, rank, per, n);
+            if (!group_sync(gb, err, gtarget, per, spin_limit, local)) return;
+            run_phase<T, PH_PRED>(reps, items, lo, hi, rank, per, n);
+            if (!group_sync(gb, err, gtarget, per, spin_limit, local)) return;
+            run_phase<T, PH_CORR>(reps, items, lo, hi, rank, per, n);
+            if (!group_sync(gb, err, gtarget, per, spin_limit, local)) return;
+        }
     }
-    // every block has read gcur before the last barrier: advance it once
-    if (blockIdx.x == 0 && (nsteps & 1))
-        for (int r = threadIdx.x; r < n_reps; r += BLK)
-            if (reps[r].flow) reps[r].gcur ^= 1;
+    // every block of the group has read gcur of its boxes before the group's
+    // last barrier: the group's first block advances it once per box
+    if (rank == 0 && (nsteps & 1))
+        for (int it = xlo[grp] + int(threadIdx.x); it < xlo[grp + 1]; it += BLK) {
+            const int4 w = items[it];
+            if (w.y == 0 && reps[w.x].flow) reps[w.x].gcur ^= 1;
+        }
 }
 
 // The alternative launch form: one ordinary kernel per phase, one block per
@@ -240,14 +261,17 @@ __global__ void k_flip(Rep<T> *__restrict__ reps, int n_reps)
     if (r < n_reps && reps[r].flow) reps[r].gcur ^= 1;
 }
 
-__global__ void k_batch_reset(unsigned *bar, int *err, int *misplaced, int *xcnt)
+__global__ void k_batch_reset(unsigned *bar, int *err, int *misplaced, int *xcnt, unsigned *gbar)
 {
     if (threadIdx.x == 0) {
         *bar = 0u;
         *err = 0;
         *misplaced = 0;
     }
-    if (threadIdx.x < 8) xcnt[threadIdx.x] = 0;
+    if (threadIdx.x < 8) {
+        xcnt[threadIdx.x] = 0;
+        if (gbar) gbar[threadIdx.x * GBAR_STRIDE] = 0u;
+    }
 }
 
 template <typename T>
@@ -303,23 +327,23 @@ hipError_t batch_grid(bool fp32, int n_items, int blocks_per_cu, int *grid)
     return hipSuccess;
 }
 
-hipError_t batch_launch(bool fp32, void *d_reps, int n_reps, const int *d_items, const int *d_xlo, unsigned *d_bar,
-                        int *d_err, int *d_misplaced, int *d_xcnt, bool allow_local, int nsteps, int grid,
-                        hipStream_t stream)
+hipError_t batch_launch(bool fp32, void *d_reps, const int *d_items, const int *d_xlo, const int *d_slo,
+                        const int *d_sgx, unsigned *d_bar, unsigned *d_gbar, int *d_err, int *d_misplaced,
+                        int *d_xcnt, bool allow_local, int nsteps, int grid, hipStream_t stream)
 {
     // polls per barrier before giving up: each sleeps ~50 ns and waits for one
     // device-scope load, so a stalled barrier is abandoned after about 1-10 s
     const unsigned spin_limit = 1u << 24;
-    k_batch_reset<<<1, 64, 0, stream>>>(d_bar, d_err, d_misplaced, d_xcnt);
+    k_batch_reset<<<1, 64, 0, stream>>>(d_bar, d_err, d_misplaced, d_xcnt, d_gbar);
     const int4 *items = reinterpret_cast<const int4 *>(d_items);
     if (fp32)
-        k_batch<float><<<grid, BLK, 0, stream>>>(static_cast<Rep<float> *>(d_reps), n_reps, items, d_xlo, d_bar,
-                                                 d_err, d_misplaced, d_xcnt, int(allow_local), nsteps,
-                                                 spin_limit);
+        k_batch<float><<<grid, BLK, 0, stream>>>(static_cast<Rep<float> *>(d_reps), items, d_xlo, d_slo, d_sgx,
+                                                 d_bar, d_gbar, d_err, d_misplaced, d_xcnt, int(allow_local),
+                                                 nsteps, spin_limit);
     else
-        k_batch<double><<<grid, BLK, 0, stream>>>(static_cast<Rep<double> *>(d_reps), n_reps, items, d_xlo, d_bar,
-                                                  d_err, d_misplaced, d_xcnt, int(allow_local), nsteps,
-                                                 spin_limit);
+        k_batch<double><<<grid, BLK, 0, stream>>>(static_cast<Rep<double> *>(d_reps), items, d_xlo, d_slo, d_sgx,
+                                                  d_bar, d_gbar, d_err, d_misplaced, d_xcnt, int(allow_local),
+                                                  nsteps, spin_limit);
     return hipGetLastError();
 }
 
@@ -348,7 +372,7 @@ hipError_t batch_launch_phases(bool fp32, void *d_reps, int n_reps, const int *d
                                unsigned *d_bar, int *d_err, int *d_misplaced, int *d_xcnt, int nsteps,
                                hipStream_t stream)
 {
-    k_batch_reset<<<1, 64, 0, stream>>>(d_bar, d_err, d_misplaced, d_xcnt);
+    k_batch_reset<<<1, 64, 0, stream>>>(d_bar, d_err, d_misplaced, d_xcnt, nullptr);
     if (ngroups < 1 || nsteps < 1) return hipGetLastError();
     return fp32 ? launch_phases_t<float>(d_reps, n_reps, d_items, clo, ngroups, nsteps, stream)
                 : launch_phases_t<double>(d_reps, n_reps, d_items, clo, ngroups, nsteps, stream);

@@ -34,12 +34,17 @@ struct hlb_batch {
     int *d_misplaced;
     int *d_xlo;     // item offsets of the 8 XCD groups (9 ints)
     int *d_xcnt;    // workgroups per XCD of the running launch (8 ints)
+    int *d_slo;     // item offsets of the cache groups of the persistent form (n + 9 ints)
+    int *d_sgx;     // cache groups of each XCD group: [sgx[x], sgx[x + 1]) (9 ints)
+    unsigned *d_gbar;  // barrier counters of the 8 XCD groups (64-byte stride)
     int xlo[9];
+    int sgx[9];
+    std::vector<int> slo;
     int grid;
     int bpc;                         // blocks per compute unit of the persistent grid (0: max)
     bool xcd_local = true;           // keep each box on one XCD when the launch allows it
-    int launch_form = HLB_BATCH_PERSISTENT;  // or HLB_BATCH_PHASES
-    long long group_sites = 1 << 20;          // cache-group budget of the phase form (sites)
+    int launch_form = HLB_BATCH_PHASES;       // or HLB_BATCH_PERSISTENT
+    long long group_sites = 1 << 21;          // cache-group budget (sites; per XCD group: 1/8 of it)
     std::vector<int> clo;                     // item offsets of the cache groups (phase form)
     bool dirty;                      // descriptor table / work list must be rebuilt
     hipGraph_t graph;
@@ -162,18 +167,44 @@ int rebuild(hlb_batch *b)
         b->clo.push_back(int(items.size() / 4));
         for (int g = 0; g <= 8; ++g) b->xlo[g] = g == 8 ? int(items.size() / 4) : 0;
     } else {
+        // XCD groups, each cut into cache groups of at most group_sites / 8
+        // sites (a larger box alone): the persistent kernel runs all steps of
+        // one cache group of its XCD before the next
+        const long long budget = std::max(1ll, b->group_sites / 8);
+        b->slo.clear();
         for (int g = 0; g < 8; ++g) {
             b->xlo[g] = int(items.size() / 4);
-            for (int i = 0; i < b->n; ++i)
-                if (group[i] == g) add_box(i);
+            b->sgx[g] = int(b->slo.size());
+            long long in_sub = 0;
+            bool open = false;
+            for (int i = 0; i < b->n; ++i) {
+                if (group[i] != g) continue;
+                const long long N = b->box[i].G.N;
+                if (!open || in_sub + N > budget) {
+                    b->slo.push_back(int(items.size() / 4));
+                    in_sub = 0;
+                    open = true;
+                }
+                add_box(i);
+                in_sub += N;
+            }
         }
+        b->sgx[8] = int(b->slo.size());
     }
     b->n_items = int(items.size() / 4);
     b->xlo[8] = b->n_items;
+    if (b->launch_form == HLB_BATCH_PHASES) {
+        b->slo.clear();
+        for (int g = 0; g <= 8; ++g) b->sgx[g] = 0;
+    }
+    b->slo.push_back(b->n_items);  // end of the last cache group
+    if (b->slo.size() > size_t(b->n + 9)) return bset_error(b, HLB_ERR_ARG, "cache-group list overflow");
     if (size_t(b->n_items) > b->items_cap) return bset_error(b, HLB_ERR_ARG, "work list overflow");
     B_TRY(b, hipMemcpyAsync(b->d_reps, blob.data(), blob.size(), hipMemcpyHostToDevice, b->stream));
     B_TRY(b, hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
     B_TRY(b, hipMemcpyAsync(b->d_xlo, b->xlo, sizeof(b->xlo), hipMemcpyHostToDevice, b->stream));
+    B_TRY(b, hipMemcpyAsync(b->d_sgx, b->sgx, sizeof(b->sgx), hipMemcpyHostToDevice, b->stream));
+    B_TRY(b, hipMemcpyAsync(b->d_slo, b->slo.data(), b->slo.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
     B_TRY(b, hipStreamSynchronize(b->stream));
     B_TRY(b, hlb::batch_grid(b->fp32, b->n_items, b->bpc, &b->grid));
     b->dirty = false;
@@ -213,8 +244,8 @@ hipError_t enqueue(hlb_batch *b, int nsteps)
     if (b->launch_form == HLB_BATCH_PHASES)
         return hlb::batch_launch_phases(b->fp32, b->d_reps, b->n, b->d_items, b->clo.data(), int(b->clo.size()) - 1,
                                         b->d_bar, b->d_err, b->d_misplaced, b->d_xcnt, nsteps, b->stream);
-    return hlb::batch_launch(b->fp32, b->d_reps, b->n, b->d_items, b->d_xlo, b->d_bar, b->d_err, b->d_misplaced,
-                             b->d_xcnt, b->xcd_local, nsteps, b->grid, b->stream);
+    return hlb::batch_launch(b->fp32, b->d_reps, b->d_items, b->d_xlo, b->d_slo, b->d_sgx, b->d_bar, b->d_gbar,
+                             b->d_err, b->d_misplaced, b->d_xcnt, b->xcd_local, nsteps, b->grid, b->stream);
 }
 
 }  // namespace
@@ -235,6 +266,7 @@ size_t hlb_batch_workspace_bytes(int n, const int *dims, int precision)
     total += align256(n * hlb::batch_rep_bytes(fp32));
     total += align256(items_upper_bound(n, dims) * 16);
     total += 256 + part_max + 256;
+    total += 512 + align256(size_t(n + 9) * 4) + 256;  // group barriers, cache-group offsets
     return total;
 }
 
@@ -263,6 +295,12 @@ int hlb_batch_create(int n, const int *dims, int precision, void *ws, size_t ws_
     b->d_misplaced = reinterpret_cast<int *>(p + 128);
     b->d_xlo = reinterpret_cast<int *>(p + 160);   // 9 ints
     b->d_xcnt = reinterpret_cast<int *>(p + 224);  // 8 ints
+    p += 256;
+    b->d_gbar = reinterpret_cast<unsigned *>(p);
+    p += 512;
+    b->d_slo = reinterpret_cast<int *>(p);
+    p += align256(size_t(n + 9) * 4);
+    b->d_sgx = reinterpret_cast<int *>(p);
     p += 256;
     size_t part_max = 0;
     for (int i = 0; i < n; ++i) {
@@ -453,12 +491,12 @@ int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunk
     B_TRY(b, hipEventCreate(&ea));
     B_TRY(b, hipEventCreate(&eb));
     int rc = HLB_OK;
-    // coordinate descent: the launch form (key -1), blocks per CU of the
-    // persistent form (key 0), then the chunk of each box size in turn
-    // (key -2: the cache-group budget of the phase form jointly with one chunk
-    // for every box size -- the two interact through the blocks per group;
-    // option k: budget 2^(19 + k % 5) sites (k % 5 == 4: all boxes in one
-    // group), chunk 256 for k < 5 else 1024)
+    // coordinate descent: the launch form (key -1), the cache-group budget
+    // jointly with one chunk for every box size (key -2; the two interact
+    // through the blocks per group; option k: budget 2^(19 + k % 5) sites
+    // (k % 5 == 4: all boxes in one group), chunk 256 for k < 5 else 1024),
+    // blocks per CU of the persistent form (key 0), then the chunk of each
+    // box size in turn
     auto set_joint = [&](int k) {
         b->group_sites = (k % 5 == 4) ? (1ll << 40) : (1ll << (19 + k % 5));
         for (int N : sizes) b->chunk_of_n[N] = k < 5 ? 256 : 1024;
@@ -468,7 +506,6 @@ int hlb_batch_autotune(hlb_batch *b, int trial_steps, int *sizes_out, int *chunk
     keys.insert(keys.end(), sizes.begin(), sizes.end());
     for (int N : keys) {
         if (N == 0 && b->launch_form != HLB_BATCH_PERSISTENT) continue;
-        if (N == -2 && b->launch_form != HLB_BATCH_PHASES) continue;
         double best = 1e300;
         int pick = N == -1 ? b->launch_form
                  : N == -2 ? joint

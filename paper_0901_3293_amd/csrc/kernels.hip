@@ -460,11 +460,12 @@ __global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGr
 __device__ __forceinline__ int site_index() { return logical_block() * BLK + int(threadIdx.x); }
 
 // SPLIT: the 12 planes of the split coupling instead of the 9 of Pi.
-// Occupancy floors of the per-site Q-side kernels (blocks of 256 per CU): in
-// FP64 they bound the registers to 128 (stress, corrector) and 96
-// (predictor) without spills, 4 and 5 waves per SIMD; FP32 needs ~60 anyway.
+// Occupancy floors of the per-site Q-side kernels in FP64 (blocks of 256 per
+// CU): registers bounded to 128 (stress, corrector) and 96 (predictor)
+// without spills, 4 and 5 waves per SIMD.  FP32 is left to the compiler
+// (~60 registers, 8 waves).
 template <typename T, bool SPLIT>
-__global__ __launch_bounds__(BLK, 4) void k_stress(Geom G, Coef<T> c, const T *__restrict__ Q,
+__global__ __launch_bounds__(BLK, sizeof(T) == 8 ? 4 : 1) void k_stress(Geom G, Coef<T> c, const T *__restrict__ Q,
                                                 T *__restrict__ Pi, double *__restrict__ fpart)
 {
     const int s = site_index();
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(BLK) void k_lb(Geom G, Coef<T> c, const T *__restri
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLK, 5) void k_qpred(Geom G, Coef<T> c, const T *__restrict__ Q,
+__global__ __launch_bounds__(BLK, sizeof(T) == 8 ? 5 : 1) void k_qpred(Geom G, Coef<T> c, const T *__restrict__ Q,
                                                const T *__restrict__ u, T *__restrict__ Qs)
 {
     const int s = site_index();
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(BLK, 5) void k_qpred(Geom G, Coef<T> c, const T *__
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLK, 4) void k_qcorr(Geom G, Coef<T> c, T *__restrict__ Q, const T *__restrict__ Qs,
+__global__ __launch_bounds__(BLK, sizeof(T) == 8 ? 4 : 1) void k_qcorr(Geom G, Coef<T> c, T *__restrict__ Q, const T *__restrict__ Qs,
                                                const T *__restrict__ u)
 {
     const int s = site_index();

@@ -333,7 +333,8 @@ class Solver:
 
 
 class Batch:
-    """Many periodic boxes of uneven size advanced by one persistent launch.
+    """Many periodic boxes of uneven size advanced together (phase kernels or
+    one persistent launch per call).
 
     ``shapes``: list of (nx, ny, nz).  Arrays per box are float64 [c][z][y][x].
     """
@@ -385,8 +386,9 @@ class Batch:
     LAUNCH_FORMS = {"persistent": 0, "phases": 1}
 
     def set_launch(self, form, group_sites=0):
-        """'persistent' (one kernel, grid barriers) or 'phases' (four kernels per
-        step, cache groups of at most group_sites sites; 0 keeps the budget)."""
+        """'phases' (default: four kernels per step, cache groups of at most
+        group_sites sites) or 'persistent' (one kernel, barriers per XCD group,
+        cache groups of group_sites / 8 sites per group); 0 keeps the budget."""
         self._check(lib().hlb_batch_set_launch(self.b, self.LAUNCH_FORMS[form], int(group_sites)))
 
     def launch_form(self):

@@ -51,14 +51,16 @@ def make_batch(H, prec, rs):
 
 
 @pytest.mark.parametrize("form,local,group", [("persistent", True, 0), ("persistent", False, 0),
+                                              ("persistent", True, 2000), ("persistent", False, 2000),
                                               ("phases", False, 0), ("phases", False, 2000)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_matches_single_boxes(H, prec, form, local, group):
     """Every launch form: the persistent kernel with boxes kept on one XCD
     (XCD-scope release) or with the fixed mapping and device-scope fences,
-    and the four phase kernels per step, with all boxes in one cache group
-    or in groups of at most 2000 sites (several groups, boxes larger than
-    the budget alone)."""
+    each XCD group in one cache group or in cache groups of at most
+    2000 / 8 sites (every box its own); and the four phase kernels per step,
+    with all boxes in one cache group or in groups of at most 2000 sites
+    (several groups, boxes larger than the budget alone)."""
     say("case: batch vs single", prec, form, "xcd-local allowed", local, "group", group)
     rs = small_set()
     b = make_batch(H, prec, rs)
@@ -135,7 +137,8 @@ def test_replica_set_96_full_size(H):
             assert np.array_equal(x, y), i
 
 
-@pytest.mark.parametrize("form,local,group", [("persistent", True, 0), ("phases", False, 2000)])
+@pytest.mark.parametrize("form,local,group", [("persistent", True, 0), ("persistent", True, 2000),
+                                              ("phases", False, 2000)])
 def test_batch_fp64_matches_oracle(H, orc, form, local, group):
     """Every box of the uneven set -- cubes of 8 to 20 with their own (kappa,
     tau), the flow-off box and the 10 x 6 x 14 box -- against the FP64 oracle
