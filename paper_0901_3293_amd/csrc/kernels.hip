@@ -45,7 +45,9 @@ constexpr int TX = Shape::TX, TY = Shape::TY;
 
 __device__ __forceinline__ int logical_block() { return xcd_logical_block(); }
 
-// Fixed-order block reduction of NV doubles per thread into out[NV].
+// Fixed-order block reduction of NV doubles per thread into out[NV] (each
+// round folds the upper part of the live range onto the lower one; for a
+// power-of-two block this is the usual halving tree).
 template <int NV, int NTH>
 __device__ __forceinline__ void block_sum(double v[NV], double *out)
 {
@@ -53,11 +55,13 @@ __device__ __forceinline__ void block_sum(double v[NV], double *out)
 #pragma unroll
     for (int k = 0; k < NV; ++k) buf[k][threadIdx.x] = v[k];
     __syncthreads();
-    for (int w = NTH / 2; w > 0; w >>= 1) {
-        if (int(threadIdx.x) < w)
+    for (int n = NTH; n > 1;) {
+        const int h = (n + 1) / 2;
+        if (int(threadIdx.x) < n - h)
 #pragma unroll
-            for (int k = 0; k < NV; ++k) buf[k][threadIdx.x] += buf[k][threadIdx.x + w];
+            for (int k = 0; k < NV; ++k) buf[k][threadIdx.x] += buf[k][threadIdx.x + h];
         __syncthreads();
+        n = h;
     }
     if (threadIdx.x == 0)
 #pragma unroll
@@ -75,29 +79,37 @@ __device__ __forceinline__ void nan_fill(T *slot, int n)
     for (int i = int(threadIdx.x); i < n; i += int(blockDim.x)) slot[i] = q;
 }
 
-// Staging of one z-plane of an NC-component field into an LDS ring slot with
-// a two-site halo in x and y (periodic wrap of the global coordinates).  The
-// element -> (component, in-plane offset) assignment is computed once per
-// block.
+// Staging of one z-plane of an NC-component field into an LDS slot with a
+// two-site halo in x and y (periodic wrap of the global coordinates) by the
+// NB threads of a block.  The element -> (component, in-plane offset)
+// assignment is computed once per block.
 template <int NC>
 struct PlaneLoader {
     static constexpr int NE = NC * Shape::RN;
-    static constexpr int NL = (NE + Shape::NT - 1) / Shape::NT;
-    int comp[NL];
-    int off[NL];
+    static constexpr int NL = (NE + Shape::NB - 1) / Shape::NB;
+    // only the last k has elements past the end (t >= LAST)
+    static constexpr int LAST = NE - (NL - 1) * Shape::NB;
+    int off[NL];  // in-plane lattice offset of the element
 
     __device__ __forceinline__ void init(const Geom &G, int x0, int y0)
     {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int e = int(threadIdx.x) + k * Shape::NT;
-            if (e < NE) {
-                TileMap<Shape>::staged(e, x0, y0, G.nx, G.ny, comp[k], off[k]);
-            } else {
-                comp[k] = -1;
-                off[k] = 0;
-            }
+            const int e = int(threadIdx.x) + k * Shape::NB;
+            int comp = 0;
+            off[k] = 0;
+            if (e < NE) TileMap<Shape>::staged(e, x0, y0, G.nx, G.ny, comp, off[k]);
         }
+    }
+
+    __device__ __forceinline__ static bool valid(int k) { return k < NL - 1 || int(threadIdx.x) < LAST; }
+
+    template <typename T>
+    __device__ __forceinline__ const T *elem(const T *__restrict__ src, size_t N, int plane_off, int k) const
+    {
+        const int cb = TileMap<Shape>::comp_base(k);
+        const T *base = int(threadIdx.x) < TileMap<Shape>::comp_split(k) ? src + size_t(cb) * N : src + size_t(cb + 1) * N;
+        return base + (plane_off + off[k]);
     }
 
     template <typename T>
@@ -106,8 +118,7 @@ struct PlaneLoader {
     {
 #pragma unroll
         for (int k = 0; k < NL; ++k)
-            if (comp[k] >= 0)
-                slot[int(threadIdx.x) + k * Shape::NT] = src[size_t(comp[k]) * N + plane_off + off[k]];
+            if (valid(k)) slot[int(threadIdx.x) + k * Shape::NB] = *elem(src, N, plane_off, k);
     }
 
     // Software pipelining: issue the global loads of a plane into registers
@@ -116,8 +127,7 @@ struct PlaneLoader {
     __device__ __forceinline__ void fetch(const T *__restrict__ src, size_t N, int plane_off, T reg[NL]) const
     {
 #pragma unroll
-        for (int k = 0; k < NL; ++k)
-            reg[k] = comp[k] >= 0 ? src[size_t(comp[k]) * N + plane_off + off[k]] : T(0);
+        for (int k = 0; k < NL; ++k) reg[k] = valid(k) ? *elem(src, N, plane_off, k) : T(0);
     }
 
     template <typename T>
@@ -125,12 +135,35 @@ struct PlaneLoader {
     {
 #pragma unroll
         for (int k = 0; k < NL; ++k)
-            if (comp[k] >= 0) slot[int(threadIdx.x) + k * Shape::NT] = reg[k];
+            if (valid(k)) slot[int(threadIdx.x) + k * Shape::NB] = reg[k];
     }
 };
 
-// Derivatives of an NC=5 field staged with a two-site halo, at staged
-// coordinate r of the middle plane.
+// Derivatives of the 5-component Q at staged coordinate r of plane p: the
+// value and its in-plane neighbours from the staged slot `mid` (two-site
+// halo, RN points per component), the z-neighbours from `lo` (plane p-1,
+// registers of the thread owning the point) and the staged slot `hi`
+// (plane p+1).
+template <typename T>
+__device__ __forceinline__ void stencil_staged(const T lo[5], const T *mid, const T *hi, int r, T q[5],
+                                               T d[3][5], T lap[5])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int o = k * Shape::RN + r;
+        const T v = mid[o];
+        const T xp = mid[o + 1], xm = mid[o - 1];
+        const T yp = mid[o + Shape::RX], ym = mid[o - Shape::RX];
+        const T zp = hi[o], zm = lo[k];
+        q[k] = v;
+        d[0][k] = T(0.5) * (xp - xm);
+        d[1][k] = T(0.5) * (yp - ym);
+        d[2][k] = T(0.5) * (zp - zm);
+        lap[k] = ((xp + xm) + (yp + ym)) + (zp + zm) - T(6) * v;
+    }
+}
+
+// Same for the three-slot form (all of planes p-1, p, p+1 staged).
 template <typename T>
 __device__ __forceinline__ void stencil_ring(const T *lo, const T *mid, const T *hi, int r, T q[5],
                                              T d[3][5], T lap[5])
@@ -150,10 +183,12 @@ __device__ __forceinline__ void stencil_ring(const T *lo, const T *mid, const T 
     }
 }
 
-// Same for a field staged on the halo-1 plane layout (PX x PY).
+// Derivatives of a 5-component field held on the evaluation plane (PX x PY,
+// PN points per component) at point r: value and in-plane neighbours from
+// `mid`, z-neighbours from registers.
 template <typename T>
-__device__ __forceinline__ void stencil_p(const T *lo, const T *mid, const T *hi, int r, T q[5],
-                                          T d[3][5], T lap[5])
+__device__ __forceinline__ void stencil_eval(const T lo[5], const T *mid, const T hi[5], int r, T q[5],
+                                             T d[3][5], T lap[5])
 {
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -161,7 +196,7 @@ __device__ __forceinline__ void stencil_p(const T *lo, const T *mid, const T *hi
         const T v = mid[o];
         const T xp = mid[o + 1], xm = mid[o - 1];
         const T yp = mid[o + Shape::PX], ym = mid[o - Shape::PX];
-        const T zp = hi[o], zm = lo[o];
+        const T zp = hi[k], zm = lo[k];
         q[k] = v;
         d[0][k] = T(0.5) * (xp - xm);
         d[1][k] = T(0.5) * (yp - ym);
@@ -170,10 +205,11 @@ __device__ __forceinline__ void stencil_p(const T *lo, const T *mid, const T *hi
     }
 }
 
-// u and its centred gradient W_ab = d_b u_a at staged coordinate r.
+// u and its centred gradient W_ab = d_b u_a at staged coordinate r of plane
+// p: in-plane from `mid`, z from `lo` (registers, plane p-1) and `hi`.
 template <typename T>
-__device__ __forceinline__ void velocity_ring(const T *lo, const T *mid, const T *hi, int r, T uc[3],
-                                              T W[3][3])
+__device__ __forceinline__ void velocity_staged(const T lo[3], const T *mid, const T *hi, int r, T uc[3],
+                                                T W[3][3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -181,7 +217,7 @@ __device__ __forceinline__ void velocity_ring(const T *lo, const T *mid, const T
         uc[a] = mid[o];
         W[a][0] = T(0.5) * (mid[o + 1] - mid[o - 1]);
         W[a][1] = T(0.5) * (mid[o + Shape::RX] - mid[o - Shape::RX]);
-        W[a][2] = T(0.5) * (hi[o] - lo[o]);
+        W[a][2] = T(0.5) * (hi[o] - lo[a]);
     }
 }
 
@@ -206,13 +242,18 @@ __device__ __forceinline__ Block block_of(const Geom &G, const TileGrid &tg)
 }
 
 // ---------------------------------------------------------------- k_qforce
-// F = div Pi(Q) (Eqs. (6)-(8), (19)).  Per plane p: stage Q(p+1); evaluate
-// the stress on the tile and its one-site halo ring (x and y columns of Pi
-// kept in LDS, the z column of the thread's own site in registers); finish
-// F(p-1) with the z-difference and start F(p) with the in-plane differences.
-// With WITH_F the block also sums the free-energy density of its sites.
+// F = div Pi(Q) (Eqs. (6)-(8), (19)).  Every thread owns one point of the
+// evaluation plane (a tile site or a ring point).  Per plane p: evaluate the
+// stress at the own point from the staged planes p-1, p, p+1 (ring points
+// only where a tile site needs them), keep its z column in registers and put
+// its x and y columns in LDS; after a barrier the tile threads finish F(p-1)
+// with the z-difference and start F(p) with the in-plane differences; the
+// plane p+2, fetched into registers at the start, then replaces p-1.  With
+// WITH_F the block also sums the free-energy density of its sites.
+// FP32: at most 96 registers, five waves per SIMD (three blocks per CU); in
+// FP64 a bound that would let a second block in spills and runs slower.
 template <typename T, bool WITH_F>
-__global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGrid tg,
+__global__ __launch_bounds__(Shape::NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 5))) void k_qforce(Geom G, Coef<T> c, TileGrid tg,
                                                       const T *__restrict__ Q, T *__restrict__ F,
                                                       double *__restrict__ fpart, bool dbg_nan)
 {
@@ -227,35 +268,31 @@ __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGri
     }
     const size_t N = G.N;
     const int sxy = G.nx * G.ny;
-    const int tx = int(threadIdx.x) % Shape::TX, ty = int(threadIdx.x) / Shape::TX;
-    const int gx = B.x0 + tx, gy = B.y0 + ty;
-    const bool mine = gx < G.nx && gy < G.ny;
+    const int t = int(threadIdx.x);
+    int pc, rc;
+    const bool eval = TileMap<Shape>::point(t, pc, rc);
+    const bool tile = t < Shape::NT;
+    const int gx = B.x0 + t % Shape::TX, gy = B.y0 + t / Shape::TX;
+    const bool mine = tile && gx < G.nx && gy < G.ny;
 
     PlaneLoader<5> L;
     L.init(G, B.x0, B.y0);
-    int sb = 0, sm = 1, st = 2;  // ring slots of planes p-1, p, p+1
+    int sb = 0, sm = 1, st = 2;  // slots of planes p-1, p, p+1
     L.load(Q, N, wrapi(B.z0 - 2, G.nz) * sxy, sQ[sb]);
     L.load(Q, N, wrapi(B.z0 - 1, G.nz) * sxy, sQ[sm]);
     L.load(Q, N, wrapi(B.z0, G.nz) * sxy, sQ[st]);
     __syncthreads();
 
-    // own site in halo-1 coordinates and in staged coordinates
-    int pc, rc, hp, hr;
-    TileMap<Shape>::own(int(threadIdx.x), pc, rc);
-    TileMap<Shape>::halo(int(threadIdx.x), hp, hr);
-
     T Fin[3] = {T(0), T(0), T(0)}, Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
     double facc = 0.0;
-    // Planes are fetched into registers two iterations before they are parked
-    // in LDS (two register sets, alternating), so each load has two plane
-    // computations to complete in.
     constexpr int NL = PlaneLoader<5>::NL;
-    T preA[NL], preB[NL];
-    if (B.z0 + 1 <= B.z1 + 1) L.fetch(Q, N, wrapi(B.z0 + 1, G.nz) * sxy, preA);
-    auto plane = [&](int p, T(&cur)[NL], T(&nxt)[NL]) __attribute__((always_inline)) {
-        if (p + 3 <= B.z1 + 1) L.fetch(Q, N, wrapi(p + 3, G.nz) * sxy, nxt);
-        T Pz[3];
-        {
+    T pre[NL];
+    for (int p = B.z0 - 1; p <= B.z1; ++p) {
+        const bool more = p + 2 <= B.z1 + 1;
+        if (more) L.fetch(Q, N, wrapi(p + 2, G.nz) * sxy, pre);
+        T Pz[3] = {T(0), T(0), T(0)};
+        // ring points: only the planes whose in-plane divergence is output
+        if (eval && (tile || (p >= B.z0 && p < B.z1))) {
             T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
             stencil_ring(sQ[sb], sQ[sm], sQ[st], rc, q, d, lap);
             site_stress(c, q, d, lap, P, fd, H);
@@ -267,28 +304,20 @@ __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGri
             }
             if (WITH_F && mine && p >= B.z0 && p < B.z1) facc += double(fd);
         }
-        if (hp >= 0) {
-            T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
-            stencil_ring(sQ[sb], sQ[sm], sQ[st], hr, q, d, lap);
-            site_stress(c, q, d, lap, P, fd, H);
+        __syncthreads();
+        if (tile) {
+            if (mine && p - 1 >= B.z0) {
+                const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) F[a * N + o] = T(0.5) * (Fin[a] + (Pz[a] - Pz2[a]));
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                sP[a * Shape::PN + hp] = P[a][0];
-                sP[(3 + a) * Shape::PN + hp] = P[a][1];
+                Fin[a] = (sP[a * Shape::PN + pc + 1] - sP[a * Shape::PN + pc - 1])
+                       + (sP[(3 + a) * Shape::PN + pc + Shape::PX] - sP[(3 + a) * Shape::PN + pc - Shape::PX]);
+                Pz2[a] = Pz1[a];
+                Pz1[a] = Pz[a];
             }
-        }
-        __syncthreads();
-        if (mine && p - 1 >= B.z0) {
-            const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) F[a * N + o] = T(0.5) * (Fin[a] + (Pz[a] - Pz2[a]));
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            Fin[a] = (sP[a * Shape::PN + pc + 1] - sP[a * Shape::PN + pc - 1])
-                   + (sP[(3 + a) * Shape::PN + pc + Shape::PX] - sP[(3 + a) * Shape::PN + pc - Shape::PX]);
-            Pz2[a] = Pz1[a];
-            Pz1[a] = Pz[a];
         }
         if (dbg_nan) {  // plane p-1 and the stress of plane p are no longer read
             __syncthreads();
@@ -296,163 +325,148 @@ __global__ __launch_bounds__(Shape::NT) void k_qforce(Geom G, Coef<T> c, TileGri
             nan_fill(sP, 6 * Shape::PN);
             __syncthreads();
         }
-        if (p + 2 <= B.z1 + 1) L.store(cur, sQ[sb]);  // plane p-1 is no longer read: it becomes p+2
+        if (more) L.store(pre, sQ[sb]);  // plane p-1 is no longer read: it becomes p+2
         __syncthreads();
         const int o = sb;
         sb = sm;
         sm = st;
         st = o;
-    };
-    int p = B.z0 - 1;
-    for (; p + 1 <= B.z1; p += 2) {
-        plane(p, preA, preB);
-        plane(p + 1, preB, preA);
     }
-    if (p <= B.z1) plane(p, preA, preB);
     if (WITH_F) {
         double v[1] = {facc};
-        block_sum<1, Shape::NT>(v, fpart + logical_block());
+        block_sum<1, Shape::NB>(v, fpart + logical_block());
     }
 }
 
 // ---------------------------------------------------------------- k_qupdate
 // Predictor-corrector for the Q equation with u held at u^n (Eqs. (2)-(4)):
 //   Q* = Q + R(Q, u),  Q' = [Q + Q* + R(Q*, u)] / 2   (= Q + [R(Q) + R(Q*)]/2).
-// Per plane p: stage Q(p+1), u(p+1); evaluate Q*(p) on the tile and its halo
-// ring into a three-plane LDS ring; then apply the corrector to plane p-1.
+// Every thread owns one point of the evaluation plane.  Per plane p: the
+// predictor stage Q*(p) at the own point (in-plane stencil from the staged
+// plane p, z-neighbours from the registers holding Q(p-1), u(p-1) and the
+// staged plane p+1; ring points only where a tile site needs them); then on
+// the tile threads the corrector at plane p-1 from Q*(p-1) in LDS and
+// Q*(p-2), Q*(p) in registers, with u(p-1) and W(p-1) kept from the
+// predictor of plane p-1.  After a barrier Q*(p) replaces Q*(p-1) in LDS and
+// the plane p+2, fetched into registers at the start, replaces plane p.
 template <typename T>
-__global__ __launch_bounds__(Shape::NT) void k_qupdate(Geom G, Coef<T> c, TileGrid tg,
+__global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGrid tg,
                                                        const T *__restrict__ Qin, const T *__restrict__ u,
                                                        T *__restrict__ Qout, bool dbg_nan)
 {
-    __shared__ T sQ[3][5 * Shape::RN];
-    __shared__ T sU[3][3 * Shape::RN];
-    __shared__ T sS[3][5 * Shape::PN];
+    __shared__ T sQ[2][5 * Shape::RN];
+    __shared__ T sU[2][3 * Shape::RN];
+    __shared__ T sS[5 * Shape::PN];
     const Block B = block_of(G, tg);
     if (!B.ok) return;
     if (dbg_nan) {
-        nan_fill(&sQ[0][0], 3 * 5 * Shape::RN);
-        nan_fill(&sU[0][0], 3 * 3 * Shape::RN);
-        nan_fill(&sS[0][0], 3 * 5 * Shape::PN);
+        nan_fill(&sQ[0][0], 2 * 5 * Shape::RN);
+        nan_fill(&sU[0][0], 2 * 3 * Shape::RN);
+        nan_fill(sS, 5 * Shape::PN);
         __syncthreads();
     }
     const size_t N = G.N;
     const int sxy = G.nx * G.ny;
-    const int tx = int(threadIdx.x) % Shape::TX, ty = int(threadIdx.x) / Shape::TX;
-    const int gx = B.x0 + tx, gy = B.y0 + ty;
-    const bool mine = gx < G.nx && gy < G.ny;
+    const int t = int(threadIdx.x);
+    int pc, rc;
+    const bool eval = TileMap<Shape>::point(t, pc, rc);
+    const bool tile = t < Shape::NT;
+    const int gx = B.x0 + t % Shape::TX, gy = B.y0 + t / Shape::TX;
+    const bool mine = tile && gx < G.nx && gy < G.ny;
 
     PlaneLoader<5> LQ;
     PlaneLoader<3> LU;
     LQ.init(G, B.x0, B.y0);
     LU.init(G, B.x0, B.y0);
-    int sb = 0, sm = 1, st = 2;     // staged planes p-1, p, p+1
-    int q2 = 0, q1 = 1, q0 = 2;     // Q* planes p-2, p-1, p
-    LQ.load(Qin, N, wrapi(B.z0 - 2, G.nz) * sxy, sQ[sb]);
-    LQ.load(Qin, N, wrapi(B.z0 - 1, G.nz) * sxy, sQ[sm]);
-    LQ.load(Qin, N, wrapi(B.z0, G.nz) * sxy, sQ[st]);
-    LU.load(u, N, wrapi(B.z0 - 2, G.nz) * sxy, sU[sb]);
-    LU.load(u, N, wrapi(B.z0 - 1, G.nz) * sxy, sU[sm]);
-    LU.load(u, N, wrapi(B.z0, G.nz) * sxy, sU[st]);
+    int sc = 0, sn = 1;  // slots of planes p, p+1
+    LQ.load(Qin, N, wrapi(B.z0 - 1, G.nz) * sxy, sQ[sc]);
+    LQ.load(Qin, N, wrapi(B.z0, G.nz) * sxy, sQ[sn]);
+    LU.load(u, N, wrapi(B.z0 - 1, G.nz) * sxy, sU[sc]);
+    LU.load(u, N, wrapi(B.z0, G.nz) * sxy, sU[sn]);
+    // Q and u of plane z0 - 2 at the own site (the ring's first predictor is
+    // at plane z0, after a rotation)
+    T qm[5] = {T(0), T(0), T(0), T(0), T(0)}, um[3] = {T(0), T(0), T(0)};
+    if (tile) {
+        const int o = wrapi(B.z0 - 2, G.nz) * sxy + wrapi(B.x0 - 2 + rc % Shape::RX, G.nx)
+                    + G.nx * wrapi(B.y0 - 2 + rc / Shape::RX, G.ny);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) qm[k] = Qin[size_t(k) * N + o];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) um[a] = u[size_t(a) * N + o];
+    }
     __syncthreads();
 
-    int pc, rc, hp, hr;
-    TileMap<Shape>::own(int(threadIdx.x), pc, rc);
-    TileMap<Shape>::halo(int(threadIdx.x), hp, hr);
-
-    T qprev[5] = {T(0), T(0), T(0), T(0), T(0)};  // Q^n at the own site of plane p-1
-    T up1[3] = {T(0), T(0), T(0)};                 // u at the own site, plane p-1
-    T up2[3] = {T(0), T(0), T(0)};                 // u at the own site, plane p-2
-    // Planes are fetched into registers two iterations before they are parked
-    // in LDS (two register sets, alternating).
+    T Wm[3][3] = {};                                // W at the own site, plane p-1
+    T qs2[5] = {T(0), T(0), T(0), T(0), T(0)};      // Q* at the own site, plane p-2
     constexpr int NQ = PlaneLoader<5>::NL, NU = PlaneLoader<3>::NL;
-    T preQa[NQ], preUa[NU], preQb[NQ], preUb[NU];
-    if (B.z0 + 1 <= B.z1 + 1) {
-        LQ.fetch(Qin, N, wrapi(B.z0 + 1, G.nz) * sxy, preQa);
-        LU.fetch(u, N, wrapi(B.z0 + 1, G.nz) * sxy, preUa);
-    }
-    auto plane = [&](int p, T(&curQ)[NQ], T(&curU)[NU], T(&nxtQ)[NQ], T(&nxtU)[NU]) __attribute__((always_inline)) {
-        if (p + 3 <= B.z1 + 1) {
-            LQ.fetch(Qin, N, wrapi(p + 3, G.nz) * sxy, nxtQ);
-            LU.fetch(u, N, wrapi(p + 3, G.nz) * sxy, nxtU);
+    T preQ[NQ], preU[NU];
+    for (int p = B.z0 - 1; p <= B.z1; ++p) {
+        const bool more = p + 2 <= B.z1 + 1;
+        if (more) {
+            LQ.fetch(Qin, N, wrapi(p + 2, G.nz) * sxy, preQ);
+            LU.fetch(u, N, wrapi(p + 2, G.nz) * sxy, preU);
         }
-        T qcur[5], ucur[3];
-        {
-            T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
-            stencil_ring(sQ[sb], sQ[sm], sQ[st], rc, q, d, lap);
-            velocity_ring(sU[sb], sU[sm], sU[st], rc, uc, W);
-            site_rhs(c, q, d, lap, uc, W, R);
+        T q0[5] = {}, u0[3] = {}, W0[3][3] = {}, qs0[5] = {};
+        if (eval) {
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                sS[q0][k * Shape::PN + pc] = q[k] + R[k];
-                qcur[k] = q[k];
-            }
+            for (int k = 0; k < 5; ++k) q0[k] = sQ[sc][k * Shape::RN + rc];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) ucur[a] = uc[a];
+            for (int a = 0; a < 3; ++a) u0[a] = sU[sc][a * Shape::RN + rc];
         }
-        if (hp >= 0) {
-            T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
-            stencil_ring(sQ[sb], sQ[sm], sQ[st], hr, q, d, lap);
-            velocity_ring(sU[sb], sU[sm], sU[st], hr, uc, W);
-            site_rhs(c, q, d, lap, uc, W, R);
+        if (eval && (tile || (p >= B.z0 && p < B.z1))) {
+            T q[5], d[3][5], lap[5], uc[3], R[5];
+            stencil_staged(qm, sQ[sc], sQ[sn], rc, q, d, lap);
+            velocity_staged(um, sU[sc], sU[sn], rc, uc, W0);
+            site_rhs(c, q, d, lap, uc, W0, R);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sS[q0][k * Shape::PN + hp] = q[k] + R[k];
+            for (int k = 0; k < 5; ++k) qs0[k] = q[k] + R[k];
         }
-        __syncthreads();
-        if (p - 1 >= B.z0) {
-            // corrector at plane p-1: Q* stencil from the LDS ring, u of plane
-            // p-1 in-plane from the staged slot sb, z-neighbours from registers
-            T q[5], d[3][5], lap[5], uc[3], W[3][3], R[5];
-            stencil_p(sS[q2], sS[q1], sS[q0], pc, q, d, lap);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int o = a * Shape::RN + rc;
-                uc[a] = up1[a];
-                W[a][0] = T(0.5) * (sU[sb][o + 1] - sU[sb][o - 1]);
-                W[a][1] = T(0.5) * (sU[sb][o + Shape::RX] - sU[sb][o - Shape::RX]);
-                W[a][2] = T(0.5) * (ucur[a] - up2[a]);
-            }
-            site_rhs(c, q, d, lap, uc, W, R);
+        if (tile && p - 1 >= B.z0) {
+            T q[5], d[3][5], lap[5], R[5];
+            stencil_eval(qs2, sS, qs0, pc, q, d, lap);
+            site_rhs(c, q, d, lap, um, Wm, R);
             if (mine) {
                 const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) Qout[k * N + o] = T(0.5) * (qprev[k] + q[k] + R[k]);
+                for (int k = 0; k < 5; ++k) Qout[k * N + o] = T(0.5) * (qm[k] + q[k] + R[k]);
             }
-        }
 #pragma unroll
-        for (int k = 0; k < 5; ++k) qprev[k] = qcur[k];
+            for (int k = 0; k < 5; ++k) qs2[k] = q[k];
+        } else if (tile && p == B.z0) {
+            // Q*(z0 - 1) is not corrected but is the z-neighbour of the corrector at z0
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            up2[a] = up1[a];
-            up1[a] = ucur[a];
+            for (int k = 0; k < 5; ++k) qs2[k] = sS[k * Shape::PN + pc];
         }
-        __syncthreads();  // slot sb (plane p-1) and the Q* slot q2 are free now
+        __syncthreads();  // plane p, Q*(p-1) are no longer read
         if (dbg_nan) {
-            nan_fill(sQ[sb], 5 * Shape::RN);
-            nan_fill(sU[sb], 3 * Shape::RN);
-            nan_fill(sS[q2], 5 * Shape::PN);
+            nan_fill(sQ[sc], 5 * Shape::RN);
+            nan_fill(sU[sc], 3 * Shape::RN);
+            nan_fill(sS, 5 * Shape::PN);
             __syncthreads();
         }
-        if (p + 2 <= B.z1 + 1) {
-            LQ.store(curQ, sQ[sb]);
-            LU.store(curU, sU[sb]);
+        if (eval && (tile || (p >= B.z0 && p < B.z1)))
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sS[k * Shape::PN + pc] = qs0[k];
+        if (more) {
+            LQ.store(preQ, sQ[sc]);
+            LU.store(preU, sU[sc]);
         }
         __syncthreads();
-        int o = sb;
-        sb = sm;
-        sm = st;
-        st = o;
-        o = q2;
-        q2 = q1;
-        q1 = q0;
-        q0 = o;
-    };
-    int p = B.z0 - 1;
-    for (; p + 1 <= B.z1; p += 2) {
-        plane(p, preQa, preUa, preQb, preUb);
-        plane(p + 1, preQb, preUb, preQa, preUa);
+        if (eval) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) qm[k] = q0[k];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) um[a] = u0[a];
+        }
+        if (tile)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b2 = 0; b2 < 3; ++b2) Wm[a][b2] = W0[a][b2];
+        const int o = sc;
+        sc = sn;
+        sn = o;
     }
-    if (p <= B.z1) plane(p, preQa, preUa, preQb, preUb);
 }
 
 // ---------------------------------------------------------------- per-site kernels
@@ -988,7 +1002,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             if (fused_q) {
                 if (e == hipSuccess)
                     e = mark(K_QUPDATE, [&] {
-                        k_qupdate<T><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Q, u, Qs, dbg_nan);
+                        k_qupdate<T><<<tg.launch, Shape::NB, 0, D.stream>>>(G, c, tg, Q, u, Qs, dbg_nan);
                     });
                 D.qcur ^= 1;
             } else {
@@ -1007,7 +1021,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
                 T *gin = static_cast<T *>(D.g[D.gcur]);
                 T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
                 e = mark(K_QFORCE, [&] {
-                    k_qforce<T, false><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Qn, Pi, nullptr,
+                    k_qforce<T, false><<<tg.launch, Shape::NB, 0, D.stream>>>(G, c, tg, Qn, Pi, nullptr,
                                                                               dbg_nan);
                 });
                 if (e == hipSuccess)
@@ -1016,7 +1030,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             }
             if (e == hipSuccess)
                 e = mark(K_QUPDATE, [&] {
-                    k_qupdate<T><<<tg.launch, Shape::NT, 0, D.stream>>>(G, c, tg, Qn, u, Qn1, dbg_nan);
+                    k_qupdate<T><<<tg.launch, Shape::NB, 0, D.stream>>>(G, c, tg, Qn, u, Qn1, dbg_nan);
                 });
             D.qcur ^= 1;
         }

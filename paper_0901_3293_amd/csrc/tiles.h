@@ -1,9 +1,11 @@
 // tiles.h -- geometry of the 2.5D z-marching tiles used by the fused
-// Q-side kernels.  A block of TX*TY threads owns a TX x TY column of sites and
-// marches along z through a chunk of planes.  Input planes are staged in LDS
-// with a two-site halo (ring of three planes); intermediate quantities that
-// are needed at stencil neighbours (the stress, the predictor stage) are
-// evaluated on the tile plus a one-site halo ring.
+// Q-side kernels.  A block owns a TX x TY column of sites and marches along z
+// through a chunk of planes.  Quantities needed at stencil neighbours (the
+// stress, the predictor stage) are evaluated on the tile plus a one-site halo
+// ring, the "evaluation plane" of PX x PY points; every thread of the block
+// owns one evaluation point for the whole march (threads [0, NT) the tile's
+// own sites, [NT, PN) the ring, the last few none), so its z-neighbours can
+// stay in registers.  Input planes are staged in LDS with a two-site halo.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,13 +15,14 @@ namespace hlb {
 template <int TX_, int TY_>
 struct TileShape {
     static constexpr int TX = TX_, TY = TY_;
-    static constexpr int NT = TX * TY;                  // threads
+    static constexpr int NT = TX * TY;                  // tile sites
     static constexpr int RX = TX + 4, RY = TY + 4;      // staged input plane (halo 2)
     static constexpr int RN = RX * RY;
     static constexpr int PX = TX + 2, PY = TY + 2;      // evaluated plane (halo 1)
     static constexpr int PN = PX * PY;
     static constexpr int NH = PN - NT;                  // halo-ring points
-    static_assert(NH <= NT, "halo ring must fit in one pass of the block");
+    static constexpr int NB = (PN + 63) / 64 * 64;      // threads per block (whole waves)
+    static_assert(NB <= 1024, "one evaluation point per thread");
 
     // Halo-ring point h in [0, NH) -> (i, j) in halo-1 plane coordinates:
     // bottom row, top row, then left/right columns.
@@ -52,7 +55,7 @@ __host__ __device__ __forceinline__ int wrapi(int v, int n)
 // check of their halo coverage.
 template <class S>
 struct TileMap {
-    // Own site of thread t: its place on the halo-1 plane (pc) and on the
+    // Tile site t in [0, NT): its place on the halo-1 plane (pc) and on the
     // staged plane (rc).
     __host__ __device__ static __forceinline__ void own(int t, int &pc, int &rc)
     {
@@ -60,8 +63,8 @@ struct TileMap {
         pc = (ty + 1) * S::PX + (tx + 1);
         rc = (ty + 2) * S::RX + (tx + 2);
     }
-    // Halo-ring point of thread t < NH on the halo-1 plane (hp) and on the
-    // staged plane (hr); -1 for the other threads.
+    // Halo-ring point t < NH on the halo-1 plane (hp) and on the staged plane
+    // (hr); -1 otherwise.
     __host__ __device__ static __forceinline__ void halo(int t, int &hp, int &hr)
     {
         hp = hr = -1;
@@ -72,10 +75,27 @@ struct TileMap {
             hr = (j + 1) * S::RX + (i + 1);
         }
     }
-    // Element e of an NC-component staged plane (component-major, RN points
-    // per component): its component and its in-plane offset in the lattice
-    // for a tile at (x0, y0), periodic wrap.  The block stages element
-    // e = t + k NT from thread t, k = 0, 1, ...
+    // Evaluation point of thread t of a block: tile site t for t < NT, ring
+    // point t - NT for NT <= t < PN (pc, rc as above); returns false, with
+    // pc = rc = -1, for the threads past PN.
+    __host__ __device__ static __forceinline__ bool point(int t, int &pc, int &rc)
+    {
+        if (t < S::NT) {
+            own(t, pc, rc);
+            return true;
+        }
+        halo(t - S::NT, pc, rc);
+        return pc >= 0;
+    }
+    // Thread t of a block stages the elements e = t + k NB (k = 0, 1, ...) of
+    // a staged plane (component-major, RN points per component).  Since
+    // NB <= RN, the elements of one k lie in component comp_base(k) for
+    // t < comp_split(k) and in the next one above.
+    static_assert(S::NB <= S::RN, "the elements of one k span at most two components");
+    __host__ __device__ static constexpr int comp_base(int k) { return k * S::NB / S::RN; }
+    __host__ __device__ static constexpr int comp_split(int k) { return (comp_base(k) + 1) * S::RN - k * S::NB; }
+    // Element e of an NC-component staged plane: its component and its
+    // in-plane offset in the lattice for a tile at (x0, y0), periodic wrap.
     __host__ __device__ static __forceinline__ void staged(int e, int x0, int y0, int nx, int ny, int &comp, int &off)
     {
         comp = e / S::RN;

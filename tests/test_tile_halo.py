@@ -3,9 +3,10 @@ host: tests/hostcheck/tile_halo.cpp stages a plane with the kernels' own
 index maps (tiles.h) into an array prefilled with NaN, as the kernels'
 HLB_DEBUG_NAN_LDS mode does to their LDS, and reads every value the stencils
 read.  With the maps as built nothing reads NaN or a wrong site and every
-site of the halo-1 plane is evaluated exactly once; a staging that misses a
-halo column or row (planted in the checker, not in the library) surfaces as
-NaN reads."""
+point of the halo-1 plane is evaluated by exactly one thread (the tile sites
+by their own threads); a staging that misses a halo column or row (planted in
+the checker, not in the library) surfaces as NaN reads, and a loader that
+takes the wrong component for some elements as wrong values."""
 import os
 import subprocess
 
@@ -41,3 +42,8 @@ def test_tile_maps_cover_every_halo_read(checker):
 def test_missed_halo_surfaces_as_nan(checker, drop):
     nan, bad, cover = run(checker, drop)
     assert nan > 0 and bad == 0
+
+
+def test_wrong_component_split_surfaces_as_wrong_values(checker):
+    nan, bad, cover = run(checker, 3)
+    assert bad > 0 and cover == 0
