@@ -22,6 +22,23 @@ import sqlite3
 from collections import defaultdict
 
 
+# Sources of the step kernels; their hash tags traffic records so that a
+# record taken on other kernels is not used.
+KERNEL_SOURCES = ["kernels.hip", "site.h", "sitekern.h", "tiles.h", "kernels.h"]
+
+
+def kernel_source_sha():
+    """sha256 (first 16 hex digits) of the step kernels' sources."""
+    import hashlib
+    import os
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def short(name):
     m = re.search(r"k_conv<(\d+), (\d+), (\d+)", name)
     if m:  # keep the channel counts and epilogue mode of the convolutions
@@ -113,6 +130,9 @@ def main():
     ap.add_argument("--command", default="")
     ap.add_argument("--mfma", action="store_true")
     ap.add_argument("--valu", default=None, help="database of a VALU counter pass")
+    ap.add_argument("--traffic-json", default=None, metavar="PREC",
+                    help="also print the line 'bench-traffic: {json}' with the HBM bytes per dispatch of "
+                         "every step kernel for precision PREC (fp32/fp64), tagged with the kernel sources' hash")
     a = ap.parse_args()
     alg = {k: float(v) for k, v in (x.split("=") for x in a.alg)}
     t = trace(a.trace_db)
@@ -153,6 +173,7 @@ def main():
         return
     print(f"{'kernel':12s} {'calls':>5s} {'avg_us':>9s} {'fetch_MB':>9s} {'write_MB':>9s} {'hbm_MB':>8s} "
           f"{'alg_MB':>8s} {'hbm/alg':>7s} {'alg_GB/s':>9s} {'hbm_GB/s':>9s}")
+    rec = {}
     for k, (n, us) in sorted(t.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
         if k == cname:
             continue
@@ -161,6 +182,12 @@ def main():
         al = alg.get(k, float("nan")) * a.esz * a.sites / 1e6
         print(f"{k:12s} {n:5d} {us:9.2f} {f:9.1f} {w:9.1f} {f + w:8.1f} {al:8.1f} {(f + w) / al:7.2f} "
               f"{al / us * 1e3:9.0f} {(f + w) / us * 1e3:9.0f}")
+        if k in alg and f + w == f + w:  # step kernels with counter readings
+            rec[k] = round((f + w) * 1e6)
+    if a.traffic_json:
+        import json
+
+        print("bench-traffic: " + json.dumps({"kernel_source_sha": kernel_source_sha(), a.traffic_json: rec}))
 
 
 if __name__ == "__main__":
