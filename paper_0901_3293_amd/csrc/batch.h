@@ -28,7 +28,8 @@ hipError_t batch_grid(bool fp32, int n_items, int blocks_per_cu, int *grid);
 // group is cut into cache groups, items [d_slo[j], d_slo[j + 1]) for j in
 // [d_sgx[x], d_sgx[x + 1]); all nsteps steps of a cache group run before the
 // next, and the workgroups of a group synchronise among themselves (counter
-// d_gbar[16 x]).  d_xcnt: 8 ints of scratch (workgroups per XCD).
+// d_gbar[16 x]) and claim the items of each phase from the group's 64-bit
+// counter (d_gbar + 16 x + 2).  d_xcnt: 8 ints of scratch (workgroups per XCD).
 // d_misplaced: flag set when some XCD got no workgroup or allow_local is
 // false; that launch then maps groups to blockIdx and uses device-scope
 // fences throughout.

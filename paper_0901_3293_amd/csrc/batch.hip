@@ -4,10 +4,10 @@
 // Work list: every box is cut into chunks of `chunk` consecutive sites; the
 // boxes are packed into 8 groups of about equal site count, one per XCD.  At
 // the start of a launch every workgroup reads the XCD it runs on and draws a
-// rank among the workgroups of that XCD; the workgroups of an XCD then take
-// the items of its group in turn, so each box is read and written by one XCD
-// only (if some XCD got no workgroup, the launch falls back to a fixed
-// blockIdx mapping and device-scope fences).  One step is four phases over
+// rank among the workgroups of that XCD; the workgroups of an XCD then claim
+// the items of its group one at a time from the group's counter, so each box
+// is read and written by one XCD only (if some XCD got no workgroup, the
+// launch falls back to a fixed blockIdx mapping and device-scope fences).  One step is four phases over
 // the items (stress, LB, predictor, corrector -- the per-site device
 // functions of sitekern.h), separated by barriers among the workgroups of
 // the group: the groups hold disjoint boxes and never wait for each other.
@@ -178,8 +178,45 @@ __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 
     }
 }
 
-// Barrier counters of the 8 work-list groups, one per 64-byte line.
+// Barrier counters of the 8 work-list groups, one per 64-byte line; the
+// group's 64-bit item counter sits in the same line, 8 bytes in.
 constexpr int GBAR_STRIDE = 16;
+constexpr int GCTR_OFFSET = 2;
+
+// The items [lo, hi) of a group, claimed one at a time by the group's `per`
+// blocks from the group's counter, so a block that finishes early takes more
+// (the static round-robin left blocks waiting up to half their time at the
+// barriers).  Phase instance m of the group owns the counter values
+// [base, base + n + per): the first n claims name items, and every block
+// stops after its first claim past them, so exactly `per` claims overshoot
+// and the next instance starts at base + n + per.  Thread 0 claims the next
+// item while the block works on the current one; the claim goes to LDS
+// (two slots, one barrier per item).
+template <typename T, int PH>
+__device__ __forceinline__ void run_phase_claimed(Rep<T> *__restrict__ reps, const int4 *__restrict__ items, int lo,
+                                                  int hi, unsigned long long *ctr, unsigned long long base,
+                                                  int step, int *s_item)
+{
+    const unsigned long long n = (unsigned long long)(hi - lo);
+    auto claim = [&]() {
+        const unsigned long long v = __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return (v - base < n) ? int(v - base) : -1;
+    };
+    if (threadIdx.x == 0) s_item[0] = claim();
+    __syncthreads();
+    int slot = 0;
+    int it = s_item[0];
+#pragma unroll 1
+    while (it >= 0) {
+        int nxt = -1;
+        if (threadIdx.x == 0) nxt = claim();
+        run_phase<T, PH>(reps, items, lo + it, lo + it + 1, 0, 1, step);
+        if (threadIdx.x == 0) s_item[slot ^ 1] = nxt;
+        __syncthreads();
+        slot ^= 1;
+        it = s_item[slot];
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, const int4 *__restrict__ items,
@@ -214,16 +251,24 @@ __global__ __launch_bounds__(BLK) void k_batch(Rep<T> *__restrict__ reps, const 
     // the next), so a cache group's fields stay in the caches across steps.
     unsigned gtarget = 0;
     unsigned *gb = gbar + grp * GBAR_STRIDE;
+    auto *ctr = reinterpret_cast<unsigned long long *>(gb + GCTR_OFFSET);
+    __shared__ int s_item[2];
+    unsigned long long base = 0;
     for (int j = sgx[grp]; j < sgx[grp + 1]; ++j) {
         const int lo = slo[j], hi = slo[j + 1];
+        const unsigned long long span = (unsigned long long)(hi - lo) + per;
         for (int n = 0; n < nsteps; ++n) {
-            run_phase<T, PH_STRESS>(reps, items, lo, hi, rank, per, n);
+            run_phase_claimed<T, PH_STRESS>(reps, items, lo, hi, ctr, base, n, s_item);
+            base += span;
             if (!group_sync(gb, err, gtarget, per, spin_limit, local)) return;
-            run_phase<T, PH_LB>(reps, items, lo, hi, rank, per, n);
+            run_phase_claimed<T, PH_LB>(reps, items, lo, hi, ctr, base, n, s_item);
+            base += span;
             if (!group_sync(gb, err, gtarget, per, spin_limit, local)) return;
-            run_phase<T, PH_PRED>(reps, items, lo, hi, rank, per, n);
+            run_phase_claimed<T, PH_PRED>(reps, items, lo, hi, ctr, base, n, s_item);
+            base += span;
             if (!group_sync(gb, err, gtarget, per, spin_limit, local)) return;
-            run_phase<T, PH_CORR>(reps, items, lo, hi, rank, per, n);
+            run_phase_claimed<T, PH_CORR>(reps, items, lo, hi, ctr, base, n, s_item);
+            base += span;
             if (!group_sync(gb, err, gtarget, per, spin_limit, local)) return;
         }
     }
@@ -270,7 +315,10 @@ __global__ void k_batch_reset(unsigned *bar, int *err, int *misplaced, int *xcnt
     }
     if (threadIdx.x < 8) {
         xcnt[threadIdx.x] = 0;
-        if (gbar) gbar[threadIdx.x * GBAR_STRIDE] = 0u;
+        if (gbar) {
+            gbar[threadIdx.x * GBAR_STRIDE] = 0u;
+            *reinterpret_cast<unsigned long long *>(gbar + threadIdx.x * GBAR_STRIDE + GCTR_OFFSET) = 0ull;
+        }
     }
 }
 
