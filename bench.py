@@ -514,6 +514,47 @@ def run_surrogate_growth(n=96, kappa=1.0, tau_ldg=0.0, target=44, every=128, max
     }
 
 
+def run_sizes(sizes=(64, 96, 128, 192, 256, 384, 512), site_updates=2.0e9):
+    """The autotuned step on the O2 workload at several lattice sizes, FP32 and
+    FP64: schedule picked, MLUPS over about `site_updates` site updates, and
+    the kernels' times per launch.  Up to 128^3 the fields that the Q-side
+    kernels read (Q, u, the stress) fit in the 256 MB last-level cache
+    between kernels; beyond, they come from HBM."""
+    import torch
+
+    from paper_0901_3293_amd import hlb
+    from paper_0901_3293_amd import inputs as I
+
+    rows = []
+    for n in sizes:
+        p, Q, u, rho = I.bpii_case(n=n)
+        for prec in ("fp32", "fp64"):
+            s = hlb.Solver((n, n, n), prec)
+            s.set_params(p)
+            s.set_fields(Q, u, rho)
+            sched, tz, _ = s.autotune(20)
+            steps = max(20, int(site_updates / n ** 3))
+            s.step(5)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(s.stream)
+            s.step(steps)
+            ev1.record(s.stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / steps
+            km = s.step_timed(5)
+            rows.append({"n": n, "precision": prec, "schedule": {"name": sched, "tz": tz}, "steps": steps,
+                         "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3,
+                         "kernel_us_per_launch": {k: v / 5 * 1e3 for k, v in km.items() if v > 0}})
+            log(f"bench: size {n}^3 {prec}: {sched} tz {tz}, {rows[-1]['mlups']:.0f} MLUPS")
+            s.close()
+            del s
+            torch.cuda.empty_cache()
+        del Q, u, rho
+    return {"workload": "blue-phase O2 lattice n^3 (cells of 32), autotuned schedule", "rows": rows}
+
+
 def run_slab(steps=20000, every=100, kappas=(0.5, 0.8, 1.0), prec="fp32"):
     """The domain-growth slab (64 x 64 x 256, O2 seed for z < 32 inside an
     x-helix, tau_LdG = 0) for each chirality: `steps` steps with the
@@ -651,7 +692,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "batched", "surrogate", "surrogate-mixed", "network", "order",
-                                       "slab"], default=None,
+                                       "slab", "sizes"], default=None,
                     help="run one leg only (profiling runs)")
     ap.add_argument("--coupling", choices=["force", "split"], default="force",
                     help="fluid coupling of the --only fp32/fp64 profiling legs")
@@ -706,9 +747,11 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy probe 512 MiB x3 done")
         del src, dst
-    if a.only in ("batched", "surrogate", "surrogate-mixed", "network", "order", "slab"):
+    if a.only in ("batched", "surrogate", "surrogate-mixed", "network", "order", "slab", "sizes"):
         if a.only == "order":
             out = run_order(a.n)
+        elif a.only == "sizes":
+            out = run_sizes()
         elif a.only == "slab":
             out = run_slab()
         elif a.only == "batched":
