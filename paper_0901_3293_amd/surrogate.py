@@ -4,7 +4,7 @@ The surrogate replaces k solver steps by one application of a small 3D CNN
 that maps the current state (Q, u) and the recent history of Q (the last
 k-step increment d1 and its change s2) to the increment of Q over the next k
 steps, as a correction to the extrapolation d1 + beta s2.  The plain step
-stays the judge of its error: every M-th jump is repeated with k plain steps
+checks its error: every M-th jump is repeated with k plain steps
 and the whole cycle is redone with plain steps when the relative residual
 reaches a threshold (``hlb_surrogate_advance``).
 
