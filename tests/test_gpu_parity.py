@@ -190,6 +190,26 @@ def test_deterministic(H, sched):
         assert t1[0] == t2[0] and t1[2] == t2[2] and np.array_equal(t1[1], t2[1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("sched", [("sites", 0), ("tiled", 8), ("mixed", 8)])
+def test_isotropic_rest_state_is_exact_fixed_point(H, prec, sched):
+    """Q = 0, u = 0, rho = rho0 (the isotropic phase at rest) is a fixed point
+    of the method: H, the stress and the force vanish, and the populations
+    stay at equilibrium.  It must hold exactly (bitwise zero Q and u, rho =
+    rho0) on a ragged lattice in every schedule and both precisions, the
+    chiral and elastic terms switched on."""
+    shape = (19, 12, 10)
+    nx, ny, nz = shape
+    say("case: isotropic rest state", shape, prec, sched)
+    p = I.PhysParams(K=0.04, q0=0.6, gamma=2.5)
+    s = make(H, p, np.zeros((5, nz, ny, nx)), np.zeros((3, nz, ny, nx)), np.full((nz, ny, nx), p.rho0), prec,
+             sched)
+    s.step(20)
+    Qg, ug, rg = s.fields()
+    assert not Qg.any() and not ug.any()
+    assert np.all(rg == p.rho0)
+
+
 def test_nonfinite_detected(H):
     say("case: nonfinite")
     p, Q, u, rho = I.helix_case(n=8, q0=2 * math.pi / 8)
