@@ -383,40 +383,44 @@ __global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGr
     LQ.load(Qin, N, wrapi(B.z0, G.nz) * sxy, sQ[sn]);
     LU.load(u, N, wrapi(B.z0 - 1, G.nz) * sxy, sU[sc]);
     LU.load(u, N, wrapi(B.z0, G.nz) * sxy, sU[sn]);
-    // Q and u of plane z0 - 2 at the own site (the ring's first predictor is
-    // at plane z0, after a rotation)
-    T qm[5] = {T(0), T(0), T(0), T(0), T(0)}, um[3] = {T(0), T(0), T(0)};
+    // Plane state of the own point in two register sets that swap roles from
+    // one plane to the next (the loop is unrolled by two, so nothing is
+    // copied): one holds Q, u and, on tile sites, W of plane p-1, the other
+    // receives those of plane p.  First Q and u of plane z0 - 2 (the ring's
+    // first predictor is at plane z0).
+    T qA[5] = {T(0), T(0), T(0), T(0), T(0)}, uA[3] = {T(0), T(0), T(0)}, WA[3][3], qB[5], uB[3], WB[3][3];
     if (tile) {
         const int o = wrapi(B.z0 - 2, G.nz) * sxy + wrapi(B.x0 - 2 + rc % Shape::RX, G.nx)
                     + G.nx * wrapi(B.y0 - 2 + rc / Shape::RX, G.ny);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) qm[k] = Qin[size_t(k) * N + o];
+        for (int k = 0; k < 5; ++k) qA[k] = Qin[size_t(k) * N + o];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) um[a] = u[size_t(a) * N + o];
+        for (int a = 0; a < 3; ++a) uA[a] = u[size_t(a) * N + o];
     }
     __syncthreads();
 
-    T Wm[3][3] = {};                                // W at the own site, plane p-1
-    T qs2[5] = {T(0), T(0), T(0), T(0), T(0)};      // Q* at the own site, plane p-2
+    T qs2[5] = {T(0), T(0), T(0), T(0), T(0)};  // Q* at the own site, plane p-2
     constexpr int NQ = PlaneLoader<5>::NL, NU = PlaneLoader<3>::NL;
     T preQ[NQ], preU[NU];
-    for (int p = B.z0 - 1; p <= B.z1; ++p) {
+    auto plane = [&](int p, const T (&qmm)[5], const T (&umm)[3], const T (&Wmm)[3][3], T (&q0)[5], T (&u0)[3],
+                     T (&W0)[3][3]) __attribute__((always_inline)) {
         const bool more = p + 2 <= B.z1 + 1;
         if (more) {
             LQ.fetch(Qin, N, wrapi(p + 2, G.nz) * sxy, preQ);
             LU.fetch(u, N, wrapi(p + 2, G.nz) * sxy, preU);
         }
-        T q0[5] = {}, u0[3] = {}, W0[3][3] = {}, qs0[5] = {};
+        T qs0[5];
         if (eval) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) q0[k] = sQ[sc][k * Shape::RN + rc];
 #pragma unroll
             for (int a = 0; a < 3; ++a) u0[a] = sU[sc][a * Shape::RN + rc];
         }
-        if (eval && (tile || (p >= B.z0 && p < B.z1))) {
+        const bool pred = eval && (tile || (p >= B.z0 && p < B.z1));
+        if (pred) {
             T q[5], d[3][5], lap[5], uc[3], R[5];
-            stencil_staged(qm, sQ[sc], sQ[sn], rc, q, d, lap);
-            velocity_staged(um, sU[sc], sU[sn], rc, uc, W0);
+            stencil_staged(qmm, sQ[sc], sQ[sn], rc, q, d, lap);
+            velocity_staged(umm, sU[sc], sU[sn], rc, uc, W0);
             site_rhs(c, q, d, lap, uc, W0, R);
 #pragma unroll
             for (int k = 0; k < 5; ++k) qs0[k] = q[k] + R[k];
@@ -424,11 +428,11 @@ __global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGr
         if (tile && p - 1 >= B.z0) {
             T q[5], d[3][5], lap[5], R[5];
             stencil_eval(qs2, sS, qs0, pc, q, d, lap);
-            site_rhs(c, q, d, lap, um, Wm, R);
+            site_rhs(c, q, d, lap, umm, Wmm, R);
             if (mine) {
                 const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) Qout[k * N + o] = T(0.5) * (qm[k] + q[k] + R[k]);
+                for (int k = 0; k < 5; ++k) Qout[k * N + o] = T(0.5) * (qmm[k] + q[k] + R[k]);
             }
 #pragma unroll
             for (int k = 0; k < 5; ++k) qs2[k] = q[k];
@@ -444,7 +448,7 @@ __global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGr
             nan_fill(sS, 5 * Shape::PN);
             __syncthreads();
         }
-        if (eval && (tile || (p >= B.z0 && p < B.z1)))
+        if (pred)
 #pragma unroll
             for (int k = 0; k < 5; ++k) sS[k * Shape::PN + pc] = qs0[k];
         if (more) {
@@ -452,20 +456,31 @@ __global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGr
             LU.store(preU, sU[sc]);
         }
         __syncthreads();
-        if (eval) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) qm[k] = q0[k];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) um[a] = u0[a];
-        }
-        if (tile)
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b2 = 0; b2 < 3; ++b2) Wm[a][b2] = W0[a][b2];
         const int o = sc;
         sc = sn;
         sn = o;
+    };
+    int p = B.z0 - 1;
+    if constexpr (sizeof(T) == 4) {
+        for (; p + 1 <= B.z1; p += 2) {
+            plane(p, qA, uA, WA, qB, uB, WB);
+            plane(p + 1, qB, uB, WB, qA, uA, WA);
+        }
+        if (p <= B.z1) plane(p, qA, uA, WA, qB, uB, WB);
+    } else {
+        // FP64: a second copy of the plane code costs more registers than the
+        // copies of the plane state it saves
+        for (; p <= B.z1; ++p) {
+            plane(p, qA, uA, WA, qB, uB, WB);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) qA[k] = qB[k];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                uA[a] = uB[a];
+#pragma unroll
+                for (int b2 = 0; b2 < 3; ++b2) WA[a][b2] = WB[a][b2];
+            }
+        }
     }
 }
 
