@@ -383,11 +383,11 @@ __global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGr
     LQ.load(Qin, N, wrapi(B.z0, G.nz) * sxy, sQ[sn]);
     LU.load(u, N, wrapi(B.z0 - 1, G.nz) * sxy, sU[sc]);
     LU.load(u, N, wrapi(B.z0, G.nz) * sxy, sU[sn]);
-    // Plane state of the own point in two register sets that swap roles from
-    // one plane to the next (the loop is unrolled by two, so nothing is
-    // copied): one holds Q, u and, on tile sites, W of plane p-1, the other
-    // receives those of plane p.  First Q and u of plane z0 - 2 (the ring's
-    // first predictor is at plane z0).
+    // Plane state of the own point in two register sets: one holds Q, u and,
+    // on tile sites, W of plane p-1, the other receives those of plane p.  In
+    // FP32 they swap roles from one plane to the next (the loop below is
+    // unrolled by two); in FP64 the new set is copied over the old.  First Q
+    // and u of plane z0 - 2 (the ring's first predictor is at plane z0).
     T qA[5] = {T(0), T(0), T(0), T(0), T(0)}, uA[3] = {T(0), T(0), T(0)}, WA[3][3], qB[5], uB[3], WB[3][3];
     if (tile) {
         const int o = wrapi(B.z0 - 2, G.nz) * sxy + wrapi(B.x0 - 2 + rc % Shape::RX, G.nx)

@@ -184,3 +184,39 @@ def test_noalloc_totals_reject_large_lattice_before_gpu_work(H):
     assert "26843136" in L.hlb_last_error(c.ctx).decode()
     assert L.hlb_get_totals_noalloc(c.ctx, ctypes.byref(m), None, None) == -6
     c.close()
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/hlb.h is a C header: a C99 program that takes the address of
+    every declared function compiles with -pedantic -Werror, links against
+    libhlb.so and, on the CPU, gets the documented workspace size and the
+    reduced-unit mapping (Sec. 2.1, Eqs. (9)-(10)) through it."""
+    import shutil
+    import subprocess
+
+    from paper_0901_3293_amd import hlb
+
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = sorted(declared_functions())
+    src = tmp_path / "abi.c"
+    src.write_text(
+        "#include <stdio.h>\n#include \"hlb.h\"\n"
+        "typedef void (*fn)(void);\n"
+        "static const fn all[] = {" + ", ".join(f"(fn)&{n}" for n in names) + "};\n"
+        "int main(void)\n{\n"
+        "    hlb_fe_params fe;\n"
+        "    size_t b = hlb_workspace_bytes(128, 128, 128, HLB_FP32);\n"
+        "    int rc = hlb_fe_from_reduced(1.0, 0.0, 0.39269908169872414, 0.01, &fe);\n"
+        "    printf(\"%zu %d %.17g %u\\n\", b, rc, fe.gamma, (unsigned)(sizeof(all) / sizeof(all[0])));\n"
+        "    return 0;\n}\n")
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(hlb.LIB_PATH)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I" + os.path.join(ROOT, "include"), str(src), "-L" + libdir, "-lhlb",
+                    "-Wl,-rpath," + libdir, "-o", str(exe)], check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert int(out[0]) == hlb.lib().hlb_workspace_bytes(128, 128, 128, hlb.HLB_FP32) > 0
+    assert int(out[1]) == 0 and float(out[2]) == pytest.approx(3.0, rel=1e-15)
+    assert int(out[3]) == len(names)
