@@ -143,8 +143,9 @@ __device__ __forceinline__ Coef<T> uni(const Coef<T> &c)
 
 // The items [lo, hi) of this block's group, taken by its `per` blocks in
 // turn starting at `rank`.  STREAM: nontemporal population loads and stores
-// in the LB phase (see pop_load in sitekern.h); measured faster for the phase
-// kernels in cache groups, slower for the persistent kernel.
+// in the LB phase (see pop_load in sitekern.h), which both launch forms use:
+// the populations are read and written once per step, and streaming them
+// leaves the last-level cache to the cache group's Q, u and stress.
 template <typename T, int PH, bool STREAM = false>
 __device__ __forceinline__ void run_phase(Rep<T> *__restrict__ reps, const int4 *__restrict__ items, int lo, int hi,
                                           int rank, int per, int step)
@@ -210,7 +211,7 @@ __device__ __forceinline__ void run_phase_claimed(Rep<T> *__restrict__ reps, con
     while (it >= 0) {
         int nxt = -1;
         if (threadIdx.x == 0) nxt = claim();
-        run_phase<T, PH>(reps, items, lo + it, lo + it + 1, 0, 1, step);
+        run_phase<T, PH, true>(reps, items, lo + it, lo + it + 1, 0, 1, step);
         if (threadIdx.x == 0) s_item[slot ^ 1] = nxt;
         __syncthreads();
         slot ^= 1;

@@ -106,8 +106,8 @@ __device__ __forceinline__ unsigned pull_off(const Off<T> &O, int cx, int cy, in
 // last-level cache between the kernels of a step.  (The predicted
 // populations of the first D3Q15 pass are read once, by the second pass right
 // after it, but at 15 values per site they are too many to stay cached beside
-// the rest: they are streamed too.)  The batched kernels keep a cache group's
-// populations resident on purpose and use plain accesses.
+// the rest: they are streamed too.)  The batched kernels stream them as
+// well, so that a cache group's other fields stay in the last-level cache.
 template <bool STREAM, typename T>
 __device__ __forceinline__ T pop_load(const T *P, unsigned b)
 {
