@@ -238,7 +238,8 @@ int hlb_set_state(hlb_ctx *ctx, const void *host_buf, size_t nbytes);
  * thread (stress to HBM, LB with its divergence, predictor, corrector in
  * place).  HLB_SCHED_TILED: three sweeps in which 2.5D z-marching LDS tiles
  * hold the stress and the predictor stage (recomputed on a one-site halo
- * ring), tz planes per tile column (0: 16).  HLB_SCHED_MIXED: the per-site
+ * ring; tiles of 32 x 8 sites in FP32 and 16 x 12 in FP64), tz planes per
+ * tile column (0: 16).  HLB_SCHED_MIXED: the per-site
  * stress and LB sweeps, then the tiled predictor-corrector.  All give the
  * same step to rounding.  The default is HLB_SCHED_SITES.  With the split
  * coupling or the D3Q15 scheme, HLB_SCHED_TILED is rejected (HLB_ERR_STATE). */
@@ -257,8 +258,9 @@ enum { HLB_DEBUG_NAN_LDS = 1 };
 int hlb_set_debug(hlb_ctx *ctx, int flags);
 
 /* Autotuner: time trial_steps steps of every candidate schedule (per-site;
- * tiled and mixed with tz = 8, 16, 32; no tiled with the split coupling or
- * the D3Q15 scheme) on this context's lattice and precision with HIP events
+ * tiled and mixed with tz = 8, 16, 32 and the tz whose tiled launch fills the
+ * device's resident block slots once or twice; no tiled with the split
+ * coupling or the D3Q15 scheme) on this context's lattice and precision with HIP events
  * on its stream, in two passes over the candidates (each scored by its faster
  * pass, 2 untimed steps before every trial), keep the fastest, and put the
  * state back as it was

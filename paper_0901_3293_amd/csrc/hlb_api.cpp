@@ -353,17 +353,27 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
     struct Cand {
         int sched, tz;
     };
-    const Cand cands[] = {{HLB_SCHED_SITES, 0}, {HLB_SCHED_TILED, 8},  {HLB_SCHED_TILED, 16},
-                          {HLB_SCHED_TILED, 32}, {HLB_SCHED_MIXED, 8}, {HLB_SCHED_MIXED, 16},
-                          {HLB_SCHED_MIXED, 32}};
+    // z-chunks of 8, 16 and 32 planes, and those whose tiled launches fill the
+    // device's resident block slots once or twice
+    int tzs[5] = {8, 16, 32, hlb::tile_tz_fill(c->D, 1), hlb::tile_tz_fill(c->D, 2)};
+    int ntz = 3;
+    for (int i = 3; i < 5; ++i) {
+        bool dup = tzs[i] < 1;
+        for (int j = 0; j < ntz; ++j) dup = dup || tzs[j] == tzs[i];
+        if (!dup) tzs[ntz++] = tzs[i];
+    }
+    Cand cands[1 + 2 * 5];
+    int NC = 0;
+    cands[NC++] = {HLB_SCHED_SITES, 0};
+    for (int j = 0; j < ntz; ++j) cands[NC++] = {HLB_SCHED_TILED, tzs[j]};
+    for (int j = 0; j < ntz; ++j) cands[NC++] = {HLB_SCHED_MIXED, tzs[j]};
     hipEvent_t a, b;
     HIP_TRY(c, hipEventCreate(&a));
     HIP_TRY(c, hipEventCreate(&b));
     // Two passes over the candidates, each candidate scored by its faster
     // pass: the first trials of a call can run before the clocks and caches
     // have settled, which would penalise whichever candidate comes first.
-    constexpr int NC = sizeof(cands) / sizeof(cands[0]);
-    double t[NC];
+    double t[1 + 2 * 5];
     for (int i = 0; i < NC; ++i) t[i] = 1e300;
     for (int pass = 0; pass < 2; ++pass) {
         for (int i = 0; i < NC; ++i) {

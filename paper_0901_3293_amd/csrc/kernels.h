@@ -106,6 +106,10 @@ struct KernelTimer {
 // event pair is recorded on the stream around every launch.
 hipError_t run_steps(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer = nullptr);
 
+// z-chunk of the tiled kernels whose blocks fill the current device's
+// resident block slots `rounds` times over (0 if none does).
+int tile_tz_fill(const Device &D, int rounds);
+
 // stage: device FP64 [rho N][u 3N][Q 5N] (must not alias g[gcur] or Q[qcur]);
 // writes g[gcur] and Q[qcur], zeroes u.
 hipError_t run_init(Device &D, const PhysParams &p, const double *stage);

@@ -28,6 +28,8 @@
 // its predicted populations so (pop_load / pop_store in sitekern.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "site.h"
 #include "sitekern.h"
@@ -38,8 +40,6 @@ namespace hlb {
 namespace {
 
 constexpr int BLK = 256;  // per-site kernels
-using Shape = KernelTile;
-constexpr int TX = Shape::TX, TY = Shape::TY;
 
 // ---------------------------------------------------------------- helpers
 
@@ -83,7 +83,7 @@ __device__ __forceinline__ void nan_fill(T *slot, int n)
 // two-site halo in x and y (periodic wrap of the global coordinates) by the
 // NB threads of a block.  The element -> (component, in-plane offset)
 // assignment is computed once per block.
-template <int NC>
+template <class Shape, int NC>
 struct PlaneLoader {
     static constexpr int NE = NC * Shape::RN;
     static constexpr int NL = (NE + Shape::NB - 1) / Shape::NB;
@@ -144,7 +144,7 @@ struct PlaneLoader {
 // halo, RN points per component), the z-neighbours from `lo` (plane p-1,
 // registers of the thread owning the point) and the staged slot `hi`
 // (plane p+1).
-template <typename T>
+template <class Shape, typename T>
 __device__ __forceinline__ void stencil_staged(const T lo[5], const T *mid, const T *hi, int r, T q[5],
                                                T d[3][5], T lap[5])
 {
@@ -164,7 +164,7 @@ __device__ __forceinline__ void stencil_staged(const T lo[5], const T *mid, cons
 }
 
 // Same for the three-slot form (all of planes p-1, p, p+1 staged).
-template <typename T>
+template <class Shape, typename T>
 __device__ __forceinline__ void stencil_ring(const T *lo, const T *mid, const T *hi, int r, T q[5],
                                              T d[3][5], T lap[5])
 {
@@ -186,7 +186,7 @@ __device__ __forceinline__ void stencil_ring(const T *lo, const T *mid, const T 
 // Derivatives of a 5-component field held on the evaluation plane (PX x PY,
 // PN points per component) at point r: value and in-plane neighbours from
 // `mid`, z-neighbours from registers.
-template <typename T>
+template <class Shape, typename T>
 __device__ __forceinline__ void stencil_eval(const T lo[5], const T *mid, const T hi[5], int r, T q[5],
                                              T d[3][5], T lap[5])
 {
@@ -207,7 +207,7 @@ __device__ __forceinline__ void stencil_eval(const T lo[5], const T *mid, const 
 
 // u and its centred gradient W_ab = d_b u_a at staged coordinate r of plane
 // p: in-plane from `mid`, z from `lo` (registers, plane p-1) and `hi`.
-template <typename T>
+template <class Shape, typename T>
 __device__ __forceinline__ void velocity_staged(const T lo[3], const T *mid, const T *hi, int r, T uc[3],
                                                 T W[3][3])
 {
@@ -226,6 +226,7 @@ struct Block {
     bool ok;
 };
 
+template <class Shape>
 __device__ __forceinline__ Block block_of(const Geom &G, const TileGrid &tg)
 {
     Block b;
@@ -253,13 +254,14 @@ __device__ __forceinline__ Block block_of(const Geom &G, const TileGrid &tg)
 // FP32: at most 96 registers, five waves per SIMD (three blocks per CU); in
 // FP64 a bound that would let a second block in spills and runs slower.
 template <typename T, bool WITH_F>
-__global__ __launch_bounds__(Shape::NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 5))) void k_qforce(Geom G, Coef<T> c, TileGrid tg,
+__global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 5))) void k_qforce(Geom G, Coef<T> c, TileGrid tg,
                                                       const T *__restrict__ Q, T *__restrict__ F,
                                                       double *__restrict__ fpart, bool dbg_nan)
 {
+    using Shape = KernelTile<T>;
     __shared__ T sQ[3][5 * Shape::RN];
     __shared__ T sP[6 * Shape::PN];
-    const Block B = block_of(G, tg);
+    const Block B = block_of<Shape>(G, tg);
     if (!B.ok) return;
     if (dbg_nan) {
         nan_fill(&sQ[0][0], 3 * 5 * Shape::RN);
@@ -275,7 +277,7 @@ __global__ __launch_bounds__(Shape::NB) __attribute__((amdgpu_waves_per_eu(sizeo
     const int gx = B.x0 + t % Shape::TX, gy = B.y0 + t / Shape::TX;
     const bool mine = tile && gx < G.nx && gy < G.ny;
 
-    PlaneLoader<5> L;
+    PlaneLoader<Shape, 5> L;
     L.init(G, B.x0, B.y0);
     int sb = 0, sm = 1, st = 2;  // slots of planes p-1, p, p+1
     L.load(Q, N, wrapi(B.z0 - 2, G.nz) * sxy, sQ[sb]);
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(Shape::NB) __attribute__((amdgpu_waves_per_eu(sizeo
 
     T Fin[3] = {T(0), T(0), T(0)}, Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
     double facc = 0.0;
-    constexpr int NL = PlaneLoader<5>::NL;
+    constexpr int NL = PlaneLoader<Shape, 5>::NL;
     T pre[NL];
     for (int p = B.z0 - 1; p <= B.z1; ++p) {
         const bool more = p + 2 <= B.z1 + 1;
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(Shape::NB) __attribute__((amdgpu_waves_per_eu(sizeo
         // ring points: only the planes whose in-plane divergence is output
         if (eval && (tile || (p >= B.z0 && p < B.z1))) {
             T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
-            stencil_ring(sQ[sb], sQ[sm], sQ[st], rc, q, d, lap);
+            stencil_ring<Shape>(sQ[sb], sQ[sm], sQ[st], rc, q, d, lap);
             site_stress(c, q, d, lap, P, fd, H);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -350,14 +352,15 @@ __global__ __launch_bounds__(Shape::NB) __attribute__((amdgpu_waves_per_eu(sizeo
 // predictor of plane p-1.  After a barrier Q*(p) replaces Q*(p-1) in LDS and
 // the plane p+2, fetched into registers at the start, replaces plane p.
 template <typename T>
-__global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGrid tg,
+__global__ __launch_bounds__(KernelTile<T>::NB) void k_qupdate(Geom G, Coef<T> c, TileGrid tg,
                                                        const T *__restrict__ Qin, const T *__restrict__ u,
                                                        T *__restrict__ Qout, bool dbg_nan)
 {
+    using Shape = KernelTile<T>;
     __shared__ T sQ[2][5 * Shape::RN];
     __shared__ T sU[2][3 * Shape::RN];
     __shared__ T sS[5 * Shape::PN];
-    const Block B = block_of(G, tg);
+    const Block B = block_of<Shape>(G, tg);
     if (!B.ok) return;
     if (dbg_nan) {
         nan_fill(&sQ[0][0], 2 * 5 * Shape::RN);
@@ -374,8 +377,8 @@ __global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGr
     const int gx = B.x0 + t % Shape::TX, gy = B.y0 + t / Shape::TX;
     const bool mine = tile && gx < G.nx && gy < G.ny;
 
-    PlaneLoader<5> LQ;
-    PlaneLoader<3> LU;
+    PlaneLoader<Shape, 5> LQ;
+    PlaneLoader<Shape, 3> LU;
     LQ.init(G, B.x0, B.y0);
     LU.init(G, B.x0, B.y0);
     int sc = 0, sn = 1;  // slots of planes p, p+1
@@ -400,7 +403,7 @@ __global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGr
     __syncthreads();
 
     T qs2[5] = {T(0), T(0), T(0), T(0), T(0)};  // Q* at the own site, plane p-2
-    constexpr int NQ = PlaneLoader<5>::NL, NU = PlaneLoader<3>::NL;
+    constexpr int NQ = PlaneLoader<Shape, 5>::NL, NU = PlaneLoader<Shape, 3>::NL;
     T preQ[NQ], preU[NU];
     auto plane = [&](int p, const T (&qmm)[5], const T (&umm)[3], const T (&Wmm)[3][3], T (&q0)[5], T (&u0)[3],
                      T (&W0)[3][3]) __attribute__((always_inline)) {
@@ -419,15 +422,15 @@ __global__ __launch_bounds__(Shape::NB) void k_qupdate(Geom G, Coef<T> c, TileGr
         const bool pred = eval && (tile || (p >= B.z0 && p < B.z1));
         if (pred) {
             T q[5], d[3][5], lap[5], uc[3], R[5];
-            stencil_staged(qmm, sQ[sc], sQ[sn], rc, q, d, lap);
-            velocity_staged(umm, sU[sc], sU[sn], rc, uc, W0);
+            stencil_staged<Shape>(qmm, sQ[sc], sQ[sn], rc, q, d, lap);
+            velocity_staged<Shape>(umm, sU[sc], sU[sn], rc, uc, W0);
             site_rhs(c, q, d, lap, uc, W0, R);
 #pragma unroll
             for (int k = 0; k < 5; ++k) qs0[k] = q[k] + R[k];
         }
         if (tile && p - 1 >= B.z0) {
             T q[5], d[3][5], lap[5], R[5];
-            stencil_eval(qs2, sS, qs0, pc, q, d, lap);
+            stencil_eval<Shape>(qs2, sS, qs0, pc, q, d, lap);
             site_rhs(c, q, d, lap, umm, Wmm, R);
             if (mine) {
                 const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
@@ -973,6 +976,25 @@ struct Marks {
 
 int tile_tz(const Device &D) { return D.tz > 0 ? D.tz : 16; }
 
+// z-chunk for which the blocks of the tiled kernels fill the device's
+// resident block slots `rounds` times: a launch of whole rounds leaves no CU
+// idle at the end (0 if the tile columns alone exceed the slots).
+template <typename T>
+int tz_fill_t(const Device &D, int rounds)
+{
+    using S = KernelTile<T>;
+    int dev = 0, cus = 0, bq = 0, bf = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bq, k_qupdate<T>, S::NB, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, k_qforce<T, false>, S::NB, 0) != hipSuccess) return 0;
+    const long long slots = (long long)cus * std::max(1, std::min(bq, bf)) * rounds;
+    const long long cols = (long long)((D.G.nx + S::TX - 1) / S::TX) * ((D.G.ny + S::TY - 1) / S::TY);
+    const long long chunks = slots / cols;
+    if (chunks < 1) return 0;
+    return int((D.G.nz + chunks - 1) / chunks);
+}
+
 template <typename T, bool SPLIT>
 hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer)
 {
@@ -990,7 +1012,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
         k_fill<T><<<1024, BLK, 0, D.stream>>>(u, 3 * size_t(G.N), T(0));
     if (D.sched == SCHED_SITES || D.sched == SCHED_MIXED) {
         const bool fused_q = D.sched == SCHED_MIXED;
-        const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, TX, TY, tile_tz(D));
+        const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, KernelTile<T>::TX, KernelTile<T>::TY, tile_tz(D));
         for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
             T *Q = static_cast<T *>(D.Q[D.qcur]);
             T *Qs = static_cast<T *>(D.Q[D.qcur ^ 1]);
@@ -1017,7 +1039,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             if (fused_q) {
                 if (e == hipSuccess)
                     e = mark(K_QUPDATE, [&] {
-                        k_qupdate<T><<<tg.launch, Shape::NB, 0, D.stream>>>(G, c, tg, Q, u, Qs, dbg_nan);
+                        k_qupdate<T><<<tg.launch, KernelTile<T>::NB, 0, D.stream>>>(G, c, tg, Q, u, Qs, dbg_nan);
                     });
                 D.qcur ^= 1;
             } else {
@@ -1028,7 +1050,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             }
         }
     } else {
-        const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, TX, TY, tile_tz(D));
+        const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, KernelTile<T>::TX, KernelTile<T>::TY, tile_tz(D));
         for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
             T *Qn = static_cast<T *>(D.Q[D.qcur]);
             T *Qn1 = static_cast<T *>(D.Q[D.qcur ^ 1]);
@@ -1036,7 +1058,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
                 T *gin = static_cast<T *>(D.g[D.gcur]);
                 T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
                 e = mark(K_QFORCE, [&] {
-                    k_qforce<T, false><<<tg.launch, Shape::NB, 0, D.stream>>>(G, c, tg, Qn, Pi, nullptr,
+                    k_qforce<T, false><<<tg.launch, KernelTile<T>::NB, 0, D.stream>>>(G, c, tg, Qn, Pi, nullptr,
                                                                               dbg_nan);
                 });
                 if (e == hipSuccess)
@@ -1045,7 +1067,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             }
             if (e == hipSuccess)
                 e = mark(K_QUPDATE, [&] {
-                    k_qupdate<T><<<tg.launch, Shape::NB, 0, D.stream>>>(G, c, tg, Qn, u, Qn1, dbg_nan);
+                    k_qupdate<T><<<tg.launch, KernelTile<T>::NB, 0, D.stream>>>(G, c, tg, Qn, u, Qn1, dbg_nan);
                 });
             D.qcur ^= 1;
         }
@@ -1185,6 +1207,11 @@ hipError_t run_steps(Device &D, const PhysParams &p, int nsteps, KernelTimer *ti
     if (p.flow == FLOW_SPLIT)
         return D.fp32 ? steps_t<float, true>(D, p, nsteps, timer) : steps_t<double, true>(D, p, nsteps, timer);
     return D.fp32 ? steps_t<float, false>(D, p, nsteps, timer) : steps_t<double, false>(D, p, nsteps, timer);
+}
+
+int tile_tz_fill(const Device &D, int rounds)
+{
+    return D.fp32 ? tz_fill_t<float>(D, rounds) : tz_fill_t<double>(D, rounds);
 }
 
 hipError_t run_init(Device &D, const PhysParams &p, const double *stage)

@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace hlb {
 
 template <int TX_, int TY_>
@@ -42,8 +44,14 @@ struct TileShape {
     }
 };
 
-// The tile of the fused Q-side kernels: 32 x 8 sites per block.
-using KernelTile = TileShape<32, 8>;
+// The tile of the fused Q-side kernels, per precision.  FP32: 32 x 8 sites
+// (340 evaluation points, six waves; the FP32 kernels fit five waves per
+// SIMD).  FP64: 16 x 12 sites (252 points, four waves): the FP64 kernels hold
+// about 190 and 254 registers, two waves per SIMD, so two four-wave blocks
+// share a CU where a six-wave block would run alone with a quarter of the
+// CU's wave slots empty.
+template <typename T>
+using KernelTile = typename std::conditional<sizeof(T) == 8, TileShape<16, 12>, TileShape<32, 8>>::type;
 
 __host__ __device__ __forceinline__ int wrapi(int v, int n)
 {

@@ -11,7 +11,8 @@
 // not its thread's own, is counted too.  argv[1] plants a mistake in the
 // staging: 0 none, 1 the last halo column is never staged, 2 the first halo
 // row is never staged, 3 the component split of k = 1 is taken 8 elements late.
-// Prints "nan bad cover" summed over a set of tile positions and lattices.
+// Prints "nan bad cover" summed over a set of tile positions and lattices,
+// one line for each tile shape (FP32, FP64).
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -20,17 +21,19 @@
 #include "../../paper_0901_3293_amd/csrc/tiles.h"
 
 using hlb::wrapi;
-using S = hlb::KernelTile;
-using M = hlb::TileMap<S>;
 
 static double tag(int c, int off) { return 1e7 * c + off; }
 
-int main(int argc, char **argv)
+template <class S>
+static void check(int drop)
 {
-    const int drop = argc > 1 ? std::atoi(argv[1]) : 0;
+    using M = hlb::TileMap<S>;
     const int NC = 5;
-    const int cases[][4] = {{128, 128, 0, 0},   {128, 128, 96, 120}, {100, 37, 96, 32}, {4, 4, 0, 0},
-                            {13, 7, 0, 0},      {70, 5, 64, 0},      {255, 129, 224, 128}, {33, 9, 32, 8}};
+    // lattice (nx, ny) and tile origin (x0, y0): origins of both tile shapes,
+    // last tiles that overhang the lattice, lattices smaller than a tile
+    const int cases[][4] = {{128, 128, 0, 0},     {128, 128, 96, 120},  {100, 37, 96, 32}, {4, 4, 0, 0},
+                            {13, 7, 0, 0},        {70, 5, 64, 0},       {255, 129, 224, 128}, {33, 9, 32, 8},
+                            {128, 128, 112, 120}, {100, 37, 96, 36},    {255, 129, 240, 120}, {33, 9, 32, 0}};
     long nan = 0, bad = 0, cover = 0;
     for (const auto &cs : cases) {
         const int nx = cs[0], ny = cs[1], x0 = cs[2], y0 = cs[3];
@@ -76,5 +79,12 @@ int main(int argc, char **argv)
         for (int v : evaluated) cover += v != 1;
     }
     std::printf("%ld %ld %ld\n", nan, bad, cover);
+}
+
+int main(int argc, char **argv)
+{
+    const int drop = argc > 1 ? std::atoi(argv[1]) : 0;
+    check<hlb::KernelTile<float>>(drop);   // one line per tile shape
+    check<hlb::KernelTile<double>>(drop);
     return 0;
 }

@@ -29,21 +29,24 @@ def checker(tmp_path_factory):
 
 
 def run(exe, drop):
-    out = subprocess.run([exe, str(drop)], capture_output=True, text=True, check=True).stdout.split()
-    return tuple(int(v) for v in out)
+    """(nan, bad, cover) for each tile shape: FP32's, then FP64's."""
+    out = subprocess.run([exe, str(drop)], capture_output=True, text=True, check=True).stdout
+    rows = [tuple(int(v) for v in line.split()) for line in out.strip().splitlines()]
+    assert len(rows) == 2
+    return rows
 
 
 def test_tile_maps_cover_every_halo_read(checker):
-    nan, bad, cover = run(checker, 0)
-    assert (nan, bad, cover) == (0, 0, 0)
+    for nan, bad, cover in run(checker, 0):
+        assert (nan, bad, cover) == (0, 0, 0)
 
 
 @pytest.mark.parametrize("drop", [1, 2])
 def test_missed_halo_surfaces_as_nan(checker, drop):
-    nan, bad, cover = run(checker, drop)
-    assert nan > 0 and bad == 0
+    for nan, bad, cover in run(checker, drop):
+        assert nan > 0 and bad == 0
 
 
 def test_wrong_component_split_surfaces_as_wrong_values(checker):
-    nan, bad, cover = run(checker, 3)
-    assert bad > 0 and cover == 0
+    for nan, bad, cover in run(checker, 3):
+        assert bad > 0 and cover == 0
