@@ -112,6 +112,58 @@ def test_fp64_ragged_shapes(H, orc, shape, sched):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tiled_any_chunk_depth(H, orc, prec):
+    """The tiled kernels march z-chunks of any depth tz (the autotuner may pick
+    a depth that fills the device's block slots, e.g. 26 or 39 planes): on a
+    ragged lattice (37 x 29 x 23: no side a multiple of a tile side, a prime
+    depth) tz = 1, 2, 3, 5, 7 and 23 against tz = 16 in the tiled and mixed
+    schedules, 6 steps.  A site's arithmetic does not depend on where the
+    chunks start, so FP64 agrees bitwise (and stays within the oracle bars).
+    The FP32 plane loop is unrolled by two, and the compiler fuses
+    multiply-adds differently in the copies of the plane step, so a chunk
+    whose planes fall differently on them rounds a few sites differently (a
+    build with contraction off agrees bitwise at every depth): FP32 is held to
+    1e-6 relative, about 15 units in the last place of the largest Q
+    (measured at most 1.6e-7); a staging or halo mistake at a chunk edge
+    would show as a difference of the order of the field's variation."""
+    shape = (37, 29, 23)
+    rng = np.random.default_rng(37)
+    nx, ny, nz = shape
+    p = I.PhysParams(K=0.02, q0=0.35, gamma=3.1)
+    Q = I.smooth_field(shape, amp=0.2, seed=8) + rng.uniform(-0.02, 0.02, size=(5, nz, ny, nx))
+    u = rng.uniform(-1e-3, 1e-3, size=(3, nz, ny, nx))
+    rho = 1 + rng.uniform(-1e-3, 1e-3, size=(nz, ny, nx))
+    steps = 6
+    ref = None
+    if prec == "fp64":
+        o = orc.State(oracle_params(orc, p), Q, u, rho)
+        o.step(steps)
+        ref = o.fields()
+    for name in ("tiled", "mixed"):
+        base = make(H, p, Q, u, rho, prec, (name, 16))
+        base.step(steps)
+        Qb, ub, rb = base.fields()
+        base.close()
+        for tz in (1, 2, 3, 5, 7, 23):
+            say(f"case: {prec} {name} tz {tz} on 37x29x23, {steps} steps")
+            g = make(H, p, Q, u, rho, prec, (name, tz))
+            g.step(steps)
+            Qg, ug, rg = g.fields()
+            g.close()
+            if prec == "fp64":
+                assert np.array_equal(Qg, Qb) and np.array_equal(ug, ub) and np.array_equal(rg, rb), (name, tz)
+            else:
+                eQ, eu, er = rel(Qg, Qb), rel(ug, ub), rel(rg, rb)
+                say(f"against tz 16: Q {eQ:.2e} u {eu:.2e} rho {er:.2e}")
+                assert eQ <= 1e-6 and eu <= 1e-6 and er <= 1e-6, (name, tz, eQ, eu, er)
+        if ref is not None:
+            Qr, ur, rr = ref
+            eQ, eu, er = rel(Qb, Qr), rel(ub, ur), rel(rb, rr)
+            say(f"{name} vs oracle: Q {eQ:.2e} u {eu:.2e} rho {er:.2e}")
+            assert eQ <= 1e-12 and eu <= 1e-11 and er <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_large_ragged_lattice(H, orc, prec):
     """A 2.2M-site lattice with no power-of-two side (255 x 129 x 67): the
     kernels split site indices up to 2.2M by multiply-high division by 255
