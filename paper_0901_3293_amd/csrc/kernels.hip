@@ -247,25 +247,27 @@ __device__ __forceinline__ Block block_of(const Geom &G, const TileGrid &tg)
 // evaluation plane (a tile site or a ring point).  Per plane p: evaluate the
 // stress at the own point from the staged planes p-1, p, p+1 (ring points
 // only where a tile site needs them), keep its z column in registers and put
-// its x and y columns in LDS; after a barrier the tile threads finish F(p-1)
-// with the z-difference and start F(p) with the in-plane differences; the
-// plane p+2, fetched into registers at the start, then replaces p-1.  With
-// WITH_F the block also sums the free-energy density of its sites.
+// its x and y columns into one of two LDS buffers; the tile threads finish
+// F(p-1) from the other buffer (the stress of plane p-1) and the z columns of
+// planes p and p-2, and the plane p+2, fetched into registers at the start,
+// goes into the fourth staging slot.  One barrier per plane: no slot or
+// buffer is written in the plane in which it is read.  With WITH_F the block
+// also sums the free-energy density of its sites.
 // FP32: at most 96 registers, five waves per SIMD (three blocks per CU); in
-// FP64 a bound that would let a second block in spills and runs slower.
+// FP64 a bound that would let another block in spills and runs slower.
 template <typename T, bool WITH_F>
 __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 5))) void k_qforce(Geom G, Coef<T> c, TileGrid tg,
                                                       const T *__restrict__ Q, T *__restrict__ F,
                                                       double *__restrict__ fpart, bool dbg_nan)
 {
     using Shape = KernelTile<T>;
-    __shared__ T sQ[3][5 * Shape::RN];
-    __shared__ T sP[6 * Shape::PN];
+    __shared__ T sQ[4][5 * Shape::RN];
+    __shared__ T sP[2][6 * Shape::PN];
     const Block B = block_of<Shape>(G, tg);
     if (!B.ok) return;
     if (dbg_nan) {
-        nan_fill(&sQ[0][0], 3 * 5 * Shape::RN);
-        nan_fill(sP, 6 * Shape::PN);
+        nan_fill(&sQ[0][0], 4 * 5 * Shape::RN);
+        nan_fill(&sP[0][0], 2 * 6 * Shape::PN);
         __syncthreads();
     }
     const size_t N = G.N;
@@ -279,60 +281,64 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
 
     PlaneLoader<Shape, 5> L;
     L.init(G, B.x0, B.y0);
-    int sb = 0, sm = 1, st = 2;  // slots of planes p-1, p, p+1
-    L.load(Q, N, wrapi(B.z0 - 2, G.nz) * sxy, sQ[sb]);
-    L.load(Q, N, wrapi(B.z0 - 1, G.nz) * sxy, sQ[sm]);
-    L.load(Q, N, wrapi(B.z0, G.nz) * sxy, sQ[st]);
+    int s0 = 0, s1 = 1, s2 = 2, s3 = 3;  // s1, s2, s3: planes p-1, p, p+1; s0 free
+    L.load(Q, N, wrapi(B.z0 - 2, G.nz) * sxy, sQ[s1]);
+    L.load(Q, N, wrapi(B.z0 - 1, G.nz) * sxy, sQ[s2]);
+    L.load(Q, N, wrapi(B.z0, G.nz) * sxy, sQ[s3]);
     __syncthreads();
 
-    T Fin[3] = {T(0), T(0), T(0)}, Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
+    T Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
     double facc = 0.0;
     constexpr int NL = PlaneLoader<Shape, 5>::NL;
     T pre[NL];
     for (int p = B.z0 - 1; p <= B.z1; ++p) {
         const bool more = p + 2 <= B.z1 + 1;
         if (more) L.fetch(Q, N, wrapi(p + 2, G.nz) * sxy, pre);
+        T *Pc = sP[p & 1];        // stress of plane p (written now)
+        const T *Pp = sP[~p & 1];  // stress of plane p-1 (written in the last plane)
         T Pz[3] = {T(0), T(0), T(0)};
         // ring points: only the planes whose in-plane divergence is output
         if (eval && (tile || (p >= B.z0 && p < B.z1))) {
             T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
-            stencil_ring<Shape>(sQ[sb], sQ[sm], sQ[st], rc, q, d, lap);
+            stencil_ring<Shape>(sQ[s1], sQ[s2], sQ[s3], rc, q, d, lap);
             site_stress(c, q, d, lap, P, fd, H);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                sP[a * Shape::PN + pc] = P[a][0];
-                sP[(3 + a) * Shape::PN + pc] = P[a][1];
+                Pc[a * Shape::PN + pc] = P[a][0];
+                Pc[(3 + a) * Shape::PN + pc] = P[a][1];
                 Pz[a] = P[a][2];
             }
             if (WITH_F && mine && p >= B.z0 && p < B.z1) facc += double(fd);
         }
-        __syncthreads();
         if (tile) {
             if (mine && p - 1 >= B.z0) {
                 const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) F[a * N + o] = T(0.5) * (Fin[a] + (Pz[a] - Pz2[a]));
+                for (int a = 0; a < 3; ++a) {
+                    const T Fin = (Pp[a * Shape::PN + pc + 1] - Pp[a * Shape::PN + pc - 1])
+                                + (Pp[(3 + a) * Shape::PN + pc + Shape::PX] - Pp[(3 + a) * Shape::PN + pc - Shape::PX]);
+                    F[a * N + o] = T(0.5) * (Fin + (Pz[a] - Pz2[a]));
+                }
             }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                Fin[a] = (sP[a * Shape::PN + pc + 1] - sP[a * Shape::PN + pc - 1])
-                       + (sP[(3 + a) * Shape::PN + pc + Shape::PX] - sP[(3 + a) * Shape::PN + pc - Shape::PX]);
                 Pz2[a] = Pz1[a];
                 Pz1[a] = Pz[a];
             }
         }
-        if (dbg_nan) {  // plane p-1 and the stress of plane p are no longer read
+        if (dbg_nan) {  // the free slot and the stress of plane p-1 are no longer read
             __syncthreads();
-            nan_fill(sQ[sb], 5 * Shape::RN);
-            nan_fill(sP, 6 * Shape::PN);
+            nan_fill(sQ[s0], 5 * Shape::RN);
+            nan_fill(const_cast<T *>(Pp), 6 * Shape::PN);
             __syncthreads();
         }
-        if (more) L.store(pre, sQ[sb]);  // plane p-1 is no longer read: it becomes p+2
+        if (more) L.store(pre, sQ[s0]);  // plane p+2 into the free slot
         __syncthreads();
-        const int o = sb;
-        sb = sm;
-        sm = st;
-        st = o;
+        const int o = s0;
+        s0 = s1;
+        s1 = s2;
+        s2 = s3;
+        s3 = o;
     }
     if (WITH_F) {
         double v[1] = {facc};
@@ -349,23 +355,29 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
 // staged plane p+1; ring points only where a tile site needs them); then on
 // the tile threads the corrector at plane p-1 from Q*(p-1) in LDS and
 // Q*(p-2), Q*(p) in registers, with u(p-1) and W(p-1) kept from the
-// predictor of plane p-1.  After a barrier Q*(p) replaces Q*(p-1) in LDS and
-// the plane p+2, fetched into registers at the start, replaces plane p.
+// predictor of plane p-1.  FP32: Q*(p) goes into the other of two LDS
+// buffers and the plane p+2, fetched into registers at the start, into the
+// third staging slot, so a plane takes one barrier.  FP64 (where three slots
+// and two buffers would not leave LDS for two blocks per CU): after a barrier
+// Q*(p) replaces Q*(p-1) in LDS and the plane p+2 replaces plane p, and a
+// second barrier ends the plane.
 template <typename T>
 __global__ __launch_bounds__(KernelTile<T>::NB) void k_qupdate(Geom G, Coef<T> c, TileGrid tg,
                                                        const T *__restrict__ Qin, const T *__restrict__ u,
                                                        T *__restrict__ Qout, bool dbg_nan)
 {
     using Shape = KernelTile<T>;
-    __shared__ T sQ[2][5 * Shape::RN];
-    __shared__ T sU[2][3 * Shape::RN];
-    __shared__ T sS[5 * Shape::PN];
+    constexpr bool ONE = sizeof(T) == 4;      // one barrier per plane
+    constexpr int NQS = ONE ? 3 : 2, NSS = ONE ? 2 : 1;
+    __shared__ T sQ[NQS][5 * Shape::RN];
+    __shared__ T sU[NQS][3 * Shape::RN];
+    __shared__ T sS[NSS][5 * Shape::PN];
     const Block B = block_of<Shape>(G, tg);
     if (!B.ok) return;
     if (dbg_nan) {
-        nan_fill(&sQ[0][0], 2 * 5 * Shape::RN);
-        nan_fill(&sU[0][0], 2 * 3 * Shape::RN);
-        nan_fill(sS, 5 * Shape::PN);
+        nan_fill(&sQ[0][0], NQS * 5 * Shape::RN);
+        nan_fill(&sU[0][0], NQS * 3 * Shape::RN);
+        nan_fill(&sS[0][0], NSS * 5 * Shape::PN);
         __syncthreads();
     }
     const size_t N = G.N;
@@ -381,7 +393,7 @@ __global__ __launch_bounds__(KernelTile<T>::NB) void k_qupdate(Geom G, Coef<T> c
     PlaneLoader<Shape, 3> LU;
     LQ.init(G, B.x0, B.y0);
     LU.init(G, B.x0, B.y0);
-    int sc = 0, sn = 1;  // slots of planes p, p+1
+    int sc = 0, sn = 1, sf = NQS - 1;  // slots of planes p, p+1; FP32: the free slot
     LQ.load(Qin, N, wrapi(B.z0 - 1, G.nz) * sxy, sQ[sc]);
     LQ.load(Qin, N, wrapi(B.z0, G.nz) * sxy, sQ[sn]);
     LU.load(u, N, wrapi(B.z0 - 1, G.nz) * sxy, sU[sc]);
@@ -413,6 +425,8 @@ __global__ __launch_bounds__(KernelTile<T>::NB) void k_qupdate(Geom G, Coef<T> c
             LU.fetch(u, N, wrapi(p + 2, G.nz) * sxy, preU);
         }
         T qs0[5];
+        T *Scur = sS[ONE ? (p & 1) : 0];         // receives Q*(p)
+        const T *Sprev = sS[ONE ? (~p & 1) : 0];  // holds Q*(p-1)
         if (eval) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) q0[k] = sQ[sc][k * Shape::RN + rc];
@@ -427,10 +441,13 @@ __global__ __launch_bounds__(KernelTile<T>::NB) void k_qupdate(Geom G, Coef<T> c
             site_rhs(c, q, d, lap, uc, W0, R);
 #pragma unroll
             for (int k = 0; k < 5; ++k) qs0[k] = q[k] + R[k];
+            if (ONE)
+#pragma unroll
+                for (int k = 0; k < 5; ++k) Scur[k * Shape::PN + pc] = qs0[k];
         }
         if (tile && p - 1 >= B.z0) {
             T q[5], d[3][5], lap[5], R[5];
-            stencil_eval<Shape>(qs2, sS, qs0, pc, q, d, lap);
+            stencil_eval<Shape>(qs2, Sprev, qs0, pc, q, d, lap);
             site_rhs(c, q, d, lap, umm, Wmm, R);
             if (mine) {
                 const size_t o = size_t(p - 1) * sxy + size_t(gy) * G.nx + gx;
@@ -442,26 +459,45 @@ __global__ __launch_bounds__(KernelTile<T>::NB) void k_qupdate(Geom G, Coef<T> c
         } else if (tile && p == B.z0) {
             // Q*(z0 - 1) is not corrected but is the z-neighbour of the corrector at z0
 #pragma unroll
-            for (int k = 0; k < 5; ++k) qs2[k] = sS[k * Shape::PN + pc];
+            for (int k = 0; k < 5; ++k) qs2[k] = Sprev[k * Shape::PN + pc];
         }
-        __syncthreads();  // plane p, Q*(p-1) are no longer read
-        if (dbg_nan) {
-            nan_fill(sQ[sc], 5 * Shape::RN);
-            nan_fill(sU[sc], 3 * Shape::RN);
-            nan_fill(sS, 5 * Shape::PN);
+        if constexpr (ONE) {
+            if (dbg_nan) {  // the free slots and Q*(p-1) are no longer read
+                __syncthreads();
+                nan_fill(sQ[sf], 5 * Shape::RN);
+                nan_fill(sU[sf], 3 * Shape::RN);
+                nan_fill(const_cast<T *>(Sprev), 5 * Shape::PN);
+                __syncthreads();
+            }
+            if (more) {
+                LQ.store(preQ, sQ[sf]);
+                LU.store(preU, sU[sf]);
+            }
             __syncthreads();
-        }
-        if (pred)
+            const int o = sc;
+            sc = sn;
+            sn = sf;
+            sf = o;
+        } else {
+            __syncthreads();  // plane p, Q*(p-1) are no longer read
+            if (dbg_nan) {
+                nan_fill(sQ[sc], 5 * Shape::RN);
+                nan_fill(sU[sc], 3 * Shape::RN);
+                nan_fill(Scur, 5 * Shape::PN);
+                __syncthreads();
+            }
+            if (pred)
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sS[k * Shape::PN + pc] = qs0[k];
-        if (more) {
-            LQ.store(preQ, sQ[sc]);
-            LU.store(preU, sU[sc]);
+                for (int k = 0; k < 5; ++k) Scur[k * Shape::PN + pc] = qs0[k];
+            if (more) {
+                LQ.store(preQ, sQ[sc]);
+                LU.store(preU, sU[sc]);
+            }
+            __syncthreads();
+            const int o = sc;
+            sc = sn;
+            sn = o;
         }
-        __syncthreads();
-        const int o = sc;
-        sc = sn;
-        sn = o;
     };
     int p = B.z0 - 1;
     if constexpr (sizeof(T) == 4) {

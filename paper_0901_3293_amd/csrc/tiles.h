@@ -45,11 +45,11 @@ struct TileShape {
 };
 
 // The tile of the fused Q-side kernels, per precision.  FP32: 32 x 8 sites
-// (340 evaluation points, six waves; the FP32 kernels fit five waves per
-// SIMD).  FP64: 16 x 12 sites (252 points, four waves): the FP64 kernels hold
-// about 190 and 254 registers, two waves per SIMD, so two four-wave blocks
-// share a CU where a six-wave block would run alone with a quarter of the
-// CU's wave slots empty.
+// (340 evaluation points, six waves; three blocks of the stress kernel or two
+// of the Q update share a CU).  FP64: 16 x 12 sites (252 points, four waves):
+// the FP64 kernels hold about 180 and 254 registers, two waves per SIMD, so
+// two four-wave blocks share a CU where a six-wave block would run alone with
+// a quarter of the CU's wave slots empty.
 template <typename T>
 using KernelTile = typename std::conditional<sizeof(T) == 8, TileShape<16, 12>, TileShape<32, 8>>::type;
 
