@@ -423,24 +423,28 @@ def test_free_energy_profile(H, orc, prec):
     assert abs(fz[:8].mean() - fz[-8:].mean()) > 1e-3 * np.abs(fz).max()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("sched", [("tiled", 8), ("mixed", 8), ("tiled", 16)])
 @pytest.mark.parametrize("shape", [(13, 7, 9), (37, 5, 6), (64, 16, 20)])
-def test_tiled_kernels_with_nan_filled_lds(H, orc, shape, sched):
+def test_tiled_kernels_with_nan_filled_lds(H, orc, shape, sched, prec):
     """Debug mode HLB_DEBUG_NAN_LDS: every LDS plane of the tiled kernels is
     NaN before it is staged or evaluated into, so a halo point the kernels
     never write would come out as NaN.  The results stay finite and bitwise
-    equal to the run without the fills, and within the FP64 bars of the
-    oracle (ragged tiles, lattices narrower than a tile)."""
-    say("case: nan-filled LDS", shape, sched)
+    equal to the run without the fills, and within the bars of the oracle
+    (FP64: 1e-12; FP32: Q within 1e-5), on ragged tiles and lattices narrower
+    than a tile, for both tile shapes (FP32 32 x 8, FP64 16 x 12) and both
+    plane structures (one barrier per plane with double-buffered LDS, and
+    the FP64 Q update's two)."""
+    say("case: nan-filled LDS", shape, sched, prec)
     rng = np.random.default_rng(sum(shape) + 3)
     nx, ny, nz = shape
     p = I.PhysParams(K=0.02, q0=0.35, gamma=3.1)
     Q = I.smooth_field(shape, amp=0.2, seed=8) + rng.uniform(-0.02, 0.02, size=(5, nz, ny, nx))
     u = rng.uniform(-1e-3, 1e-3, size=(3, nz, ny, nx))
     rho = 1 + rng.uniform(-1e-3, 1e-3, size=(nz, ny, nx))
-    dbg = make(H, p, Q, u, rho, sched=sched)
+    dbg = make(H, p, Q, u, rho, prec, sched)
     dbg.set_debug(nan_lds=True)
-    plain = make(H, p, Q, u, rho, sched=sched)
+    plain = make(H, p, Q, u, rho, prec, sched)
     dbg.step(5)
     plain.step(5)
     a, b = dbg.fields(), plain.fields()
@@ -449,5 +453,8 @@ def test_tiled_kernels_with_nan_filled_lds(H, orc, shape, sched):
     ref = orc.State(oracle_params(orc, p), Q, u, rho)
     ref.step(5)
     Qr, ur, rr = ref.fields()
-    assert rel(a[0], Qr) <= 1e-12 and rel(a[1], ur) <= 1e-11 and rel(a[2], rr) <= 1e-12
+    if prec == "fp64":
+        assert rel(a[0], Qr) <= 1e-12 and rel(a[1], ur) <= 1e-11 and rel(a[2], rr) <= 1e-12
+    else:
+        assert rel(a[0], Qr) <= 1e-5
     assert math.isfinite(dbg.totals()[2])
