@@ -40,14 +40,19 @@ KERNEL_VALUES = {
     "k_qforce": 5 + 3,            # Q -> F
     "k_lbf": (19 + 3) + (19 + 3),  # g, F -> g', u
     "k_qupdate": (5 + 3) + 5,     # Q, u -> Q'
+    # fused schedules: the stress in LDS tiles fused with the LB step (with
+    # the per-site predictor and corrector 77 values per site per step, with
+    # the tiled Q update 59)
+    "k_qlb": 5 + 19 + (19 + 3),   # Q, g -> g', u
 }
 # Algorithmic values of the step of the method each kernel carries out: the
 # Q-side stencil Q -> F (5 + 3), the LB step g, F -> g', u (22 + 22), the
 # predictor Q, u -> Q* (8 + 5), the corrector Q, Q*, u -> Q (13 + 5), the fused
-# predictor-corrector Q, u -> Q (8 + 5).  The stress sweep of the per-site
-# schedule is half of the Q-side stencil; it is counted with its own bytes.
+# predictor-corrector Q, u -> Q (8 + 5), the stencil fused into the LB step
+# Q, g -> g', u (5 + 19 + 22).  The stress sweep of the per-site schedule is
+# half of the Q-side stencil; it is counted with its own bytes.
 METHOD_VALUES = {"k_lb": 44, "k_lbf": 44, "k_qforce": 8, "k_qupdate": 13, "k_qpred": 13, "k_qcorr": 18,
-                 "k_stress": 14}
+                 "k_stress": 14, "k_qlb": 46}
 # Values per site per step of the whole step by design: four launches
 # (stencil | LB | predictor | corrector), three (fused predictor-corrector),
 # two (stencil fused into the LB step), and the state itself (populations and
@@ -699,9 +704,9 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the FP32 split-coupling and D3Q15 legs")
     ap.add_argument("--lb-model", choices=["d3q19", "d3q15"], default="d3q19",
                     help="LB scheme of the --only fp32/fp64 profiling legs (d3q15 implies --coupling split)")
-    ap.add_argument("--schedule", choices=["auto", "sites", "tiled", "mixed"], default="auto",
-                    help="step schedule (auto: the library's autotuner picks)")
-    ap.add_argument("--tz", type=int, default=0, help="planes per tile column for a fixed tiled/mixed schedule")
+    ap.add_argument("--schedule", choices=["auto", "sites", "tiled", "mixed", "fused", "fused-tiled"],
+                    default="auto", help="step schedule (auto: the library's autotuner picks)")
+    ap.add_argument("--tz", type=int, default=0, help="planes per tile column for a fixed schedule with tiles")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the 96-box batched FP32 run (0: skip)")
     ap.add_argument("--batch-graph-steps", type=int, default=50, help="steps per batched graph replay")

@@ -239,16 +239,27 @@ int hlb_set_state(hlb_ctx *ctx, const void *host_buf, size_t nbytes);
  * place).  HLB_SCHED_TILED: three sweeps in which 2.5D z-marching LDS tiles
  * hold the stress and the predictor stage (recomputed on a one-site halo
  * ring; tiles of 32 x 8 sites in FP32 and 16 x 12 in FP64), tz planes per
- * tile column (0: 16).  HLB_SCHED_MIXED: the per-site
- * stress and LB sweeps, then the tiled predictor-corrector.  All give the
- * same step to rounding.  The default is HLB_SCHED_SITES.  With the split
- * coupling or the D3Q15 scheme, HLB_SCHED_TILED is rejected (HLB_ERR_STATE). */
-enum { HLB_SCHED_SITES = 0, HLB_SCHED_TILED = 1, HLB_SCHED_MIXED = 2 };
+ * tile column (0: 16).  HLB_SCHED_MIXED: the per-site stress and LB sweeps,
+ * then the tiled predictor-corrector.  HLB_SCHED_FUSED: the tiled stress
+ * fused with the LB step (the force never leaves the CU), then the per-site
+ * predictor and corrector.  HLB_SCHED_FUSED_TILED: the fused stress and LB
+ * step, then the tiled predictor-corrector (two sweeps).  All give the same
+ * step to rounding.  The default is HLB_SCHED_SITES.  With the split
+ * coupling or the D3Q15 scheme, HLB_SCHED_TILED, HLB_SCHED_FUSED and
+ * HLB_SCHED_FUSED_TILED are rejected (HLB_ERR_STATE). */
+enum {
+    HLB_SCHED_SITES = 0,
+    HLB_SCHED_TILED = 1,
+    HLB_SCHED_MIXED = 2,
+    HLB_SCHED_FUSED = 3,
+    HLB_SCHED_FUSED_TILED = 4
+};
 int hlb_set_schedule(hlb_ctx *ctx, int schedule, int tz);
 int hlb_get_schedule(const hlb_ctx *ctx, int *schedule, int *tz);
 
-/* Debug flags.  HLB_DEBUG_NAN_LDS: the tiled kernels (HLB_SCHED_TILED, and
- * the Q update of HLB_SCHED_MIXED) overwrite every LDS plane with NaN before
+/* Debug flags.  HLB_DEBUG_NAN_LDS: the tiled kernels (the tiled stress and
+ * the tiled Q update of every schedule but HLB_SCHED_SITES) overwrite every
+ * LDS plane with NaN before
  * staging a lattice plane into it or evaluating the stress or the predictor
  * stage into it, so a halo point the kernels fail to write surfaces as NaN
  * in Q, u and the totals (HLB_ERR_NONFINITE) instead of a stale value; the
@@ -258,9 +269,10 @@ enum { HLB_DEBUG_NAN_LDS = 1 };
 int hlb_set_debug(hlb_ctx *ctx, int flags);
 
 /* Autotuner: time trial_steps steps of every candidate schedule (per-site;
- * tiled and mixed with tz = 8, 16, 32 and the tz whose tiled launch fills the
- * device's resident block slots once or twice; no tiled with the split
- * coupling or the D3Q15 scheme) on this context's lattice and precision with HIP events
+ * tiled, mixed, fused and fused-tiled with tz = 8, 16, 32 and the tz whose
+ * tiled launch fills the device's resident block slots once or twice; only
+ * the per-site and mixed schedules with the split coupling or the D3Q15
+ * scheme) on this context's lattice and precision with HIP events
  * on its stream, in two passes over the candidates (each scored by its faster
  * pass, 2 untimed steps before every trial), keep the fastest, and put the
  * state back as it was

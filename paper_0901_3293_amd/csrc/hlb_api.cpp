@@ -180,6 +180,13 @@ int hlb_fe_from_reduced(double kappa, double tau_ldg, double q0, double A0, hlb_
     return HLB_OK;
 }
 
+// Schedules whose stress is evaluated in LDS tiles (the whole-stress force
+// and the D3Q19 LB only).
+static bool tiled_stress(int sched)
+{
+    return sched == HLB_SCHED_TILED || sched == HLB_SCHED_FUSED || sched == HLB_SCHED_FUSED_TILED;
+}
+
 int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe, const hlb_be_params *be)
 {
     HLB_GUARD(c);
@@ -190,7 +197,7 @@ int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe,
         return set_error(c, HLB_ERR_PARAM, "tau = %g must exceed 1/2", lb->tau);
     if (lb->model == HLB_LB_D3Q15_PC && !(lb->tau > 0.0))
         return set_error(c, HLB_ERR_PARAM, "tau = %g must be positive", lb->tau);
-    if (lb->model == HLB_LB_D3Q15_PC && c->D.sched == HLB_SCHED_TILED)
+    if (lb->model == HLB_LB_D3Q15_PC && tiled_stress(c->D.sched))
         return set_error(c, HLB_ERR_STATE, "the D3Q15 scheme needs the sites or mixed schedule");
     if (!(lb->rho0 > 0.0)) return set_error(c, HLB_ERR_PARAM, "rho0 = %g must be positive", lb->rho0);
     if (!(fe->A0 > 0.0)) return set_error(c, HLB_ERR_PARAM, "A0 = %g must be positive", fe->A0);
@@ -201,7 +208,7 @@ int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe,
     if (!std::isfinite(be->xi)) return set_error(c, HLB_ERR_PARAM, "xi not finite");
     if (be->flow_coupling < HLB_FLOW_OFF || be->flow_coupling > HLB_FLOW_SPLIT)
         return set_error(c, HLB_ERR_PARAM, "flow_coupling = %d is not one of 0, 1, 2", be->flow_coupling);
-    if (be->flow_coupling == HLB_FLOW_SPLIT && c->D.sched == HLB_SCHED_TILED)
+    if (be->flow_coupling == HLB_FLOW_SPLIT && tiled_stress(c->D.sched))
         return set_error(c, HLB_ERR_STATE, "the split coupling needs the sites or mixed schedule");
     if (!(12.0 * be->Gamma * fe->K < 2.0))
         return set_error(c, HLB_ERR_PARAM, "12 Gamma K = %g violates the explicit diffusion bound 2",
@@ -313,12 +320,12 @@ int hlb_get_totals_noalloc(hlb_ctx *c, double *mass, double *mom3, double *free_
 int hlb_set_schedule(hlb_ctx *c, int schedule, int tz)
 {
     HLB_GUARD(c);
-    if ((schedule != HLB_SCHED_SITES && schedule != HLB_SCHED_TILED && schedule != HLB_SCHED_MIXED) || tz < 0)
+    if (schedule < HLB_SCHED_SITES || schedule > HLB_SCHED_FUSED_TILED || tz < 0)
         return set_error(c, HLB_ERR_ARG, "schedule %d / tz %d", schedule, tz);
-    if (schedule == HLB_SCHED_TILED && c->have_params && c->p.flow == HLB_FLOW_SPLIT)
-        return set_error(c, HLB_ERR_STATE, "the tiled schedule carries the whole-stress force only");
-    if (schedule == HLB_SCHED_TILED && c->have_params && c->p.model == HLB_LB_D3Q15_PC)
-        return set_error(c, HLB_ERR_STATE, "the tiled schedule runs the D3Q19 LB only");
+    if (tiled_stress(schedule) && c->have_params && c->p.flow == HLB_FLOW_SPLIT)
+        return set_error(c, HLB_ERR_STATE, "schedule %d carries the whole-stress force only", schedule);
+    if (tiled_stress(schedule) && c->have_params && c->p.model == HLB_LB_D3Q15_PC)
+        return set_error(c, HLB_ERR_STATE, "schedule %d runs the D3Q19 LB only", schedule);
     c->D.sched = schedule;
     c->D.tz = tz;
     return HLB_OK;
@@ -362,24 +369,25 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
         for (int j = 0; j < ntz; ++j) dup = dup || tzs[j] == tzs[i];
         if (!dup) tzs[ntz++] = tzs[i];
     }
-    Cand cands[1 + 2 * 5];
+    const int tiledsc[4] = {HLB_SCHED_TILED, HLB_SCHED_MIXED, HLB_SCHED_FUSED, HLB_SCHED_FUSED_TILED};
+    Cand cands[1 + 4 * 5];
     int NC = 0;
     cands[NC++] = {HLB_SCHED_SITES, 0};
-    for (int j = 0; j < ntz; ++j) cands[NC++] = {HLB_SCHED_TILED, tzs[j]};
-    for (int j = 0; j < ntz; ++j) cands[NC++] = {HLB_SCHED_MIXED, tzs[j]};
+    for (int sc : tiledsc)
+        for (int j = 0; j < ntz; ++j) cands[NC++] = {sc, tzs[j]};
     hipEvent_t a, b;
     HIP_TRY(c, hipEventCreate(&a));
     HIP_TRY(c, hipEventCreate(&b));
     // Two passes over the candidates, each candidate scored by its faster
     // pass: the first trials of a call can run before the clocks and caches
     // have settled, which would penalise whichever candidate comes first.
-    double t[1 + 2 * 5];
+    double t[1 + 4 * 5];
     for (int i = 0; i < NC; ++i) t[i] = 1e300;
     for (int pass = 0; pass < 2; ++pass) {
         for (int i = 0; i < NC; ++i) {
             const Cand &k = cands[i];
             if (k.sched != HLB_SCHED_SITES && k.tz > c->D.G.nz && k.tz != 8) continue;
-            if (k.sched == HLB_SCHED_TILED && (c->p.flow == HLB_FLOW_SPLIT || c->p.model == HLB_LB_D3Q15_PC))
+            if (tiled_stress(k.sched) && (c->p.flow == HLB_FLOW_SPLIT || c->p.model == HLB_LB_D3Q15_PC))
                 continue;
             c->D.sched = k.sched;
             c->D.tz = k.tz;

@@ -62,7 +62,7 @@ struct PhysParams {
 enum DebugFlags { DEBUG_NAN_LDS = 1 };
 
 // Step schedules (see kernels.hip).
-enum Schedule { SCHED_SITES = 0, SCHED_TILED = 1, SCHED_MIXED = 2 };
+enum Schedule { SCHED_SITES = 0, SCHED_TILED = 1, SCHED_MIXED = 2, SCHED_FUSED = 3, SCHED_FUSED_TILED = 4 };
 
 // Device buffers of one context (all inside the caller's workspace) and the
 // ping-pong state indices.
@@ -90,7 +90,8 @@ enum KernelKind {
     K_STRESS = 0, K_LB = 1, K_QPRED = 2, K_QCORR = 3,  // per-site schedule
     K_QFORCE = 4, K_LBF = 5, K_QUPDATE = 6,            // tiled schedule
     K_PC1 = 7, K_PC2 = 8,                              // D3Q15 predictor-corrector LB
-    K_COUNT = 9
+    K_QLB = 9,                                         // stress fused with the LB step
+    K_COUNT = 10
 };
 const char *kernel_name(int k);
 

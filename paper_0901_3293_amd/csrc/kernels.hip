@@ -21,9 +21,13 @@
 //   k_qforce  Q^n -> F^n;  k_lbf  g, F^n -> g', u^n;  k_qupdate  Q^n, u^n -> Q^{n+1}
 //  MIXED (3 sweeps: the per-site stress and LB, then the tiled Q update;
 //  77 values):  k_stress, k_lb, k_qupdate
+//  FUSED (3 sweeps: the stress of the tiles fused with the LB step, then the
+//  per-site predictor and corrector; 77 values):
+//   k_qlb  Q^n, g -> g', u^n;  k_qpred;  k_qcorr
+//  FUSED_TILED (2 sweeps; 59 values):  k_qlb, k_qupdate
 // The split coupling (Sec. 2.2) runs the SITES and MIXED schedules with
 // k_stress / k_lb writing and reading the split terms (101 and 83 values).
-// The population sweeps (k_lb, k_lbf, the second D3Q15 pass k_pc2) load and
+// The population sweeps (k_lb, k_lbf, k_qlb, the second D3Q15 pass k_pc2) load and
 // store the populations nontemporally, and the first D3Q15 pass k_pc1 stores
 // its predicted populations so (pop_load / pop_store in sitekern.h).
 #include <hip/hip_runtime.h>
@@ -343,6 +347,131 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
     if (WITH_F) {
         double v[1] = {facc};
         block_sum<1, Shape::NB>(v, fpart + logical_block());
+    }
+}
+
+// ---------------------------------------------------------------- k_qlb
+// The stress kernel fused with the LB step (Eqs. (6)-(8), (19) with the
+// collision and streaming of Sec. 2.2): the plane march of k_qforce, but
+// instead of writing F(p-1) each tile thread collides its site of plane p-1
+// with it, pulling the populations from gin and writing gout and u^n, so F
+// never goes to HBM.  In FP32 the 19 pulled populations are loaded at the
+// start of the plane and arrive while the stress is evaluated; in FP64 they
+// are loaded after it (their registers on top of the stress would leave one
+// wave per SIMD).
+// FP32: at most 128 registers (four waves per SIMD, two blocks per CU).
+template <typename T>
+__global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 4))) void k_qlb(Geom G, Coef<T> c, TileGrid tg,
+                                                      const T *__restrict__ Q, const T *__restrict__ gin,
+                                                      T *__restrict__ gout, T *__restrict__ u, bool dbg_nan)
+{
+    using Shape = KernelTile<T>;
+    constexpr bool EARLY = sizeof(T) == 4;
+    __shared__ T sQ[4][5 * Shape::RN];
+    __shared__ T sP[2][6 * Shape::PN];
+    const Block B = block_of<Shape>(G, tg);
+    if (!B.ok) return;
+    if (dbg_nan) {
+        nan_fill(&sQ[0][0], 4 * 5 * Shape::RN);
+        nan_fill(&sP[0][0], 2 * 6 * Shape::PN);
+        __syncthreads();
+    }
+    const int N = G.N;
+    const int sxy = G.nx * G.ny;
+    const int t = int(threadIdx.x);
+    int pc, rc;
+    const bool eval = TileMap<Shape>::point(t, pc, rc);
+    const bool tile = t < Shape::NT;
+    const int gx = B.x0 + t % Shape::TX, gy = B.y0 + t / Shape::TX;
+    const bool mine = tile && gx < G.nx && gy < G.ny;
+
+    PlaneLoader<Shape, 5> L;
+    L.init(G, B.x0, B.y0);
+    int s0 = 0, s1 = 1, s2 = 2, s3 = 3;  // s1, s2, s3: planes p-1, p, p+1; s0 free
+    L.load(Q, size_t(N), wrapi(B.z0 - 2, G.nz) * sxy, sQ[s1]);
+    L.load(Q, size_t(N), wrapi(B.z0 - 1, G.nz) * sxy, sQ[s2]);
+    L.load(Q, size_t(N), wrapi(B.z0, G.nz) * sxy, sQ[s3]);
+    __syncthreads();
+
+    T Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
+    constexpr int NL = PlaneLoader<Shape, 5>::NL;
+    T pre[NL];
+    for (int p = B.z0 - 1; p <= B.z1; ++p) {
+        const bool more = p + 2 <= B.z1 + 1;
+        if (more) L.fetch(Q, size_t(N), wrapi(p + 2, G.nz) * sxy, pre);
+        const bool lb = mine && p - 1 >= B.z0;  // this plane collides site (gx, gy, p-1)
+        Off<T> O;
+        T g[19];
+        if (lb) {
+            Nbr S;
+            S.x = gx;
+            S.y = gy;
+            S.z = p - 1;
+            S.s = S.z * sxy + gy * G.nx + gx;
+            S.nb[0] = (gx == G.nx - 1) ? S.s - (G.nx - 1) : S.s + 1;
+            S.nb[1] = (gx == 0) ? S.s + (G.nx - 1) : S.s - 1;
+            S.nb[2] = (gy == G.ny - 1) ? S.s - G.nx * (G.ny - 1) : S.s + G.nx;
+            S.nb[3] = (gy == 0) ? S.s + G.nx * (G.ny - 1) : S.s - G.nx;
+            S.nb[4] = (S.z == G.nz - 1) ? S.s - sxy * (G.nz - 1) : S.s + sxy;
+            S.nb[5] = (S.z == 0) ? S.s + sxy * (G.nz - 1) : S.s - sxy;
+            O = offsets<T>(S);
+            if (EARLY)
+#pragma unroll
+                for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
+        }
+        T *Pc = sP[p & 1];         // stress of plane p (written now)
+        const T *Pp = sP[~p & 1];  // stress of plane p-1 (written in the last plane)
+        T Pz[3] = {T(0), T(0), T(0)};
+        // ring points: only the planes whose in-plane divergence is used
+        if (eval && (tile || (p >= B.z0 && p < B.z1))) {
+            T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
+            stencil_ring<Shape>(sQ[s1], sQ[s2], sQ[s3], rc, q, d, lap);
+            site_stress(c, q, d, lap, P, fd, H);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Pc[a * Shape::PN + pc] = P[a][0];
+                Pc[(3 + a) * Shape::PN + pc] = P[a][1];
+                Pz[a] = P[a][2];
+            }
+        }
+        if (tile) {
+            if (lb) {
+                T f[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const T Fin = (Pp[a * Shape::PN + pc + 1] - Pp[a * Shape::PN + pc - 1])
+                                + (Pp[(3 + a) * Shape::PN + pc + Shape::PX] - Pp[(3 + a) * Shape::PN + pc - Shape::PX]);
+                    f[a] = T(0.5) * (Fin + (Pz[a] - Pz2[a]));
+                }
+                if (!EARLY)
+#pragma unroll
+                    for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
+                T uu[3], rho;
+                lb_collide(c, g, f, uu, rho);
+#pragma unroll
+                for (int i = 0; i < 19; ++i) pop_store<true>(plane(gout, i, N), O.s, g[i]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) *at(plane(u, a, N), O.s) = uu[a];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Pz2[a] = Pz1[a];
+                Pz1[a] = Pz[a];
+            }
+        }
+        if (dbg_nan) {  // the free slot and the stress of plane p-1 are no longer read
+            __syncthreads();
+            nan_fill(sQ[s0], 5 * Shape::RN);
+            nan_fill(const_cast<T *>(Pp), 6 * Shape::PN);
+            __syncthreads();
+        }
+        if (more) L.store(pre, sQ[s0]);  // plane p+2 into the free slot
+        __syncthreads();
+        const int o = s0;
+        s0 = s1;
+        s1 = s2;
+        s2 = s3;
+        s3 = o;
     }
 }
 
@@ -1019,12 +1148,13 @@ template <typename T>
 int tz_fill_t(const Device &D, int rounds)
 {
     using S = KernelTile<T>;
-    int dev = 0, cus = 0, bq = 0, bf = 0;
+    int dev = 0, cus = 0, bq = 0, bf = 0, bl = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bq, k_qupdate<T>, S::NB, 0) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, k_qforce<T, false>, S::NB, 0) != hipSuccess) return 0;
-    const long long slots = (long long)cus * std::max(1, std::min(bq, bf)) * rounds;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_qlb<T>, S::NB, 0) != hipSuccess) return 0;
+    const long long slots = (long long)cus * std::max(1, std::min(bq, std::min(bf, bl))) * rounds;
     const long long cols = (long long)((D.G.nx + S::TX - 1) / S::TX) * ((D.G.ny + S::TY - 1) / S::TY);
     const long long chunks = slots / cols;
     if (chunks < 1) return 0;
@@ -1034,9 +1164,13 @@ int tz_fill_t(const Device &D, int rounds)
 template <typename T, bool SPLIT>
 hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *timer)
 {
-    // the tiled kernels carry the whole stress and the D3Q19 LB only
-    if ((SPLIT || p.model == LB_D3Q15_PC) && D.sched == SCHED_TILED) return hipErrorNotSupported;
     const bool pc = p.model == LB_D3Q15_PC;
+    const int sc = D.sched;
+    // the tiled stress kernels carry the whole stress and the D3Q19 LB only
+    const bool tiled_stress = sc == SCHED_TILED || sc == SCHED_FUSED || sc == SCHED_FUSED_TILED;
+    if ((SPLIT || pc) && tiled_stress) return hipErrorNotSupported;
+    // the Q update: tiled predictor-corrector, or the per-site predictor and corrector
+    const bool tiled_q = sc == SCHED_TILED || sc == SCHED_MIXED || sc == SCHED_FUSED_TILED;
     const bool dbg_nan = (D.debug & DEBUG_NAN_LDS) != 0;
     const Geom G = D.G;
     const Coef<T> c = make_coef<T>(p);
@@ -1046,15 +1180,23 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
     hipError_t e = hipSuccess;
     if (!p.flow && nsteps > 0)  // pure relaxation: u == 0 (Sec. 2.1)
         k_fill<T><<<1024, BLK, 0, D.stream>>>(u, 3 * size_t(G.N), T(0));
-    if (D.sched == SCHED_SITES || D.sched == SCHED_MIXED) {
-        const bool fused_q = D.sched == SCHED_MIXED;
-        const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, KernelTile<T>::TX, KernelTile<T>::TY, tile_tz(D));
-        for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
-            T *Q = static_cast<T *>(D.Q[D.qcur]);
-            T *Qs = static_cast<T *>(D.Q[D.qcur ^ 1]);
-            if (p.flow) {
-                T *gin = static_cast<T *>(D.g[D.gcur]);
-                T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
+    const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, KernelTile<T>::TX, KernelTile<T>::TY, tile_tz(D));
+    const int tb = KernelTile<T>::NB;
+    for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+        T *Q = static_cast<T *>(D.Q[D.qcur]);
+        T *Qs = static_cast<T *>(D.Q[D.qcur ^ 1]);  // predictor stage, or Q^{n+1} of the tiled update
+        if (p.flow) {
+            T *gin = static_cast<T *>(D.g[D.gcur]);
+            T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
+            if (sc == SCHED_FUSED || sc == SCHED_FUSED_TILED) {
+                e = mark(K_QLB, [&] { k_qlb<T><<<tg.launch, tb, 0, D.stream>>>(G, c, tg, Q, gin, gout, u, dbg_nan); });
+            } else if (sc == SCHED_TILED) {
+                e = mark(K_QFORCE, [&] {
+                    k_qforce<T, false><<<tg.launch, tb, 0, D.stream>>>(G, c, tg, Q, Pi, nullptr, dbg_nan);
+                });
+                if (e == hipSuccess)
+                    e = mark(K_LBF, [&] { k_lbf<T><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
+            } else {
                 e = mark(K_STRESS, [&] { k_stress<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, Q, Pi, nullptr); });
                 if (pc) {
                     T *P = static_cast<T *>(D.aux);
@@ -1070,42 +1212,20 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
                 } else if (e == hipSuccess) {
                     e = mark(K_LB, [&] { k_lb<T, SPLIT><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
                 }
-                D.gcur ^= 1;
             }
-            if (fused_q) {
-                if (e == hipSuccess)
-                    e = mark(K_QUPDATE, [&] {
-                        k_qupdate<T><<<tg.launch, KernelTile<T>::NB, 0, D.stream>>>(G, c, tg, Q, u, Qs, dbg_nan);
-                    });
-                D.qcur ^= 1;
-            } else {
-                if (e == hipSuccess)
-                    e = mark(K_QPRED, [&] { k_qpred<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, u, Qs); });
-                if (e == hipSuccess)
-                    e = mark(K_QCORR, [&] { k_qcorr<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Qs, u); });
-            }
+            D.gcur ^= 1;
         }
-    } else {
-        const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, KernelTile<T>::TX, KernelTile<T>::TY, tile_tz(D));
-        for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
-            T *Qn = static_cast<T *>(D.Q[D.qcur]);
-            T *Qn1 = static_cast<T *>(D.Q[D.qcur ^ 1]);
-            if (p.flow) {
-                T *gin = static_cast<T *>(D.g[D.gcur]);
-                T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
-                e = mark(K_QFORCE, [&] {
-                    k_qforce<T, false><<<tg.launch, KernelTile<T>::NB, 0, D.stream>>>(G, c, tg, Qn, Pi, nullptr,
-                                                                              dbg_nan);
-                });
-                if (e == hipSuccess)
-                    e = mark(K_LBF, [&] { k_lbf<T><<<nb, BLK, 0, D.stream>>>(G, c, gin, Pi, gout, u); });
-                D.gcur ^= 1;
-            }
+        if (tiled_q) {
             if (e == hipSuccess)
                 e = mark(K_QUPDATE, [&] {
-                    k_qupdate<T><<<tg.launch, KernelTile<T>::NB, 0, D.stream>>>(G, c, tg, Qn, u, Qn1, dbg_nan);
+                    k_qupdate<T><<<tg.launch, tb, 0, D.stream>>>(G, c, tg, Q, u, Qs, dbg_nan);
                 });
             D.qcur ^= 1;
+        } else {
+            if (e == hipSuccess)
+                e = mark(K_QPRED, [&] { k_qpred<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, u, Qs); });
+            if (e == hipSuccess)
+                e = mark(K_QCORR, [&] { k_qcorr<T><<<nb, BLK, 0, D.stream>>>(G, c, Q, Qs, u); });
         }
     }
     if (e != hipSuccess) return e;
@@ -1234,7 +1354,7 @@ size_t partial_doubles(int nx, int ny, int nz)
 const char *kernel_name(int k)
 {
     static const char *names[K_COUNT] = {"k_stress", "k_lb", "k_qpred", "k_qcorr", "k_qforce", "k_lbf",
-                                         "k_qupdate", "k_pc1", "k_pc2"};
+                                         "k_qupdate", "k_pc1", "k_pc2", "k_qlb"};
     return (k >= 0 && k < K_COUNT) ? names[k] : nullptr;
 }
 

@@ -18,8 +18,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhlb.so")
 
 HLB_FP64, HLB_FP32 = 0, 1
-SCHED_SITES, SCHED_TILED, SCHED_MIXED = 0, 1, 2
-SCHEDULES = {"sites": SCHED_SITES, "tiled": SCHED_TILED, "mixed": SCHED_MIXED}
+SCHED_SITES, SCHED_TILED, SCHED_MIXED, SCHED_FUSED, SCHED_FUSED_TILED = 0, 1, 2, 3, 4
+SCHEDULES = {"sites": SCHED_SITES, "tiled": SCHED_TILED, "mixed": SCHED_MIXED, "fused": SCHED_FUSED,
+             "fused-tiled": SCHED_FUSED_TILED}
 STATUS = {0: "HLB_OK", -1: "HLB_ERR_ARG", -2: "HLB_ERR_PARAM", -3: "HLB_ERR_HIP",
           -4: "HLB_ERR_NONFINITE", -5: "HLB_ERR_STATE", -6: "HLB_ERR_NOMEM"}
 

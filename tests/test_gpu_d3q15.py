@@ -122,14 +122,16 @@ def test_d3q15_flow_off_and_rejections(H, orc):
     Qg, ug, rg = gpu.fields()
     assert rel(Qg, ref.fields()[0]) <= 1e-12
     assert np.abs(ug).max() == 0.0 and np.abs(rg - 1).max() == 0.0
-    s = H.Solver((8, 8, 8), "fp64")
-    s.set_schedule("tiled", 8)
-    with pytest.raises(H.HlbError):
-        s.set_params(p)
+    for name in ("tiled", "fused", "fused-tiled"):  # the schedules whose stress is tiled
+        s = H.Solver((8, 8, 8), "fp64")
+        s.set_schedule(name, 8)
+        with pytest.raises(H.HlbError):
+            s.set_params(p)
     s2 = H.Solver((8, 8, 8), "fp64", lb_model=getattr(p, "lb_model", "d3q19"), coupling=p.coupling)
     s2.set_params(p)
-    with pytest.raises(H.HlbError):
-        s2.set_schedule("tiled", 8)
+    for name in ("tiled", "fused", "fused-tiled"):
+        with pytest.raises(H.HlbError):
+            s2.set_schedule(name, 8)
     b = H.Batch([(8, 8, 8)], "fp32")
     with pytest.raises(H.HlbError):
         b.set_params(0, p)

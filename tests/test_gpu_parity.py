@@ -28,7 +28,9 @@ def H():
     return hlb
 
 
-SCHEDS = [("sites", 0), ("tiled", 8), ("mixed", 8), ("tiled", 16)]
+SCHEDS = [("sites", 0), ("tiled", 8), ("mixed", 8), ("fused", 8), ("fused-tiled", 8), ("tiled", 16)]
+# one schedule per kind of stress kernel: per-site, tiled, tiled and fused with the LB step
+SCHEDS_CORE = [("sites", 0), ("tiled", 8), ("fused", 8)]
 
 
 def make(H, p, Q, u, rho, prec="fp64", sched=("sites", 0)):
@@ -39,10 +41,10 @@ def make(H, p, Q, u, rho, prec="fp64", sched=("sites", 0)):
     return s
 
 
-@pytest.mark.parametrize("sched", SCHEDS[:3])
+@pytest.mark.parametrize("sched", SCHEDS[:5])
 def test_fp64_helix_32cubed_every_step(H, orc, sched):
     """32^3 helix (q0 = 2 pi/16, kappa = 1, tau = 0, noise 1e-4, seed 1), 100
-    steps: Q, u, rho and F_total at every step, both schedules."""
+    steps: Q, u, rho and F_total at every step, every schedule."""
     say("case: fp64 helix 32^3, 100 steps", sched)
     p, Q, u, rho = I.helix_case()
     gpu = make(H, p, Q, u, rho, sched=sched)
@@ -68,7 +70,7 @@ def test_fp64_helix_32cubed_every_step(H, orc, sched):
     say("fp64 32^3 worst relative errors:", worst)
 
 
-@pytest.mark.parametrize("sched", SCHEDS[:3])
+@pytest.mark.parametrize("sched", SCHEDS[:5])
 def test_fp32_helix_1000_steps(H, orc, sched):
     """FP32 form vs FP64 oracle after 1000 steps: Q within 1e-5 relative."""
     say("case: fp32 helix 32^3, 1000 steps", sched)
@@ -116,8 +118,8 @@ def test_tiled_any_chunk_depth(H, orc, prec):
     """The tiled kernels march z-chunks of any depth tz (the autotuner may pick
     a depth that fills the device's block slots, e.g. 26 or 39 planes): on a
     ragged lattice (37 x 29 x 23: no side a multiple of a tile side, a prime
-    depth) tz = 1, 2, 3, 5, 7 and 23 against tz = 16 in the tiled and mixed
-    schedules, 6 steps.  A site's arithmetic does not depend on where the
+    depth) tz = 1, 2, 3, 5, 7 and 23 against tz = 16 in every schedule with
+    tiles, 6 steps.  A site's arithmetic does not depend on where the
     chunks start, so FP64 agrees bitwise (and stays within the oracle bars).
     The FP32 plane loop is unrolled by two, and the compiler fuses
     multiply-adds differently in the copies of the plane step, so a chunk
@@ -139,7 +141,7 @@ def test_tiled_any_chunk_depth(H, orc, prec):
         o = orc.State(oracle_params(orc, p), Q, u, rho)
         o.step(steps)
         ref = o.fields()
-    for name in ("tiled", "mixed"):
+    for name in ("tiled", "mixed", "fused", "fused-tiled"):
         base = make(H, p, Q, u, rho, prec, (name, 16))
         base.step(steps)
         Qb, ub, rb = base.fields()
@@ -193,7 +195,7 @@ def test_large_ragged_lattice(H, orc, prec):
         assert eQ <= 1e-5
 
 
-@pytest.mark.parametrize("sched", SCHEDS[:2])
+@pytest.mark.parametrize("sched", SCHEDS_CORE)
 def test_fp64_flow_off(H, orc, sched):
     """Pure relaxation (u == 0, populations untouched)."""
     say("case: fp64 flow off 24x20x16", sched)
@@ -210,7 +212,7 @@ def test_fp64_flow_off(H, orc, sched):
     assert np.abs(rg - 1).max() == 0.0
 
 
-@pytest.mark.parametrize("sched", SCHEDS[:2])
+@pytest.mark.parametrize("sched", SCHEDS_CORE)
 def test_checkpoint_restart_bitwise(H, sched):
     say("case: checkpoint 16^3", sched)
     p, Q, u, rho = I.helix_case(n=16, q0=2 * math.pi / 8)
@@ -226,7 +228,7 @@ def test_checkpoint_restart_bitwise(H, sched):
     assert np.array_equal(Qa, Qb) and np.array_equal(ua, ub) and np.array_equal(ra, rb)
 
 
-@pytest.mark.parametrize("sched", SCHEDS[:2])
+@pytest.mark.parametrize("sched", SCHEDS_CORE)
 def test_deterministic(H, sched):
     say("case: determinism 20^3 fp64+fp32", sched)
     p, Q, u, rho = I.helix_case(n=20, q0=2 * math.pi / 10)
@@ -243,7 +245,7 @@ def test_deterministic(H, sched):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("sched", [("sites", 0), ("tiled", 8), ("mixed", 8)])
+@pytest.mark.parametrize("sched", SCHEDS[:5])
 def test_isotropic_rest_state_is_exact_fixed_point(H, prec, sched):
     """Q = 0, u = 0, rho = rho0 (the isotropic phase at rest) is a fixed point
     of the method: H, the stress and the force vanish, and the populations
@@ -424,7 +426,7 @@ def test_free_energy_profile(H, orc, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("sched", [("tiled", 8), ("mixed", 8), ("tiled", 16)])
+@pytest.mark.parametrize("sched", [("tiled", 8), ("mixed", 8), ("fused", 8), ("fused-tiled", 8), ("tiled", 16)])
 @pytest.mark.parametrize("shape", [(13, 7, 9), (37, 5, 6), (64, 16, 20)])
 def test_tiled_kernels_with_nan_filled_lds(H, orc, shape, sched, prec):
     """Debug mode HLB_DEBUG_NAN_LDS: every LDS plane of the tiled kernels is

@@ -111,14 +111,16 @@ def test_split_rejections(H):
     say("case: split coupling rejections")
     p, Q, u, rho = I.helix_case(n=8, q0=2 * math.pi / 8)
     p.coupling = "split"
-    s = H.Solver((8, 8, 8), "fp64")
-    s.set_schedule("tiled", 8)
-    with pytest.raises(H.HlbError):
-        s.set_params(p)  # split with the tiled schedule selected
+    for name in ("tiled", "fused", "fused-tiled"):  # the schedules whose stress is tiled
+        s = H.Solver((8, 8, 8), "fp64")
+        s.set_schedule(name, 8)
+        with pytest.raises(H.HlbError):
+            s.set_params(p)  # split with the tiled schedule selected
     s2 = H.Solver((8, 8, 8), "fp64", lb_model=getattr(p, "lb_model", "d3q19"), coupling=p.coupling)
     s2.set_params(p)
-    with pytest.raises(H.HlbError):
-        s2.set_schedule("tiled", 8)
+    for name in ("tiled", "fused", "fused-tiled"):
+        with pytest.raises(H.HlbError):
+            s2.set_schedule(name, 8)
     b = H.Batch([(8, 8, 8)], "fp32")
     with pytest.raises(H.HlbError):
         b.set_params(0, p)
