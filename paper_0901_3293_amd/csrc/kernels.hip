@@ -355,18 +355,17 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
 // collision and streaming of Sec. 2.2): the plane march of k_qforce, but
 // instead of writing F(p-1) each tile thread collides its site of plane p-1
 // with it, pulling the populations from gin and writing gout and u^n, so F
-// never goes to HBM.  In FP32 the 19 pulled populations are loaded at the
-// start of the plane and arrive while the stress is evaluated; in FP64 they
-// are loaded after it (their registers on top of the stress would leave one
-// wave per SIMD).
-// FP32: at most 128 registers (four waves per SIMD, two blocks per CU).
+// never goes to HBM.  The 19 pulled populations are loaded at the start of
+// the plane and arrive while the stress is evaluated (loaded after it, the
+// FP64 kernel ran 4% slower).
+// FP32: at most 128 registers (four waves per SIMD, two blocks per CU); FP64:
+// about 230 (two waves per SIMD, two four-wave blocks per CU).
 template <typename T>
 __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 4))) void k_qlb(Geom G, Coef<T> c, TileGrid tg,
                                                       const T *__restrict__ Q, const T *__restrict__ gin,
                                                       T *__restrict__ gout, T *__restrict__ u, bool dbg_nan)
 {
     using Shape = KernelTile<T>;
-    constexpr bool EARLY = sizeof(T) == 4;
     __shared__ T sQ[4][5 * Shape::RN];
     __shared__ T sP[2][6 * Shape::PN];
     const Block B = block_of<Shape>(G, tg);
@@ -415,9 +414,8 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
             S.nb[4] = (S.z == G.nz - 1) ? S.s - sxy * (G.nz - 1) : S.s + sxy;
             S.nb[5] = (S.z == 0) ? S.s + sxy * (G.nz - 1) : S.s - sxy;
             O = offsets<T>(S);
-            if (EARLY)
 #pragma unroll
-                for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
+            for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
         }
         T *Pc = sP[p & 1];         // stress of plane p (written now)
         const T *Pp = sP[~p & 1];  // stress of plane p-1 (written in the last plane)
@@ -443,9 +441,6 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
                                 + (Pp[(3 + a) * Shape::PN + pc + Shape::PX] - Pp[(3 + a) * Shape::PN + pc - Shape::PX]);
                     f[a] = T(0.5) * (Fin + (Pz[a] - Pz2[a]));
                 }
-                if (!EARLY)
-#pragma unroll
-                    for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
                 T uu[3], rho;
                 lb_collide(c, g, f, uu, rho);
 #pragma unroll
