@@ -97,7 +97,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling="force", lb_model="d3q19"):
+def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling="force", lb_model="d3q19",
+             tz_update=0):
     import torch
 
     from paper_0901_3293_amd import hlb
@@ -118,7 +119,9 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
         sched, tz, _ = s.autotune(40)
     else:
         s.set_schedule(schedule, tz)
+        s.set_update_chunk(tz_update)
         sched, tz = s.schedule()
+    tzq = s.update_chunk()
     stream = s.stream
     s.step(warmup)
     torch.cuda.synchronize()
@@ -149,7 +152,7 @@ def run_form(prec, n, steps, warmup, prof_steps, schedule="auto", tz=0, coupling
         "mlups": mlups,
         "coupling": coupling,
         "lb_model": lb_model,
-        "schedule": {"name": sched, "tz": tz},
+        "schedule": {"name": sched, "tz": tz, "tz_update": tzq},
         "ms_per_step": ms_step,
         "kernel_ms_per_launch": per_launch,
         "dominant_kernel": dom,
@@ -549,7 +552,8 @@ def run_sizes(sizes=(64, 96, 128, 192, 256, 384, 512), site_updates=2.0e9):
             torch.cuda.synchronize()
             ms = ev0.elapsed_time(ev1) / steps
             km = s.step_timed(5)
-            rows.append({"n": n, "precision": prec, "schedule": {"name": sched, "tz": tz}, "steps": steps,
+            rows.append({"n": n, "precision": prec,
+                         "schedule": {"name": sched, "tz": tz, "tz_update": s.update_chunk()}, "steps": steps,
                          "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3,
                          "kernel_us_per_launch": {k: v / 5 * 1e3 for k, v in km.items() if v > 0}})
             log(f"bench: size {n}^3 {prec}: {sched} tz {tz}, {rows[-1]['mlups']:.0f} MLUPS")
@@ -707,6 +711,8 @@ def main():
     ap.add_argument("--schedule", choices=["auto", "sites", "tiled", "mixed", "fused", "fused-tiled"],
                     default="auto", help="step schedule (auto: the library's autotuner picks)")
     ap.add_argument("--tz", type=int, default=0, help="planes per tile column for a fixed schedule with tiles")
+    ap.add_argument("--tz-update", type=int, default=0,
+                    help="planes per tile column of the tiled Q update, if other than --tz")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the 96-box batched FP32 run (0: skip)")
     ap.add_argument("--batch-graph-steps", type=int, default=50, help="steps per batched graph replay")
@@ -780,7 +786,7 @@ def main():
         if a.only and a.lb_model == "d3q15":
             a.coupling = "split"
         res[prec] = run_form(prec, a.n, a.steps, a.warmup, a.prof_steps, a.schedule, a.tz,
-                             a.coupling if a.only else "force", a.lb_model if a.only else "d3q19")
+                             a.coupling if a.only else "force", a.lb_model if a.only else "d3q19", a.tz_update)
         log(f"bench: {prec} {res[prec]['mlups']:.1f} MLUPS, kernels {res[prec]['kernel_ms_per_launch']}")
     split = d3q15 = None
     if not a.only and not a.no_split:

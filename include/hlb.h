@@ -257,6 +257,13 @@ enum {
 int hlb_set_schedule(hlb_ctx *ctx, int schedule, int tz);
 int hlb_get_schedule(const hlb_ctx *ctx, int *schedule, int *tz);
 
+/* z-chunk of the tiled predictor-corrector (HLB_SCHED_TILED, HLB_SCHED_MIXED,
+ * HLB_SCHED_FUSED_TILED) where it should differ from the schedule's tz
+ * (0: the schedule's tz; hlb_set_schedule resets it to 0).  The step is the
+ * same at any chunk to rounding (bitwise in FP64).  HLB_ERR_ARG for tzq < 0. */
+int hlb_set_update_chunk(hlb_ctx *ctx, int tzq);
+int hlb_get_update_chunk(const hlb_ctx *ctx, int *tzq);
+
 /* Debug flags.  HLB_DEBUG_NAN_LDS: the tiled kernels (the tiled stress and
  * the tiled Q update of every schedule but HLB_SCHED_SITES) overwrite every
  * LDS plane with NaN before
@@ -274,10 +281,12 @@ int hlb_set_debug(hlb_ctx *ctx, int flags);
  * the per-site and mixed schedules with the split coupling or the D3Q15
  * scheme) on this context's lattice and precision with HIP events
  * on its stream, in two passes over the candidates (each scored by its faster
- * pass, 2 untimed steps before every trial), keep the fastest, and put the
- * state back as it was
- * (through a host copy of hlb_state_bytes bytes).  *best_ms_per_step (may be
- * NULL) receives the winner's time per step.  Synchronises the stream. */
+ * pass, 2 untimed steps before every trial), keep the fastest; if that is
+ * HLB_SCHED_TILED or HLB_SCHED_FUSED_TILED, time the other chunks for the Q
+ * update the same way (hlb_set_update_chunk) and keep a faster one; put the
+ * state back as it was (through a host copy of hlb_state_bytes bytes).
+ * *best_ms_per_step (may be NULL) receives the winner's time per step.
+ * Synchronises the stream. */
 int hlb_autotune(hlb_ctx *ctx, int trial_steps, double *best_ms_per_step);
 
 /* Diagnostics: enqueue nsteps steps with a HIP event pair recorded on the

@@ -328,6 +328,22 @@ int hlb_set_schedule(hlb_ctx *c, int schedule, int tz)
         return set_error(c, HLB_ERR_STATE, "schedule %d runs the D3Q19 LB only", schedule);
     c->D.sched = schedule;
     c->D.tz = tz;
+    c->D.tzq = 0;
+    return HLB_OK;
+}
+
+int hlb_set_update_chunk(hlb_ctx *c, int tzq)
+{
+    HLB_GUARD(c);
+    if (tzq < 0) return set_error(c, HLB_ERR_ARG, "update chunk %d", tzq);
+    c->D.tzq = tzq;
+    return HLB_OK;
+}
+
+int hlb_get_update_chunk(const hlb_ctx *c, int *tzq)
+{
+    if (!c || !tzq) return HLB_ERR_ARG;
+    *tzq = c->D.tzq;
     return HLB_OK;
 }
 
@@ -378,6 +394,26 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
     hipEvent_t a, b;
     HIP_TRY(c, hipEventCreate(&a));
     HIP_TRY(c, hipEventCreate(&b));
+    // time trial_steps steps of one setting (2 untimed steps first); ms per step
+    auto trial = [&](int sched, int tz, int tzq, double &ms_step) -> hipError_t {
+        c->D.sched = sched;
+        c->D.tz = tz;
+        c->D.tzq = tzq;
+        hipError_t e = hlb::run_steps(c->D, c->p, 2);
+        if (e == hipSuccess) e = hipEventRecord(a, c->D.stream);
+        if (e == hipSuccess) e = hlb::run_steps(c->D, c->p, trial_steps);
+        if (e == hipSuccess) e = hipEventRecord(b, c->D.stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        ms_step = double(ms) / trial_steps;
+        return e;
+    };
+    auto fail = [&](hipError_t e) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return hip_fail(c, e, "hlb_autotune trial");
+    };
     // Two passes over the candidates, each candidate scored by its faster
     // pass: the first trials of a call can run before the clocks and caches
     // have settled, which would penalise whichever candidate comes first.
@@ -389,21 +425,10 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
             if (k.sched != HLB_SCHED_SITES && k.tz > c->D.G.nz && k.tz != 8) continue;
             if (tiled_stress(k.sched) && (c->p.flow == HLB_FLOW_SPLIT || c->p.model == HLB_LB_D3Q15_PC))
                 continue;
-            c->D.sched = k.sched;
-            c->D.tz = k.tz;
-            hipError_t e = hlb::run_steps(c->D, c->p, 2);  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(a, c->D.stream);
-            if (e == hipSuccess) e = hlb::run_steps(c->D, c->p, trial_steps);
-            if (e == hipSuccess) e = hipEventRecord(b, c->D.stream);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (e != hipSuccess) {
-                (void)hipEventDestroy(a);
-                (void)hipEventDestroy(b);
-                return hip_fail(c, e, "hlb_autotune trial");
-            }
-            t[i] = std::min(t[i], double(ms) / trial_steps);
+            double ms = 0.0;
+            const hipError_t e = trial(k.sched, k.tz, 0, ms);
+            if (e != hipSuccess) return fail(e);
+            t[i] = std::min(t[i], ms);
         }
     }
     double best = 1e300;
@@ -413,10 +438,31 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
             best = t[i];
             pick = cands[i];
         }
+    // Where a tiled stress kernel is followed by the tiled Q update, the two
+    // may prefer different z-chunks: try the other chunks for the Q update.
+    int pick_tzq = 0;
+    if (pick.sched == HLB_SCHED_TILED || pick.sched == HLB_SCHED_FUSED_TILED) {
+        double tq[5];
+        for (int j = 0; j < ntz; ++j) tq[j] = 1e300;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < ntz; ++j) {
+                if (tzs[j] == pick.tz || (tzs[j] > c->D.G.nz && tzs[j] != 8)) continue;
+                double ms = 0.0;
+                const hipError_t e = trial(pick.sched, pick.tz, tzs[j], ms);
+                if (e != hipSuccess) return fail(e);
+                tq[j] = std::min(tq[j], ms);
+            }
+        for (int j = 0; j < ntz; ++j)
+            if (tq[j] < best) {
+                best = tq[j];
+                pick_tzq = tzs[j];
+            }
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     c->D.sched = pick.sched;
     c->D.tz = pick.tz;
+    c->D.tzq = pick_tzq;
     c->D.gcur = g0;
     c->D.qcur = q0;
     rc = hlb_set_state(c, saved.data(), saved.size());

@@ -79,6 +79,7 @@ struct Device {
     int gcur, qcur;
     int sched;     // Schedule
     int tz;        // z-chunk of the tiled kernels (0: default)
+    int tzq;       // z-chunk of the tiled Q update (0: tz)
     int debug;     // debug flags (DEBUG_NAN_LDS)
     hipStream_t stream;
 };

@@ -1135,6 +1135,7 @@ struct Marks {
 };
 
 int tile_tz(const Device &D) { return D.tz > 0 ? D.tz : 16; }
+int tile_tzq(const Device &D) { return D.tzq > 0 ? D.tzq : tile_tz(D); }
 
 // z-chunk for which the blocks of the tiled kernels fill the device's
 // resident block slots `rounds` times: a launch of whole rounds leaves no CU
@@ -1176,6 +1177,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
     if (!p.flow && nsteps > 0)  // pure relaxation: u == 0 (Sec. 2.1)
         k_fill<T><<<1024, BLK, 0, D.stream>>>(u, 3 * size_t(G.N), T(0));
     const TileGrid tg = tile_grid(G.nx, G.ny, G.nz, KernelTile<T>::TX, KernelTile<T>::TY, tile_tz(D));
+    const TileGrid tgq = tile_grid(G.nx, G.ny, G.nz, KernelTile<T>::TX, KernelTile<T>::TY, tile_tzq(D));
     const int tb = KernelTile<T>::NB;
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
         T *Q = static_cast<T *>(D.Q[D.qcur]);
@@ -1213,7 +1215,7 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
         if (tiled_q) {
             if (e == hipSuccess)
                 e = mark(K_QUPDATE, [&] {
-                    k_qupdate<T><<<tg.launch, tb, 0, D.stream>>>(G, c, tg, Q, u, Qs, dbg_nan);
+                    k_qupdate<T><<<tgq.launch, tb, 0, D.stream>>>(G, c, tgq, Q, u, Qs, dbg_nan);
                 });
             D.qcur ^= 1;
         } else {

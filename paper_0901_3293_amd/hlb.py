@@ -111,6 +111,8 @@ def lib():
         L.hlb_set_schedule.argtypes = [vp, I, I]
         L.hlb_set_debug.argtypes = [vp, I]
         L.hlb_get_schedule.argtypes = [vp, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.hlb_set_update_chunk.argtypes = [vp, I]
+        L.hlb_get_update_chunk.argtypes = [vp, ctypes.POINTER(I)]
         L.hlb_autotune.argtypes = [vp, I, dp]
         L.hlb_step_timed.argtypes = [vp, I, dp, I]
         L.hlb_kernel_name.argtypes = [I]
@@ -239,6 +241,16 @@ class Solver:
         self._check(lib().hlb_get_schedule(self.ctx, ctypes.byref(sc), ctypes.byref(tz)))
         name = {v: k for k, v in SCHEDULES.items()}[sc.value]
         return name, tz.value
+
+    def set_update_chunk(self, tzq=0):
+        """z-chunk of the tiled Q update when it should differ from the
+        schedule's (0: the same; set_schedule resets it)."""
+        self._check(lib().hlb_set_update_chunk(self.ctx, int(tzq)))
+
+    def update_chunk(self):
+        v = ctypes.c_int()
+        self._check(lib().hlb_get_update_chunk(self.ctx, ctypes.byref(v)))
+        return v.value
 
     def autotune(self, trial_steps=10):
         """Pick the fastest step schedule for this lattice and precision (the

@@ -119,7 +119,8 @@ def test_tiled_any_chunk_depth(H, orc, prec):
     a depth that fills the device's block slots, e.g. 26 or 39 planes): on a
     ragged lattice (37 x 29 x 23: no side a multiple of a tile side, a prime
     depth) tz = 1, 2, 3, 5, 7 and 23 against tz = 16 in every schedule with
-    tiles, 6 steps.  A site's arithmetic does not depend on where the
+    tiles, and the tiled Q update on chunks of 1, 5 and 23 planes of its own
+    (hlb_set_update_chunk), 6 steps.  A site's arithmetic does not depend on where the
     chunks start, so FP64 agrees bitwise (and stays within the oracle bars).
     The FP32 plane loop is unrolled by two, and the compiler fuses
     multiply-adds differently in the copies of the plane step, so a chunk
@@ -146,18 +147,22 @@ def test_tiled_any_chunk_depth(H, orc, prec):
         base.step(steps)
         Qb, ub, rb = base.fields()
         base.close()
-        for tz in (1, 2, 3, 5, 7, 23):
-            say(f"case: {prec} {name} tz {tz} on 37x29x23, {steps} steps")
+        runs = [(tz, 0) for tz in (1, 2, 3, 5, 7, 23)]
+        if name in ("tiled", "mixed", "fused-tiled"):  # the tiled Q update on a chunk of its own
+            runs += [(16, tzq) for tzq in (1, 5, 23)]
+        for tz, tzq in runs:
+            say(f"case: {prec} {name} tz {tz} update chunk {tzq} on 37x29x23, {steps} steps")
             g = make(H, p, Q, u, rho, prec, (name, tz))
+            g.set_update_chunk(tzq)
             g.step(steps)
             Qg, ug, rg = g.fields()
             g.close()
             if prec == "fp64":
-                assert np.array_equal(Qg, Qb) and np.array_equal(ug, ub) and np.array_equal(rg, rb), (name, tz)
+                assert np.array_equal(Qg, Qb) and np.array_equal(ug, ub) and np.array_equal(rg, rb), (name, tz, tzq)
             else:
                 eQ, eu, er = rel(Qg, Qb), rel(ug, ub), rel(rg, rb)
                 say(f"against tz 16: Q {eQ:.2e} u {eu:.2e} rho {er:.2e}")
-                assert eQ <= 1e-6 and eu <= 1e-6 and er <= 1e-6, (name, tz, eQ, eu, er)
+                assert eQ <= 1e-6 and eu <= 1e-6 and er <= 1e-6, (name, tz, tzq, eQ, eu, er)
         if ref is not None:
             Qr, ur, rr = ref
             eQ, eu, er = rel(Qb, Qr), rel(ub, ur), rel(rb, rr)
