@@ -54,9 +54,12 @@ def equal_to_cell(big, small, reps):
     return ok
 
 
+SCHEDS_LARGE = (("sites", 0), ("tiled", 32), ("fused-tiled", 32))
+
+
 @pytest.mark.parametrize("prec,reps,scheds", [
-    ("fp64", (16, 16, 17), (("sites", 0), ("tiled", 32))),   # 640 x 640 x 680 = 278.5M sites > 2^28
-    ("fp32", (21, 20, 20), (("sites", 0), ("tiled", 32))),   # 840 x 800 x 800 = 537.6M sites > 2^29
+    ("fp64", (16, 16, 17), SCHEDS_LARGE),   # 640 x 640 x 680 = 278.5M sites > 2^28
+    ("fp32", (21, 20, 20), SCHEDS_LARGE),   # 840 x 800 x 800 = 537.6M sites > 2^29
 ])
 def test_lattice_past_2gib_planes_equals_its_cell(H, orc, prec, reps, scheds):
     import torch
