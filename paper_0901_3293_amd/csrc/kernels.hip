@@ -402,18 +402,7 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
         Off<T> O;
         T g[19];
         if (lb) {
-            Nbr S;
-            S.x = gx;
-            S.y = gy;
-            S.z = p - 1;
-            S.s = S.z * sxy + gy * G.nx + gx;
-            S.nb[0] = (gx == G.nx - 1) ? S.s - (G.nx - 1) : S.s + 1;
-            S.nb[1] = (gx == 0) ? S.s + (G.nx - 1) : S.s - 1;
-            S.nb[2] = (gy == G.ny - 1) ? S.s - G.nx * (G.ny - 1) : S.s + G.nx;
-            S.nb[3] = (gy == 0) ? S.s + G.nx * (G.ny - 1) : S.s - G.nx;
-            S.nb[4] = (S.z == G.nz - 1) ? S.s - sxy * (G.nz - 1) : S.s + sxy;
-            S.nb[5] = (S.z == 0) ? S.s + sxy * (G.nz - 1) : S.s - sxy;
-            O = offsets<T>(S);
+            O = offsets<T>(nbr_at(G, (p - 1) * sxy + gy * G.nx + gx, gx, gy, p - 1));
 #pragma unroll
             for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
         }

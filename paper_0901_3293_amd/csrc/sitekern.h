@@ -24,22 +24,30 @@ struct Nbr {
     int nb[6];  // x+1, x-1, y+1, y-1, z+1, z-1 (periodic)
 };
 
-__device__ __forceinline__ Nbr nbr_of(const Geom &G, int s)
+// The site s = x + nx (y + ny z) at (x, y, z) and its six periodic neighbours.
+__device__ __forceinline__ Nbr nbr_at(const Geom &G, int s, int x, int y, int z)
 {
     Nbr S;
-    S.s = s;
-    const int yz = int(fastdiv(unsigned(s), G.dx));
-    S.x = s - yz * G.nx;
-    S.z = int(fastdiv(unsigned(yz), G.dy));
-    S.y = yz - S.z * G.ny;
     const int sxy = G.nx * G.ny;
-    S.nb[0] = (S.x == G.nx - 1) ? s - (G.nx - 1) : s + 1;
-    S.nb[1] = (S.x == 0) ? s + (G.nx - 1) : s - 1;
-    S.nb[2] = (S.y == G.ny - 1) ? s - G.nx * (G.ny - 1) : s + G.nx;
-    S.nb[3] = (S.y == 0) ? s + G.nx * (G.ny - 1) : s - G.nx;
-    S.nb[4] = (S.z == G.nz - 1) ? s - sxy * (G.nz - 1) : s + sxy;
-    S.nb[5] = (S.z == 0) ? s + sxy * (G.nz - 1) : s - sxy;
+    S.s = s;
+    S.x = x;
+    S.y = y;
+    S.z = z;
+    S.nb[0] = (x == G.nx - 1) ? s - (G.nx - 1) : s + 1;
+    S.nb[1] = (x == 0) ? s + (G.nx - 1) : s - 1;
+    S.nb[2] = (y == G.ny - 1) ? s - G.nx * (G.ny - 1) : s + G.nx;
+    S.nb[3] = (y == 0) ? s + G.nx * (G.ny - 1) : s - G.nx;
+    S.nb[4] = (z == G.nz - 1) ? s - sxy * (G.nz - 1) : s + sxy;
+    S.nb[5] = (z == 0) ? s + sxy * (G.nz - 1) : s - sxy;
     return S;
+}
+
+// The same from the linear site index.
+__device__ __forceinline__ Nbr nbr_of(const Geom &G, int s)
+{
+    const int yz = int(fastdiv(unsigned(s), G.dx));
+    const int z = int(fastdiv(unsigned(yz), G.dy));
+    return nbr_at(G, s, s - yz * G.nx, yz - z * G.ny, z);
 }
 
 // Byte offsets of a site and of its six neighbours within one field plane of
