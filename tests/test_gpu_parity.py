@@ -171,6 +171,38 @@ def test_tiled_any_chunk_depth(H, orc, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_kernel_equals_stress_and_lb_kernels(H, prec):
+    """The stress evaluated inside the LB step (k_qlb) computes the force with
+    the same arithmetic as the tiled stress kernel and collides with it as the
+    LB kernel does, so the fused-tiled schedule reproduces the tiled one and
+    the fused schedule the tiled stress followed by the per-site Q update:
+    bitwise in FP64 (30 steps, ragged 37 x 29 x 23); FP32 within 1e-6 (the
+    compiler may fuse the force's last multiply-add into the collision)."""
+    shape = (37, 29, 23)
+    rng = np.random.default_rng(41)
+    nx, ny, nz = shape
+    p = I.PhysParams(K=0.02, q0=0.35, gamma=3.1)
+    Q = I.smooth_field(shape, amp=0.2, seed=9) + rng.uniform(-0.02, 0.02, size=(5, nz, ny, nx))
+    u = rng.uniform(-1e-3, 1e-3, size=(3, nz, ny, nx))
+    rho = 1 + rng.uniform(-1e-3, 1e-3, size=(nz, ny, nx))
+    out = {}
+    for sched in ("tiled", "fused-tiled", "fused"):
+        say(f"case: {prec} {sched} tz 5 on 37x29x23, 30 steps")
+        g = make(H, p, Q, u, rho, prec, (sched, 5))
+        g.step(30)
+        out[sched] = g.fields()
+        g.close()
+    a, b = out["fused-tiled"], out["tiled"]
+    if prec == "fp64":
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    else:
+        assert all(rel(x, y) <= 1e-6 for x, y in zip(a, b))
+    # the fused schedule's Q update is the per-site one: the same step to rounding
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert all(rel(x, y) <= tol for x, y in zip(out["fused"], out["tiled"]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_large_ragged_lattice(H, orc, prec):
     """A 2.2M-site lattice with no power-of-two side (255 x 129 x 67): the
     kernels split site indices up to 2.2M by multiply-high division by 255
