@@ -461,10 +461,14 @@ def run_surrogate_growth(n=96, kappa=1.0, tau_ldg=0.0, target=44, every=128, max
 
     case = S.growth_run(n, **grow)
     plain = S.new_solver(case)
+    # the plain FP32 step at its fastest schedule; every predictor's run uses the same
+    sched, tz, _ = plain.autotune(20)
+    tzq = plain.update_chunk()
     T, t_plain, track_plain, _ = S.time_to_domain(plain, plain.step, target, every, max_steps)
     q_plain = plain.fields()[0] if T is not None else None
     start = track_plain[0][1] if track_plain else None
-    res = {"plain": {"steps_to_target": T, "seconds": t_plain, "planes_every_read": [b for _, b in track_plain]}}
+    res = {"plain": {"steps_to_target": T, "seconds": t_plain, "planes_every_read": [b for _, b in track_plain],
+                     "schedule": {"name": sched, "tz": tz, "tz_update": tzq}}}
     preds = {"network": net}
     for name, beta in (("linear_extrapolation", 0.0), ("quadratic_extrapolation", 1.0)):
         e = hlb.Net((n, n, n))
@@ -472,6 +476,8 @@ def run_surrogate_growth(n=96, kappa=1.0, tau_ldg=0.0, target=44, every=128, max
         preds[name] = e
     for name, nn_ in preds.items():
         sv = S.new_solver(case)
+        sv.set_schedule(sched, tz)
+        sv.set_update_chunk(tzq)
         R = S.Runner(sv, nn_, k=k, M=M)
         cross, secs, track, snap = S.time_to_domain(sv, R.advance, target, every, max_steps, snap_at=T)
         qe = float(np.linalg.norm(snap - q_plain) / np.linalg.norm(q_plain)) if snap is not None else None
