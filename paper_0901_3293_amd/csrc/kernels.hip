@@ -10,7 +10,7 @@
 //                 tau, h; see sitekern.h)
 // Scalars of one run are passed by value (Coef<T>).
 //
-// Two schedules of one step (Sec. 2.2), chosen per lattice and precision by
+// Five schedules of one step (Sec. 2.2), chosen per lattice and precision by
 // the autotuner:
 //  SITES (4 sweeps, one site per thread, neighbours through L2; 95 values
 //  per site cross HBM):
@@ -27,9 +27,10 @@
 //  FUSED_TILED (2 sweeps; 59 values):  k_qlb, k_qupdate
 // The split coupling (Sec. 2.2) runs the SITES and MIXED schedules with
 // k_stress / k_lb writing and reading the split terms (101 and 83 values).
-// The population sweeps (k_lb, k_lbf, k_qlb, the second D3Q15 pass k_pc2) load and
-// store the populations nontemporally, and the first D3Q15 pass k_pc1 stores
-// its predicted populations so (pop_load / pop_store in sitekern.h).
+// The population sweeps (k_lb, k_lbf, k_qlb, the second D3Q15 pass k_pc2)
+// load and store the populations nontemporally, and the first D3Q15 pass
+// k_pc1 stores its predicted populations so (pop_load / pop_store in
+// sitekern.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -257,8 +258,10 @@ __device__ __forceinline__ Block block_of(const Geom &G, const TileGrid &tg)
 // goes into the fourth staging slot.  One barrier per plane: no slot or
 // buffer is written in the plane in which it is read.  With WITH_F the block
 // also sums the free-energy density of its sites.
-// FP32: at most 96 registers, five waves per SIMD (three blocks per CU); in
-// FP64 a bound that would let another block in spills and runs slower.
+// FP32: at most 96 registers, five waves per SIMD (three blocks per CU).  In
+// FP64 (about 180 registers, two four-wave blocks per CU) a bound that would
+// let a third block in spills (36 bytes per lane); with six-wave blocks such
+// a bound spilled and ran slower.
 template <typename T, bool WITH_F>
 __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 5))) void k_qforce(Geom G, Coef<T> c, TileGrid tg,
                                                       const T *__restrict__ Q, T *__restrict__ F,
