@@ -421,6 +421,7 @@ def test_autotune_keeps_state(H):
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
     b = make(H, p, Q, u, rho, sched=sched[:2])
+    b.set_update_chunk(a.update_chunk())
     b.step(3)
     a.step(4)
     b.step(4)
@@ -428,14 +429,15 @@ def test_autotune_keeps_state(H):
         assert np.array_equal(x, y)
 
 
-def test_schedules_agree_fp32(H):
-    """Per-site and tiled schedules give the same FP32 step to rounding."""
-    say("case: schedules agree fp32 40x24x20")
+@pytest.mark.parametrize("sched", SCHEDS[1:5])
+def test_schedules_agree_fp32(H, sched):
+    """Every schedule gives the per-site FP32 step to rounding."""
+    say("case: schedules agree fp32 40x24x20", sched)
     p, Q, u, rho = I.helix_case(n=40, q0=2 * math.pi / 10)
     Q = Q[:, :20, :24, :40].copy()
     u, rho = u[:, :20, :24, :40].copy(), rho[:20, :24, :40].copy()
     a = make(H, p, Q, u, rho, "fp32", ("sites", 0))
-    b = make(H, p, Q, u, rho, "fp32", ("tiled", 8))
+    b = make(H, p, Q, u, rho, "fp32", sched)
     a.step(50)
     b.step(50)
     Qa, ua, ra = a.fields()
