@@ -96,7 +96,7 @@ typedef struct {
  *                      b_a = d_b tau_ab - H:d_a Q (tau the antisymmetric
  *                      stress), which vanishes with H, so an equilibrium
  *                      structure has no spurious flow.  Single-box contexts
- *                      with the sites or mixed schedule only.
+ *                      with any schedule but HLB_SCHED_TILED.
  * Other values are rejected with HLB_ERR_PARAM. */
 enum { HLB_FLOW_OFF = 0, HLB_FLOW_FORCE = 1, HLB_FLOW_SPLIT = 2 };
 typedef struct {
@@ -141,8 +141,9 @@ int hlb_fe_from_reduced(double kappa, double tau_ldg, double q0, double A0,
  * (D3Q19) or <= 0 (D3Q15), rho0 <= 0, A0 <= 0, gamma <= 0, K < 0,
  * Gamma <= 0, the explicit diffusion bound 12 Gamma K >= 2 of the
  * forward-Euler predictor, an unknown flow_coupling or LB model;
- * HLB_ERR_STATE for the split coupling or the D3Q15 scheme while the tiled
- * schedule is selected; HLB_ERR_NOMEM if the context's workspace is smaller
+ * HLB_ERR_STATE for the split coupling while HLB_SCHED_TILED is selected, or
+ * the D3Q15 scheme while HLB_SCHED_TILED, HLB_SCHED_FUSED or
+ * HLB_SCHED_FUSED_TILED is; HLB_ERR_NOMEM if the context's workspace is smaller
  * than hlb_workspace_bytes_for this model and coupling.  Must be called
  * before hlb_set_fields; changing the LB model invalidates the fields (call
  * hlb_set_fields again). */
@@ -244,9 +245,11 @@ int hlb_set_state(hlb_ctx *ctx, const void *host_buf, size_t nbytes);
  * fused with the LB step (the force never leaves the CU), then the per-site
  * predictor and corrector.  HLB_SCHED_FUSED_TILED: the fused stress and LB
  * step, then the tiled predictor-corrector (two sweeps).  All give the same
- * step to rounding.  The default is HLB_SCHED_SITES.  With the split
- * coupling or the D3Q15 scheme, HLB_SCHED_TILED, HLB_SCHED_FUSED and
- * HLB_SCHED_FUSED_TILED are rejected (HLB_ERR_STATE). */
+ * step to rounding.  The default is HLB_SCHED_SITES.  With the D3Q15
+ * scheme, HLB_SCHED_TILED, HLB_SCHED_FUSED and HLB_SCHED_FUSED_TILED are
+ * rejected (HLB_ERR_STATE), with the split coupling HLB_SCHED_TILED (its
+ * stress kernel writes the whole-stress force; the fused kernel evaluates
+ * the split terms and the split body force in its tiles). */
 enum {
     HLB_SCHED_SITES = 0,
     HLB_SCHED_TILED = 1,
@@ -278,8 +281,8 @@ int hlb_set_debug(hlb_ctx *ctx, int flags);
 /* Autotuner: time trial_steps steps of every candidate schedule (per-site;
  * tiled, mixed, fused and fused-tiled with tz = 8, 16, 32 and the tz whose
  * tiled launch fills the device's resident block slots once or twice; only
- * the per-site and mixed schedules with the split coupling or the D3Q15
- * scheme) on this context's lattice and precision with HIP events
+ * the per-site and mixed schedules with the D3Q15 scheme, no tiled one with
+ * the split coupling) on this context's lattice and precision with HIP events
  * on its stream, in two passes over the candidates (each scored by its faster
  * pass, 2 untimed steps before every trial), keep the fastest; if that is
  * HLB_SCHED_TILED or HLB_SCHED_FUSED_TILED, time the other chunks for the Q

@@ -180,12 +180,14 @@ int hlb_fe_from_reduced(double kappa, double tau_ldg, double q0, double A0, hlb_
     return HLB_OK;
 }
 
-// Schedules whose stress is evaluated in LDS tiles (the whole-stress force
-// and the D3Q19 LB only).
+// Schedules whose stress is evaluated in LDS tiles (the D3Q19 LB only), and
+// the one whose tiled stress kernel writes the whole-stress force (no split).
 static bool tiled_stress(int sched)
 {
     return sched == HLB_SCHED_TILED || sched == HLB_SCHED_FUSED || sched == HLB_SCHED_FUSED_TILED;
 }
+
+static bool no_split(int sched) { return sched == HLB_SCHED_TILED; }
 
 int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe, const hlb_be_params *be)
 {
@@ -208,8 +210,8 @@ int hlb_set_params(hlb_ctx *c, const hlb_lb_params *lb, const hlb_fe_params *fe,
     if (!std::isfinite(be->xi)) return set_error(c, HLB_ERR_PARAM, "xi not finite");
     if (be->flow_coupling < HLB_FLOW_OFF || be->flow_coupling > HLB_FLOW_SPLIT)
         return set_error(c, HLB_ERR_PARAM, "flow_coupling = %d is not one of 0, 1, 2", be->flow_coupling);
-    if (be->flow_coupling == HLB_FLOW_SPLIT && tiled_stress(c->D.sched))
-        return set_error(c, HLB_ERR_STATE, "the split coupling needs the sites or mixed schedule");
+    if (be->flow_coupling == HLB_FLOW_SPLIT && no_split(c->D.sched))
+        return set_error(c, HLB_ERR_STATE, "the split coupling needs a schedule other than tiled");
     if (!(12.0 * be->Gamma * fe->K < 2.0))
         return set_error(c, HLB_ERR_PARAM, "12 Gamma K = %g violates the explicit diffusion bound 2",
                          12.0 * be->Gamma * fe->K);
@@ -322,7 +324,7 @@ int hlb_set_schedule(hlb_ctx *c, int schedule, int tz)
     HLB_GUARD(c);
     if (schedule < HLB_SCHED_SITES || schedule > HLB_SCHED_FUSED_TILED || tz < 0)
         return set_error(c, HLB_ERR_ARG, "schedule %d / tz %d", schedule, tz);
-    if (tiled_stress(schedule) && c->have_params && c->p.flow == HLB_FLOW_SPLIT)
+    if (no_split(schedule) && c->have_params && c->p.flow == HLB_FLOW_SPLIT)
         return set_error(c, HLB_ERR_STATE, "schedule %d carries the whole-stress force only", schedule);
     if (tiled_stress(schedule) && c->have_params && c->p.model == HLB_LB_D3Q15_PC)
         return set_error(c, HLB_ERR_STATE, "schedule %d runs the D3Q19 LB only", schedule);
@@ -423,7 +425,8 @@ int hlb_autotune(hlb_ctx *c, int trial_steps, double *best_ms_per_step)
         for (int i = 0; i < NC; ++i) {
             const Cand &k = cands[i];
             if (k.sched != HLB_SCHED_SITES && k.tz > c->D.G.nz && k.tz != 8) continue;
-            if (tiled_stress(k.sched) && (c->p.flow == HLB_FLOW_SPLIT || c->p.model == HLB_LB_D3Q15_PC))
+            if ((tiled_stress(k.sched) && c->p.model == HLB_LB_D3Q15_PC) ||
+                (no_split(k.sched) && c->p.flow == HLB_FLOW_SPLIT))
                 continue;
             double ms = 0.0;
             const hipError_t e = trial(k.sched, k.tz, 0, ms);

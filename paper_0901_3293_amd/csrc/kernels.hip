@@ -361,9 +361,14 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
 // never goes to HBM.  The 19 pulled populations are loaded at the start of
 // the plane and arrive while the stress is evaluated (loaded after it, the
 // FP64 kernel ran 4% slower).
+// SPLIT (Eqs. (17)-(21)): the evaluation gives sigma^xi, tau and h; the LDS
+// buffers hold tau (xy, xz, yz) for the in-plane differences of the body
+// force b_a = d_b tau_ab + h_a, and a tile thread keeps sigma^xi and h of its
+// site of plane p-1 in registers for the collision with sigma^xi in the
+// equilibrium.
 // FP32: at most 128 registers (four waves per SIMD, two blocks per CU); FP64:
 // about 230 (two waves per SIMD, two four-wave blocks per CU).
-template <typename T>
+template <typename T, bool SPLIT>
 __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 4))) void k_qlb(Geom G, Coef<T> c, TileGrid tg,
                                                       const T *__restrict__ Q, const T *__restrict__ gin,
                                                       T *__restrict__ gout, T *__restrict__ u, bool dbg_nan)
@@ -395,7 +400,9 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
     L.load(Q, size_t(N), wrapi(B.z0, G.nz) * sxy, sQ[s3]);
     __syncthreads();
 
+    // z columns of the own point at planes p-1 and p-2: Pi_az, or (SPLIT) tau xz, yz
     T Pz1[3] = {T(0), T(0), T(0)}, Pz2[3] = {T(0), T(0), T(0)};
+    T sig1[6], h1[3];  // SPLIT: sigma^xi and h of the own site at plane p-1
     constexpr int NL = PlaneLoader<Shape, 5>::NL;
     T pre[NL];
     for (int p = B.z0 - 1; p <= B.z1; ++p) {
@@ -409,32 +416,53 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
 #pragma unroll
             for (int i = 0; i < 19; ++i) g[i] = pop_load<true>(plane(gin, i, N), pull_off(O, CX[i], CY[i], CZ[i]));
         }
-        T *Pc = sP[p & 1];         // stress of plane p (written now)
-        const T *Pp = sP[~p & 1];  // stress of plane p-1 (written in the last plane)
+        T *Pc = sP[p & 1];         // stress (tau) of plane p (written now)
+        const T *Pp = sP[~p & 1];  // stress (tau) of plane p-1 (written in the last plane)
         T Pz[3] = {T(0), T(0), T(0)};
+        T sig0[6], h0[3];
         // ring points: only the planes whose in-plane divergence is used
         if (eval && (tile || (p >= B.z0 && p < B.z1))) {
-            T q[5], d[3][5], lap[5], P[3][3], fd, H[5];
+            T q[5], d[3][5], lap[5], fd;
             stencil_ring<Shape>(sQ[s1], sQ[s2], sQ[s3], rc, q, d, lap);
-            site_stress(c, q, d, lap, P, fd, H);
+            if constexpr (SPLIT) {
+                T tau3[3];
+                site_split(c, q, d, lap, sig0, tau3, h0, fd);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                Pc[a * Shape::PN + pc] = P[a][0];
-                Pc[(3 + a) * Shape::PN + pc] = P[a][1];
-                Pz[a] = P[a][2];
+                for (int k = 0; k < 3; ++k) Pc[k * Shape::PN + pc] = tau3[k];
+                Pz[0] = tau3[1];
+                Pz[1] = tau3[2];
+            } else {
+                T P[3][3], H[5];
+                site_stress(c, q, d, lap, P, fd, H);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    Pc[a * Shape::PN + pc] = P[a][0];
+                    Pc[(3 + a) * Shape::PN + pc] = P[a][1];
+                    Pz[a] = P[a][2];
+                }
             }
         }
         if (tile) {
             if (lb) {
-                T f[3];
+                T f[3], uu[3], rho;
+                if constexpr (SPLIT) {
+                    // b_a = d_b tau_ab + h_a at plane p-1: in-plane differences from LDS,
+                    // z differences from the own point's tau at planes p and p-2
+                    const T *txy = Pp, *txz = Pp + Shape::PN, *tyz = Pp + 2 * Shape::PN;
+                    f[0] = T(0.5) * ((txy[pc + Shape::PX] - txy[pc - Shape::PX]) + (Pz[0] - Pz2[0])) + h1[0];
+                    f[1] = T(0.5) * ((Pz[1] - Pz2[1]) - (txy[pc + 1] - txy[pc - 1])) + h1[1];
+                    f[2] = T(0.5) * (-(txz[pc + 1] - txz[pc - 1]) - (tyz[pc + Shape::PX] - tyz[pc - Shape::PX])) +
+                           h1[2];
+                    lb_collide_split(c, g, f, sig1, uu, rho);
+                } else {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const T Fin = (Pp[a * Shape::PN + pc + 1] - Pp[a * Shape::PN + pc - 1])
-                                + (Pp[(3 + a) * Shape::PN + pc + Shape::PX] - Pp[(3 + a) * Shape::PN + pc - Shape::PX]);
-                    f[a] = T(0.5) * (Fin + (Pz[a] - Pz2[a]));
+                    for (int a = 0; a < 3; ++a) {
+                        const T Fin = (Pp[a * Shape::PN + pc + 1] - Pp[a * Shape::PN + pc - 1])
+                                    + (Pp[(3 + a) * Shape::PN + pc + Shape::PX] - Pp[(3 + a) * Shape::PN + pc - Shape::PX]);
+                        f[a] = T(0.5) * (Fin + (Pz[a] - Pz2[a]));
+                    }
+                    lb_collide(c, g, f, uu, rho);
                 }
-                T uu[3], rho;
-                lb_collide(c, g, f, uu, rho);
 #pragma unroll
                 for (int i = 0; i < 19; ++i) pop_store<true>(plane(gout, i, N), O.s, g[i]);
 #pragma unroll
@@ -444,6 +472,12 @@ __global__ __launch_bounds__(KernelTile<T>::NB) __attribute__((amdgpu_waves_per_
             for (int a = 0; a < 3; ++a) {
                 Pz2[a] = Pz1[a];
                 Pz1[a] = Pz[a];
+            }
+            if constexpr (SPLIT) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) sig1[k] = sig0[k];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) h1[a] = h0[a];
             }
         }
         if (dbg_nan) {  // the free slot and the stress of plane p-1 are no longer read
@@ -1141,7 +1175,7 @@ int tz_fill_t(const Device &D, int rounds)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bq, k_qupdate<T>, S::NB, 0) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, k_qforce<T, false>, S::NB, 0) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_qlb<T>, S::NB, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_qlb<T, false>, S::NB, 0) != hipSuccess) return 0;
     const long long slots = (long long)cus * std::max(1, std::min(bq, std::min(bf, bl))) * rounds;
     const long long cols = (long long)((D.G.nx + S::TX - 1) / S::TX) * ((D.G.ny + S::TY - 1) / S::TY);
     const long long chunks = slots / cols;
@@ -1154,9 +1188,9 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
 {
     const bool pc = p.model == LB_D3Q15_PC;
     const int sc = D.sched;
-    // the tiled stress kernels carry the whole stress and the D3Q19 LB only
+    // the tiled stress kernels run the D3Q19 LB only, and k_qforce the whole stress only
     const bool tiled_stress = sc == SCHED_TILED || sc == SCHED_FUSED || sc == SCHED_FUSED_TILED;
-    if ((SPLIT || pc) && tiled_stress) return hipErrorNotSupported;
+    if ((pc && tiled_stress) || (SPLIT && sc == SCHED_TILED)) return hipErrorNotSupported;
     // the Q update: tiled predictor-corrector, or the per-site predictor and corrector
     const bool tiled_q = sc == SCHED_TILED || sc == SCHED_MIXED || sc == SCHED_FUSED_TILED;
     const bool dbg_nan = (D.debug & DEBUG_NAN_LDS) != 0;
@@ -1178,7 +1212,9 @@ hipError_t steps_t(Device &D, const PhysParams &p, int nsteps, KernelTimer *time
             T *gin = static_cast<T *>(D.g[D.gcur]);
             T *gout = static_cast<T *>(D.g[D.gcur ^ 1]);
             if (sc == SCHED_FUSED || sc == SCHED_FUSED_TILED) {
-                e = mark(K_QLB, [&] { k_qlb<T><<<tg.launch, tb, 0, D.stream>>>(G, c, tg, Q, gin, gout, u, dbg_nan); });
+                e = mark(K_QLB, [&] {
+                    k_qlb<T, SPLIT><<<tg.launch, tb, 0, D.stream>>>(G, c, tg, Q, gin, gout, u, dbg_nan);
+                });
             } else if (sc == SCHED_TILED) {
                 e = mark(K_QFORCE, [&] {
                     k_qforce<T, false><<<tg.launch, tb, 0, D.stream>>>(G, c, tg, Q, Pi, nullptr, dbg_nan);

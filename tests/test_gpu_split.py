@@ -42,7 +42,7 @@ def make(H, p, Q, u, rho, prec="fp64", sched=("sites", 0)):
     return s
 
 
-SCHEDS = [("sites", 0), ("mixed", 8)]
+SCHEDS = [("sites", 0), ("mixed", 8), ("fused", 8), ("fused-tiled", 8)]
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
@@ -71,11 +71,12 @@ def test_split_fp64_helix_every_step(H, orc, sched):
     say("split fp64 worst:", worst)
 
 
-def test_split_fp32_helix_1000_steps(H, orc):
-    say("case: split fp32 helix 32^3, 1000 steps")
+@pytest.mark.parametrize("sched", [("sites", 0), ("fused", 8)])
+def test_split_fp32_helix_1000_steps(H, orc, sched):
+    say("case: split fp32 helix 32^3, 1000 steps", sched)
     p, Q, u, rho = I.helix_case()
     p.coupling = "split"
-    gpu = make(H, p, Q, u, rho, "fp32")
+    gpu = make(H, p, Q, u, rho, "fp32", sched)
     ref = orc.State(oracle_params(orc, p), Q, u, rho)
     gpu.step(1000)
     ref.step(1000)
@@ -111,29 +112,32 @@ def test_split_rejections(H):
     say("case: split coupling rejections")
     p, Q, u, rho = I.helix_case(n=8, q0=2 * math.pi / 8)
     p.coupling = "split"
-    for name in ("tiled", "fused", "fused-tiled"):  # the schedules whose stress is tiled
-        s = H.Solver((8, 8, 8), "fp64")
-        s.set_schedule(name, 8)
-        with pytest.raises(H.HlbError):
-            s.set_params(p)  # split with the tiled schedule selected
+    s = H.Solver((8, 8, 8), "fp64")
+    s.set_schedule("tiled", 8)  # its stress kernel writes the whole-stress force
+    with pytest.raises(H.HlbError):
+        s.set_params(p)  # split with the tiled schedule selected
     s2 = H.Solver((8, 8, 8), "fp64", lb_model=getattr(p, "lb_model", "d3q19"), coupling=p.coupling)
     s2.set_params(p)
-    for name in ("tiled", "fused", "fused-tiled"):
-        with pytest.raises(H.HlbError):
-            s2.set_schedule(name, 8)
+    with pytest.raises(H.HlbError):
+        s2.set_schedule("tiled", 8)
+    s3 = H.Solver((8, 8, 8), "fp64", lb_model=getattr(p, "lb_model", "d3q19"), coupling=p.coupling)
+    s3.set_params(p)
+    for name in ("fused", "fused-tiled"):  # the fused kernel carries the split terms
+        s3.set_schedule(name, 8)  # (errors are sticky: a context that failed a call stays failed)
     b = H.Batch([(8, 8, 8)], "fp32")
     with pytest.raises(H.HlbError):
         b.set_params(0, p)
     b.close()
 
 
+@pytest.mark.parametrize("sched", [("sites", 0), ("fused", 8)])
 @pytest.mark.parametrize("cell", [16, 32])
-def test_split_no_spurious_velocity(H, cell):
+def test_split_no_spurious_velocity(H, cell, sched):
     """One double-twist (O2) unit cell relaxed with the flow off until H
     vanishes to rounding (Gamma = 5 reaches the fixed point sooner), then the
     fluid is coupled for 50 steps: the split coupling keeps it at rest to
     rounding, the whole-stress force drives a spurious flow."""
-    say("case: spurious velocity, O2 cell", cell)
+    say("case: spurious velocity, O2 cell", cell, sched)
     p, Q, _, _ = I.bpii_case(n=cell, cell=cell, kappa=0.7, tau_ldg=-0.5)
     relax = I.PhysParams(**{**p.as_dict(), "Gamma": 5.0, "flow": False})
     s = make(H, relax, Q, None, None)
@@ -142,7 +146,7 @@ def test_split_no_spurious_velocity(H, cell):
     umax = {}
     for c in ("force", "split"):
         pc = I.PhysParams(**{**p.as_dict(), "coupling": c})
-        t = make(H, pc, Qr, None, None)
+        t = make(H, pc, Qr, None, None, sched=sched)
         t.step(50)
         umax[c] = float(np.abs(t.fields()[1]).max())
     say("max |u| after 50 steps:", umax)
