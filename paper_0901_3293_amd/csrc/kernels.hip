@@ -26,7 +26,9 @@
 //   k_qlb  Q^n, g -> g', u^n;  k_qpred;  k_qcorr
 //  FUSED_TILED (2 sweeps; 59 values):  k_qlb, k_qupdate
 // The split coupling (Sec. 2.2) runs the SITES and MIXED schedules with
-// k_stress / k_lb writing and reading the split terms (101 and 83 values).
+// k_stress / k_lb writing and reading the split terms (101 and 83 values),
+// and the FUSED and FUSED_TILED schedules with k_qlb<T, true>, which
+// evaluates them in its tiles (77 and 59 values).
 // The population sweeps (k_lb, k_lbf, k_qlb, the second D3Q15 pass k_pc2)
 // load and store the populations nontemporally, and the first D3Q15 pass
 // k_pc1 stores its predicted populations so (pop_load / pop_store in
