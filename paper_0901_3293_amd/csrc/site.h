@@ -393,13 +393,45 @@ __host__ __device__ __forceinline__ void lb_moments(const T g[19], T &drho, T j[
     j[2] = (g[5] - g[6]) + (g[11] - g[12]) + (g[14] - g[13]) + (g[15] - g[16]) + (g[18] - g[17]);
 }
 
+// a b + c with one rounding in either precision.  The collision spells out
+// its fused products so that every inlined copy of it rounds alike.
+template <typename T>
+__host__ __device__ __forceinline__ T fmat(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_fma(a, b, c);
+}
+
+// Update of the opposite pair (i, i+1), e_{i+1} = -e_i, from the even part s
+// (the same for both) and the odd part o of omega g^eq + src:
+//   s = c0 + a2 (e.u)^2 + b2 (e.u)(e.F),  o = a1 (e.u) + b1 (e.F).
+template <typename T>
+__host__ __device__ __forceinline__ void lb_pair(T g[19], int i, T keep, T c0, T a2, T b2, T a1, T b1, T eu, T eF)
+{
+    const T s = fmat(eu, fmat(a2, eu, b2 * eF), c0);
+    const T o = fmat(a1, eu, b1 * eF);
+    g[i] = fmat(keep, g[i], s + o);
+    g[i + 1] = fmat(keep, g[i + 1], s - o);
+}
+
 // BGK collision with second-order forcing on the deviations (Eq. (16) on
 // D3Q19): rho = rho0 + drho, u = (j + F/2)/rho,
 //   g_i' = g_i - (g_i - g_i^eq)/tau + (1 - 1/(2 tau)) w_i [3(e_i - u) + 9 (e_i.u) e_i].F,
-//   g_i^eq = w_i drho + w_i rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2).
+//   g_i^eq = w_i drho + w_i rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2)
+// and, with SIG (the split coupling, Eq. (17)), the symmetric stress sig
+// (xx, xy, xz, yy, yz, zz) in the second moment of the equilibrium,
+//   g_i^eq += -(9/2) w_i [sig:e_i e_i - tr(sig)/3],
+// a term with zero mass and momentum.  Evaluated per pair of opposite
+// velocities: with keep = 1 - omega, omega g^eq + src is
+//   w [omega (drho - (3/2) rho u^2) - 3 pref u.F + (9/2) omega rho (e.u)^2
+//      + 9 pref (e.u)(e.F) - (9/2) omega (sig:ee - tr(sig)/3)]      (even in e)
+//   + w [3 omega rho (e.u) + 3 pref (e.F)]                           (odd in e).
 // g is updated in place; u and rho are returned.
-template <typename T>
-__host__ __device__ __forceinline__ void lb_collide(const Coef<T> &c, T g[19], const T F[3], T u[3], T &rho)
+template <typename T, bool SIG>
+__host__ __device__ __forceinline__ void lb_update(const Coef<T> &c, T g[19], const T F[3], const T *sig, T u[3],
+                                                   T &rho)
 {
     T drho, j[3];
     lb_moments(g, drho, j);
@@ -410,48 +442,56 @@ __host__ __device__ __forceinline__ void lb_collide(const Coef<T> &c, T g[19], c
     const T uu15 = T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
     const T keep = T(1) - c.omega;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const T w = lb_weight<T>(i);
-        const T eu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
-        const T eF = T(CX[i]) * F[0] + T(CY[i]) * F[1] + T(CZ[i]) * F[2];
-        const T geq = w * drho + w * rho * (T(3) * eu + T(4.5) * eu * eu - uu15);
-        const T src = c.pref * w * (T(3) * (eF - uF) + T(9) * eu * eF);
-        g[i] = keep * g[i] + c.omega * geq + src;
+    const T orho = c.omega * rho;
+    const T base = fmat(c.omega, fmat(-rho, uu15, drho), T(-3) * c.pref * uF);
+    // faces (w = 1/18) and edges (w = 1/36)
+    const T c1 = (T(1) / T(18)) * base, c2 = (T(1) / T(36)) * base;
+    T c0 = (T(1) / T(3)) * base;
+    const T a21 = T(0.25) * orho, a22 = T(0.125) * orho;
+    const T b21 = T(0.5) * c.pref, b22 = T(0.25) * c.pref;
+    const T a11 = (T(1) / T(6)) * orho, a12 = (T(1) / T(12)) * orho;
+    const T b11 = (T(1) / T(6)) * c.pref, b12 = (T(1) / T(12)) * c.pref;
+    T cx = c1, cy = c1, cz = c1, cxy = c2, cxy_ = c2, cxz = c2, cxz_ = c2, cyz = c2, cyz_ = c2;
+    if constexpr (SIG) {
+        const T tr3 = (sig[0] + sig[3] + sig[5]) / T(3);
+        const T m1 = T(-0.25) * c.omega, m2 = T(-0.125) * c.omega;
+        c0 = fmat(T(1.5) * c.omega, tr3, c0);  // the rest velocity: sig:ee = 0
+        cx = fmat(m1, sig[0] - tr3, c1);
+        cy = fmat(m1, sig[3] - tr3, c1);
+        cz = fmat(m1, sig[5] - tr3, c1);
+        const T exy = (sig[0] + sig[3]) - tr3, exz = (sig[0] + sig[5]) - tr3, eyz = (sig[3] + sig[5]) - tr3;
+        cxy = fmat(m2, fmat(T(2), sig[1], exy), c2);
+        cxy_ = fmat(m2, fmat(T(-2), sig[1], exy), c2);
+        cxz = fmat(m2, fmat(T(2), sig[2], exz), c2);
+        cxz_ = fmat(m2, fmat(T(-2), sig[2], exz), c2);
+        cyz = fmat(m2, fmat(T(2), sig[4], eyz), c2);
+        cyz_ = fmat(m2, fmat(T(-2), sig[4], eyz), c2);
     }
+    g[0] = fmat(keep, g[0], c0);
+    lb_pair(g, 1, keep, cx, a21, b21, a11, b11, u[0], F[0]);
+    lb_pair(g, 3, keep, cy, a21, b21, a11, b11, u[1], F[1]);
+    lb_pair(g, 5, keep, cz, a21, b21, a11, b11, u[2], F[2]);
+    lb_pair(g, 7, keep, cxy, a22, b22, a12, b12, u[0] + u[1], F[0] + F[1]);
+    lb_pair(g, 9, keep, cxy_, a22, b22, a12, b12, u[0] - u[1], F[0] - F[1]);
+    lb_pair(g, 11, keep, cxz, a22, b22, a12, b12, u[0] + u[2], F[0] + F[2]);
+    lb_pair(g, 13, keep, cxz_, a22, b22, a12, b12, u[0] - u[2], F[0] - F[2]);
+    lb_pair(g, 15, keep, cyz, a22, b22, a12, b12, u[1] + u[2], F[1] + F[2]);
+    lb_pair(g, 17, keep, cyz_, a22, b22, a12, b12, u[1] - u[2], F[1] - F[2]);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void lb_collide(const Coef<T> &c, T g[19], const T F[3], T u[3], T &rho)
+{
+    lb_update<T, false>(c, g, F, nullptr, u, rho);
 }
 
 // The same collision in the split coupling: F is the split body force b and
-// the equilibrium carries the symmetric stress sig (xx, xy, xz, yy, yz, zz)
-// in its second moment (Eq. (17)),
-//   g_i^eq += -(9/2) w_i [sig:e_i e_i - tr(sig)/3],
-// a term with zero mass and momentum.
+// sig the symmetric stress of the equilibrium.
 template <typename T>
 __host__ __device__ __forceinline__ void lb_collide_split(const Coef<T> &c, T g[19], const T F[3], const T sig[6], T u[3],
                                                  T &rho)
 {
-    T drho, j[3];
-    lb_moments(g, drho, j);
-    rho = c.rho0 + drho;
-    const T irho = T(1) / rho;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = (j[a] + T(0.5) * F[a]) * irho;
-    const T uu15 = T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-    const T keep = T(1) - c.omega;
-    const T tr3 = (sig[0] + sig[3] + sig[5]) / T(3);
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const T w = lb_weight<T>(i);
-        const T ex = T(CX[i]), ey = T(CY[i]), ez = T(CZ[i]);
-        const T eu = ex * u[0] + ey * u[1] + ez * u[2];
-        const T eF = ex * F[0] + ey * F[1] + ez * F[2];
-        const T see = sig[0] * ex * ex + sig[3] * ey * ey + sig[5] * ez * ez
-                    + T(2) * (sig[1] * ex * ey + sig[2] * ex * ez + sig[4] * ey * ez);
-        const T geq = w * drho + w * rho * (T(3) * eu + T(4.5) * eu * eu - uu15) - T(4.5) * w * (see - tr3);
-        const T src = c.pref * w * (T(3) * (eF - uF) + T(9) * eu * eF);
-        g[i] = keep * g[i] + c.omega * geq + src;
-    }
+    lb_update<T, true>(c, g, F, sig, u, rho);
 }
 
 // ---------------------------------------------------------------- D3Q15

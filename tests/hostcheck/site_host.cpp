@@ -7,17 +7,63 @@
 //
 // input  (doubles): nx ny nz, A0 gamma K q0 Gamma xi tau rho0, Q [5][N], u [3][N]
 // output (doubles): H [5][N], f [N], Pi [9][N] (row-major 3x3), R [5][N]
+//
+// With a third argument `lb`, the D3Q19 collision instead: pulls the
+// populations g_i(x - e_i) and applies lb_collide with the force F, then
+// lb_collide_split with the body force F and the stress sig.
+// input  (doubles): the 11 header values, g [19][N], F [3][N], sig [6][N] (xx xy xz yy yz zz)
+// output (doubles): g' [19][N], rho [N], u [3][N] of lb_collide, then the same of lb_collide_split
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "../../paper_0901_3293_amd/csrc/kernels.h"
 #include "../../paper_0901_3293_amd/csrc/site.h"
 #include "../../paper_0901_3293_amd/csrc/sitekern.h"
 
+static int collide(const hlb::Coef<double> &c, int nx, int ny, int nz, FILE *fi, const char *outpath)
+{
+    const long N = long(nx) * ny * nz;
+    std::vector<double> g(19 * N), F(3 * N), sig(6 * N);
+    if (std::fread(g.data(), sizeof(double), 19 * N, fi) != size_t(19 * N)) return 5;
+    if (std::fread(F.data(), sizeof(double), 3 * N, fi) != size_t(3 * N)) return 6;
+    if (std::fread(sig.data(), sizeof(double), 6 * N, fi) != size_t(6 * N)) return 6;
+    auto at = [&](int x, int y, int z) {
+        x = (x + nx) % nx;
+        y = (y + ny) % ny;
+        z = (z + nz) % nz;
+        return long(x) + nx * (long(y) + ny * long(z));
+    };
+    std::vector<double> out(46 * N);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const long s = at(x, y, z);
+                double gp[19], gs[19], f[3], sg[6], u[3], rho;
+                for (int i = 0; i < 19; ++i)
+                    gp[i] = gs[i] = g[i * N + at(x - hlb::CX[i], y - hlb::CY[i], z - hlb::CZ[i])];
+                for (int a = 0; a < 3; ++a) f[a] = F[a * N + s];
+                for (int k = 0; k < 6; ++k) sg[k] = sig[k * N + s];
+                hlb::lb_collide(c, gp, f, u, rho);
+                for (int i = 0; i < 19; ++i) out[i * N + s] = gp[i];
+                out[19 * N + s] = rho;
+                for (int a = 0; a < 3; ++a) out[(20 + a) * N + s] = u[a];
+                hlb::lb_collide_split(c, gs, f, sg, u, rho);
+                for (int i = 0; i < 19; ++i) out[(23 + i) * N + s] = gs[i];
+                out[42 * N + s] = rho;
+                for (int a = 0; a < 3; ++a) out[(43 + a) * N + s] = u[a];
+            }
+    FILE *fo = std::fopen(outpath, "wb");
+    if (!fo) return 7;
+    std::fwrite(out.data(), sizeof(double), out.size(), fo);
+    std::fclose(fo);
+    return 0;
+}
+
 int main(int argc, char **argv)
 {
-    if (argc != 3) return 2;
+    if (argc != 3 && !(argc == 4 && std::string(argv[3]) == "lb")) return 2;
     FILE *fi = std::fopen(argv[1], "rb");
     if (!fi) return 3;
     double hdr[11];
@@ -33,11 +79,16 @@ int main(int argc, char **argv)
     p.xi = hdr[8];
     p.tau = hdr[9];
     p.rho0 = hdr[10];
+    const hlb::Coef<double> c = hlb::make_coef<double>(p);
+    if (argc == 4) {
+        const int rc = collide(c, nx, ny, nz, fi, argv[2]);
+        std::fclose(fi);
+        return rc;
+    }
     std::vector<double> Q(5 * N), u(3 * N);
     if (std::fread(Q.data(), sizeof(double), 5 * N, fi) != size_t(5 * N)) return 5;
     if (std::fread(u.data(), sizeof(double), 3 * N, fi) != size_t(3 * N)) return 6;
     std::fclose(fi);
-    const hlb::Coef<double> c = hlb::make_coef<double>(p);
     auto at = [&](int x, int y, int z) {
         x = (x + nx) % nx;
         y = (y + ny) % ny;

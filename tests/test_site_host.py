@@ -63,3 +63,37 @@ def test_site_physics_matches_oracle(orc, site_host, tmp_path, shape, seed, q0, 
     Rr5 = np.stack([Rr[3 * a + b] for a, b in Q5_TO_9])
     errs = {"H": rel(H5, Hr5), "f": rel(f, fr), "Pi": rel(Pi9, Pir), "R": rel(R5, Rr5)}
     assert max(errs.values()) <= 1e-13, errs
+
+
+def collide_host(exe, tmp, p, g, F3, sig6):
+    nz, ny, nx = g.shape[1:]
+    hdr = np.array([nx, ny, nz, p.A0, p.gamma, p.K, p.q0, p.Gamma, p.xi, p.tau, p.rho0], dtype=np.float64)
+    fin, fout = os.path.join(tmp, "lbin.bin"), os.path.join(tmp, "lbout.bin")
+    np.concatenate([hdr, g.ravel(), F3.ravel(), sig6.ravel()]).tofile(fin)
+    subprocess.check_call([exe, fin, fout, "lb"])
+    out = np.fromfile(fout, dtype=np.float64).reshape(46, nz, ny, nx)
+    return (out[0:19], out[19], out[20:23]), (out[23:42], out[42], out[43:46])
+
+
+@pytest.mark.parametrize("shape,seed", [((7, 5, 6), 4), ((4, 9, 3), 5)])
+@pytest.mark.parametrize("tau", [0.8, 2.5])
+def test_collision_matches_oracle(orc, site_host, tmp_path, shape, seed, tau):
+    """The D3Q19 collision of the kernels (lb_collide, and lb_collide_split
+    with the stress in the equilibrium; Eqs. (16), (17)), applied to the
+    pulled populations of a perturbed lattice with a force and a stress of
+    the size of the flow's, equals the oracle's LB step (g', rho, u) within
+    1e-13 relative per field."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    p = I.PhysParams(K=0.02, q0=0.3, gamma=3.1, xi=0.7, Gamma=0.4, tau=tau)
+    op = orc.params(**p.as_dict())
+    rho = 1.0 + rng.uniform(-0.02, 0.02, size=(nz, ny, nx))
+    u3 = rng.uniform(-0.05, 0.05, size=(3, nz, ny, nx))
+    g = orc.init_g(op, rho, u3) + rng.uniform(-2e-3, 2e-3, size=(19, nz, ny, nx))
+    F3 = rng.uniform(-1e-3, 1e-3, size=(3, nz, ny, nx))
+    sig6 = rng.uniform(-1e-3, 1e-3, size=(6, nz, ny, nx))
+    sig9 = np.stack([sig6[k] for k in (0, 1, 2, 1, 3, 4, 2, 4, 5)])
+    plain, split = collide_host(site_host, str(tmp_path), p, g, F3, sig6)
+    for got, ref in ((plain, orc.lb(op, g, F3)), (split, orc.lb_split(op, g, F3, sig9))):
+        errs = {name: rel(a, b) for name, a, b in zip(("g", "rho", "u"), got, ref)}
+        assert max(errs.values()) <= 1e-13, errs
