@@ -1,9 +1,11 @@
 """The per-site physics of the HIP path (site.h: molecular field, free
-energy, chemical stress, right-hand side of the Q equation), built for the
-host and evaluated at every site of small periodic lattices with the
-kernels' own stencils (tests/hostcheck/site_host.cpp), against the FP64
-oracle's lattice routines: H, f, Pi and R within 1e-13 relative per field.
-This checks the GPU arithmetic on the CPU, before any kernel runs."""
+energy, chemical stress, right-hand side of the Q equation, and the D3Q19
+collision with and without the split coupling's equilibrium stress), built
+for the host and evaluated at every site of small periodic lattices with the
+kernels' own stencils and pulls (tests/hostcheck/site_host.cpp), against the
+FP64 oracle's lattice routines: H, f, Pi and R, and g', rho and u of the LB
+step, within 1e-13 relative per field.  This checks the GPU arithmetic on the
+CPU, before any kernel runs."""
 import os
 import subprocess
 
