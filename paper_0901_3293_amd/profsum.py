@@ -11,6 +11,9 @@ usage: python -m paper_0901_3293_amd.profsum TRACE_DB [FETCH_DB WRITE_DB]
                    GRBM_GUI_ACTIVE: VALU instructions per site and the time
                    their issue takes at the chip's vector rate against the
                    kernel's duration)
+       [--stall DB] (a pass of SQ_WAVE_CYCLES and other SQ_ cycle counters,
+                   e.g. SQ_WAIT_ANY, SQ_WAIT_INST_ANY, SQ_ACTIVE_INST_*: each
+                   as a share of the cycles the waves were resident)
 With the trace alone: calls, average and total duration per kernel, and the
 algorithmic rate where --alg gives the kernel's values per site.
 """
@@ -88,8 +91,9 @@ def counter(db, cname):
         d[k].append(red(vals))
     if COPY in d:
         top = max(d[COPY])
-        d[COPY] = [v for v in d[COPY] if v > 0.5 * top]
-    return {k: sum(v) / len(v) for k, v in d.items()}
+        if top > 0:
+            d[COPY] = [v for v in d[COPY] if v > 0.5 * top]
+    return {k: sum(v) / len(v) for k, v in d.items() if v}
 
 
 # Vector issue rate of the chip: 256 CUs x 4 SIMDs, one 64-lane VALU
@@ -117,6 +121,23 @@ def valu_table(t, db, sites):
               f"{alu_us / us:7.2f} {gui / us:8.0f}")
 
 
+def stall_table(t, db):
+    """Per kernel: every SQ_ counter of the pass (summed over the chip per
+    dispatch) as a share of SQ_WAVE_CYCLES, the cycles its waves were
+    resident -- the share of wave time spent waiting, or issuing a given
+    kind of instruction."""
+    con = sqlite3.connect(db)
+    names = sorted(r[0] for r in con.execute("select distinct counter_name from pmc_events")
+                   if r[0].startswith("SQ_") and r[0] != "SQ_WAVE_CYCLES")
+    cyc = counter(db, "SQ_WAVE_CYCLES")
+    cs = {c: counter(db, c) for c in names}
+    print(f"{'kernel':12s} {'avg_us':>8s} " + " ".join(f"{c[3:]:>16s}" for c in names))
+    for k, (n, us) in sorted(t.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+        if k == COPY or not cyc.get(k):
+            continue
+        print(f"{k:12s} {us:8.2f} " + " ".join(f"{cs[c].get(k, float('nan')) / cyc[k]:16.3f}" for c in names))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("trace_db")
@@ -130,12 +151,17 @@ def main():
     ap.add_argument("--command", default="")
     ap.add_argument("--mfma", action="store_true")
     ap.add_argument("--valu", default=None, help="database of a VALU counter pass")
+    ap.add_argument("--stall", default=None, help="database of a pass of SQ_ cycle counters with SQ_WAVE_CYCLES")
     ap.add_argument("--traffic-json", default=None, metavar="PREC",
                     help="also print the line 'bench-traffic: {json}' with the HBM bytes per dispatch of "
                          "every step kernel for precision PREC (fp32/fp64), tagged with the kernel sources' hash")
     a = ap.parse_args()
     alg = {k: float(v) for k, v in (x.split("=") for x in a.alg)}
     t = trace(a.trace_db)
+    if a.stall:
+        print(f"# {a.title}")
+        stall_table(t, a.stall)
+        return
     if a.valu:
         print(f"# {a.title}")
         if a.command:
